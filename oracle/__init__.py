@@ -1,0 +1,39 @@
+"""FP64 CPU oracle for the VQ-NQS local-energy path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) may import or call this package; only the tests, the
+smoke check and the CPU-baseline leg of the benchmark use it.  It shares no
+code with the GPU implementation: only the seeded input generators in
+``workloads`` serve both.
+
+Plain, slow, obviously-correct NumPy float64 code that follows the paper:
+
+* ``lattice``  - nearest-neighbour bonds of the L x L lattice, the exact
+  diagonal of the Heisenberg Hamiltonian and its off-diagonal (spin-exchange)
+  neighbours in the Marshall-rotated basis (Sec. 2 k-local discussion; Sec. 4
+  Hamiltonian and Marshall sign rule).
+* ``network``  - the autoregressive transformer with a vector quantizer after
+  each self-attention (Sec. 3.1, eqs. 4-6; chain-rule distribution of Sec. 2),
+  log psi = 1/2 log P with zero phase (Sec. 4).
+* ``eloc``     - the local energy of eq. (2) by naive re-evaluation of psi on
+  every neighbour, and the code-diff deduplicated evaluation of Sec. 3.2 as a
+  cross-check with its changed-row counters.
+* ``ed``       - exact diagonalisation from an independent Pauli Kronecker
+  construction of the Hamiltonian (pins units, boundary conditions and sign).
+* ``grad``     - reference d log psi / d theta with the straight-through
+  estimator of eqs. (7)-(8), in float64 autograd on the CPU.
+
+Pins (tests/test_oracle_*.py):
+  lattice/eloc: exact-diagonalisation energies (the paper's 4x4 table entry),
+    the sum rule <psi|H|psi>/<psi|psi> = Born-weighted mean of E_loc, zero
+    variance for exact eigenstates, closed forms for constant psi.
+  network: normalisation of the autoregressive distribution over all 2^N
+    states, causal-prefix invariance, per-operation reduction to library
+    routines (layer norm, causal attention, GELU, nearest-codeword search),
+    head-permutation invariance.
+  eloc_dedup: identical codes and equal E_loc to the naive evaluation.
+  grad: central finite differences of the relaxed straight-through surrogate.
+  The absolute value of log psi for a random network has no external value to
+  compare against ("parity unpinned" beyond the structural pins above).
+"""
+from . import lattice, network, eloc, ed  # noqa: F401

@@ -1,0 +1,84 @@
+"""Workload configurations (lattice + transformer shape + batch).
+
+The five workloads mirror the paper's setting (2-D spin-1/2 Heisenberg model,
+Sec. 4; autoregressive transformer with a vector quantizer after every
+self-attention, Sec. 3.1) at the sizes this project measures:
+
+  small   4x4,   d=16,  1 layer,  2 heads, MLP 64,   Q=16,   B=256,  fp64
+  medium  10x10, d=64,  4 layers, 4 heads, MLP 256,  Q=256,  B=4096, fp32
+  large   16x16, d=128, 8 layers, 8 heads, MLP 512,  Q=1024, B=8192, bf16
+  multi   6x6..20x20 lattices, d=128, 6 layers, 8 heads, MLP 512, Q=512, bf16
+  grad    20x20, d=256, 12 layers, 8 heads, MLP 1024, Q=1024, B=2048, bf16
+
+Lattices are periodic with J=1 in the Marshall-rotated basis unless stated.
+"""
+from dataclasses import dataclass, replace, asdict
+
+PRECISIONS = ("f64", "f32", "bf16")
+
+
+@dataclass(frozen=True)
+class ModelConfig:
+    name: str
+    L: int
+    d_model: int
+    n_layers: int
+    n_heads: int
+    d_ff: int
+    codebook_size: int          # Q, codes per quantizer head
+    vq_heads: int = 1           # H of the multi-head quantizer
+    periodic: bool = True
+    marshall: bool = True
+    J: float = 1.0
+    precision: str = "f64"
+    batch: int = 256
+    spin_seed: int = 1000
+    param_seed: int = 0
+
+    @property
+    def N(self) -> int:
+        return self.L * self.L
+
+    @property
+    def d_head(self) -> int:
+        return self.d_model // self.n_heads
+
+    def as_dict(self):
+        return asdict(self)
+
+
+CONFIGS = {
+    "small": ModelConfig("small", L=4, d_model=16, n_layers=1, n_heads=2,
+                         d_ff=64, codebook_size=16, precision="f64",
+                         batch=256, spin_seed=1001),
+    "medium": ModelConfig("medium", L=10, d_model=64, n_layers=4, n_heads=4,
+                          d_ff=256, codebook_size=256, precision="f32",
+                          batch=4096, spin_seed=1002),
+    "large": ModelConfig("large", L=16, d_model=128, n_layers=8, n_heads=8,
+                         d_ff=512, codebook_size=1024, precision="bf16",
+                         batch=8192, spin_seed=1003),
+    "grad": ModelConfig("grad", L=20, d_model=256, n_layers=12, n_heads=8,
+                        d_ff=1024, codebook_size=1024, precision="bf16",
+                        batch=2048, spin_seed=1005),
+}
+
+# Mixed-lattice batch: one parameter buffer per lattice, uneven sample counts.
+MULTI_LATTICE = tuple(
+    ModelConfig(f"multi_L{L}", L=L, d_model=128, n_layers=6, n_heads=8,
+                d_ff=512, codebook_size=512, precision="bf16", batch=B,
+                spin_seed=1400 + k, param_seed=k)
+    for k, (L, B) in enumerate([(6, 512), (8, 1024), (12, 2048), (16, 4096),
+                                (20, 8192)]))
+
+
+def config_by_name(name: str) -> ModelConfig:
+    if name in CONFIGS:
+        return CONFIGS[name]
+    for c in MULTI_LATTICE:
+        if c.name == name:
+            return c
+    raise KeyError(name)
+
+
+def with_batch(cfg: ModelConfig, batch: int, **kw) -> ModelConfig:
+    return replace(cfg, batch=batch, **kw)

@@ -1,0 +1,47 @@
+"""Flat parameter layout of the VQ transformer (storage order, row-major).
+
+Every weight matrix is stored [in][out] and applied as x @ W.  Token ids:
+0 = spin +1, 1 = spin -1, 2 = beginning-of-sequence.
+
+  tok_emb[3][d]  pos_emb[N][d]
+  per layer:
+    ln1_g[d] ln1_b[d]  W_qkv[d][3d] b_qkv[3d]  codebook[H][Q][d/H]
+    W_o[d][d] b_o[d]   ln2_g[d] ln2_b[d]
+    W1[d][d_ff] b1[d_ff]  W2[d_ff][d] b2[d]
+  lnf_g[d] lnf_b[d]  W_head[d][2] b_head[2]
+
+Each entry carries a ``kind`` tag used only by the seeded initialiser:
+"w" (Gaussian), "gain" (set to 1) or "bias" (set to 0).
+"""
+
+
+def param_layout(cfg):
+    d, N, Q, H, F = (cfg.d_model, cfg.N, cfg.codebook_size, cfg.vq_heads,
+                     cfg.d_ff)
+    ent = [("tok_emb", (3, d), "w"), ("pos_emb", (N, d), "w")]
+    for l in range(cfg.n_layers):
+        p = f"l{l}."
+        ent += [
+            (p + "ln1_g", (d,), "gain"), (p + "ln1_b", (d,), "bias"),
+            (p + "W_qkv", (d, 3 * d), "w"), (p + "b_qkv", (3 * d,), "bias"),
+            (p + "codebook", (H, Q, d // H), "w"),
+            (p + "W_o", (d, d), "w"), (p + "b_o", (d,), "bias"),
+            (p + "ln2_g", (d,), "gain"), (p + "ln2_b", (d,), "bias"),
+            (p + "W1", (d, F), "w"), (p + "b1", (F,), "bias"),
+            (p + "W2", (F, d), "w"), (p + "b2", (d,), "bias"),
+        ]
+    ent += [("lnf_g", (d,), "gain"), ("lnf_b", (d,), "bias"),
+            ("W_head", (d, 2), "w"), ("b_head", (2,), "bias")]
+    out, off = [], 0
+    for name, shape, kind in ent:
+        n = 1
+        for s in shape:
+            n *= s
+        out.append((name, shape, kind, off, n))
+        off += n
+    return out
+
+
+def param_count(cfg) -> int:
+    lay = param_layout(cfg)
+    return lay[-1][3] + lay[-1][4]
