@@ -1,0 +1,181 @@
+/*
+ * vqnqs.h - C ABI of the VQ-NQS local-energy library for MI355X (gfx950).
+ *
+ * The library evaluates a vector-quantized autoregressive transformer wave
+ * function psi (Sharir, Chan, Anandkumar: "Towards Neural Variational Monte
+ * Carlo That Scales Linearly with System Size", Sec. 3.1, eqs. 4-6) and the
+ * variational Monte Carlo local energy of eq. (2),
+ *
+ *     E_loc(s) = sum_s' H_{s,s'} psi(s') / psi(s),
+ *
+ * for the spin-1/2 Heisenberg model H = J sum_<ij> S_i . S_j on an L x L
+ * square lattice (Sec. 4), in the Marshall-rotated basis where the
+ * off-diagonal element of every anti-aligned bond is -J/2 and psi > 0
+ * (zero phase, Sec. 4).  The neighbours s' of a sample s are the
+ * configurations with the two spins of one anti-aligned nearest-neighbour
+ * bond exchanged (k-local rows, Sec. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers marked DEVICE are device (HBM) addresses owned by the caller;
+ * HOST pointers are ordinary host memory.  The library never allocates,
+ * frees or keeps caller memory, and never synchronises the host: every
+ * compute call only enqueues kernels on `stream` (a hipStream_t; NULL is the
+ * legacy default stream) and returns.  Argument errors are detected on the
+ * host before anything is enqueued and are returned as a status; a status of
+ * VQNQS_ERR_HIP means a HIP runtime call failed while enqueueing.
+ *
+ * Spins: int8 array [batch][N], N = L*L, row-major sites i = r*L + c, values
+ * +1 or -1.  Any other value sets VQNQS_ERR_BAD_SPIN in the device status
+ * word of the workspace (read it with vqnqs_workspace_status); results for
+ * such a batch are unspecified.
+ *
+ * Parameters: one flat DEVICE buffer in this order (row-major, every
+ * matrix stored [in][out] and applied as x W; token 0 = spin +1, 1 = spin
+ * -1, 2 = beginning of sequence):
+ *     tok_emb[3][d]  pos_emb[N][d]
+ *     per layer: ln1_g[d] ln1_b[d] W_qkv[d][3d] b_qkv[3d]
+ *                codebook[H][Q][d/H] W_o[d][d] b_o[d] ln2_g[d] ln2_b[d]
+ *                W1[d][d_ff] b1[d_ff] W2[d_ff][d] b2[d]
+ *     lnf_g[d] lnf_b[d] W_head[d][2] b_head[2]
+ * The element type is double for VQNQS_F64 and float otherwise (FP32
+ * master copy; the BF16 mode converts to bfloat16 inside the workspace).
+ *
+ * Network (Sec. 3.1): one token per spin, the input at position i is the
+ * previous spin's token (beginning-of-sequence at i = 0); pre-LayerNorm
+ * blocks  h = LN1(x), [q|k|v] = h W_qkv + b, a = causal MHSA(q,k,v),
+ * z = VQ(a) (nearest codeword per quantizer head, lowest index on ties),
+ * x' = x + z W_o + b_o, x = x' + W2 GELU(LN2(x') W1 + b1) + b2;  final LN,
+ * head d->2, log-softmax;  log psi(s) = 1/2 sum_i log P(s_i | s_<i).
+ *
+ * Workspace: a DEVICE buffer of ws_bytes bytes, 256-byte aligned.  The call
+ * processes the batch in chunks of as many samples as fit; the minimum that
+ * works is vqnqs_workspace_size(cfg, batch, mode, 1, &bytes).  Concurrent
+ * calls must use distinct workspaces.  Identical inputs give bitwise
+ * identical outputs.
+ */
+#ifndef VQNQS_H
+#define VQNQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VQNQS_OK = 0,
+    VQNQS_ERR_NULL_POINTER = 1,      /* a required pointer is NULL            */
+    VQNQS_ERR_INVALID_CONFIG = 2,    /* inconsistent vqnqs_config             */
+    VQNQS_ERR_INVALID_SHAPE = 3,     /* batch < 0, or sizes out of range      */
+    VQNQS_ERR_WORKSPACE_TOO_SMALL = 4,
+    VQNQS_ERR_UNSUPPORTED = 5,       /* valid but not implemented (e.g. d/n_heads) */
+    VQNQS_ERR_BAD_SPIN = 6,          /* a spin value other than +1/-1          */
+    VQNQS_ERR_HIP = 7                /* a HIP runtime call failed             */
+} vqnqs_status;
+
+typedef enum { VQNQS_F64 = 0, VQNQS_F32 = 1, VQNQS_BF16 = 2 } vqnqs_precision;
+
+/* PLAIN re-evaluates psi from scratch on every neighbour (the definition of
+ * eq. 2).  DEDUP reuses the sample's own evaluation and recomputes the
+ * per-location operations only on rows whose input or VQ code differs
+ * (Sec. 3.2); attention and the quantizer run on every row at or after the
+ * first changed input, the rows before it being provably unchanged. */
+typedef enum { VQNQS_PLAIN = 0, VQNQS_DEDUP = 1 } vqnqs_mode;
+
+/* flags (DEDUP only): keep the sample's VQ code without a codebook search
+ * when the attention output moved by less than half the gap between its
+ * best and second-best code distances (exact by the triangle inequality,
+ * with a floating-point allowance).  Results are unchanged by this flag. */
+#define VQNQS_FLAG_CERTIFIED_VQ 1
+
+typedef struct {
+    int32_t L;             /* lattice side, N = L*L sites (3 <= L when periodic) */
+    int32_t periodic;      /* 1 periodic, 0 open boundaries                      */
+    int32_t marshall;      /* 1: off-diagonal -J/2 (needs a bipartite lattice)   */
+    double  J;             /* exchange coupling                                  */
+    int32_t d_model;       /* model width d                                      */
+    int32_t n_layers;
+    int32_t n_heads;       /* attention heads; d_model/n_heads in {4,8,16,32,64} */
+    int32_t d_ff;          /* MLP width                                          */
+    int32_t codebook_size; /* Q codes per quantizer head                         */
+    int32_t vq_heads;      /* H quantizer heads; d_model % vq_heads == 0         */
+    int32_t precision;     /* vqnqs_precision                                    */
+    int32_t flags;         /* VQNQS_FLAG_*                                       */
+} vqnqs_config;
+
+/* Counters written by vqnqs_local_energy (int64, VQNQS_NCOUNTERS entries,
+ * accumulated over the call; the call zeroes them first). */
+#define VQNQS_NCOUNTERS 96
+enum {
+    VQNQS_CTR_SAMPLES = 0,      /* samples evaluated                        */
+    VQNQS_CTR_NEIGHBOURS = 1,   /* sum of neighbour counts                  */
+    VQNQS_CTR_ATTN_ROWS = 2,    /* query rows through attention, all layers */
+    VQNQS_CTR_ATTN_PAIRS = 3,   /* (query, key) pairs through attention     */
+    VQNQS_CTR_VQ_ROWS = 4,      /* rows with a full codebook search         */
+    VQNQS_CTR_VQ_CERTIFIED = 5, /* rows whose code was certified unchanged  */
+    VQNQS_CTR_QKV_ROWS = 6,     /* rows through LN1 + QKV projection        */
+    VQNQS_CTR_MLP_ROWS = 7,     /* rows through out-projection + MLP        */
+    VQNQS_CTR_HEAD_ROWS = 8,    /* rows through the output head             */
+    VQNQS_CTR_CHANGED0 = 16     /* [16 + l] = sum over neighbours of |C_l|,
+                                   l = 0 (changed inputs) .. n_layers       */
+};
+
+/* Number of parameters of the flat buffer; < 0 for an invalid config. */
+int64_t vqnqs_param_count(const vqnqs_config* cfg);
+
+/* Workspace bytes needed to evaluate `batch` samples in `mode` processing
+ * `chunk` samples at a time (chunk <= 0 means the whole batch at once).
+ * mode is a vqnqs_mode for vqnqs_local_energy, or -1 for
+ * vqnqs_forward_logpsi / vqnqs_neighbours. */
+vqnqs_status vqnqs_workspace_size(const vqnqs_config* cfg, int64_t batch,
+                                  int32_t mode, int64_t chunk, size_t* bytes);
+
+/* Neighbour enumeration (k-local rows, Sec. 2; Heisenberg bonds, Sec. 4).
+ * Bonds are numbered b = 2*i + dir for site i = r*L + c, dir 0 linking
+ * (r, c)-(r, c+1 mod L), dir 1 linking (r, c)-(r+1 mod L, c); open
+ * boundaries drop the wrapping bonds.
+ *   bonds [batch][2N] int16 DEVICE out: anti-aligned bond ids in increasing
+ *         order, entries past count[b] set to -1
+ *   count [batch]     int32 DEVICE out: number of anti-aligned bonds
+ *   diag  [batch]     double DEVICE out, nullable: (J/4) sum_b s_i s_j      */
+vqnqs_status vqnqs_neighbours(const vqnqs_config* cfg, const int8_t* spins,
+                              int64_t batch, int16_t* bonds, int32_t* count,
+                              double* diag, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* log psi(s) = 1/2 log P(s) for every sample (chain rule, Sec. 2; network
+ * of Sec. 3.1).
+ *   logpsi [batch] double DEVICE out
+ *   codes  [batch][n_layers][N][vq_heads] int32 DEVICE out, nullable: the
+ *          quantizer indices I_VQ of eq. (5) at every layer and position    */
+vqnqs_status vqnqs_forward_logpsi(const vqnqs_config* cfg, const void* params,
+                                  const int8_t* spins, int64_t batch,
+                                  double* logpsi, int32_t* codes, void* ws,
+                                  size_t ws_bytes, void* stream);
+
+/* Local energy of eq. (2) for every sample, in `mode`.
+ *   eloc     [batch] double DEVICE out
+ *   stats    [2] double DEVICE out, nullable: batch mean and (biased)
+ *            variance of E_loc (the estimator of eq. 1 for Born samples)
+ *   ratios   [batch][2N] double DEVICE out, nullable: psi(s')/psi(s) per
+ *            neighbour in bond order (entries past the count are 0)
+ *   counters [VQNQS_NCOUNTERS] int64 DEVICE out, nullable: work counters   */
+vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
+                                const int8_t* spins, int64_t batch,
+                                int32_t mode, double* eloc, double* stats,
+                                double* ratios, int64_t* counters, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* Reads the device status word of a workspace used by a previous call:
+ * synchronises `stream`, then returns VQNQS_OK or VQNQS_ERR_BAD_SPIN. */
+vqnqs_status vqnqs_workspace_status(const void* ws, void* stream);
+
+const char* vqnqs_status_string(vqnqs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VQNQS_H */

@@ -1,0 +1,17 @@
+"""VQ-NQS local energy on MI355X: Python binding of libvqnqs.so.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library (see include/vqnqs.h for the contract).  PyTorch supplies device
+memory and the current stream.  Importing this package does not load the
+library; the first call does, and fails loudly if it has not been built.
+"""
+from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
+                  NCOUNTERS, CTR, VQNQSError, library_path, load_library,
+                  exported_symbols, param_count, workspace_size, neighbours,
+                  forward_logpsi, local_energy, make_config)
+
+__all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
+           "FLAG_CERTIFIED_VQ", "NCOUNTERS", "CTR", "VQNQSError",
+           "library_path", "load_library", "exported_symbols", "param_count",
+           "workspace_size", "neighbours", "forward_logpsi", "local_energy",
+           "make_config"]

@@ -1,0 +1,195 @@
+"""ctypes binding of the C ABI in include/vqnqs.h (same entry-point names)."""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+F64, F32, BF16 = 0, 1, 2
+PLAIN, DEDUP = 0, 1
+FLAG_CERTIFIED_VQ = 1
+NCOUNTERS = 96
+CTR = dict(samples=0, neighbours=1, attn_rows=2, attn_pairs=3, vq_rows=4,
+           vq_certified=5, qkv_rows=6, mlp_rows=7, head_rows=8, changed0=16)
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16}
+_STATUS = {0: "ok", 1: "null pointer", 2: "invalid config", 3: "invalid shape",
+           4: "workspace too small", 5: "unsupported configuration",
+           6: "spin value other than +1/-1", 7: "HIP runtime error"}
+
+EXPORTS = ["vqnqs_param_count", "vqnqs_workspace_size", "vqnqs_neighbours",
+           "vqnqs_forward_logpsi", "vqnqs_local_energy",
+           "vqnqs_workspace_status", "vqnqs_status_string"]
+
+
+class VQNQSError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__(f"{fn}: {_STATUS.get(status, status)} ({status})")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("periodic", ctypes.c_int32),
+                ("marshall", ctypes.c_int32), ("J", ctypes.c_double),
+                ("d_model", ctypes.c_int32), ("n_layers", ctypes.c_int32),
+                ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
+                ("codebook_size", ctypes.c_int32), ("vq_heads", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+def make_config(mc, precision=None, flags=0):
+    """Config from any object with the workload fields (L, d_model, ...)."""
+    prec = mc.precision if precision is None else precision
+    prec = _PREC.get(prec, prec)
+    return Config(mc.L, int(mc.periodic), int(mc.marshall), float(mc.J),
+                  mc.d_model, mc.n_layers, mc.n_heads, mc.d_ff,
+                  mc.codebook_size, mc.vq_heads, int(prec), int(flags))
+
+
+_lib = None
+
+
+def library_path():
+    return os.path.join(PKG, "libvqnqs.so")
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is not built: run paper_2212_11296_amd.build.build() "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, SZ = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                       ctypes.c_size_t)
+    C = ctypes.POINTER(Config)
+    lib.vqnqs_param_count.argtypes = [C]
+    lib.vqnqs_param_count.restype = I64
+    lib.vqnqs_workspace_size.argtypes = [C, I64, I32, I64,
+                                         ctypes.POINTER(SZ)]
+    lib.vqnqs_workspace_size.restype = ctypes.c_int
+    lib.vqnqs_neighbours.argtypes = [C, P, I64, P, P, P, P, SZ, P]
+    lib.vqnqs_neighbours.restype = ctypes.c_int
+    lib.vqnqs_forward_logpsi.argtypes = [C, P, P, I64, P, P, P, SZ, P]
+    lib.vqnqs_forward_logpsi.restype = ctypes.c_int
+    lib.vqnqs_local_energy.argtypes = [C, P, P, I64, I32, P, P, P, P, P, SZ,
+                                       P]
+    lib.vqnqs_local_energy.restype = ctypes.c_int
+    lib.vqnqs_workspace_status.argtypes = [P, P]
+    lib.vqnqs_workspace_status.restype = ctypes.c_int
+    lib.vqnqs_status_string.argtypes = [ctypes.c_int]
+    lib.vqnqs_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    lib = load_library()
+    return {name: hasattr(lib, name) for name in EXPORTS}
+
+
+def _check(fn, st):
+    if st != 0:
+        raise VQNQSError(fn, st)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def param_count(cfg):
+    n = load_library().vqnqs_param_count(ctypes.byref(cfg))
+    if n < 0:
+        raise VQNQSError("vqnqs_param_count", -n)
+    return n
+
+
+def workspace_size(cfg, batch, mode, chunk=0):
+    out = ctypes.c_size_t(0)
+    _check("vqnqs_workspace_size",
+           load_library().vqnqs_workspace_size(ctypes.byref(cfg), batch, mode,
+                                               chunk, ctypes.byref(out)))
+    return out.value
+
+
+def _workspace(cfg, batch, mode, ws, budget):
+    import torch
+    if ws is not None:
+        return ws
+    need_all = workspace_size(cfg, max(batch, 1), mode, 0)
+    size = min(need_all, max(budget, workspace_size(cfg, max(batch, 1), mode,
+                                                    1)))
+    return torch.empty(size, dtype=torch.uint8, device="cuda")
+
+
+def _check_status(ws):
+    _check("vqnqs_workspace_status",
+           load_library().vqnqs_workspace_status(_ptr(ws), _stream()))
+
+
+def neighbours(cfg, spins, ws=None, check=True):
+    import torch
+    B = spins.shape[0]
+    N = cfg.L * cfg.L
+    ws = _workspace(cfg, B, -1, ws, 1 << 20)
+    bonds = torch.empty((B, 2 * N), dtype=torch.int16, device="cuda")
+    count = torch.empty(B, dtype=torch.int32, device="cuda")
+    diag = torch.empty(B, dtype=torch.float64, device="cuda")
+    _check("vqnqs_neighbours", load_library().vqnqs_neighbours(
+        ctypes.byref(cfg), _ptr(spins), B, _ptr(bonds), _ptr(count),
+        _ptr(diag), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)
+    return bonds, count, diag
+
+
+def forward_logpsi(cfg, params, spins, codes=False, ws=None,
+                   budget=8 << 30, check=True):
+    import torch
+    B = spins.shape[0]
+    N = cfg.L * cfg.L
+    ws = _workspace(cfg, B, -1, ws, budget)
+    lp = torch.empty(B, dtype=torch.float64, device="cuda")
+    cd = (torch.empty((B, cfg.n_layers, N, cfg.vq_heads), dtype=torch.int32,
+                      device="cuda") if codes else None)
+    _check("vqnqs_forward_logpsi", load_library().vqnqs_forward_logpsi(
+        ctypes.byref(cfg), _ptr(params), _ptr(spins), B, _ptr(lp), _ptr(cd),
+        _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)
+    return (lp, cd) if codes else lp
+
+
+def local_energy(cfg, params, spins, mode=DEDUP, stats=True, ratios=False,
+                 counters=False, ws=None, budget=8 << 30, check=True,
+                 out=None):
+    """Returns a dict of device tensors: eloc [B], and optionally stats [2]
+    (mean, variance), ratios [B][2N], counters [NCOUNTERS]."""
+    import torch
+    B = spins.shape[0]
+    N = cfg.L * cfg.L
+    ws = _workspace(cfg, B, mode, ws, budget)
+    o = out if out is not None else {}
+    if "eloc" not in o:
+        o["eloc"] = torch.empty(B, dtype=torch.float64, device="cuda")
+    if stats and "stats" not in o:
+        o["stats"] = torch.empty(2, dtype=torch.float64, device="cuda")
+    if ratios and "ratios" not in o:
+        o["ratios"] = torch.empty((B, 2 * N), dtype=torch.float64,
+                                  device="cuda")
+    if counters and "counters" not in o:
+        o["counters"] = torch.empty(NCOUNTERS, dtype=torch.int64,
+                                    device="cuda")
+    _check("vqnqs_local_energy", load_library().vqnqs_local_energy(
+        ctypes.byref(cfg), _ptr(params), _ptr(spins), B, mode,
+        _ptr(o["eloc"]), _ptr(o.get("stats")), _ptr(o.get("ratios")),
+        _ptr(o.get("counters")), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)
+    return o

@@ -1,0 +1,151 @@
+// C ABI entry points: argument validation (host only, before any HIP call)
+// and dispatch to the engine.
+#include <cmath>
+
+#include "engine.h"
+#include "kernels.h"
+
+namespace {
+
+bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
+    if (!c) {
+        *err = VQNQS_ERR_NULL_POINTER;
+        return false;
+    }
+    *err = VQNQS_ERR_INVALID_CONFIG;
+    if (c->L < 1 || c->L > 32) return false;
+    if (c->periodic != 0 && c->periodic != 1) return false;
+    if (c->marshall != 0 && c->marshall != 1) return false;
+    if (c->periodic && c->L < 3) return false;              // repeated bonds
+    if (c->periodic && c->marshall && (c->L & 1)) return false;  // not bipartite
+    if (!std::isfinite(c->J)) return false;
+    if (c->d_model < 1 || c->n_layers < 0 || c->n_heads < 1 || c->d_ff < 1 ||
+        c->codebook_size < 1 || c->vq_heads < 1)
+        return false;
+    if (c->d_model % c->n_heads || c->d_model % c->vq_heads) return false;
+    if (c->precision < VQNQS_F64 || c->precision > VQNQS_BF16) return false;
+    if (c->flags & ~VQNQS_FLAG_CERTIFIED_VQ) return false;
+    *err = VQNQS_ERR_UNSUPPORTED;
+    const int dh = c->d_model / c->n_heads;
+    if (dh != 4 && dh != 8 && dh != 16 && dh != 32 && dh != 64) return false;
+    if (c->d_model > 512 || c->d_ff > 4096 || c->n_layers > VQNQS_NCOUNTERS - 17 ||
+        c->codebook_size > 65536)
+        return false;
+    const int N = c->L * c->L;
+    const size_t act = c->precision == VQNQS_F64 ? 8 : 4;
+    if (2 * (size_t)N * dh * act > 128 * 1024) return false;  // attention K/V in LDS
+    m->L = c->L;
+    m->N = N;
+    m->d = c->d_model;
+    m->nl = c->n_layers;
+    m->nh = c->n_heads;
+    m->dh = dh;
+    m->dff = c->d_ff;
+    m->Q = c->codebook_size;
+    m->H = c->vq_heads;
+    m->dseg = c->d_model / c->vq_heads;
+    m->periodic = c->periodic;
+    m->marshall = c->marshall;
+    m->precision = c->precision;
+    m->flags = c->flags;
+    m->J = c->J;
+    m->mfma = 0;
+    m->mfma = c->precision == VQNQS_BF16 && vq::mfma_shapes_ok(*m);
+    *err = VQNQS_OK;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t vqnqs_param_count(const vqnqs_config* cfg) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return -(int64_t)e;
+    return vq::param_count(m);
+}
+
+vqnqs_status vqnqs_workspace_size(const vqnqs_config* cfg, int64_t batch,
+                                  int32_t mode, int64_t chunk, size_t* bytes) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (!bytes) return VQNQS_ERR_NULL_POINTER;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP && mode != -1)
+        return VQNQS_ERR_INVALID_CONFIG;
+    if (chunk <= 0 || chunk > batch) chunk = batch > 0 ? batch : 1;
+    *bytes = vq::workspace_bytes(m, mode, chunk);
+    return VQNQS_OK;
+}
+
+vqnqs_status vqnqs_neighbours(const vqnqs_config* cfg, const int8_t* spins,
+                              int64_t batch, int16_t* bonds, int32_t* count,
+                              double* diag, void* ws, size_t ws_bytes,
+                              void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (batch < 0 || batch > ((int64_t)1 << 31) - 1) return VQNQS_ERR_INVALID_SHAPE;
+    if (!ws || (batch > 0 && (!spins || !bonds || !count)))
+        return VQNQS_ERR_NULL_POINTER;
+    return vq::neighbours(m, spins, batch, bonds, count, diag, ws, ws_bytes,
+                          (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_forward_logpsi(const vqnqs_config* cfg, const void* params,
+                                  const int8_t* spins, int64_t batch,
+                                  double* logpsi, int32_t* codes, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (!ws || (batch > 0 && (!params || !spins || !logpsi)))
+        return VQNQS_ERR_NULL_POINTER;
+    return vq::forward_logpsi(m, params, spins, batch, logpsi, codes, ws,
+                              ws_bytes, (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
+                                const int8_t* spins, int64_t batch,
+                                int32_t mode, double* eloc, double* stats,
+                                double* ratios, int64_t* counters, void* ws,
+                                size_t ws_bytes, void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP) return VQNQS_ERR_INVALID_CONFIG;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (!ws || (batch > 0 && (!params || !spins || !eloc)))
+        return VQNQS_ERR_NULL_POINTER;
+    return vq::local_energy(m, params, spins, batch, mode, eloc, stats, ratios,
+                            counters, ws, ws_bytes, (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_workspace_status(const void* ws, void* stream) {
+    if (!ws) return VQNQS_ERR_NULL_POINTER;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return VQNQS_ERR_HIP;
+    int32_t v = 0;
+    if (hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+        return VQNQS_ERR_HIP;
+    return v ? VQNQS_ERR_BAD_SPIN : VQNQS_OK;
+}
+
+const char* vqnqs_status_string(vqnqs_status s) {
+    switch (s) {
+        case VQNQS_OK: return "ok";
+        case VQNQS_ERR_NULL_POINTER: return "null pointer";
+        case VQNQS_ERR_INVALID_CONFIG: return "invalid config";
+        case VQNQS_ERR_INVALID_SHAPE: return "invalid shape";
+        case VQNQS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case VQNQS_ERR_UNSUPPORTED: return "unsupported configuration";
+        case VQNQS_ERR_BAD_SPIN: return "spin value other than +1/-1";
+        case VQNQS_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

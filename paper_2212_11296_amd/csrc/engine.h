@@ -1,0 +1,25 @@
+// Internal interface between the C ABI and the kernel orchestration.
+#pragma once
+#include "common.h"
+
+namespace vq {
+
+int64_t param_count(const ModelDims& m);
+size_t workspace_bytes(const ModelDims& m, int mode, int64_t chunk);
+int64_t pick_chunk(const ModelDims& m, int mode, int64_t batch, size_t ws);
+int64_t max_overlay_rows_per_sample(const ModelDims& m);
+
+vqnqs_status local_energy(const ModelDims& m, const void* params,
+                          const int8_t* spins, int64_t batch, int mode,
+                          double* eloc, double* stats, double* ratios,
+                          int64_t* counters, void* ws, size_t ws_bytes,
+                          hipStream_t st);
+vqnqs_status forward_logpsi(const ModelDims& m, const void* params,
+                            const int8_t* spins, int64_t batch, double* logpsi,
+                            int32_t* codes, void* ws, size_t ws_bytes,
+                            hipStream_t st);
+vqnqs_status neighbours(const ModelDims& m, const int8_t* spins, int64_t batch,
+                        int16_t* bonds, int32_t* count, double* diag, void* ws,
+                        size_t ws_bytes, hipStream_t st);
+
+}  // namespace vq

@@ -1,0 +1,158 @@
+// Kernel launchers of the VQ-NQS library (internal header).
+#pragma once
+#include "common.h"
+
+namespace vq {
+
+// A set of rows of a row-major [rows][width] buffer: either the contiguous
+// range [0, n) or the rows idx[0..n) of an index list, where n is the host
+// value n_host or, when n_dev is set, the device value *n_dev (bounded above
+// by n_host, which sizes the grid).
+struct RowSet {
+    const int64_t* idx;
+    const int32_t* n_dev;
+    int64_t n_host;
+    int32_t mult;      // rows = (*n_dev) * mult when n_dev is set
+};
+
+// Per-row sources and destinations of one transformer block.
+template <class P>
+struct BlockIO {
+    using act = typename P::act;
+    using acc = typename P::acc;
+    acc* x;            // residual rows (read, and written by the MLP stage)
+    const acc* x_in;   // MLP-stage input rows (may equal x)
+    act *q, *k, *v;    // projections
+    act* a;            // attention output
+    int32_t* codes;    // [row][H]
+    acc* margin;       // [row][H] half gap of the two best distances, nullable
+};
+
+hipError_t launch_neighbours(const int8_t* spins, int64_t batch,
+                             const ModelDims& m, int16_t* bonds,
+                             int32_t* count, double* diag, int64_t* rows_cap,
+                             int32_t* status, hipStream_t st);
+hipError_t launch_scan_desc(const int16_t* bonds, const int32_t* count,
+                            const int64_t* rows_cap, int n, int L,
+                            int32_t* nb_off, int64_t* row_off,
+                            int32_t* n_nb_total, int32_t* n_rows_total,
+                            NbDesc* desc, hipStream_t st);
+hipError_t launch_eloc(const double* diag, const int32_t* count,
+                       const int32_t* nb_off, const double* r, int n, int N,
+                       double h_off, double* eloc, double* ratios_out,
+                       hipStream_t st);
+hipError_t launch_stats(const double* e, int64_t n, double* stats,
+                        hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, int n, int64_t v, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);
+hipError_t launch_counter_add(int64_t* ctr, int slot, const int32_t* v,
+                              int64_t scale, hipStream_t st);
+hipError_t launch_counter_add_const(int64_t* ctr, int slot, int64_t v,
+                                    hipStream_t st);
+hipError_t launch_copy_codes(const int32_t* src, int64_t n, int N, int H,
+                             int nl, int l, int32_t* dst, hipStream_t st);
+
+// ---- parameter preparation (tables, norms, BF16 packs)
+template <class P>
+hipError_t launch_prepare(const ModelDims& m, const LayerW<typename P::acc>& w,
+                          typename P::acc* table, typename P::acc* cnorm,
+                          bf16* Wqkv_p, bf16* W1_p, bf16* W2_p, bf16* cb_p,
+                          hipStream_t st);
+
+// ---- BF16 matrix-core path
+bool mfma_shapes_ok(const ModelDims& m);
+hipError_t launch_round_bf16(const float* src, int64_t n, float* dst,
+                             hipStream_t st);
+hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
+                             bf16* Wqkv_p, bf16* W1_p, bf16* W2_p, bf16* cb_p,
+                             hipStream_t st);
+hipError_t launch_qkv_mfma(const ModelDims& m, const LayerW<float>& w,
+                           RowSet rows, const BlockIO<PrecBF16>& io,
+                           hipStream_t st);
+hipError_t launch_mlp_mfma(const ModelDims& m, const LayerW<float>& w,
+                           RowSet rows, const BlockIO<PrecBF16>& io,
+                           hipStream_t st);
+hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
+                          RowSet rows, const BlockIO<PrecBF16>& io,
+                          hipStream_t st);
+
+// ---- full-sequence forward pieces (samples or materialised neighbours)
+hipError_t launch_materialise(const int8_t* spins, const NbDesc* desc,
+                              const int32_t* n_dev, int64_t n_max, int N,
+                              int8_t* out, hipStream_t st);
+template <class P>
+hipError_t launch_embed(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                        const int8_t* spins, const int32_t* n_dev,
+                        int64_t n_seq, typename P::acc* x, hipStream_t st);
+template <class P>
+hipError_t launch_qkv(const ModelDims& m, const LayerW<typename P::acc>& w,
+                      RowSet rows, const BlockIO<P>& io, hipStream_t st);
+template <class P>
+hipError_t launch_attention_seq(const ModelDims& m, const int32_t* n_dev,
+                                int64_t n_seq, const BlockIO<P>& io,
+                                int64_t* ctr, hipStream_t st);
+template <class P>
+hipError_t launch_vq(const ModelDims& m, const LayerW<typename P::acc>& w,
+                     RowSet rows, const BlockIO<P>& io, hipStream_t st);
+template <class P>
+hipError_t launch_mlp(const ModelDims& m, const LayerW<typename P::acc>& w,
+                      RowSet rows, const BlockIO<P>& io, hipStream_t st);
+template <class P>
+hipError_t launch_head_seq(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                           const int8_t* spins, const int32_t* n_dev,
+                           int64_t n_seq, const typename P::acc* x,
+                           typename P::acc* lp, double* logpsi,
+                           hipStream_t st);
+
+// ---- deduplicated neighbour evaluation
+template <class P>
+struct DedupIO {
+    using act = typename P::act;
+    using acc = typename P::acc;
+    const NbDesc* desc;       // [n_nb]
+    const int32_t* n_nb;      // device count of neighbours in the chunk
+    int64_t n_nb_max;
+    const int32_t* n_rows;    // device: overlay rows of the chunk
+    int64_t rows_max;
+    const int8_t* spins;      // chunk samples [n][N]
+    int32_t* slot_nb;         // [rows] owning neighbour of every overlay row
+    // sample caches of the current layer: [n][N][...]
+    const acc* bx;            // block input
+    const act *bq, *bk, *bv, *ba;
+    const int32_t* bcode;
+    const acc* bmargin;       // [n][N][H][2] bounds on best / second distance
+    const acc* wmax;          // [H] largest codeword norm per quantizer head
+    // overlay rows of the neighbours: [rows][...]
+    acc* ox;
+    act *oq, *ok, *ov, *oa;
+    int32_t* ocode;
+    uint64_t* mask;           // [n_nb][W] rows in C (current layer)
+    int mask_words;
+    int64_t* list;            // rows of C (slots), capacity rows_max
+    int32_t* list_n;          // device count
+    int64_t* vq_list;         // rows needing a codebook search
+    int32_t* vq_n;
+};
+
+template <class P>
+hipError_t launch_dedup_init(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                             const DedupIO<P>& d, hipStream_t st);
+template <class P>
+hipError_t launch_attention_dedup(const ModelDims& m, const DedupIO<P>& d,
+                                  int64_t* ctr, hipStream_t st);
+template <class P>
+hipError_t launch_certify(const ModelDims& m, const DedupIO<P>& d,
+                          int certified, int64_t* ctr, hipStream_t st);
+template <class P>
+hipError_t launch_code_diff(const ModelDims& m, const DedupIO<P>& d,
+                            hipStream_t st);
+template <class P>
+hipError_t launch_head_dedup(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                             const DedupIO<P>& d, const typename P::acc* blp,
+                             const double* bell_unused, double* ratio,
+                             int64_t* ctr, hipStream_t st);
+hipError_t launch_ratio_plain(const double* logpsi_nb, const double* logpsi_s,
+                              const NbDesc* desc, const int32_t* n_dev,
+                              int64_t n_max, double* ratio, hipStream_t st);
+
+}  // namespace vq

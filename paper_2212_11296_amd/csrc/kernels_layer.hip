@@ -1,0 +1,1020 @@
+// Transformer-block kernels of the VQ wave function (paper Sec. 3.1):
+// embedding, LN1 + QKV projection, causal multi-head attention, the vector
+// quantizer (eqs. 4-6), output projection + residual + MLP, output head.
+// VALU implementations for every precision; each per-row result depends
+// only on that row's inputs, so evaluating a row inside a full sequence or
+// inside a neighbour's overlay gives bitwise identical values.
+#include "kernels.h"
+
+namespace vq {
+
+constexpr int kThreads = 256;
+constexpr int kGridCap = 8192;
+
+static inline unsigned grid_for(int64_t units) {
+    if (units <= 0) return 1;
+    return (unsigned)(units < kGridCap ? units : kGridCap);
+}
+
+__device__ inline int64_t rowset_n(const RowSet& r) {
+    return r.n_dev ? (int64_t)(*r.n_dev) * r.mult : r.n_host;
+}
+__device__ inline int64_t rowset_slot(const RowSet& r, int64_t k) {
+    return r.idx ? r.idx[k] : k;
+}
+__device__ inline bool mask_bit(const uint64_t* m, int i) {
+    return (m[i >> 6] >> (i & 63)) & 1ull;
+}
+
+// Wave computes LayerNorm statistics of a row of width d (biased variance,
+// two passes, eps 1e-5); every lane gets the same values.
+template <typename C, typename X>
+__device__ inline void ln_stats(const X* x, int d, C& mean, C& rstd) {
+    const int lane = threadIdx.x & 63;
+    C s = 0;
+    for (int k = lane; k < d; k += 64) s += cvt<C>(x[k]);
+    mean = wave_sum(s) / (C)d;
+    C v = 0;
+    for (int k = lane; k < d; k += 64) {
+        const C t = cvt<C>(x[k]) - mean;
+        v += t * t;
+    }
+    v = wave_sum(v) / (C)d;
+    rstd = (C)1 / dsqrt(v + (C)1e-5);
+}
+
+// ------------------------------------------------------------ preparation
+// table[h][c][:] = codeword (h,c) times the rows of W_o of segment h;
+// cnorm[h][c] = squared norm of the codeword as the distance kernel sees it
+// (bfloat16-rounded in the BF16 mode); wmax[h] = max_c sqrt(cnorm).
+template <class P>
+__global__ void k_prepare_table(ModelDims m, LayerW<typename P::acc> w,
+                                typename P::acc* table,
+                                typename P::acc* cnorm) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    const int hc = blockIdx.x;              // h*Q + c
+    const int h = hc / m.Q;
+    const acc* cw = w.codebook + (int64_t)hc * m.dseg;
+    for (int col = threadIdx.x; col < m.d; col += blockDim.x) {
+        acc s = 0;
+        for (int k = 0; k < m.dseg; ++k)
+            s += cw[k] * w.W_o[(int64_t)(h * m.dseg + k) * m.d + col];
+        table[(int64_t)hc * m.d + col] = s;
+    }
+    if (threadIdx.x < 64) {
+        acc s = 0;
+        for (int k = threadIdx.x; k < m.dseg; k += 64) {
+            const acc v = cvt<acc>(cvt<act>(cw[k]));
+            s += v * v;
+        }
+        s = wave_sum(s);
+        if (threadIdx.x == 0) cnorm[hc] = s;
+    }
+}
+
+template <class P>
+__global__ void k_prepare_wmax(ModelDims m, typename P::acc* cnorm) {
+    using acc = typename P::acc;
+    // cnorm holds H*Q norms followed by H slots for the per-head maximum
+    const int h = blockIdx.x;
+    if (threadIdx.x < 64) {
+        acc mx = 0;
+        for (int c = threadIdx.x; c < m.Q; c += 64) {
+            const acc v = cnorm[(int64_t)h * m.Q + c];
+            mx = v > mx ? v : mx;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const acc t = __shfl_xor(mx, o, 64);
+            mx = t > mx ? t : mx;
+        }
+        if (threadIdx.x == 0) cnorm[(int64_t)m.H * m.Q + h] = dsqrt(mx);
+    }
+}
+
+template <class P>
+hipError_t launch_prepare(const ModelDims& m, const LayerW<typename P::acc>& w,
+                          typename P::acc* table, typename P::acc* cnorm,
+                          bf16*, bf16*, bf16*, bf16*, hipStream_t st) {
+    hipLaunchKernelGGL(k_prepare_table<P>, dim3(m.H * m.Q), dim3(128), 0, st,
+                       m, w, table, cnorm);
+    hipLaunchKernelGGL(k_prepare_wmax<P>, dim3(m.H), dim3(64), 0, st, m,
+                       cnorm);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- sequences
+__global__ void k_materialise(const int8_t* __restrict__ spins,
+                              const NbDesc* __restrict__ desc,
+                              const int32_t* n_dev, int64_t n_max, int N,
+                              int8_t* __restrict__ out) {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+    const int64_t total = n * N;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = e / N;
+        const int i = (int)(e - k * N);
+        const NbDesc dd = desc[k];
+        int src = i;
+        if (i == dd.p1) src = dd.p2;
+        else if (i == dd.p2) src = dd.p1;
+        out[e] = spins[(int64_t)dd.sigma * N + src];
+    }
+}
+
+hipError_t launch_materialise(const int8_t* spins, const NbDesc* desc,
+                              const int32_t* n_dev, int64_t n_max, int N,
+                              int8_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_materialise, dim3(grid_for((n_max * N + 255) / 256)),
+                       dim3(256), 0, st, spins, desc, n_dev, n_max, N, out);
+    return hipGetLastError();
+}
+
+// x[s][i] = tok[u_i] + pos[i], u_0 = BOS (2), u_i = token of spin i-1.
+template <class P>
+__global__ void k_embed(ModelDims m, HeadW<typename P::acc> hw,
+                        const int8_t* __restrict__ spins, const int32_t* n_dev,
+                        int64_t n_seq, typename P::acc* __restrict__ x) {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_seq;
+    const int64_t total = n * m.N * m.d;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = e / m.d;
+        const int col = (int)(e - row * m.d);
+        const int i = (int)(row % m.N);
+        const int u = i == 0 ? 2 : (spins[row - 1] < 0 ? 1 : 0);
+        x[e] = hw.tok[u * m.d + col] + hw.pos[(int64_t)i * m.d + col];
+    }
+}
+
+template <class P>
+hipError_t launch_embed(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                        const int8_t* spins, const int32_t* n_dev,
+                        int64_t n_seq, typename P::acc* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_embed<P>,
+                       dim3(grid_for((n_seq * m.N * m.d + 255) / 256)),
+                       dim3(256), 0, st, m, hw, spins, n_dev, n_seq, x);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ LN1 + QKV
+template <class P, int TR>
+__global__ void __launch_bounds__(kThreads) k_qkv(ModelDims m,
+                                                  LayerW<typename P::acc> w,
+                                                  RowSet rows, BlockIO<P> io) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    acc* hs = reinterpret_cast<acc*>(smem_raw);            // [TR][d]
+    __shared__ int64_t slot[TR];
+    const int64_t n = rowset_n(rows);
+    const int64_t ntiles = (n + TR - 1) / TR;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int d = m.d, d3 = 3 * m.d;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (int rr = wave; rr < TR; rr += kThreads / 64) {
+            const int64_t r = t * TR + rr;
+            if (r < n) {
+                const int64_t s = rowset_slot(rows, r);
+                if (lane == 0) slot[rr] = s;
+                const acc* x = io.x + s * d;
+                acc mean, rstd;
+                ln_stats<acc>(x, d, mean, rstd);
+                for (int k = lane; k < d; k += 64)
+                    hs[rr * d + k] = (x[k] - mean) * rstd * w.ln1_g[k] + w.ln1_b[k];
+            } else {
+                if (lane == 0) slot[rr] = -1;
+                for (int k = lane; k < d; k += 64) hs[rr * d + k] = 0;
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < d3; c += kThreads) {
+            acc s[TR];
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr) s[rr] = 0;
+            for (int k = 0; k < d; ++k) {
+                const acc wv = cvt<acc>(cvt<act>(w.W_qkv[(int64_t)k * d3 + c]));
+#pragma unroll
+                for (int rr = 0; rr < TR; ++rr)
+                    s[rr] += cvt<acc>(cvt<act>(hs[rr * d + k])) * wv;
+            }
+            act* dst = c < d ? io.q : (c < 2 * d ? io.k : io.v);
+            const int cc = c < d ? c : (c < 2 * d ? c - d : c - 2 * d);
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr)
+                if (slot[rr] >= 0)
+                    dst[slot[rr] * d + cc] = cvt<act>(s[rr] + w.b_qkv[c]);
+        }
+        __syncthreads();
+    }
+}
+
+template <class P>
+hipError_t launch_qkv(const ModelDims& m, const LayerW<typename P::acc>& w,
+                      RowSet rows, const BlockIO<P>& io, hipStream_t st) {
+    constexpr int TR = 16;
+    const size_t sm = sizeof(typename P::acc) * TR * m.d;
+    hipLaunchKernelGGL((k_qkv<P, TR>), dim3(grid_for((rows.n_host + TR - 1) / TR)),
+                       dim3(kThreads), sm, st, m, w, rows, io);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- attention
+// One query row against keys 0..i held in LDS (online softmax).  Shared by
+// the full-sequence and the overlay kernels so both give identical bits.
+template <typename C, int DH, typename A>
+__device__ inline void attend_row(const C (&q)[DH], const A* __restrict__ Ks,
+                                  const A* __restrict__ Vs, int i,
+                                  C (&o)[DH]) {
+    C mx = neg_inf<C>(), l = 0;
+#pragma unroll
+    for (int c = 0; c < DH; ++c) o[c] = 0;
+    for (int j = 0; j <= i; ++j) {
+        C s = 0;
+#pragma unroll
+        for (int c = 0; c < DH; ++c) s += q[c] * cvt<C>(Ks[j * DH + c]);
+        if (s > mx) {
+            const C al = dexp(mx - s);
+            l *= al;
+#pragma unroll
+            for (int c = 0; c < DH; ++c) o[c] *= al;
+            mx = s;
+        }
+        const C p = dexp(s - mx);
+        l += p;
+#pragma unroll
+        for (int c = 0; c < DH; ++c) o[c] += p * cvt<C>(Vs[j * DH + c]);
+    }
+    const C inv = (C)1 / l;
+#pragma unroll
+    for (int c = 0; c < DH; ++c) o[c] *= inv;
+}
+
+template <class P, int DH>
+__global__ void __launch_bounds__(kThreads) k_attn_seq(ModelDims m,
+                                                       const int32_t* n_dev,
+                                                       int64_t n_seq,
+                                                       BlockIO<P> io,
+                                                       int64_t* ctr) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    act* Ks = reinterpret_cast<act*>(smem_raw);
+    act* Vs = Ks + m.N * DH;
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_seq;
+    const int64_t units = n * m.nh;
+    const acc scale = (acc)1 / dsqrt((acc)DH);
+    const int d = m.d, N = m.N;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t s = u / m.nh;
+        const int h = (int)(u - s * m.nh);
+        const int64_t base = s * N * d + h * DH;
+        for (int e = threadIdx.x; e < N * DH; e += kThreads) {
+            const int j = e / DH, c = e - (e / DH) * DH;
+            Ks[e] = io.k[base + (int64_t)j * d + c];
+            Vs[e] = io.v[base + (int64_t)j * d + c];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += kThreads) {
+            acc q[DH], o[DH];
+#pragma unroll
+            for (int c = 0; c < DH; ++c)
+                q[c] = cvt<acc>(io.q[base + (int64_t)i * d + c]) * scale;
+            attend_row<acc, DH, act>(q, Ks, Vs, i, o);
+#pragma unroll
+            for (int c = 0; c < DH; ++c)
+                io.a[base + (int64_t)i * d + c] = cvt<act>(o[c]);
+        }
+        __syncthreads();
+    }
+    if (ctr && blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
+                  (unsigned long long)(n * N));
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_PAIRS),
+                  (unsigned long long)(n * ((int64_t)N * (N + 1) / 2) * m.nh));
+    }
+}
+
+template <class P, int DH>
+static hipError_t attn_seq_dh(const ModelDims& m, const int32_t* n_dev,
+                              int64_t n_seq, const BlockIO<P>& io,
+                              int64_t* ctr, hipStream_t st) {
+    const size_t sm = sizeof(typename P::act) * 2 * m.N * DH;
+    if (sm > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_attn_seq<P, DH>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sm);
+    hipLaunchKernelGGL((k_attn_seq<P, DH>), dim3(grid_for(n_seq * m.nh)),
+                       dim3(kThreads), sm, st, m, n_dev, n_seq, io, ctr);
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_attention_seq(const ModelDims& m, const int32_t* n_dev,
+                                int64_t n_seq, const BlockIO<P>& io,
+                                int64_t* ctr, hipStream_t st) {
+    switch (m.dh) {
+        case 4: return attn_seq_dh<P, 4>(m, n_dev, n_seq, io, ctr, st);
+        case 8: return attn_seq_dh<P, 8>(m, n_dev, n_seq, io, ctr, st);
+        case 16: return attn_seq_dh<P, 16>(m, n_dev, n_seq, io, ctr, st);
+        case 32: return attn_seq_dh<P, 32>(m, n_dev, n_seq, io, ctr, st);
+        case 64: return attn_seq_dh<P, 64>(m, n_dev, n_seq, io, ctr, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Overlay attention of the neighbours: keys/values/queries of rows in the
+// changed set C come from the neighbour's overlay rows, all others from the
+// sample's cached rows.  Only query rows i >= p1 + 1 are evaluated.
+template <class P, int DH>
+__global__ void __launch_bounds__(kThreads) k_attn_dedup(ModelDims m,
+                                                         DedupIO<P> dd,
+                                                         int64_t* ctr) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    act* Ks = reinterpret_cast<act*>(smem_raw);
+    act* Vs = Ks + m.N * DH;
+    const int64_t n = (int64_t)*dd.n_nb;
+    const int64_t units = n * m.nh;
+    const acc scale = (acc)1 / dsqrt((acc)DH);
+    const int d = m.d, N = m.N, W = dd.mask_words;
+    int64_t my_rows = 0, my_pairs = 0;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t nb = u / m.nh;
+        const int h = (int)(u - nb * m.nh);
+        const NbDesc D = dd.desc[nb];
+        const int pmin = D.p1 + 1;
+        const uint64_t* mk = dd.mask + nb * W;
+        const int64_t sb = (int64_t)D.sigma * N * d + h * DH;
+        const int64_t ob = (D.ov - pmin) * (int64_t)d + h * DH;   // row i at ob + i*d
+        for (int e = threadIdx.x; e < N * DH; e += kThreads) {
+            const int j = e / DH, c = e - (e / DH) * DH;
+            const bool ovl = j >= pmin && mask_bit(mk, j);
+            const int64_t off = (ovl ? ob : sb) + (int64_t)j * d + c;
+            Ks[e] = (ovl ? dd.ok : dd.bk)[off];
+            Vs[e] = (ovl ? dd.ov : dd.bv)[off];
+        }
+        __syncthreads();
+        for (int i = pmin + threadIdx.x; i < N; i += kThreads) {
+            const bool ovl = mask_bit(mk, i);
+            const act* qsrc = (ovl ? dd.oq + ob : dd.bq + sb) + (int64_t)i * d;
+            acc q[DH], o[DH];
+#pragma unroll
+            for (int c = 0; c < DH; ++c) q[c] = cvt<acc>(qsrc[c]) * scale;
+            attend_row<acc, DH, act>(q, Ks, Vs, i, o);
+            act* dst = dd.oa + ob + (int64_t)i * d;
+#pragma unroll
+            for (int c = 0; c < DH; ++c) dst[c] = cvt<act>(o[c]);
+        }
+        if (h == 0 && threadIdx.x == 0) {
+            my_rows += N - pmin;
+            my_pairs += ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2;
+        }
+        __syncthreads();
+    }
+    if (ctr && threadIdx.x == 0 && my_rows) {
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
+                  (unsigned long long)my_rows);
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_PAIRS),
+                  (unsigned long long)(my_pairs * m.nh));
+    }
+}
+
+template <class P, int DH>
+static hipError_t attn_dedup_dh(const ModelDims& m, const DedupIO<P>& d,
+                                int64_t* ctr, hipStream_t st) {
+    const size_t sm = sizeof(typename P::act) * 2 * m.N * DH;
+    if (sm > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_attn_dedup<P, DH>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sm);
+    hipLaunchKernelGGL((k_attn_dedup<P, DH>), dim3(grid_for(d.n_nb_max * m.nh)),
+                       dim3(kThreads), sm, st, m, d, ctr);
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_attention_dedup(const ModelDims& m, const DedupIO<P>& d,
+                                  int64_t* ctr, hipStream_t st) {
+    switch (m.dh) {
+        case 4: return attn_dedup_dh<P, 4>(m, d, ctr, st);
+        case 8: return attn_dedup_dh<P, 8>(m, d, ctr, st);
+        case 16: return attn_dedup_dh<P, 16>(m, d, ctr, st);
+        case 32: return attn_dedup_dh<P, 32>(m, d, ctr, st);
+        case 64: return attn_dedup_dh<P, 64>(m, d, ctr, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------- vector quantizer
+// Running best / second-best of (score, index); ties go to the lower index.
+template <typename C>
+struct Top2 {
+    C b;
+    int i;
+    C s;
+};
+template <typename C>
+__device__ inline Top2<C> top2_merge(Top2<C> x, Top2<C> y) {
+    Top2<C> r;
+    if (y.b < x.b || (y.b == x.b && y.i < x.i)) {
+        r.b = y.b;
+        r.i = y.i;
+        r.s = x.b < y.s ? x.b : y.s;
+    } else {
+        r.b = x.b;
+        r.i = x.i;
+        r.s = y.b < x.s ? y.b : x.s;
+    }
+    return r;
+}
+
+// Unit roundoff of the distance arithmetic and a bound on the error of a
+// computed score |w|^2 - 2 a.w (length-n sums, any summation order).
+template <typename C>
+__device__ inline C unit_roundoff();
+template <>
+__device__ inline float unit_roundoff<float>() {
+    return 5.9604645e-8f;
+}
+template <>
+__device__ inline double unit_roundoff<double>() {
+    return 1.1102230246251565e-16;
+}
+template <typename C>
+__device__ inline C score_err(int n, C na, C wmax) {
+    const C g = (C)(n + 4) * unit_roundoff<C>() * (C)1.0625;
+    return g * ((C)2 * na * wmax + wmax * wmax + na * na);
+}
+
+// Scores of TR rows against all Q codes of one quantizer head per pass; the
+// result per row is the code, plus bounds U1 >= best distance and
+// L2 <= second-best distance used by the certified-reuse test.
+template <class P, int TR>
+__global__ void __launch_bounds__(kThreads) k_vq(ModelDims m,
+                                                 LayerW<typename P::acc> w,
+                                                 RowSet rows, BlockIO<P> io) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    acc* as = reinterpret_cast<acc*>(smem_raw);          // [TR][dseg]
+    __shared__ acc a2[TR];
+    __shared__ int64_t slot[TR];
+    __shared__ Top2<acc> part[kThreads / 64][TR];
+    const int64_t n = rowset_n(rows);
+    const int64_t ntiles = (n + TR - 1) / TR;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ds = m.dseg;
+    const acc inf = -neg_inf<acc>();
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (int hq = 0; hq < m.H; ++hq) {
+            for (int rr = wave; rr < TR; rr += kThreads / 64) {
+                const int64_t r = t * TR + rr;
+                acc s2 = 0;
+                if (r < n) {
+                    const int64_t s = rowset_slot(rows, r);
+                    if (lane == 0) slot[rr] = s;
+                    const act* a = io.a + s * m.d + hq * ds;
+                    for (int k = lane; k < ds; k += 64) {
+                        const acc v = cvt<acc>(a[k]);
+                        as[rr * ds + k] = v;
+                        s2 += v * v;
+                    }
+                } else {
+                    if (lane == 0) slot[rr] = -1;
+                    for (int k = lane; k < ds; k += 64) as[rr * ds + k] = 0;
+                }
+                s2 = wave_sum(s2);
+                if (lane == 0) a2[rr] = s2;
+            }
+            __syncthreads();
+            Top2<acc> best[TR];
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr) best[rr] = Top2<acc>{inf, 0x7fffffff, inf};
+            const acc* cb = w.codebook + (int64_t)hq * m.Q * ds;
+            const acc* cn = w.cnorm + (int64_t)hq * m.Q;
+            for (int c = threadIdx.x; c < m.Q; c += kThreads) {
+                acc dot[TR];
+#pragma unroll
+                for (int rr = 0; rr < TR; ++rr) dot[rr] = 0;
+                for (int k = 0; k < ds; ++k) {
+                    const acc wv = cvt<acc>(cvt<act>(cb[(int64_t)c * ds + k]));
+#pragma unroll
+                    for (int rr = 0; rr < TR; ++rr) dot[rr] += as[rr * ds + k] * wv;
+                }
+#pragma unroll
+                for (int rr = 0; rr < TR; ++rr) {
+                    const acc sc = cn[c] - (acc)2 * dot[rr];
+                    best[rr] = top2_merge(best[rr], Top2<acc>{sc, c, inf});
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr) {
+                Top2<acc> v = best[rr];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    Top2<acc> y;
+                    y.b = __shfl_xor(v.b, o, 64);
+                    y.i = __shfl_xor(v.i, o, 64);
+                    y.s = __shfl_xor(v.s, o, 64);
+                    // combine in lane order so every lane agrees
+                    v = (lane & o) ? top2_merge(y, v) : top2_merge(v, y);
+                }
+                if (lane == 0) part[wave][rr] = v;
+            }
+            __syncthreads();
+            if (threadIdx.x < TR) {
+                const int rr = threadIdx.x;
+                Top2<acc> v = part[0][rr];
+                for (int wv = 1; wv < kThreads / 64; ++wv) v = top2_merge(v, part[wv][rr]);
+                const int64_t s = slot[rr];
+                if (s >= 0) {
+                    io.codes[s * m.H + hq] = v.i;
+                    if (io.margin) {
+                        const acc wmax = w.cnorm[(int64_t)m.H * m.Q + hq];
+                        const acc na = dsqrt(a2[rr]);
+                        const acc E = score_err<acc>(ds, na, wmax);
+                        const acc u1 = v.b + a2[rr] + E;
+                        const acc l2 = v.s + a2[rr] - E;
+                        io.margin[(s * m.H + hq) * 2 + 0] = dsqrt(u1 > 0 ? u1 : (acc)0);
+                        io.margin[(s * m.H + hq) * 2 + 1] = dsqrt(l2 > 0 ? l2 : (acc)0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <class P>
+hipError_t launch_vq(const ModelDims& m, const LayerW<typename P::acc>& w,
+                     RowSet rows, const BlockIO<P>& io, hipStream_t st) {
+    constexpr int TR = 8;
+    const size_t sm = sizeof(typename P::acc) * TR * m.dseg;
+    hipLaunchKernelGGL((k_vq<P, TR>), dim3(grid_for((rows.n_host + TR - 1) / TR)),
+                       dim3(kThreads), sm, st, m, w, rows, io);
+    return hipGetLastError();
+}
+
+// ---------------------------------------- output projection + residual + MLP
+// x' = x_in + b_o + sum_h table[h][code_h];  x = x' + W2 GELU(LN2(x') W1 + b1) + b2
+template <class P, int TR>
+__global__ void __launch_bounds__(kThreads) k_mlp(ModelDims m,
+                                                  LayerW<typename P::acc> w,
+                                                  RowSet rows, BlockIO<P> io) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    acc* xp = reinterpret_cast<acc*>(smem_raw);   // [TR][d]
+    acc* hn = xp + TR * m.d;                      // [TR][d]
+    acc* hid = hn + TR * m.d;                     // [TR][dff]
+    __shared__ int64_t slot[TR];
+    const int64_t n = rowset_n(rows);
+    const int64_t ntiles = (n + TR - 1) / TR;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int d = m.d, F = m.dff;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (int rr = wave; rr < TR; rr += kThreads / 64) {
+            const int64_t r = t * TR + rr;
+            if (r < n) {
+                const int64_t s = rowset_slot(rows, r);
+                if (lane == 0) slot[rr] = s;
+                const acc* x = io.x_in + s * d;
+                const int32_t* cd = io.codes + s * m.H;
+                for (int k = lane; k < d; k += 64) {
+                    acc z = w.b_o[k];
+                    for (int hq = 0; hq < m.H; ++hq)
+                        z += w.table[((int64_t)hq * m.Q + cd[hq]) * d + k];
+                    xp[rr * d + k] = x[k] + z;
+                }
+                acc mean, rstd;
+                ln_stats<acc>(xp + rr * d, d, mean, rstd);
+                for (int k = lane; k < d; k += 64)
+                    hn[rr * d + k] = (xp[rr * d + k] - mean) * rstd * w.ln2_g[k] + w.ln2_b[k];
+            } else {
+                if (lane == 0) slot[rr] = -1;
+                for (int k = lane; k < d; k += 64) {
+                    xp[rr * d + k] = 0;
+                    hn[rr * d + k] = 0;
+                }
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < F; c += kThreads) {
+            acc s[TR];
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr) s[rr] = 0;
+            for (int k = 0; k < d; ++k) {
+                const acc wv = cvt<acc>(cvt<act>(w.W1[(int64_t)k * F + c]));
+#pragma unroll
+                for (int rr = 0; rr < TR; ++rr) s[rr] += cvt<acc>(cvt<act>(hn[rr * d + k])) * wv;
+            }
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr) hid[rr * F + c] = gelu_exact(s[rr] + w.b1[c]);
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < d; c += kThreads) {
+            acc s[TR];
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr) s[rr] = 0;
+            for (int k = 0; k < F; ++k) {
+                const acc wv = cvt<acc>(cvt<act>(w.W2[(int64_t)k * d + c]));
+#pragma unroll
+                for (int rr = 0; rr < TR; ++rr) s[rr] += cvt<acc>(cvt<act>(hid[rr * F + k])) * wv;
+            }
+#pragma unroll
+            for (int rr = 0; rr < TR; ++rr)
+                if (slot[rr] >= 0) io.x[slot[rr] * d + c] = xp[rr * d + c] + (s[rr] + w.b2[c]);
+        }
+        __syncthreads();
+    }
+}
+
+template <class P>
+hipError_t launch_mlp(const ModelDims& m, const LayerW<typename P::acc>& w,
+                      RowSet rows, const BlockIO<P>& io, hipStream_t st) {
+    using acc = typename P::acc;
+    int TR = 16;
+    while (TR > 1 && sizeof(acc) * TR * (2 * m.d + m.dff) > 64 * 1024) TR >>= 1;
+    const size_t sm = sizeof(acc) * TR * (2 * m.d + m.dff);
+    const unsigned g = grid_for((rows.n_host + TR - 1) / TR);
+    switch (TR) {
+        case 16: hipLaunchKernelGGL((k_mlp<P, 16>), dim3(g), dim3(kThreads), sm, st, m, w, rows, io); break;
+        case 8: hipLaunchKernelGGL((k_mlp<P, 8>), dim3(g), dim3(kThreads), sm, st, m, w, rows, io); break;
+        case 4: hipLaunchKernelGGL((k_mlp<P, 4>), dim3(g), dim3(kThreads), sm, st, m, w, rows, io); break;
+        case 2: hipLaunchKernelGGL((k_mlp<P, 2>), dim3(g), dim3(kThreads), sm, st, m, w, rows, io); break;
+        default: hipLaunchKernelGGL((k_mlp<P, 1>), dim3(g), dim3(kThreads), sm, st, m, w, rows, io); break;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ head
+// Final LN, linear d -> 2 and log-softmax of one row, computed by one wave
+// (all lanes return the same values).
+template <typename C>
+__device__ inline void head_row(const C* x, int d, const HeadW<C>& hw, C& lp0,
+                                C& lp1) {
+    const int lane = threadIdx.x & 63;
+    C mean, rstd;
+    ln_stats<C>(x, d, mean, rstd);
+    C z0 = 0, z1 = 0;
+    for (int k = lane; k < d; k += 64) {
+        const C f = (x[k] - mean) * rstd * hw.lnf_g[k] + hw.lnf_b[k];
+        z0 += f * hw.W_head[2 * k];
+        z1 += f * hw.W_head[2 * k + 1];
+    }
+    z0 = wave_sum(z0) + hw.b_head[0];
+    z1 = wave_sum(z1) + hw.b_head[1];
+    const C mx = z0 > z1 ? z0 : z1;
+    const C lse = mx + dlog(dexp(z0 - mx) + dexp(z1 - mx));
+    lp0 = z0 - lse;
+    lp1 = z1 - lse;
+}
+
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_head_seq(
+    ModelDims m, HeadW<typename P::acc> hw, const int8_t* __restrict__ spins,
+    const int32_t* n_dev, int64_t n_seq, const typename P::acc* __restrict__ x,
+    typename P::acc* __restrict__ lp, double* __restrict__ logpsi) {
+    using acc = typename P::acc;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* ell = reinterpret_cast<double*>(smem_raw);   // [N]
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_seq;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
+        for (int i = wave; i < m.N; i += kThreads / 64) {
+            const int64_t row = s * m.N + i;
+            acc l0, l1;
+            head_row<acc>(x + row * m.d, m.d, hw, l0, l1);
+            if (lane == 0) {
+                ell[i] = (double)(spins[row] < 0 ? l1 : l0);
+                if (lp) {
+                    lp[row * 2] = l0;
+                    lp[row * 2 + 1] = l1;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double acc64 = 0.0;
+            for (int i = 0; i < m.N; ++i) acc64 += ell[i];
+            logpsi[s] = 0.5 * acc64;
+        }
+        __syncthreads();
+    }
+}
+
+template <class P>
+hipError_t launch_head_seq(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                           const int8_t* spins, const int32_t* n_dev,
+                           int64_t n_seq, const typename P::acc* x,
+                           typename P::acc* lp, double* logpsi,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_head_seq<P>, dim3(grid_for(n_seq)), dim3(kThreads),
+                       sizeof(double) * m.N, st, m, hw, spins, n_dev, n_seq, x,
+                       lp, logpsi);
+    return hipGetLastError();
+}
+
+// ratio = exp(log psi(s') - log psi(s)) for materialised neighbours (FP64)
+__global__ void k_ratio_plain(const double* __restrict__ lnb,
+                              const double* __restrict__ ls,
+                              const NbDesc* __restrict__ desc,
+                              const int32_t* n_dev, int64_t n_max,
+                              double* __restrict__ ratio) {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_max;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        ratio[k] = exp(lnb[k] - ls[desc[k].sigma]);
+}
+
+hipError_t launch_ratio_plain(const double* logpsi_nb, const double* logpsi_s,
+                              const NbDesc* desc, const int32_t* n_dev,
+                              int64_t n_max, double* ratio, hipStream_t st) {
+    hipLaunchKernelGGL(k_ratio_plain, dim3(grid_for((n_max + 255) / 256)),
+                       dim3(256), 0, st, logpsi_nb, logpsi_s, desc, n_dev,
+                       n_max, ratio);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ dedup steps
+// C_0: the changed inputs p1+1 and p2+1 (when < N) get their new
+// embeddings; every overlay row records its neighbour.
+template <class P>
+__global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
+                                                   HeadW<typename P::acc> hw,
+                                                   DedupIO<P> dd) {
+    const int64_t n = (int64_t)*dd.n_nb;
+    const int lane = threadIdx.x;
+    const int N = m.N, d = m.d, W = dd.mask_words;
+    for (int64_t nb = blockIdx.x; nb < n; nb += gridDim.x) {
+        const NbDesc D = dd.desc[nb];
+        const int pmin = D.p1 + 1;
+        for (int i = lane; i < N - pmin; i += 64) dd.slot_nb[D.ov + i] = (int32_t)nb;
+        uint64_t* mk = dd.mask + nb * W;
+        for (int wd = lane; wd < W; wd += 64) mk[wd] = 0;
+        const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
+        const int rowsC[2] = {D.p1 + 1, D.p2 + 1};
+        // spin moved into p1 is s[p2] and vice versa
+        const int tokC[2] = {sp[D.p2] < 0 ? 1 : 0, sp[D.p1] < 0 ? 1 : 0};
+        const int nC = rowsC[1] < N ? 2 : 1;
+        int64_t pos = 0;
+        if (lane == 0) pos = atomicAdd(dd.list_n, nC);
+        pos = __shfl(pos, 0, 64);
+        for (int c = 0; c < nC; ++c) {
+            const int i = rowsC[c];
+            const int64_t slot = D.ov + (i - pmin);
+            for (int k = lane; k < d; k += 64)
+                dd.ox[slot * d + k] = hw.tok[tokC[c] * d + k] + hw.pos[(int64_t)i * d + k];
+            if (lane == 0) dd.list[pos + c] = slot;
+        }
+        __syncthreads();
+        if (lane == 0) {
+            for (int c = 0; c < nC; ++c) mk[rowsC[c] >> 6] |= 1ull << (rowsC[c] & 63);
+        }
+    }
+}
+
+template <class P>
+hipError_t launch_dedup_init(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                             const DedupIO<P>& d, hipStream_t st) {
+    hipLaunchKernelGGL(k_dedup_init<P>, dim3(grid_for(d.n_nb_max)), dim3(64), 0,
+                       st, m, hw, d);
+    return hipGetLastError();
+}
+
+// Certified reuse test for every overlay row (or, without the flag, plain
+// listing of every row for the codebook search).
+template <class P>
+__global__ void __launch_bounds__(64) k_certify(ModelDims m, DedupIO<P> dd,
+                                                int certified, int64_t* ctr) {
+    using acc = typename P::acc;
+    const int64_t R = (int64_t)*dd.n_rows;
+    const int lane = threadIdx.x;
+    const int ds = m.dseg;
+    int64_t n_cert = 0;
+    for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
+        const int32_t nb = dd.slot_nb[r];
+        const NbDesc D = dd.desc[nb];
+        const int i = D.p1 + 1 + (int)(r - D.ov);
+        const int64_t brow = (int64_t)D.sigma * m.N + i;
+        bool ok = certified != 0;
+        for (int hq = 0; hq < m.H && ok; ++hq) {
+            acc dl = 0, n1 = 0, n0 = 0;
+            for (int k = lane; k < ds; k += 64) {
+                const acc x1 = cvt<acc>(dd.oa[r * m.d + hq * ds + k]);
+                const acc x0 = cvt<acc>(dd.ba[brow * m.d + hq * ds + k]);
+                dl += (x1 - x0) * (x1 - x0);
+                n1 += x1 * x1;
+                n0 += x0 * x0;
+            }
+            dl = wave_sum(dl);
+            n1 = dsqrt(wave_sum(n1));
+            n0 = dsqrt(wave_sum(n0));
+            const acc g = (acc)(ds + 4) * unit_roundoff<acc>() * (acc)2;
+            acc delta = dsqrt(dl) * ((acc)1 + g) + unit_roundoff<acc>();
+            // the matrix-core search sees hi + lo of each row, which moves a
+            // row by at most 2^-16 of its norm
+            if (m.mfma) delta += (acc)1.5258789e-5 * (n0 + n1);
+            const acc U1 = dd.bmargin[(brow * m.H + hq) * 2];
+            const acc L2 = dd.bmargin[(brow * m.H + hq) * 2 + 1];
+            const acc lo = L2 - delta, hi = U1 + delta;
+            const acc wmax = dd.wmax[hq];
+            acc E = score_err<acc>(m.mfma ? 2 * ds : ds, n1, wmax);
+            if (m.mfma) E += (acc)3.0517578e-5 * (n1 * wmax + n1 * n1);
+            // lo bounds every other code's distance from below and hi the
+            // kept code's from above; the computed scores then separate
+            // strictly when the gap exceeds twice the score-error bound
+            ok = lo > 0 && (lo * lo - hi * hi) > (acc)4 * E;
+        }
+        if (ok) {
+            for (int hq = lane; hq < m.H; hq += 64)
+                dd.ocode[r * m.H + hq] = dd.bcode[brow * m.H + hq];
+            n_cert++;
+        } else if (lane == 0) {
+            const int32_t p = atomicAdd(dd.vq_n, 1);
+            dd.vq_list[p] = r;
+        }
+    }
+    if (ctr && lane == 0 && n_cert)
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_VQ_CERTIFIED),
+                  (unsigned long long)n_cert);
+}
+
+template <class P>
+hipError_t launch_certify(const ModelDims& m, const DedupIO<P>& d,
+                          int certified, int64_t* ctr, hipStream_t st) {
+    hipLaunchKernelGGL(k_certify<P>, dim3(grid_for(d.rows_max)), dim3(64), 0,
+                       st, m, d, certified, ctr);
+    return hipGetLastError();
+}
+
+// C_l = C_{l-1} plus rows whose code differs from the sample's; rows that
+// join C get the sample's block input copied into their overlay row, and
+// all rows of C_l are listed for the MLP stage (and the next QKV stage).
+template <class P>
+__global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
+    const int64_t n = (int64_t)*dd.n_nb;
+    const int lane = threadIdx.x;
+    const int N = m.N, d = m.d, W = dd.mask_words;
+    for (int64_t nb = blockIdx.x; nb < n; nb += gridDim.x) {
+        const NbDesc D = dd.desc[nb];
+        const int pmin = D.p1 + 1;
+        uint64_t* mk = dd.mask + nb * W;
+        int total = 0;
+        for (int i0 = pmin; i0 < N; i0 += 64) {
+            const int i = i0 + lane;
+            bool inC = false, joins = false;
+            if (i < N) {
+                const int64_t slot = D.ov + (i - pmin);
+                const int64_t brow = (int64_t)D.sigma * N + i;
+                inC = mask_bit(mk, i);
+                if (!inC) {
+                    for (int hq = 0; hq < m.H; ++hq)
+                        joins |= dd.ocode[slot * m.H + hq] != dd.bcode[brow * m.H + hq];
+                }
+            }
+            const uint64_t jm = __ballot(joins);
+            // copy the sample's block input into the overlay rows that join
+            uint64_t rem = jm;
+            while (rem) {
+                const int b = __ffsll((long long)rem) - 1;
+                rem &= rem - 1;
+                const int ii = i0 + b;
+                const int64_t slot = D.ov + (ii - pmin);
+                const int64_t brow = (int64_t)D.sigma * N + ii;
+                for (int k = lane; k < d; k += 64) dd.ox[slot * d + k] = dd.bx[brow * d + k];
+            }
+            total += __popcll(__ballot(inC || joins));
+            // update the mask words covered by this group of 64 rows
+            if (lane == 0 && jm) {
+                const int w0 = i0 >> 6, sh = i0 & 63;
+                mk[w0] |= jm << sh;
+                if (sh && w0 + 1 < W) mk[w0 + 1] |= jm >> (64 - sh);
+            }
+            __syncthreads();
+        }
+        int64_t pos = 0;
+        if (lane == 0) pos = atomicAdd(dd.list_n, total);
+        pos = __shfl(pos, 0, 64);
+        int k = 0;
+        for (int i0 = pmin; i0 < N; i0 += 64) {
+            const int i = i0 + lane;
+            const bool inC = i < N && mask_bit(mk, i);
+            const uint64_t cm = __ballot(inC);
+            const uint64_t below = lane == 0 ? 0ull : (cm & (~0ull >> (64 - lane)));
+            if (inC) dd.list[pos + k + __popcll(below)] = D.ov + (i - pmin);
+            k += __popcll(cm);
+        }
+    }
+}
+
+template <class P>
+hipError_t launch_code_diff(const ModelDims& m, const DedupIO<P>& d,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_code_diff<P>, dim3(grid_for(d.n_nb_max)), dim3(64), 0,
+                       st, m, d);
+    return hipGetLastError();
+}
+
+// Delta log psi of each neighbour: rows of C_L get new head outputs, the
+// exchanged sites p1, p2 (new targets) use the sample's cached log-probs
+// when their hidden state is unchanged.  Sums in FP64, row order.
+template <class P>
+__global__ void __launch_bounds__(64) k_head_dedup(
+    ModelDims m, HeadW<typename P::acc> hw, DedupIO<P> dd,
+    const typename P::acc* __restrict__ blp, double* __restrict__ ratio,
+    int64_t* ctr) {
+    using acc = typename P::acc;
+    const int64_t n = (int64_t)*dd.n_nb;
+    const int lane = threadIdx.x;
+    const int N = m.N, W = dd.mask_words;
+    int64_t my_rows = 0;
+    for (int64_t nb = blockIdx.x; nb < n; nb += gridDim.x) {
+        const NbDesc D = dd.desc[nb];
+        const int pmin = D.p1 + 1;
+        const uint64_t* mk = dd.mask + nb * W;
+        const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
+        double delta = 0.0;
+        for (int i = D.p1; i < N; ++i) {
+            const bool inC = i >= pmin && mask_bit(mk, i);
+            const bool ex = i == D.p1 || i == D.p2;
+            if (!inC && !ex) continue;
+            // target of s' at i: exchanged sites swap spins
+            const int8_t snew = i == D.p1 ? sp[D.p2] : (i == D.p2 ? sp[D.p1] : sp[i]);
+            const int tnew = snew < 0 ? 1 : 0, told = sp[i] < 0 ? 1 : 0;
+            const int64_t brow = (int64_t)D.sigma * N + i;
+            const acc lold = blp[brow * 2 + told];
+            acc lnew;
+            if (inC) {
+                acc l0, l1;
+                head_row<acc>(dd.ox + (D.ov + (i - pmin)) * (int64_t)m.d, m.d, hw, l0, l1);
+                lnew = tnew ? l1 : l0;
+                my_rows++;
+            } else {
+                lnew = blp[brow * 2 + tnew];
+            }
+            delta += (double)lnew - (double)lold;
+        }
+        if (lane == 0) ratio[nb] = exp(0.5 * delta);
+    }
+    if (ctr && lane == 0 && my_rows)
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_HEAD_ROWS),
+                  (unsigned long long)my_rows);
+}
+
+template <class P>
+hipError_t launch_head_dedup(const ModelDims& m, const HeadW<typename P::acc>& hw,
+                             const DedupIO<P>& d, const typename P::acc* blp,
+                             const double*, double* ratio, int64_t* ctr,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_head_dedup<P>, dim3(grid_for(d.n_nb_max)), dim3(64), 0,
+                       st, m, hw, d, blp, ratio, ctr);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ instantiations
+#define VQ_INST(P)                                                            \
+    template hipError_t launch_prepare<P>(const ModelDims&,                   \
+                                          const LayerW<P::acc>&, P::acc*,     \
+                                          P::acc*, bf16*, bf16*, bf16*,       \
+                                          bf16*, hipStream_t);                \
+    template hipError_t launch_embed<P>(const ModelDims&,                     \
+                                        const HeadW<P::acc>&, const int8_t*,  \
+                                        const int32_t*, int64_t, P::acc*,     \
+                                        hipStream_t);                         \
+    template hipError_t launch_qkv<P>(const ModelDims&, const LayerW<P::acc>&, \
+                                      RowSet, const BlockIO<P>&, hipStream_t); \
+    template hipError_t launch_attention_seq<P>(const ModelDims&,             \
+                                                const int32_t*, int64_t,      \
+                                                const BlockIO<P>&, int64_t*,  \
+                                                hipStream_t);                 \
+    template hipError_t launch_vq<P>(const ModelDims&, const LayerW<P::acc>&,  \
+                                     RowSet, const BlockIO<P>&, hipStream_t);  \
+    template hipError_t launch_mlp<P>(const ModelDims&, const LayerW<P::acc>&, \
+                                      RowSet, const BlockIO<P>&, hipStream_t); \
+    template hipError_t launch_head_seq<P>(                                   \
+        const ModelDims&, const HeadW<P::acc>&, const int8_t*,                \
+        const int32_t*, int64_t, const P::acc*, P::acc*, double*,             \
+        hipStream_t);                                                         \
+    template hipError_t launch_dedup_init<P>(const ModelDims&,                \
+                                             const HeadW<P::acc>&,            \
+                                             const DedupIO<P>&, hipStream_t); \
+    template hipError_t launch_attention_dedup<P>(                            \
+        const ModelDims&, const DedupIO<P>&, int64_t*, hipStream_t);          \
+    template hipError_t launch_certify<P>(const ModelDims&,                   \
+                                          const DedupIO<P>&, int, int64_t*,   \
+                                          hipStream_t);                       \
+    template hipError_t launch_code_diff<P>(const ModelDims&,                 \
+                                            const DedupIO<P>&, hipStream_t);  \
+    template hipError_t launch_head_dedup<P>(                                 \
+        const ModelDims&, const HeadW<P::acc>&, const DedupIO<P>&,            \
+        const P::acc*, const double*, double*, int64_t*, hipStream_t);
+
+VQ_INST(PrecF64)
+VQ_INST(PrecF32)
+VQ_INST(PrecBF16)
+
+}  // namespace vq

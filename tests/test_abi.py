@@ -1,0 +1,100 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/vqnqs.h, counts parameters like the workload layout, and
+rejects bad arguments on the host before any HIP call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2212_11296_amd as vq
+from workloads import CONFIGS, MULTI_LATTICE, param_count
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "vqnqs.h")).read()
+    return sorted(set(re.findall(r"\b(vqnqs_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = vq.load_library()
+    declared = header_functions()
+    assert len(declared) >= 7
+    for name in declared:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", vq.library_path()],
+                         capture_output=True, text=True).stdout
+    for name in declared:
+        assert re.search(rf"\bT {name}$", out, re.M), name
+
+
+@pytest.mark.parametrize("mc", list(CONFIGS.values()) + list(MULTI_LATTICE))
+def test_param_count_matches_layout(mc):
+    assert vq.param_count(vq.make_config(mc)) == param_count(mc)
+
+
+def _cfg(**kw):
+    c = vq.make_config(CONFIGS["small"])
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(L=2), 2),                       # periodic needs L >= 3
+    (dict(L=5), 2),                       # periodic + Marshall needs even L
+    (dict(d_model=17), 2),                # d % n_heads
+    (dict(d_model=18), 5),                # head width 9 unsupported
+    (dict(vq_heads=3), 2),                # d % vq_heads
+    (dict(precision=7), 2),
+    (dict(flags=4), 2),
+    (dict(n_heads=16), 5),                # head width 1 unsupported
+    (dict(codebook_size=0), 2),
+])
+def test_invalid_configs_rejected(kw, status):
+    lib = vq.load_library()
+    c = _cfg(**kw)
+    assert lib.vqnqs_param_count(ctypes.byref(c)) == -status
+    sz = ctypes.c_size_t()
+    assert lib.vqnqs_workspace_size(ctypes.byref(c), 4, 1, 0,
+                                    ctypes.byref(sz)) == status
+    assert lib.vqnqs_local_energy(ctypes.byref(c), None, None, 4, 1, None,
+                                  None, None, None, None, 0, None) == status
+
+
+def test_open_odd_lattice_allowed():
+    c = _cfg(L=5, periodic=0)
+    assert vq.param_count(c) > 0
+
+
+def test_null_and_shape_errors_on_host():
+    lib = vq.load_library()
+    c = _cfg()
+    dummy = ctypes.c_void_p(16)           # never dereferenced: errors first
+    assert lib.vqnqs_local_energy(None, dummy, dummy, 4, 1, dummy, None, None,
+                                  None, dummy, 1 << 20, None) == 1
+    assert lib.vqnqs_local_energy(ctypes.byref(c), dummy, dummy, -1, 1, dummy,
+                                  None, None, None, dummy, 1 << 20, None) == 3
+    assert lib.vqnqs_local_energy(ctypes.byref(c), None, dummy, 4, 1, dummy,
+                                  None, None, None, dummy, 1 << 20, None) == 1
+    assert lib.vqnqs_local_energy(ctypes.byref(c), dummy, dummy, 4, 9, dummy,
+                                  None, None, None, dummy, 1 << 20, None) == 2
+    assert lib.vqnqs_forward_logpsi(ctypes.byref(c), dummy, dummy, 4, None,
+                                    None, dummy, 1 << 20, None) == 1
+    assert lib.vqnqs_neighbours(ctypes.byref(c), dummy, -2, dummy, dummy,
+                                None, dummy, 1 << 20, None) == 3
+    assert lib.vqnqs_workspace_status(None, None) == 1
+    assert lib.vqnqs_status_string(6) == b"spin value other than +1/-1"
+
+
+def test_workspace_size_grows_with_chunk():
+    for name in ["small", "medium", "large"]:
+        c = vq.make_config(CONFIGS[name])
+        for mode in (vq.PLAIN, vq.DEDUP, -1):
+            s1 = vq.workspace_size(c, 64, mode, 1)
+            s8 = vq.workspace_size(c, 64, mode, 8)
+            sall = vq.workspace_size(c, 64, mode, 0)
+            assert 0 < s1 < s8 < sall

@@ -9,8 +9,8 @@ draw their inputs from it without sharing any computation.
 from .configs import (ModelConfig, CONFIGS, MULTI_LATTICE, config_by_name,
                       with_batch)
 from .layout import param_layout, param_count
-from .generate import make_spins, make_params, scale_codebooks
+from .generate import make_spins, make_params, scale_codebooks, bf16_round
 
 __all__ = ["ModelConfig", "CONFIGS", "MULTI_LATTICE", "config_by_name",
            "with_batch", "param_layout", "param_count", "make_spins",
-           "make_params", "scale_codebooks"]
+           "make_params", "scale_codebooks", "bf16_round"]
