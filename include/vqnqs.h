@@ -174,6 +174,18 @@ vqnqs_status vqnqs_workspace_status(const void* ws, void* stream);
 
 const char* vqnqs_status_string(vqnqs_status s);
 
+/* Measurement support (not part of the method).  When enabled, every kernel
+ * launch of the library is bracketed by HIP events recorded on the launch
+ * stream; vqnqs_profile_read waits for them and returns, per kernel class,
+ * the summed device time in milliseconds and the number of launches.
+ *   names [max][name_len] HOST out, nullable; total_ms [max], count [max]
+ *   HOST out, nullable.  Returns the number of kernel classes (may exceed
+ *   max).  Process-wide; not for concurrent use from several threads. */
+void vqnqs_profile_enable(int on);
+void vqnqs_profile_reset(void);
+int  vqnqs_profile_read(char* names, int name_len, double* total_ms,
+                        long long* count, int max);
+
 #ifdef __cplusplus
 }
 #endif

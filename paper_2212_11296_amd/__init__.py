@@ -8,10 +8,11 @@ library; the first call does, and fails loudly if it has not been built.
 from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
                   NCOUNTERS, CTR, VQNQSError, library_path, load_library,
                   exported_symbols, param_count, workspace_size, neighbours,
-                  forward_logpsi, local_energy, make_config)
+                  forward_logpsi, local_energy, make_config, profile_enable,
+                  profile_reset, profile_read)
 
 __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "FLAG_CERTIFIED_VQ", "NCOUNTERS", "CTR", "VQNQSError",
            "library_path", "load_library", "exported_symbols", "param_count",
            "workspace_size", "neighbours", "forward_logpsi", "local_energy",
-           "make_config"]
+           "make_config", "profile_enable", "profile_reset", "profile_read"]

@@ -17,7 +17,8 @@ _STATUS = {0: "ok", 1: "null pointer", 2: "invalid config", 3: "invalid shape",
 
 EXPORTS = ["vqnqs_param_count", "vqnqs_workspace_size", "vqnqs_neighbours",
            "vqnqs_forward_logpsi", "vqnqs_local_energy",
-           "vqnqs_workspace_status", "vqnqs_status_string"]
+           "vqnqs_workspace_status", "vqnqs_status_string",
+           "vqnqs_profile_enable", "vqnqs_profile_reset", "vqnqs_profile_read"]
 
 
 class VQNQSError(RuntimeError):
@@ -80,6 +81,13 @@ def load_library():
     lib.vqnqs_workspace_status.restype = ctypes.c_int
     lib.vqnqs_status_string.argtypes = [ctypes.c_int]
     lib.vqnqs_status_string.restype = ctypes.c_char_p
+    lib.vqnqs_profile_enable.argtypes = [ctypes.c_int]
+    lib.vqnqs_profile_enable.restype = None
+    lib.vqnqs_profile_reset.argtypes = []
+    lib.vqnqs_profile_reset.restype = None
+    lib.vqnqs_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_int, P, P,
+                                       ctypes.c_int]
+    lib.vqnqs_profile_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -87,6 +95,31 @@ def load_library():
 def exported_symbols():
     lib = load_library()
     return {name: hasattr(lib, name) for name in EXPORTS}
+
+
+def profile_enable(on=True):
+    load_library().vqnqs_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load_library().vqnqs_profile_reset()
+
+
+def profile_read(max_kernels=64):
+    """{kernel class: (total device ms, launches)} from the library's event
+    timing (waits for the recorded events)."""
+    lib = load_library()
+    L = 48
+    names = ctypes.create_string_buffer(L * max_kernels)
+    ms = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_longlong * max_kernels)()
+    n = lib.vqnqs_profile_read(names, L, ctypes.cast(ms, ctypes.c_void_p),
+                               ctypes.cast(cnt, ctypes.c_void_p), max_kernels)
+    out = {}
+    for k in range(min(n, max_kernels)):
+        nm = names.raw[k * L:(k + 1) * L].split(b"\0", 1)[0].decode()
+        out[nm] = (ms[k], cnt[k])
+    return out
 
 
 def _check(fn, st):

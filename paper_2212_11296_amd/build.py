@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvqnqs.so")
 
-SOURCES = ["abi.cpp", "engine.cpp", "kernels_lattice.hip", "kernels_layer.hip",
+SOURCES = ["abi.cpp", "engine.cpp", "profiler.cpp", "kernels_lattice.hip", "kernels_layer.hip",
            "kernels_mfma.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

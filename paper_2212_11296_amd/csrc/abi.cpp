@@ -4,6 +4,7 @@
 
 #include "engine.h"
 #include "kernels.h"
+#include "profiler.h"
 
 namespace {
 
@@ -132,6 +133,16 @@ vqnqs_status vqnqs_workspace_status(const void* ws, void* stream) {
     if (hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
         return VQNQS_ERR_HIP;
     return v ? VQNQS_ERR_BAD_SPIN : VQNQS_OK;
+}
+
+void vqnqs_profile_enable(int on) { vq::Profiler::get().enable(on != 0); }
+
+void vqnqs_profile_reset(void) { vq::Profiler::get().reset(); }
+
+int vqnqs_profile_read(char* names, int name_len, double* total_ms,
+                       long long* count, int max) {
+    if (max < 0 || (names && name_len < 2)) return -1;
+    return vq::Profiler::get().read(names, name_len, total_ms, count, max);
 }
 
 const char* vqnqs_status_string(vqnqs_status s) {

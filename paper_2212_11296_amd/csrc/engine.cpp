@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "kernels.h"
+#include "profiler.h"
 
 namespace vq {
 
@@ -252,6 +253,16 @@ int64_t param_count(const ModelDims& m) {
         if (e_ != hipSuccess) return VQNQS_ERR_HIP; \
     } while (0)
 
+// Launch with optional per-kernel event timing on the launch stream.
+#define LK(name, x)                                         \
+    do {                                                    \
+        Profiler& pf_ = Profiler::get();                    \
+        if (pf_.enabled()) pf_.begin(name, st);             \
+        hipError_t e_ = (x);                                \
+        if (pf_.enabled()) pf_.end(st);                     \
+        if (e_ != hipSuccess) return VQNQS_ERR_HIP;         \
+    } while (0)
+
 template <class P>
 struct Runner {
     using acc = typename P::acc;
@@ -296,17 +307,17 @@ struct Runner {
     vqnqs_status prepare() {
         if constexpr (std::is_same<P, PrecBF16>::value) {
             // the BF16 mode evaluates the network at bf16-rounded parameters
-            CK(launch_round_bf16(params, param_count(m), w.prm, st));
+            LK("round_bf16", launch_round_bf16(params, param_count(m), w.prm, st));
             params = w.prm;
         }
         for (int l = 0; l < m.nl; ++l) {
             LayerW<acc> lw = layer(l);
-            CK(launch_prepare<P>(m, lw, const_cast<acc*>(lw.table),
+            LK("prepare", launch_prepare<P>(m, lw, const_cast<acc*>(lw.table),
                                  const_cast<acc*>(lw.cnorm), nullptr, nullptr,
                                  nullptr, nullptr, st));
             if constexpr (std::is_same<P, PrecBF16>::value)
                 if (m.mfma)
-                    CK(launch_pack_layer(m, lw, const_cast<bf16*>(lw.Wqkv_p),
+                    LK("pack_layer", launch_pack_layer(m, lw, const_cast<bf16*>(lw.Wqkv_p),
                                          const_cast<bf16*>(lw.W1_p),
                                          const_cast<bf16*>(lw.W2_p),
                                          const_cast<bf16*>(lw.cb_p), st));
@@ -331,7 +342,7 @@ struct Runner {
     vqnqs_status forward(const SeqBufs& b, const int32_t* n_dev, int64_t n,
                          bool count_rows) {
         const int64_t rows = n * m.N, sd = rows * m.d, sh = rows * m.H;
-        CK(launch_embed<P>(m, head(), b.spins, n_dev, n, b.x, st));
+        LK("embed", launch_embed<P>(m, head(), b.spins, n_dev, n, b.x, st));
         for (int l = 0; l < m.nl; ++l) {
             const int64_t cl = b.cache ? l : 0;
             BlockIO<P> io{};
@@ -346,15 +357,15 @@ struct Runner {
             RowSet rs{nullptr, n_dev, rows, (int32_t)m.N};
             BlockIO<P> qio = io;
             qio.x = const_cast<acc*>(io.x_in);
-            CK(qkv(layer(l), rs, qio));
-            CK(launch_attention_seq<P>(m, n_dev, n, io, count_rows ? ctr : nullptr, st));
-            CK(vqs(layer(l), rs, io));
-            CK(mlp(layer(l), rs, io));
+            LK("qkv", qkv(layer(l), rs, qio));
+            LK("attention_seq", launch_attention_seq<P>(m, n_dev, n, io, count_rows ? ctr : nullptr, st));
+            LK("vq", vqs(layer(l), rs, io));
+            LK("mlp", mlp(layer(l), rs, io));
             if (b.codes_out)
-                CK(launch_copy_codes(io.codes, n, m.N, m.H, m.nl, l, b.codes_out, st));
+                LK("copy_codes", launch_copy_codes(io.codes, n, m.N, m.H, m.nl, l, b.codes_out, st));
         }
         const acc* xf = b.x + (b.cache ? (int64_t)m.nl * sd : 0);
-        CK(launch_head_seq<P>(m, head(), b.spins, n_dev, n, xf, b.lp, b.logpsi, st));
+        LK("head_seq", launch_head_seq<P>(m, head(), b.spins, n_dev, n, xf, b.lp, b.logpsi, st));
         if (count_rows && ctr) {
             if (n_dev) {
                 CK(launch_counter_add(ctr, VQNQS_CTR_QKV_ROWS, n_dev, (int64_t)m.N * m.nl, st));
@@ -372,9 +383,9 @@ struct Runner {
     }
 
     vqnqs_status neighbours(const int8_t* spins, int64_t n) {
-        CK(launch_neighbours(spins, n, m, w.bonds, w.count, w.diag, w.rows_cap,
+        LK("neighbours", launch_neighbours(spins, n, m, w.bonds, w.count, w.diag, w.rows_cap,
                              w.status, st));
-        CK(launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, w.nb_off,
+        LK("scan_desc", launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, w.nb_off,
                             w.row_off, w.n_nb, w.n_rows, w.desc, st));
         if (ctr) {
             CK(launch_counter_add_const(ctr, VQNQS_CTR_SAMPLES, n, st));
@@ -391,12 +402,12 @@ struct Runner {
         s = forward(sb, nullptr, n, true);
         if (s) return s;
         const int64_t nbmax = n * 2 * m.N;
-        CK(launch_materialise(spins, w.desc, w.n_nb, nbmax, m.N, w.nspins, st));
+        LK("materialise", launch_materialise(spins, w.desc, w.n_nb, nbmax, m.N, w.nspins, st));
         SeqBufs nbuf{w.nspins, w.nx, w.nq, w.nk, w.nv, w.na, w.ncode, nullptr,
                      nullptr, w.logpsi_nb, false, nullptr};
         s = forward(nbuf, w.n_nb, nbmax, true);
         if (s) return s;
-        CK(launch_ratio_plain(w.logpsi_nb, w.logpsi_s, w.desc, w.n_nb, nbmax,
+        LK("ratio_plain", launch_ratio_plain(w.logpsi_nb, w.logpsi_s, w.desc, w.n_nb, nbmax,
                               w.ratio, st));
         return VQNQS_OK;
     }
@@ -433,7 +444,7 @@ struct Runner {
         dd.vq_list = w.vq_list;
         dd.vq_n = w.vq_n;
         CK(launch_fill_i32(w.list_n, 1, 0, st));
-        CK(launch_dedup_init<P>(m, head(), dd, st));
+        LK("dedup_init", launch_dedup_init<P>(m, head(), dd, st));
         if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_CHANGED0, w.list_n, 1, st));
         const bool certified = (m.flags & VQNQS_FLAG_CERTIFIED_VQ) != 0;
         for (int l = 0; l < m.nl; ++l) {
@@ -458,28 +469,28 @@ struct Runner {
             io.margin = nullptr;
             RowSet cl{w.list, w.list_n, R, 1};
             if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_QKV_ROWS, w.list_n, 1, st));
-            CK(qkv(lw, cl, io));
-            CK(launch_attention_dedup<P>(m, dd, ctr, st));
+            LK("qkv", qkv(lw, cl, io));
+            LK("attention_dedup", launch_attention_dedup<P>(m, dd, ctr, st));
             if (certified) {
                 CK(launch_fill_i32(w.vq_n, 1, 0, st));
-                CK(launch_certify<P>(m, dd, 1, ctr, st));
+                LK("certify", launch_certify<P>(m, dd, 1, ctr, st));
                 RowSet vr{w.vq_list, w.vq_n, R, 1};
-                CK(vqs(lw, vr, io));
+                LK("vq", vqs(lw, vr, io));
                 if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_VQ_ROWS, w.vq_n, 1, st));
             } else {
                 RowSet vr{nullptr, w.n_rows, R, 1};
-                CK(vqs(lw, vr, io));
+                LK("vq", vqs(lw, vr, io));
                 if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_VQ_ROWS, w.n_rows, 1, st));
             }
             CK(launch_fill_i32(w.list_n, 1, 0, st));
-            CK(launch_code_diff<P>(m, dd, st));
+            LK("code_diff", launch_code_diff<P>(m, dd, st));
             if (ctr) {
                 CK(launch_counter_add(ctr, VQNQS_CTR_CHANGED0 + l + 1, w.list_n, 1, st));
                 CK(launch_counter_add(ctr, VQNQS_CTR_MLP_ROWS, w.list_n, 1, st));
             }
-            CK(mlp(lw, cl, io));
+            LK("mlp", mlp(lw, cl, io));
         }
-        CK(launch_head_dedup<P>(m, head(), dd, w.blp, nullptr, w.ratio, ctr, st));
+        LK("head_dedup", launch_head_dedup<P>(m, head(), dd, w.blp, nullptr, w.ratio, ctr, st));
         return VQNQS_OK;
     }
 };
@@ -508,11 +519,11 @@ static vqnqs_status run_local_energy(const ModelDims& m, const void* params,
         const int8_t* sp = spins + c0 * m.N;
         s = mode == VQNQS_PLAIN ? r.plain_chunk(sp, n) : r.dedup_chunk(sp, n);
         if (s) return s;
-        CK(launch_eloc(r.w.diag, r.w.count, r.w.nb_off, r.w.ratio, (int)n, m.N,
+        LK("eloc", launch_eloc(r.w.diag, r.w.count, r.w.nb_off, r.w.ratio, (int)n, m.N,
                        h_off, eloc + c0,
                        ratios ? ratios + c0 * 2 * m.N : nullptr, st));
     }
-    if (stats) CK(launch_stats(eloc, batch, stats, st));
+    if (stats) LK("stats", launch_stats(eloc, batch, stats, st));
     return VQNQS_OK;
 }
 
@@ -554,7 +565,7 @@ static vqnqs_status run_forward(const ModelDims& m, const void* params,
         const int64_t n = std::min(chunk, batch - c0);
         const int8_t* sp = spins + c0 * m.N;
         // spin validation shares the neighbour kernel
-        CK(launch_neighbours(sp, n, m, r.w.bonds, r.w.count, nullptr, nullptr,
+        LK("neighbours", launch_neighbours(sp, n, m, r.w.bonds, r.w.count, nullptr, nullptr,
                              r.w.status, st));
         typename Runner<P>::SeqBufs sb{
             sp, r.w.bx, r.w.bq, r.w.bk, r.w.bv, r.w.ba, r.w.bcode, nullptr,
@@ -589,7 +600,7 @@ vqnqs_status neighbours(const ModelDims& m, const int8_t* spins, int64_t batch,
     if (ws_bytes < workspace_bytes(m, -2, 0)) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
     Workspace<PrecF64> w = carve<PrecF64>(m, Job::Neighbours, 0, ws);
     CK(launch_fill_i32(w.status, 1, 0, st));
-    CK(launch_neighbours(spins, batch, m, bonds, count, diag, nullptr, w.status,
+    LK("neighbours", launch_neighbours(spins, batch, m, bonds, count, diag, nullptr, w.status,
                          st));
     return VQNQS_OK;
 }

@@ -1,0 +1,129 @@
+"""GPU parity of the BF16 matrix-core path against the FP64 oracle.
+
+The BF16 mode evaluates the network at bfloat16 parameters (the workloads
+generate bfloat16-representable values, so the oracle sees the same ones),
+with FP32 activations entering the matrix core as hi+lo bfloat16 pairs.
+Tolerances: the mean energy within 1e-3 relative (the target for this
+path); per-sample E_loc within 1e-2 relative; neighbour ratios with median
+relative error below 1e-4 and 99th percentile below 1e-3 (an activation
+carries ~2^-16 relative error, amplified through the layers and the
+exponential of the log-psi difference), the rest within 5e-2: those are
+quantizer near-ties resolved to the other, equally valid, code, which moves
+one ratio by a finite step; log psi within 1e-3 absolute.  VQ
+codes are integers decided in floating point: they must equal the oracle's
+except where the oracle's best and second-best distances are within the
+BF16 path's error bound (a valid near-tie), checked at the first differing
+layer of each sequence.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2212_11296_amd as vq
+from oracle import eloc as oeloc
+from oracle import lattice
+from oracle import network as net
+from workloads import CONFIGS, make_params, make_spins, with_batch
+
+from gpu_common import dev_params, dev_spins, host, needs_gpu, say
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def check_codes(mc, theta, s, gpu_codes):
+    ref = net.forward(mc, net.unpack(mc, theta), s, keep=True)
+    oc = np.transpose(ref["codes"], (1, 0, 2, 3))          # [B][nl][N][H]
+    diff = gpu_codes != oc
+    for b in range(s.shape[0]):
+        if not diff[b].any():
+            continue
+        l = int(np.nonzero(diff[b].any(axis=(1, 2)))[0][0])
+        rows, heads = np.nonzero(diff[b, l])
+        c = ref["caches"][l]
+        gap = c["d2"][b, rows, heads] - c["d1"][b, rows, heads]
+        assert (gap < 1e-3 * (1 + c["d1"][b, rows, heads])).all(), (b, l)
+    return diff.mean()
+
+
+@pytest.mark.parametrize("name,batch", [("medium", 64), ("large", 8),
+                                        ("grad", 2)])
+def test_forward_bf16(name, batch):
+    mc = with_batch(CONFIGS[name], batch, precision="bf16")
+    say(f"forward bf16 {name} B={batch}")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    lp, codes = vq.forward_logpsi(vq.make_config(mc), dev_params(theta, "bf16"),
+                                  dev_spins(s), codes=True)
+    ref = net.forward(mc, net.unpack(mc, theta), s)
+    assert np.abs(host(lp) - ref["logpsi"]).max() < 1e-3
+    rate = check_codes(mc, theta, s, host(codes))
+    assert rate < 1e-3
+
+
+@pytest.mark.parametrize("flags", [0, vq.FLAG_CERTIFIED_VQ])
+def test_local_energy_bf16_medium(flags):
+    mc = with_batch(CONFIGS["medium"], 24, precision="bf16")
+    say(f"eloc bf16 medium flags={flags}")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc, flags=flags)
+    out = vq.local_energy(cfg, dev_params(theta, "bf16"), dev_spins(s),
+                          vq.DEDUP, ratios=True)
+    E_ref, r_ref = oeloc.eloc_network_naive(mc, theta, s, return_ratios=True)
+    E = host(out["eloc"])
+    assert abs(E.mean() - E_ref.mean()) / abs(E_ref.mean()) < 1e-3
+    assert (np.abs(E - E_ref) / np.abs(E_ref)).max() < 1e-2
+    R = host(out["ratios"])
+    rel = np.concatenate([np.abs(R[b, :len(r_ref[b])] / r_ref[b] - 1)
+                          for b in range(s.shape[0])])
+    assert np.median(rel) < 1e-4
+    assert np.quantile(rel, 0.99) < 1e-3
+    assert rel.max() < 5e-2
+
+
+def test_local_energy_bf16_large_full_batch_sampled():
+    """The benchmark's launch configuration (8192 samples, one call) with
+    outputs sampled and recomputed one by one by the oracle."""
+    mc = CONFIGS["large"]
+    say("eloc bf16 large full batch")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    ws = torch.empty(min(vq.workspace_size(cfg, mc.batch, vq.DEDUP, 0),
+                         48 << 30), dtype=torch.uint8, device="cuda")
+    out = vq.local_energy(cfg, dev_params(theta, "bf16"), dev_spins(s),
+                          vq.DEDUP, ratios=True, counters=True, ws=ws)
+    E, R = host(out["eloc"]), host(out["ratios"])
+    ctr = host(out["counters"])
+    assert ctr[vq.CTR["samples"]] == mc.batch
+    P = net.unpack(mc, theta)
+    bl = lattice.bonds(mc.L, True)
+    rng = np.random.default_rng(11)
+    rel = []
+    for b in rng.choice(mc.batch, 4, replace=False):
+        nb = lattice.neighbours(s[b], bl)
+        assert np.count_nonzero(R[b]) == len(nb)
+        ks = rng.choice(len(nb), 3, replace=False)
+        seqs = np.stack([s[b]] + [lattice.swap(s[b], nb[k][1], nb[k][2])
+                                  for k in ks])
+        lps = net.forward(mc, P, seqs)["logpsi"]
+        for j, k in enumerate(ks):
+            rel.append(abs(R[b, k] / np.exp(lps[j + 1] - lps[0]) - 1))
+        # E_loc assembly from the ratios: exact diagonal + (-J/2) sum
+        diag = lattice.diagonal(s[b:b + 1], bl)[0]
+        assert abs(E[b] - (diag - 0.5 * R[b].sum())) <= 1e-12 * abs(E[b])
+    assert np.median(rel) < 1e-3 and max(rel) < 5e-2
+
+
+def test_plain_equals_dedup_large_bitwise_rows():
+    mc = with_batch(CONFIGS["large"], 6, precision="bf16")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    ra = host(vq.local_energy(cfg, p, sp, vq.PLAIN, ratios=True)["ratios"])
+    rb = host(vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)["ratios"])
+    rc = host(vq.local_energy(vq.make_config(mc, flags=1), p, sp, vq.DEDUP,
+                              ratios=True)["ratios"])
+    assert np.allclose(rb, ra, rtol=1e-12, atol=0)
+    assert np.array_equal(rb, rc)
