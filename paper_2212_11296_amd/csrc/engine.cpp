@@ -77,7 +77,8 @@ struct Workspace {
     // overlay (dedup)
     acc* ox;
     act *oq, *ok, *ov, *oa;
-    int32_t *ocode, *slot_nb;
+    int32_t *ocode, *slot_nb, *ccnt;
+    int16_t* crow;
     uint64_t* mask;
     int64_t *list, *vq_list;
     size_t bytes;
@@ -157,6 +158,8 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
         w.oa = c.take<act>(R * d);
         w.ocode = c.take<int32_t>(R * H);
         w.slot_nb = c.take<int32_t>(R);
+        w.crow = c.take<int16_t>(R);
+        w.ccnt = c.take<int32_t>(nbmax);
         w.list = c.take<int64_t>(R);
         w.vq_list = c.take<int64_t>(R);
         w.mask = c.take<uint64_t>(nbmax * W);
@@ -297,6 +300,19 @@ struct Runner {
             if (m.mfma) return launch_mlp_mfma(m, lw, rs, io, st);
         return launch_mlp<P>(m, lw, rs, io, st);
     }
+    hipError_t attn_seq(const int32_t* n_dev, int64_t n, const BlockIO<P>& io,
+                        int64_t* c) {
+        if constexpr (std::is_same<P, PrecBF16>::value)
+            if (m.mfma && attn_mfma_ok(m))
+                return launch_attn_seq_mfma(m, n_dev, n, io, c, st);
+        return launch_attention_seq<P>(m, n_dev, n, io, c, st);
+    }
+    hipError_t attn_dedup(const DedupIO<P>& dd) {
+        if constexpr (std::is_same<P, PrecBF16>::value)
+            if (m.mfma && attn_mfma_ok(m))
+                return launch_attn_dedup_mfma(m, dd, ctr, st);
+        return launch_attention_dedup<P>(m, dd, ctr, st);
+    }
     hipError_t vqs(const LayerW<acc>& lw, RowSet rs, const BlockIO<P>& io) {
         if constexpr (std::is_same<P, PrecBF16>::value)
             if (m.mfma) return launch_vq_mfma(m, lw, rs, io, st);
@@ -358,7 +374,7 @@ struct Runner {
             BlockIO<P> qio = io;
             qio.x = const_cast<acc*>(io.x_in);
             LK("qkv", qkv(layer(l), rs, qio));
-            LK("attention_seq", launch_attention_seq<P>(m, n_dev, n, io, count_rows ? ctr : nullptr, st));
+            LK("attention_seq", attn_seq(n_dev, n, io, count_rows ? ctr : nullptr));
             LK("vq", vqs(layer(l), rs, io));
             LK("mlp", mlp(layer(l), rs, io));
             if (b.codes_out)
@@ -427,10 +443,14 @@ struct Runner {
         dd.desc = w.desc;
         dd.n_nb = w.n_nb;
         dd.n_nb_max = nbmax;
+        dd.nb_off = w.nb_off;
+        dd.n_samples = n;
         dd.n_rows = w.n_rows;
         dd.rows_max = R;
         dd.spins = spins;
         dd.slot_nb = w.slot_nb;
+        dd.crow = w.crow;
+        dd.ccnt = w.ccnt;
         dd.ox = w.ox;
         dd.oq = w.oq;
         dd.ok = w.ok;
@@ -470,7 +490,7 @@ struct Runner {
             RowSet cl{w.list, w.list_n, R, 1};
             if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_QKV_ROWS, w.list_n, 1, st));
             LK("qkv", qkv(lw, cl, io));
-            LK("attention_dedup", launch_attention_dedup<P>(m, dd, ctr, st));
+            LK("attention_dedup", attn_dedup(dd));
             if (certified) {
                 CK(launch_fill_i32(w.vq_n, 1, 0, st));
                 LK("certify", launch_certify<P>(m, dd, 1, ctr, st));

@@ -75,6 +75,10 @@ hipError_t launch_mlp_mfma(const ModelDims& m, const LayerW<float>& w,
 hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
                           RowSet rows, const BlockIO<PrecBF16>& io,
                           hipStream_t st);
+bool attn_mfma_ok(const ModelDims& m);
+hipError_t launch_attn_seq_mfma(const ModelDims& m, const int32_t* n_dev,
+                                int64_t n_seq, const BlockIO<PrecBF16>& io,
+                                int64_t* ctr, hipStream_t st);
 
 // ---- full-sequence forward pieces (samples or materialised neighbours)
 hipError_t launch_materialise(const int8_t* spins, const NbDesc* desc,
@@ -110,12 +114,17 @@ struct DedupIO {
     using act = typename P::act;
     using acc = typename P::acc;
     const NbDesc* desc;       // [n_nb]
+    const int32_t* nb_off;    // [n+1] first neighbour of every sample
+    int64_t n_samples;        // samples in the chunk
     const int32_t* n_nb;      // device count of neighbours in the chunk
     int64_t n_nb_max;
     const int32_t* n_rows;    // device: overlay rows of the chunk
     int64_t rows_max;
     const int8_t* spins;      // chunk samples [n][N]
     int32_t* slot_nb;         // [rows] owning neighbour of every overlay row
+    int16_t* crow;            // [rows] rows of C of every neighbour, ascending,
+                              // at the neighbour's overlay offset
+    int32_t* ccnt;            // [n_nb] size of C of every neighbour
     // sample caches of the current layer: [n][N][...]
     const acc* bx;            // block input
     const act *bq, *bk, *bv, *ba;
@@ -151,6 +160,9 @@ hipError_t launch_head_dedup(const ModelDims& m, const HeadW<typename P::acc>& h
                              const DedupIO<P>& d, const typename P::acc* blp,
                              const double* bell_unused, double* ratio,
                              int64_t* ctr, hipStream_t st);
+hipError_t launch_attn_dedup_mfma(const ModelDims& m,
+                                  const DedupIO<PrecBF16>& d, int64_t* ctr,
+                                  hipStream_t st);
 hipError_t launch_ratio_plain(const double* logpsi_nb, const double* logpsi_s,
                               const NbDesc* desc, const int32_t* n_dev,
                               int64_t n_max, double* ratio, hipStream_t st);

@@ -1,0 +1,374 @@
+// Causal multi-head self-attention on the matrix core (gfx950, BF16 mode),
+// paper Sec. 3.1/3.2: the location-mixing operation, evaluated densely for
+// every query row at or after the first changed input.
+//
+// Scores are computed transposed, S^T = K Q^T, with 16x16x32 MFMAs: lane l
+// then holds the scores of query l%16 for keys 4g..4g+3 of each 16-key tile
+// (g = l/16), i.e. 8 keys of a 32-key block, taken in the order
+// pi(8g+j) = 4g+j (j<4), 16+4g+j-4 (j>=4).  The output is formed as
+// O^T = V^T P^T: those 8 probabilities are then exactly the lane's B-operand
+// fragment, V^T is read from LDS in the same key order, and the result
+// O^T[dh][q] leaves every lane with one query column, so the online-softmax
+// state of a query never leaves its lane.  FP32 operands enter as hi+lo
+// bfloat16 pairs: q.k = qh.kh + qh.kl + ql.kh (+ ql.kl when the head width is
+// 16, where it comes free), the terms laid end to end along the MFMA K
+// dimension, and V^T P^T = vh.ph + vl.ph + vh.pl, accumulated in FP32.
+// Softmax is online over 32-key blocks in base-2 exponentials, log2(e) and
+// 1/sqrt(d_head) folded into the query.
+//
+// One workgroup owns one (sequence, head): the sequence's K, Q (hi|lo rows)
+// and V (hi/lo, transposed) stay in LDS.  In the overlay form the workgroup
+// then walks all neighbours of its sample, rewriting only the rows changed
+// by the previous or the current neighbour.  Query tiles sit at absolute
+// 16-row positions and key blocks at absolute 32-key positions, so a row's
+// result does not depend on which form evaluated it.
+#include "kernels.h"
+
+namespace vq {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int kAT = 256;
+constexpr int kAGridCap = 8192;
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ inline f32x4 mfma_a(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline bool mbit(const uint64_t* m, int i) {
+    return (m[i >> 6] >> (i & 63)) & 1ull;
+}
+
+__device__ inline int npad32(int N) { return (N + 31) & ~31; }
+__device__ inline int ldv_of(int N) { return npad32(N) + 8; }
+
+// LDS tiles of one (sequence, head).
+template <int DH>
+struct Tiles {
+    __bf16* Kc;   // [Np][2DH]  k hi | k lo
+    __bf16* Qc;   // [Np][2DH]  q hi | q lo (q pre-scaled)
+    __bf16* Vt;   // [2DH][ldv] v hi rows then v lo rows, transposed
+    int ldv;
+    // Stores row j, column c: k, q*qs and v as hi+lo bfloat16 pairs.  The
+    // scaling and the split are kept free of FMA contraction so that a row
+    // gets the same bits whichever loop stores it (the compiler decides
+    // contraction per inlined copy otherwise).
+    __device__ void put(int j, int c, float k, float qraw, float qs,
+                        float v) const {
+#pragma clang fp contract(off)
+        const float q = qraw * qs;
+        const __bf16 kh = (__bf16)k, qh = (__bf16)q, vh = (__bf16)v;
+        Kc[j * 2 * DH + c] = kh;
+        Kc[j * 2 * DH + DH + c] = (__bf16)(k - (float)kh);
+        Qc[j * 2 * DH + c] = qh;
+        Qc[j * 2 * DH + DH + c] = (__bf16)(q - (float)qh);
+        Vt[c * ldv + j] = vh;
+        Vt[(DH + c) * ldv + j] = (__bf16)(v - (float)vh);
+    }
+};
+
+template <int DH>
+__device__ inline Tiles<DH> carve_tiles(unsigned char* smem, int N) {
+    Tiles<DH> t;
+    const int Np = npad32(N);
+    t.Kc = reinterpret_cast<__bf16*>(smem);
+    t.Qc = t.Kc + Np * 2 * DH;
+    t.Vt = t.Qc + Np * 2 * DH;
+    t.ldv = ldv_of(N);
+    return t;
+}
+
+// All rows of the sequence at row offset sb (row j at sb + j*d), padded with
+// zero rows to a multiple of 32.
+template <int DH>
+__device__ inline void load_all(const Tiles<DH>& T, int N, const float* Q,
+                                const float* K, const float* V, int64_t sb,
+                                int d, float qs) {
+    const int Np = npad32(N);
+    for (int e = threadIdx.x; e < Np * DH; e += kAT) {
+        const int j = e / DH, c = e - (e / DH) * DH;
+        float k = 0.0f, q = 0.0f, v = 0.0f;
+        if (j < N) {
+            const int64_t o = sb + (int64_t)j * d + c;
+            k = K[o];
+            q = Q[o];
+            v = V[o];
+        }
+        T.put(j, c, k, q, qs, v);
+    }
+}
+
+// One 16-query tile t against keys 0..16t+15 held in LDS; writes rows
+// i >= lo (and < N) through orow(i).
+template <int DH, class OF>
+__device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
+                                 OF orow) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    const int iq = t * 16 + c16;              // the query of this lane
+    const __bf16* qr = T.Qc + iq * 2 * DH;
+    bf16x8 b0, b1, b2;
+    if (DH == 16) {
+        // [kh(16) | kl(16)] x [qh ; qh]  and  [kh | kl] x [ql ; ql]
+        b0 = *reinterpret_cast<const bf16x8*>(qr + 8 * (g & 1));
+        b1 = *reinterpret_cast<const bf16x8*>(qr + DH + 8 * (g & 1));
+        b2 = b1;
+    } else {
+        // [kh(32)] x [qh], [kl(32)] x [qh], [kh(32)] x [ql]
+        b0 = *reinterpret_cast<const bf16x8*>(qr + 8 * g);
+        b1 = b0;
+        b2 = *reinterpret_cast<const bf16x8*>(qr + DH + 8 * g);
+    }
+    constexpr int NT = DH / 16;
+    f32x4 o[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) o[u] = f32x4{0, 0, 0, 0};
+    float mrow = -__builtin_inff(), lrow = 0.0f;
+    const int nblk = (t * 16 + 15) / 32 + 1;
+    for (int blk = 0; blk < nblk; ++blk) {
+        const int j0 = blk * 32;
+        float s[8];
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            const __bf16* kr = T.Kc + (j0 + sub * 16 + c16) * 2 * DH;
+            f32x4 acc = f32x4{0, 0, 0, 0};
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(kr + 8 * g);
+            if (DH == 16) {
+                acc = mfma_a(a0, b0, acc);
+                acc = mfma_a(a0, b1, acc);
+            } else {
+                const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(kr + DH + 8 * g);
+                acc = mfma_a(a0, b0, acc);
+                acc = mfma_a(a1, b1, acc);
+                acc = mfma_a(a0, b2, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s[sub * 4 + r] = acc[r];
+        }
+        // keys beyond the query (or the sequence) only in the last blocks
+        if (j0 + 31 > t * 16 || j0 + 31 >= N) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int key = j0 + (k >> 2) * 16 + 4 * g + (k & 3);
+                if (key > iq || key >= N) s[k] = -__builtin_inff();
+            }
+        }
+        float mb = s[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) mb = fmaxf(mb, s[k]);
+        mb = fmaxf(mb, __shfl_xor(mb, 16, 64));
+        mb = fmaxf(mb, __shfl_xor(mb, 32, 64));
+        const float mn = fmaxf(mrow, mb);
+        const float alpha = exp2f(mrow - mn);
+        float p[8], ps = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            p[k] = exp2f(s[k] - mn);
+            ps += p[k];
+        }
+        ps += __shfl_xor(ps, 16, 64);
+        ps += __shfl_xor(ps, 32, 64);
+        lrow = lrow * alpha + ps;
+        mrow = mn;
+        bf16x8 ph, pl;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            ph[k] = (__bf16)p[k];
+            pl[k] = (__bf16)(p[k] - (float)ph[k]);
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int vc = u * 16 + c16;
+            const __bf16* vh_row = T.Vt + vc * T.ldv + j0 + 4 * g;
+            const __bf16* vl_row = T.Vt + (DH + vc) * T.ldv + j0 + 4 * g;
+            const bf16x4 h0 = *reinterpret_cast<const bf16x4*>(vh_row);
+            const bf16x4 h1 = *reinterpret_cast<const bf16x4*>(vh_row + 16);
+            const bf16x4 l0 = *reinterpret_cast<const bf16x4*>(vl_row);
+            const bf16x4 l1 = *reinterpret_cast<const bf16x4*>(vl_row + 16);
+            const bf16x8 vh = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+            const bf16x8 vl = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[u][r] *= alpha;
+            o[u] = mfma_a(vh, ph, o[u]);
+            o[u] = mfma_a(vl, ph, o[u]);
+            o[u] = mfma_a(vh, pl, o[u]);
+        }
+    }
+    if (iq >= lo && iq < N) {
+        float* dst = orow(iq);
+        const float inv = 1.0f / lrow;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            float4 v;
+            v.x = o[u][0] * inv;
+            v.y = o[u][1] * inv;
+            v.z = o[u][2] * inv;
+            v.w = o[u][3] * inv;
+            *reinterpret_cast<float4*>(dst + u * 16 + 4 * g) = v;
+        }
+    }
+}
+
+// Full sequences (the samples themselves, or materialised neighbours).
+template <int DH>
+__global__ void __launch_bounds__(kAT) k_attn_seq_mfma(ModelDims m,
+                                                      const int32_t* n_dev,
+                                                      int64_t n_seq,
+                                                      BlockIO<PrecBF16> io,
+                                                      int64_t* ctr) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int N = m.N, d = m.d;
+    const Tiles<DH> T = carve_tiles<DH>(smem_raw, N);
+    const float qs = kLog2e / sqrtf((float)DH);
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_seq;
+    const int64_t units = n * m.nh;
+    const int wave = threadIdx.x >> 6;
+    const int NTQ = (N + 15) / 16;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t s = u / m.nh;
+        const int h = (int)(u - s * m.nh);
+        const int64_t sb = s * N * d + h * DH;
+        __syncthreads();
+        load_all<DH>(T, N, io.q, io.k, io.v, sb, d, qs);
+        __syncthreads();
+        for (int t = NTQ - 1 - wave; t >= 0; t -= 4)
+            attn_tile<DH>(T, N, t, 0,
+                          [&](int i) { return io.a + sb + (int64_t)i * d; });
+    }
+    if (ctr && blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
+                  (unsigned long long)(n * N));
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_PAIRS),
+                  (unsigned long long)(n * ((int64_t)N * (N + 1) / 2) * m.nh));
+    }
+}
+
+// Overlay form: one workgroup per (sample, head) walks the sample's
+// neighbours.  Between two neighbours only rows in either changed set are
+// rewritten, as (row, element) pairs spread over the workgroup.
+template <int DH>
+__global__ void __launch_bounds__(kAT) k_attn_dedup_mfma(ModelDims m,
+                                                        DedupIO<PrecBF16> dd,
+                                                        int64_t* ctr) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int N = m.N, d = m.d, W = dd.mask_words;
+    const Tiles<DH> T = carve_tiles<DH>(smem_raw, N);
+    const float qs = kLog2e / sqrtf((float)DH);
+    const int64_t units = dd.n_samples * m.nh;
+    const int wave = threadIdx.x >> 6;
+    const int NTQ = (N + 15) / 16;
+    int64_t my_rows = 0, my_pairs = 0;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t sg = u / m.nh;
+        const int h = (int)(u - sg * m.nh);
+        const int64_t sb = sg * N * d + h * DH;
+        __syncthreads();
+        load_all<DH>(T, N, dd.bq, dd.bk, dd.bv, sb, d, qs);
+        const int k0 = dd.nb_off[sg], k1 = dd.nb_off[sg + 1];
+        for (int k = k0; k <= k1; ++k) {
+            __syncthreads();
+            // the previous neighbour's rows go back to the sample's values
+            // (unless this neighbour changes them too) ...
+            if (k > k0) {
+                const NbDesc P = dd.desc[k - 1];
+                const int cp = dd.ccnt[k - 1];
+                const uint64_t* cur = k < k1 ? dd.mask + (int64_t)k * W : nullptr;
+                for (int e = threadIdx.x; e < cp * DH; e += kAT) {
+                    const int j = dd.crow[P.ov + e / DH], c = e % DH;
+                    if (cur && mbit(cur, j)) continue;
+                    const int64_t o = sb + (int64_t)j * d + c;
+                    T.put(j, c, dd.bk[o], dd.bq[o], qs, dd.bv[o]);
+                }
+            }
+            if (k == k1) break;
+            // ... and this neighbour's changed rows take its overlay values
+            const NbDesc D = dd.desc[k];
+            const int pmin = D.p1 + 1;
+            const int cc = dd.ccnt[k];
+            const int64_t ob0 = (D.ov - pmin) * (int64_t)d + h * DH;
+            for (int e = threadIdx.x; e < cc * DH; e += kAT) {
+                const int j = dd.crow[D.ov + e / DH], c = e % DH;
+                const int64_t o = ob0 + (int64_t)j * d + c;
+                T.put(j, c, dd.ok[o], dd.oq[o], qs, dd.ov[o]);
+            }
+            __syncthreads();
+            for (int t = NTQ - 1 - wave; t >= pmin / 16; t -= 4)
+                attn_tile<DH>(T, N, t, pmin,
+                              [&](int i) { return dd.oa + ob0 + (int64_t)i * d; });
+            if (h == 0 && threadIdx.x == 0) {
+                my_rows += N - pmin;
+                my_pairs += ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2;
+            }
+        }
+    }
+    if (ctr && threadIdx.x == 0 && my_rows) {
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
+                  (unsigned long long)my_rows);
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_PAIRS),
+                  (unsigned long long)(my_pairs * m.nh));
+    }
+}
+
+bool attn_mfma_ok(const ModelDims& m) { return m.dh == 16 || m.dh == 32; }
+
+static size_t attn_lds(const ModelDims& m) {
+    const int Np = (m.N + 31) & ~31;
+    return sizeof(__bf16) *
+           ((size_t)2 * Np * 2 * m.dh + (size_t)2 * m.dh * (Np + 8));
+}
+
+static unsigned agrid(int64_t units) {
+    if (units <= 0) return 1;
+    return (unsigned)(units < kAGridCap ? units : kAGridCap);
+}
+
+template <typename F>
+static void big_lds(F f, size_t sm) {
+    if (sm > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)f,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sm);
+}
+
+hipError_t launch_attn_seq_mfma(const ModelDims& m, const int32_t* n_dev,
+                                int64_t n_seq, const BlockIO<PrecBF16>& io,
+                                int64_t* ctr, hipStream_t st) {
+    const size_t sm = attn_lds(m);
+    const unsigned g = agrid(n_seq * m.nh);
+    if (m.dh == 16) {
+        big_lds(k_attn_seq_mfma<16>, sm);
+        hipLaunchKernelGGL(k_attn_seq_mfma<16>, dim3(g), dim3(kAT), sm, st, m,
+                           n_dev, n_seq, io, ctr);
+    } else if (m.dh == 32) {
+        big_lds(k_attn_seq_mfma<32>, sm);
+        hipLaunchKernelGGL(k_attn_seq_mfma<32>, dim3(g), dim3(kAT), sm, st, m,
+                           n_dev, n_seq, io, ctr);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_attn_dedup_mfma(const ModelDims& m,
+                                  const DedupIO<PrecBF16>& d, int64_t* ctr,
+                                  hipStream_t st) {
+    const size_t sm = attn_lds(m);
+    const unsigned g = agrid(d.n_samples * m.nh);
+    if (m.dh == 16) {
+        big_lds(k_attn_dedup_mfma<16>, sm);
+        hipLaunchKernelGGL(k_attn_dedup_mfma<16>, dim3(g), dim3(kAT), sm, st,
+                           m, d, ctr);
+    } else if (m.dh == 32) {
+        big_lds(k_attn_dedup_mfma<32>, sm);
+        hipLaunchKernelGGL(k_attn_dedup_mfma<32>, dim3(g), dim3(kAT), sm, st,
+                           m, d, ctr);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vq

@@ -754,12 +754,18 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
         const int pmin = D.p1 + 1;
         for (int i = lane; i < N - pmin; i += 64) dd.slot_nb[D.ov + i] = (int32_t)nb;
         uint64_t* mk = dd.mask + nb * W;
-        for (int wd = lane; wd < W; wd += 64) mk[wd] = 0;
         const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
         const int rowsC[2] = {D.p1 + 1, D.p2 + 1};
         // spin moved into p1 is s[p2] and vice versa
         const int tokC[2] = {sp[D.p2] < 0 ? 1 : 0, sp[D.p1] < 0 ? 1 : 0};
         const int nC = rowsC[1] < N ? 2 : 1;
+        // every mask word written once, never read back within the kernel
+        for (int wd = lane; wd < W; wd += 64) {
+            uint64_t v = 0;
+            for (int c = 0; c < nC; ++c)
+                if ((rowsC[c] >> 6) == wd) v |= 1ull << (rowsC[c] & 63);
+            mk[wd] = v;
+        }
         int64_t pos = 0;
         if (lane == 0) pos = atomicAdd(dd.list_n, nC);
         pos = __shfl(pos, 0, 64);
@@ -768,12 +774,12 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
             const int64_t slot = D.ov + (i - pmin);
             for (int k = lane; k < d; k += 64)
                 dd.ox[slot * d + k] = hw.tok[tokC[c] * d + k] + hw.pos[(int64_t)i * d + k];
-            if (lane == 0) dd.list[pos + c] = slot;
+            if (lane == 0) {
+                dd.list[pos + c] = slot;
+                dd.crow[D.ov + c] = (int16_t)i;
+            }
         }
-        __syncthreads();
-        if (lane == 0) {
-            for (int c = 0; c < nC; ++c) mk[rowsC[c] >> 6] |= 1ull << (rowsC[c] & 63);
-        }
+        if (lane == 0) dd.ccnt[nb] = nC;
     }
 }
 
@@ -856,6 +862,10 @@ hipError_t launch_certify(const ModelDims& m, const DedupIO<P>& d,
 // all rows of C_l are listed for the MLP stage (and the next QKV stage).
 template <class P>
 __global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
+    // The neighbour's mask words live in LDS while they change: global
+    // memory is read once at the start and written once at the end, so no
+    // lane ever reads back a word another lane stored in this kernel.
+    __shared__ uint64_t smk[VQ_MAX_MASK_WORDS];
     const int64_t n = (int64_t)*dd.n_nb;
     const int lane = threadIdx.x;
     const int N = m.N, d = m.d, W = dd.mask_words;
@@ -863,18 +873,17 @@ __global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
         const NbDesc D = dd.desc[nb];
         const int pmin = D.p1 + 1;
         uint64_t* mk = dd.mask + nb * W;
-        int total = 0;
+        __syncthreads();
+        for (int wd = lane; wd < W; wd += 64) smk[wd] = mk[wd];
+        __syncthreads();
         for (int i0 = pmin; i0 < N; i0 += 64) {
             const int i = i0 + lane;
-            bool inC = false, joins = false;
-            if (i < N) {
+            bool joins = false;
+            if (i < N && !mask_bit(smk, i)) {
                 const int64_t slot = D.ov + (i - pmin);
                 const int64_t brow = (int64_t)D.sigma * N + i;
-                inC = mask_bit(mk, i);
-                if (!inC) {
-                    for (int hq = 0; hq < m.H; ++hq)
-                        joins |= dd.ocode[slot * m.H + hq] != dd.bcode[brow * m.H + hq];
-                }
+                for (int hq = 0; hq < m.H; ++hq)
+                    joins |= dd.ocode[slot * m.H + hq] != dd.bcode[brow * m.H + hq];
             }
             const uint64_t jm = __ballot(joins);
             // copy the sample's block input into the overlay rows that join
@@ -887,27 +896,37 @@ __global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
                 const int64_t brow = (int64_t)D.sigma * N + ii;
                 for (int k = lane; k < d; k += 64) dd.ox[slot * d + k] = dd.bx[brow * d + k];
             }
-            total += __popcll(__ballot(inC || joins));
-            // update the mask words covered by this group of 64 rows
+            // rows of this group occupy word i0/64 and possibly the next one
+            __syncthreads();
             if (lane == 0 && jm) {
                 const int w0 = i0 >> 6, sh = i0 & 63;
-                mk[w0] |= jm << sh;
-                if (sh && w0 + 1 < W) mk[w0 + 1] |= jm >> (64 - sh);
+                smk[w0] |= jm << sh;
+                if (sh && w0 + 1 < W) smk[w0 + 1] |= jm >> (64 - sh);
             }
             __syncthreads();
         }
         int64_t pos = 0;
+        int total = 0;
+        for (int i0 = pmin; i0 < N; i0 += 64) {
+            const int i = i0 + lane;
+            total += __popcll(__ballot(i < N && mask_bit(smk, i)));
+        }
         if (lane == 0) pos = atomicAdd(dd.list_n, total);
         pos = __shfl(pos, 0, 64);
         int k = 0;
         for (int i0 = pmin; i0 < N; i0 += 64) {
             const int i = i0 + lane;
-            const bool inC = i < N && mask_bit(mk, i);
+            const bool inC = i < N && mask_bit(smk, i);
             const uint64_t cm = __ballot(inC);
             const uint64_t below = lane == 0 ? 0ull : (cm & (~0ull >> (64 - lane)));
-            if (inC) dd.list[pos + k + __popcll(below)] = D.ov + (i - pmin);
+            if (inC) {
+                dd.list[pos + k + __popcll(below)] = D.ov + (i - pmin);
+                dd.crow[D.ov + k + __popcll(below)] = (int16_t)i;
+            }
             k += __popcll(cm);
         }
+        if (lane == 0) dd.ccnt[nb] = k;
+        for (int wd = lane; wd < W; wd += 64) mk[wd] = smk[wd];
     }
 }
 

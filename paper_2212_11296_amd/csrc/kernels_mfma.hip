@@ -133,229 +133,351 @@ __device__ inline bf16x8 lds_frag(const __bf16* base, int ld, int mb, int kb,
         base + (mb * 16 + (lane & 15)) * ld + kb * 32 + 8 * (lane >> 4));
 }
 
+// ------------------------------------------------- per-wave A fragments
+// A fragments (hi/lo) of 16*MB rows x D = 32*KB columns held by one wave:
+// lane l holds row i*16 + l%16, columns kb*32 + 8*(l/16) + j.  The row's
+// LayerNorm statistics combine the four lanes sharing the row.
+template <int KB, int MB>
+__device__ inline void ln_frags(const float* const (&xr)[MB], const float* g,
+                                const float* b, bf16x8 (&ah)[MB][KB],
+                                bf16x8 (&al)[MB][KB]) {
+    constexpr int D = KB * 32;
+    const int lane = threadIdx.x & 63, gq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        float v[KB][8];
+        float s = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            if (xr[i]) {
+                const float4* p = reinterpret_cast<const float4*>(xr[i] + kb * 32 + 8 * gq);
+                const float4 v0 = p[0], v1 = p[1];
+                v[kb][0] = v0.x; v[kb][1] = v0.y; v[kb][2] = v0.z; v[kb][3] = v0.w;
+                v[kb][4] = v1.x; v[kb][5] = v1.y; v[kb][6] = v1.z; v[kb][7] = v1.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[kb][j] = 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += v[kb][j];
+        }
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        const float mean = s / (float)D;
+        float q = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float t = v[kb][j] - mean;
+                q += t * t;
+            }
+        q += __shfl_xor(q, 16, 64);
+        q += __shfl_xor(q, 32, 64);
+        const float rstd = 1.0f / sqrtf(q / (float)D + 1e-5f);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = kb * 32 + 8 * gq + j;
+                const float y = (v[kb][j] - mean) * rstd * g[k] + b[k];
+                __bf16 h, l;
+                split1(y, h, l);
+                ah[i][kb][j] = h;
+                al[i][kb][j] = l;
+            }
+    }
+}
+
+// Same as ln_frags for row values already in registers (A positions).
+template <int KB, int MB>
+__device__ inline void ln_frags_v(const float (&v)[MB][KB][8], const float* g,
+                                  const float* b, bf16x8 (&ah)[MB][KB],
+                                  bf16x8 (&al)[MB][KB]) {
+    constexpr int D = KB * 32;
+    const int gq = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        float s = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += v[i][kb][j];
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        const float mean = s / (float)D;
+        float q = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float t = v[i][kb][j] - mean;
+                q += t * t;
+            }
+        q += __shfl_xor(q, 16, 64);
+        q += __shfl_xor(q, 32, 64);
+        const float rstd = 1.0f / sqrtf(q / (float)D + 1e-5f);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = kb * 32 + 8 * gq + j;
+                const float y = (v[i][kb][j] - mean) * rstd * g[k] + b[k];
+                __bf16 h, l;
+                split1(y, h, l);
+                ah[i][kb][j] = h;
+                al[i][kb][j] = l;
+            }
+    }
+}
+
+// Cooperative copy of `cnt` fragment lanes (16 B each) into an LDS stage.
+template <int PER>
+__device__ inline void stage_fetch(bf16x8 (&pre)[PER], const bf16x8* src,
+                                   int64_t cnt) {
+    const bf16x8 z = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t e = threadIdx.x + k * kMT;
+        pre[k] = e < cnt ? src[e] : z;
+    }
+}
+template <int PER>
+__device__ inline void stage_store(const bf16x8 (&pre)[PER], bf16x8* dst) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) dst[threadIdx.x + k * kMT] = pre[k];
+}
+
 // --------------------------------------------------------------- LN1 + QKV
-// Workgroup tile: 64 rows.  LN1 output is split into hi/lo bf16 in LDS; each
-// wave computes a contiguous range of the 3d/16 output column blocks in
-// groups of four, reusing every A fragment across the group.
-template <int KB>
+// Each wave: 16*MB rows (LN1 output as register A fragments).  The 3d/16
+// output column blocks stream through a double-buffered LDS stage, NBC
+// blocks per chunk, shared by the four waves.
+template <int KB, int MB>
 __global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
                                                  RowSet rows, BlockIO<PrecBF16> io,
                                                  const bf16x8* __restrict__ Bp) {
-    constexpr int D = KB * 32, LD = D + 8, TM = 64, MB = 4;
-    __shared__ __align__(16) __bf16 Ahi[TM * LD];
-    __shared__ __align__(16) __bf16 Alo[TM * LD];
-    __shared__ int64_t slot[TM];
+    constexpr int D = KB * 32, WR = MB * 16, NBC = 4;
+    constexpr int CHUNK = NBC * KB * 64, PER = CHUNK / kMT;
+    __shared__ bf16x8 stage[2][CHUNK];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gq = lane >> 4, c16 = lane & 15;
     const int64_t n = rs_n(rows);
-    const int64_t ntiles = (n + TM - 1) / TM;
-    const int NBT = 3 * D / 16;
-    const int nbs = wave * NBT / 4, nbe = (wave + 1) * NBT / 4;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        for (int rr = wave * 16; rr < wave * 16 + 16; ++rr) {
-            const int64_t r = t * TM + rr;
-            if (r < n) {
-                const int64_t s = rs_slot(rows, r);
-                if (lane == 0) slot[rr] = s;
-                const float* x = io.x + s * D;
-                float mean, rstd;
-                row_ln(x, D, mean, rstd);
-                for (int k = lane; k < D; k += 64) {
-                    const float y = (x[k] - mean) * rstd * w.ln1_g[k] + w.ln1_b[k];
-                    split1(y, Ahi[rr * LD + k], Alo[rr * LD + k]);
-                }
-            } else {
-                if (lane == 0) slot[rr] = -1;
-                for (int k = lane; k < D; k += 64) {
-                    Ahi[rr * LD + k] = (__bf16)0.0f;
-                    Alo[rr * LD + k] = (__bf16)0.0f;
-                }
-            }
+    const int64_t ntile = (n + 4 * WR - 1) / (4 * WR);
+    constexpr int NBT = 3 * D / 16;
+    constexpr int nchunk = NBT / NBC;
+    for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+        int64_t slot[MB];
+        const float* xr[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const int64_t r = t * 4 * WR + wave * WR + i * 16 + c16;
+            slot[i] = r < n ? rs_slot(rows, r) : -1;
+            xr[i] = slot[i] >= 0 ? io.x + slot[i] * D : nullptr;
+        }
+        bf16x8 ah[MB][KB], al[MB][KB];
+        ln_frags<KB, MB>(xr, w.ln1_g, w.ln1_b, ah, al);
+        int64_t oslot[MB][4];
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) oslot[i][r] = __shfl(slot[i], 4 * gq + r, 64);
+        __syncthreads();
+        {
+            bf16x8 pre[PER];
+            stage_fetch<PER>(pre, Bp, CHUNK);
+            stage_store<PER>(pre, stage[0]);
         }
         __syncthreads();
-        for (int nb0 = nbs; nb0 < nbe; nb0 += 4) {
-            f32x4 acc[MB][4];
+        for (int c = 0; c < nchunk; ++c) {
+            bf16x8 pre[PER];
+            if (c + 1 < nchunk) stage_fetch<PER>(pre, Bp + (int64_t)(c + 1) * CHUNK, CHUNK);
+            const bf16x8* sb = stage[c & 1];
 #pragma unroll
-            for (int i = 0; i < MB; ++i)
+            for (int nbl = 0; nbl < NBC; ++nbl) {
+                f32x4 acc[MB];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+                for (int i = 0; i < MB; ++i) acc[i] = f32x4{0, 0, 0, 0};
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                bf16x8 ah[MB], al[MB];
+                for (int kb = 0; kb < KB; ++kb) {
+                    const bf16x8 b = sb[(nbl * KB + kb) * 64 + lane];
 #pragma unroll
-                for (int i = 0; i < MB; ++i) {
-                    ah[i] = lds_frag(Ahi, LD, i, kb, lane);
-                    al[i] = lds_frag(Alo, LD, i, kb, lane);
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (nb0 + j < nbe) {
-                        const bf16x8 b = Bp[((int64_t)(nb0 + j) * KB + kb) * 64 + lane];
-#pragma unroll
-                        for (int i = 0; i < MB; ++i) {
-                            acc[i][j] = mfma(ah[i], b, acc[i][j]);
-                            acc[i][j] = mfma(al[i], b, acc[i][j]);
-                        }
+                    for (int i = 0; i < MB; ++i) {
+                        acc[i] = mfma(ah[i][kb], b, acc[i]);
+                        acc[i] = mfma(al[i][kb], b, acc[i]);
                     }
                 }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (nb0 + j >= nbe) continue;
-                const int col = (nb0 + j) * 16 + (lane & 15);
+                const int col = (c * NBC + nbl) * 16 + c16;
                 float* dst = col < D ? io.q : (col < 2 * D ? io.k : io.v);
                 const int cc = col < D ? col : (col < 2 * D ? col - D : col - 2 * D);
                 const float bias = w.b_qkv[col];
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = i * 16 + 4 * (lane >> 4) + r;
-                        const int64_t s = slot[row];
-                        if (s >= 0) dst[s * D + cc] = acc[i][j][r] + bias;
-                    }
+                    for (int r = 0; r < 4; ++r)
+                        if (oslot[i][r] >= 0) dst[oslot[i][r] * D + cc] = acc[i][r] + bias;
             }
+            if (c + 1 < nchunk) stage_store<PER>(pre, stage[(c + 1) & 1]);
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
 // ------------------------------------------ out-projection + residual + MLP
-// x' = x_in + b_o + sum_h table[h][code_h]; hidden = GELU(LN2(x') W1 + b1)
-// kept in LDS as hi/lo bf16; x = x' + hidden W2 + b2.
+// Each wave: 16*MB rows.  x' = x_in + b_o + sum_h table[h][code_h] is formed
+// in the A-fragment layout, written to the output rows, and LN2(x') kept as
+// register A fragments.  The hidden layer is produced 64 columns at a time:
+// GELU(A W1[:, chunk] + b1) is transposed through a per-wave LDS scratch into
+// A fragments and multiplied into the output accumulators with W2[chunk, :].
+// The W1/W2 fragments of a chunk are staged in LDS for the four waves.
 template <int KB1, int MB>
-__global__ void __launch_bounds__(kMT) k_mlp_mfma(ModelDims m, LayerW<float> w,
+__global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_mfma(ModelDims m, LayerW<float> w,
                                                  RowSet rows, BlockIO<PrecBF16> io,
                                                  const bf16x8* __restrict__ B1,
                                                  const bf16x8* __restrict__ B2) {
     constexpr int D = KB1 * 32, F = 4 * D, KB2 = F / 32;
-    constexpr int TM = MB * 16, LDA = D + 8, LDH = F + 8;
-    __shared__ float xp[TM * D];
-    __shared__ __align__(16) __bf16 Ahi[TM * LDA];
-    __shared__ __align__(16) __bf16 Alo[TM * LDA];
-    __shared__ __align__(16) __bf16 Hhi[TM * LDH];
-    __shared__ __align__(16) __bf16 Hlo[TM * LDH];
-    __shared__ int64_t slot[TM];
+    constexpr int WR = MB * 16, HC = 64, NB1C = HC / 16, KB2C = HC / 32;
+    constexpr int NBO = D / 16;                    // output column blocks
+    constexpr int C1 = NB1C * KB1 * 64;            // W1 fragment lanes per chunk
+    constexpr int C2 = KB2C * NBO * 64;            // W2 fragment lanes per chunk
+    constexpr int PER1 = C1 / kMT, PER2 = C2 / kMT;
+    constexpr int LDH = HC + 8;
+    __shared__ bf16x8 s1[C1];
+    __shared__ bf16x8 s2[C2];
+    __shared__ __align__(16) __bf16 hs[4][2][WR * LDH];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gq = lane >> 4, c16 = lane & 15;
     const int64_t n = rs_n(rows);
-    const int64_t ntiles = (n + TM - 1) / TM;
-    const int NB1 = F / 16, NB2 = D / 16;
-    const int n1s = wave * NB1 / 4, n1e = (wave + 1) * NB1 / 4;
-    const int n2s = wave * NB2 / 4, n2e = (wave + 1) * NB2 / 4;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        for (int rr = wave; rr < TM; rr += 4) {
-            const int64_t r = t * TM + rr;
-            if (r < n) {
-                const int64_t s = rs_slot(rows, r);
-                if (lane == 0) slot[rr] = s;
+    const int64_t ntile = (n + 4 * WR - 1) / (4 * WR);
+    for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+        int64_t slot[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const int64_t r = t * 4 * WR + wave * WR + i * 16 + c16;
+            slot[i] = r < n ? rs_slot(rows, r) : -1;
+        }
+        // x' = x_in + (b_o + sum_h table) in A-fragment positions, kept in
+        // registers (never written and re-read through global memory)
+        float xv[MB][KB1][8];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const float* x = slot[i] >= 0 ? io.x_in + slot[i] * D : nullptr;
+            const int32_t* cd = slot[i] >= 0 ? io.codes + slot[i] * m.H : nullptr;
+#pragma unroll
+            for (int kb = 0; kb < KB1; ++kb)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = kb * 32 + 8 * gq + j;
+                    float val = 0.0f;
+                    if (x) {
+                        float z = w.b_o[k];
+                        for (int hq = 0; hq < m.H; ++hq)
+                            z += w.table[((int64_t)hq * m.Q + cd[hq]) * D + k];
+                        val = x[k] + z;
+                    }
+                    xv[i][kb][j] = val;
+                }
+        }
+        bf16x8 ah[MB][KB1], al[MB][KB1];
+        ln_frags_v<KB1, MB>(xv, w.ln2_g, w.ln2_b, ah, al);
+        f32x4 out[MB][NBO];
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int nb = 0; nb < NBO; ++nb) out[i][nb] = f32x4{0, 0, 0, 0};
+        __bf16* hh = hs[wave][0];
+        __bf16* hl = hs[wave][1];
+        for (int hc = 0; hc < F / HC; ++hc) {
+            __syncthreads();                       // stages free
+            {
+                bf16x8 p1[PER1];
+                stage_fetch<PER1>(p1, B1 + (int64_t)hc * C1, C1);
+                stage_store<PER1>(p1, s1);
+                // W2 rows of the chunk: k-blocks hc*KB2C .. +KB2C of every
+                // output block nb; packed index (nb*KB2 + kb)*64 + lane
+#pragma unroll
+                for (int k = 0; k < PER2; ++k) {
+                    const int e = threadIdx.x + k * kMT;
+                    const int ln = e & 63, f = e >> 6;
+                    const int kbl = f % KB2C, nb = f / KB2C;
+                    s2[e] = B2[((int64_t)nb * KB2 + hc * KB2C + kbl) * 64 + ln];
+                }
+            }
+            __syncthreads();
+            // hidden chunk = GELU(A W1[:, chunk] + b1)
+            f32x4 hacc[MB][NB1C];
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int nb = 0; nb < NB1C; ++nb) hacc[i][nb] = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int nb = 0; nb < NB1C; ++nb)
+#pragma unroll
+                for (int kb = 0; kb < KB1; ++kb) {
+                    const bf16x8 b = s1[(nb * KB1 + kb) * 64 + lane];
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) {
+                        hacc[i][nb] = mfma(ah[i][kb], b, hacc[i][nb]);
+                        hacc[i][nb] = mfma(al[i][kb], b, hacc[i][nb]);
+                    }
+                }
+            // D layout -> LDS (row-major [WR][HC]) -> A layout
+#pragma unroll
+            for (int nb = 0; nb < NB1C; ++nb) {
+                const int col = nb * 16 + c16;
+                const float bias = w.b1[hc * HC + col];
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = i * 16 + 4 * gq + r;
+                        const float h = gelu_exact(hacc[i][nb][r] + bias);
+                        split1(h, hh[row * LDH + col], hl[row * LDH + col]);
+                    }
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int kb = 0; kb < KB2C; ++kb) {
+                bf16x8 xh[MB], xl[MB];
+#pragma unroll
+                for (int i = 0; i < MB; ++i) {
+                    xh[i] = lds_frag(hh, LDH, i, kb, lane);
+                    xl[i] = lds_frag(hl, LDH, i, kb, lane);
+                }
+#pragma unroll
+                for (int nb = 0; nb < NBO; ++nb) {
+                    const bf16x8 b = s2[(nb * KB2C + kb) * 64 + lane];
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) {
+                        out[i][nb] = mfma(xh[i], b, out[i][nb]);
+                        out[i][nb] = mfma(xl[i], b, out[i][nb]);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // x = x' + hidden W2 + b2, with x' recomputed for this lane's
+        // elements in the prologue's addition order: every element is read
+        // and written by one lane only, also when x_in and x coincide
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t s = __shfl(slot[i], 4 * gq + r, 64);
+                if (s < 0) continue;
                 const float* x = io.x_in + s * D;
                 const int32_t* cd = io.codes + s * m.H;
-                for (int k = lane; k < D; k += 64) {
-                    float z = w.b_o[k];
+                float* xo = io.x + s * D;
+#pragma unroll
+                for (int nb = 0; nb < NBO; ++nb) {
+                    const int col = nb * 16 + c16;
+                    float z = w.b_o[col];
                     for (int hq = 0; hq < m.H; ++hq)
-                        z += w.table[((int64_t)hq * m.Q + cd[hq]) * D + k];
-                    xp[rr * D + k] = x[k] + z;
-                }
-                float mean, rstd;
-                row_ln(xp + rr * D, D, mean, rstd);
-                for (int k = lane; k < D; k += 64) {
-                    const float y = (xp[rr * D + k] - mean) * rstd * w.ln2_g[k] + w.ln2_b[k];
-                    split1(y, Ahi[rr * LDA + k], Alo[rr * LDA + k]);
-                }
-            } else {
-                if (lane == 0) slot[rr] = -1;
-                for (int k = lane; k < D; k += 64) {
-                    xp[rr * D + k] = 0.0f;
-                    Ahi[rr * LDA + k] = (__bf16)0.0f;
-                    Alo[rr * LDA + k] = (__bf16)0.0f;
+                        z += w.table[((int64_t)hq * m.Q + cd[hq]) * D + col];
+                    const float xp = x[col] + z;
+                    xo[col] = xp + (out[i][nb][r] + w.b2[col]);
                 }
             }
-        }
-        __syncthreads();
-        // hidden = GELU(A W1 + b1)
-        for (int nb0 = n1s; nb0 < n1e; nb0 += 4) {
-            f32x4 acc[MB][4];
-#pragma unroll
-            for (int i = 0; i < MB; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
-#pragma unroll
-            for (int kb = 0; kb < KB1; ++kb) {
-                bf16x8 ah[MB], al[MB];
-#pragma unroll
-                for (int i = 0; i < MB; ++i) {
-                    ah[i] = lds_frag(Ahi, LDA, i, kb, lane);
-                    al[i] = lds_frag(Alo, LDA, i, kb, lane);
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (nb0 + j < n1e) {
-                        const bf16x8 b = B1[((int64_t)(nb0 + j) * KB1 + kb) * 64 + lane];
-#pragma unroll
-                        for (int i = 0; i < MB; ++i) {
-                            acc[i][j] = mfma(ah[i], b, acc[i][j]);
-                            acc[i][j] = mfma(al[i], b, acc[i][j]);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (nb0 + j >= n1e) continue;
-                const int col = (nb0 + j) * 16 + (lane & 15);
-                const float bias = w.b1[col];
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = i * 16 + 4 * (lane >> 4) + r;
-                        const float h = gelu_exact(acc[i][j][r] + bias);
-                        split1(h, Hhi[row * LDH + col], Hlo[row * LDH + col]);
-                    }
-            }
-        }
-        __syncthreads();
-        // x = x' + hidden W2 + b2
-        for (int nb0 = n2s; nb0 < n2e; nb0 += 4) {
-            f32x4 acc[MB][4];
-#pragma unroll
-            for (int i = 0; i < MB; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
-            for (int kb = 0; kb < KB2; ++kb) {
-                bf16x8 ah[MB], al[MB];
-#pragma unroll
-                for (int i = 0; i < MB; ++i) {
-                    ah[i] = lds_frag(Hhi, LDH, i, kb, lane);
-                    al[i] = lds_frag(Hlo, LDH, i, kb, lane);
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (nb0 + j < n2e) {
-                        const bf16x8 b = B2[((int64_t)(nb0 + j) * KB2 + kb) * 64 + lane];
-#pragma unroll
-                        for (int i = 0; i < MB; ++i) {
-                            acc[i][j] = mfma(ah[i], b, acc[i][j]);
-                            acc[i][j] = mfma(al[i], b, acc[i][j]);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (nb0 + j >= n2e) continue;
-                const int col = (nb0 + j) * 16 + (lane & 15);
-                const float bias = w.b2[col];
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = i * 16 + 4 * (lane >> 4) + r;
-                        const int64_t s = slot[row];
-                        if (s >= 0) io.x[s * D + col] = xp[row * D + col] + (acc[i][j][r] + bias);
-                    }
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -390,24 +512,31 @@ __device__ inline float score_err_split(int n, float na, float wmax) {
            3.0517578e-5f * (na * wmax + na * na);
 }
 
-// One wave owns 16*MB rows kept in registers as hi/lo A fragments and
-// streams all codes of the quantizer head through the matrix core.
+// Each wave owns 16*MB rows kept in registers as hi/lo A fragments; the
+// four waves of a workgroup stream the codes of the quantizer head through
+// a double-buffered LDS stage (CBK code blocks of 16 codes per chunk), the
+// next chunk's global loads in flight while the current one is searched.
 template <int KBS, int MB>
 __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
                                                 RowSet rows, BlockIO<PrecBF16> io,
                                                 const bf16x8* __restrict__ cbp) {
-    constexpr int DS = KBS * 32, WR = MB * 16;
+    constexpr int DS = KBS * 32, WR = MB * 16, CBK = 4;
+    constexpr int CHUNK = CBK * KBS * 64;       // fragment lanes per chunk
+    constexpr int PER = CHUNK / kMT;             // per thread
+    __shared__ bf16x8 stage[2][CHUNK];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t n = rs_n(rows);
-    const int64_t nw = (n + WR - 1) / WR;       // wave tiles
+    const int64_t ntile = (n + 4 * WR - 1) / (4 * WR);
     const int QB = m.Q / 16;
+    const int64_t cbtot = (int64_t)QB * KBS * 64;
+    const int nchunk = (QB + CBK - 1) / CBK;
     const float inf = __builtin_inff();
-    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < nw;
-         t += (int64_t)gridDim.x * 4) {
+    const bf16x8 zero8 = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
         int64_t myslot[MB];
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
-            const int64_t r = t * WR + i * 16 + (lane & 15);
+            const int64_t r = t * 4 * WR + wave * WR + i * 16 + (lane & 15);
             myslot[i] = r < n ? rs_slot(rows, r) : -1;
         }
         for (int hq = 0; hq < m.H; ++hq) {
@@ -447,36 +576,59 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
             for (int i = 0; i < MB; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) best[i][r] = T2{inf, 0x7fffffff, inf};
-            const bf16x8* cbh = cbp + (int64_t)hq * QB * KBS * 64;
+            const bf16x8* cbh = cbp + (int64_t)hq * cbtot;
             const float* cn = w.cnorm + (int64_t)hq * m.Q;
-            for (int cb = 0; cb < QB; ++cb) {
-                f32x4 acc[MB];
+            __syncthreads();                 // stage free from the last head
 #pragma unroll
-                for (int i = 0; i < MB; ++i) acc[i] = f32x4{0, 0, 0, 0};
+            for (int k = 0; k < PER; ++k) {
+                const int e = threadIdx.x + k * kMT;
+                stage[0][e] = e < cbtot ? cbh[e] : zero8;
+            }
+            __syncthreads();
+            for (int c = 0; c < nchunk; ++c) {
+                bf16x8 pre[PER];
+                const int64_t nb = (int64_t)(c + 1) * CHUNK;
 #pragma unroll
-                for (int kb = 0; kb < KBS; ++kb) {
-                    const bf16x8 b = cbh[((int64_t)cb * KBS + kb) * 64 + lane];
-#pragma unroll
-                    for (int i = 0; i < MB; ++i) {
-                        acc[i] = mfma(ah[i][kb], b, acc[i]);
-                        acc[i] = mfma(al[i][kb], b, acc[i]);
-                    }
+                for (int k = 0; k < PER; ++k) {
+                    const int64_t e = nb + threadIdx.x + k * kMT;
+                    pre[k] = (c + 1 < nchunk && e < cbtot) ? cbh[e] : zero8;
                 }
-                const int c = cb * 16 + (lane & 15);
-                const float cnv = cn[c];
+                const bf16x8* sb = stage[c & 1];
 #pragma unroll
-                for (int i = 0; i < MB; ++i)
+                for (int cbl = 0; cbl < CBK; ++cbl) {
+                    const int cb = c * CBK + cbl;
+                    if (cb >= QB) break;
+                    f32x4 acc[MB];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float sc = cnv - 2.0f * acc[i][r];
-                        if (sc < best[i][r].b) {
-                            best[i][r].s = best[i][r].b;
-                            best[i][r].b = sc;
-                            best[i][r].i = c;
-                        } else if (sc < best[i][r].s) {
-                            best[i][r].s = sc;
+                    for (int i = 0; i < MB; ++i) acc[i] = f32x4{0, 0, 0, 0};
+#pragma unroll
+                    for (int kb = 0; kb < KBS; ++kb) {
+                        const bf16x8 b = sb[(cbl * KBS + kb) * 64 + lane];
+#pragma unroll
+                        for (int i = 0; i < MB; ++i) {
+                            acc[i] = mfma(ah[i][kb], b, acc[i]);
+                            acc[i] = mfma(al[i][kb], b, acc[i]);
                         }
                     }
+                    const int code = cb * 16 + (lane & 15);
+                    const float cnv = cn[code];
+#pragma unroll
+                    for (int i = 0; i < MB; ++i)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float sc = cnv - 2.0f * acc[i][r];
+                            if (sc < best[i][r].b) {
+                                best[i][r].s = best[i][r].b;
+                                best[i][r].b = sc;
+                                best[i][r].i = code;
+                            } else if (sc < best[i][r].s) {
+                                best[i][r].s = sc;
+                            }
+                        }
+                }
+#pragma unroll
+                for (int k = 0; k < PER; ++k) stage[(c + 1) & 1][threadIdx.x + k * kMT] = pre[k];
+                __syncthreads();
             }
             // combine the 16 column lanes of each row group
 #pragma unroll
@@ -523,11 +675,10 @@ hipError_t launch_qkv_mfma(const ModelDims& m, const LayerW<float>& w,
                            RowSet rows, const BlockIO<PrecBF16>& io,
                            hipStream_t st) {
     const bf16x8* B = reinterpret_cast<const bf16x8*>(w.Wqkv_p);
-    const unsigned g = mgrid((rows.n_host + 63) / 64);
     switch (m.d / 32) {
-        case 2: hipLaunchKernelGGL((k_qkv_mfma<2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, B); break;
-        case 4: hipLaunchKernelGGL((k_qkv_mfma<4>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, B); break;
-        case 8: hipLaunchKernelGGL((k_qkv_mfma<8>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, B); break;
+        case 2: hipLaunchKernelGGL((k_qkv_mfma<2, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B); break;
+        case 4: hipLaunchKernelGGL((k_qkv_mfma<4, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B); break;
+        case 8: hipLaunchKernelGGL((k_qkv_mfma<8, 1>), dim3(mgrid((rows.n_host + 63) / 64)), dim3(kMT), 0, st, m, w, rows, io, B); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -539,9 +690,9 @@ hipError_t launch_mlp_mfma(const ModelDims& m, const LayerW<float>& w,
     const bf16x8* B1 = reinterpret_cast<const bf16x8*>(w.W1_p);
     const bf16x8* B2 = reinterpret_cast<const bf16x8*>(w.W2_p);
     switch (m.d / 32) {
-        case 2: hipLaunchKernelGGL((k_mlp_mfma<2, 4>), dim3(mgrid((rows.n_host + 63) / 64)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
-        case 4: hipLaunchKernelGGL((k_mlp_mfma<4, 2>), dim3(mgrid((rows.n_host + 31) / 32)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
-        case 8: hipLaunchKernelGGL((k_mlp_mfma<8, 1>), dim3(mgrid((rows.n_host + 15) / 16)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
+        case 2: hipLaunchKernelGGL((k_mlp_mfma<2, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
+        case 4: hipLaunchKernelGGL((k_mlp_mfma<4, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
+        case 8: hipLaunchKernelGGL((k_mlp_mfma<8, 1>), dim3(mgrid((rows.n_host + 63) / 64)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -552,14 +703,14 @@ hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
                           hipStream_t st) {
     const bf16x8* cb = reinterpret_cast<const bf16x8*>(w.cb_p);
     const int KBS = m.dseg / 32;
-    // waves of 64 rows (32 when the segment is 256 wide), 4 waves per group
-    const int WR = KBS == 8 ? 32 : 64;
+    // 32 rows per wave (16 when the segment is 256 wide), 4 waves per group
+    const int WR = KBS == 8 ? 16 : 32;
     const unsigned g = mgrid((rows.n_host + 4 * WR - 1) / (4 * WR));
     switch (KBS) {
-        case 1: hipLaunchKernelGGL((k_vq_mfma<1, 4>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
-        case 2: hipLaunchKernelGGL((k_vq_mfma<2, 4>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
-        case 4: hipLaunchKernelGGL((k_vq_mfma<4, 4>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
-        case 8: hipLaunchKernelGGL((k_vq_mfma<8, 2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
+        case 1: hipLaunchKernelGGL((k_vq_mfma<1, 2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
+        case 2: hipLaunchKernelGGL((k_vq_mfma<2, 2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
+        case 4: hipLaunchKernelGGL((k_vq_mfma<4, 2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
+        case 8: hipLaunchKernelGGL((k_vq_mfma<8, 1>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
