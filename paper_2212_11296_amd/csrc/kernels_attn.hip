@@ -14,7 +14,9 @@
 // 16, where it comes free), the terms laid end to end along the MFMA K
 // dimension, and V^T P^T = vh.ph + vl.ph + vh.pl, accumulated in FP32.
 // Softmax is online over 32-key blocks in base-2 exponentials, log2(e) and
-// 1/sqrt(d_head) folded into the query.
+// 1/sqrt(d_head) folded into the query; p = 2^(s - m) with the hardware
+// exponential (results below the normal range flush to zero, a relative
+// loss under 2^-126 of the row's largest term).
 //
 // One workgroup owns one (sequence, head): the sequence's K, Q (hi|lo rows)
 // and V (hi/lo, transposed) stay in LDS.  In the overlay form the workgroup
@@ -101,6 +103,37 @@ __device__ inline void load_all(const Tiles<DH>& T, int N, const float* Q,
     }
 }
 
+// Probabilities are formed against a per-query reference that is raised
+// lazily: only when a block's scores exceed it by more than kTau (base 2), so
+// every p stays below 2^kTau and most blocks need no rescaling at all.  The
+// reference enters the score MFMA as its accumulator input (the MFMA returns
+// s - m directly), and the normaliser sum(p) comes out of the matrix core
+// from an all-ones operand, so a block costs no cross-lane traffic unless it
+// raises a reference.  The rescaling decision is taken per query, from that
+// query's own scores, so a row's result depends on its own inputs only.
+constexpr float kTau = 8.0f;
+
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+// p as hi+lo bfloat16: hi is p truncated to its upper 16 bits, lo the exact
+// remainder rounded to bfloat16 (relative error of hi+lo at most 2^-16).
+__device__ inline void split_p(const float* p, bf16x8& ph, bf16x8& pl) {
+    uint32_t u[8];
+    float r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        u[k] = __float_as_uint(p[k]);
+        r[k] = p[k] - __uint_as_float(u[k] & 0xffff0000u);
+    }
+    u32x4 hv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        hv[i] = __builtin_amdgcn_perm(u[2 * i + 1], u[2 * i], 0x07060302u);
+    ph = __builtin_bit_cast(bf16x8, hv);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) pl[k] = (__bf16)r[k];
+}
+
 // One 16-query tile t against keys 0..16t+15 held in LDS; writes rows
 // i >= lo (and < N) through orow(i).
 template <int DH, class OF>
@@ -126,7 +159,12 @@ __device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
     f32x4 o[NT];
 #pragma unroll
     for (int u = 0; u < NT; ++u) o[u] = f32x4{0, 0, 0, 0};
-    float mrow = -__builtin_inff(), lrow = 0.0f;
+    f32x4 osum = f32x4{0, 0, 0, 0};
+    bf16x8 ones;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ones[k] = (__bf16)1.0f;
+    float mref = 0.0f;                        // reference of this query
+    f32x4 negm = f32x4{0, 0, 0, 0};
     const int nblk = (t * 16 + 15) / 32 + 1;
     for (int blk = 0; blk < nblk; ++blk) {
         const int j0 = blk * 32;
@@ -134,14 +172,14 @@ __device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
             const __bf16* kr = T.Kc + (j0 + sub * 16 + c16) * 2 * DH;
-            f32x4 acc = f32x4{0, 0, 0, 0};
+            f32x4 acc;
             const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(kr + 8 * g);
             if (DH == 16) {
-                acc = mfma_a(a0, b0, acc);
+                acc = mfma_a(a0, b0, negm);
                 acc = mfma_a(a0, b1, acc);
             } else {
                 const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(kr + DH + 8 * g);
-                acc = mfma_a(a0, b0, acc);
+                acc = mfma_a(a0, b0, negm);
                 acc = mfma_a(a1, b1, acc);
                 acc = mfma_a(a0, b2, acc);
             }
@@ -156,29 +194,39 @@ __device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
                 if (key > iq || key >= N) s[k] = -__builtin_inff();
             }
         }
-        float mb = s[0];
+        float lm = s[0];
 #pragma unroll
-        for (int k = 1; k < 8; ++k) mb = fmaxf(mb, s[k]);
-        mb = fmaxf(mb, __shfl_xor(mb, 16, 64));
-        mb = fmaxf(mb, __shfl_xor(mb, 32, 64));
-        const float mn = fmaxf(mrow, mb);
-        const float alpha = exp2f(mrow - mn);
-        float p[8], ps = 0.0f;
+        for (int k = 1; k < 8; ++k) lm = __builtin_fmaxf(lm, s[k]);
+        const bool first = blk == 0;
+        if (first || __builtin_amdgcn_ballot_w64(lm > kTau) != 0) {
+            float dm = __builtin_fmaxf(lm, __shfl_xor(lm, 16, 64));
+            dm = __builtin_fmaxf(dm, __shfl_xor(dm, 32, 64));
+            // the first block sets the reference to its maximum; later
+            // blocks raise it only past kTau
+            const float delta = first ? dm : (dm > kTau ? dm : 0.0f);
+            if (delta != 0.0f) {
+                if (!first) {
+                    const float alpha = __builtin_amdgcn_exp2f(-delta);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            p[k] = exp2f(s[k] - mn);
-            ps += p[k];
+                    for (int u = 0; u < NT; ++u)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) o[u][r] *= alpha;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) osum[r] *= alpha;
+                }
+                mref += delta;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) s[k] -= delta;
+                negm = f32x4{-mref, -mref, -mref, -mref};
+            }
         }
-        ps += __shfl_xor(ps, 16, 64);
-        ps += __shfl_xor(ps, 32, 64);
-        lrow = lrow * alpha + ps;
-        mrow = mn;
+        float p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] = __builtin_amdgcn_exp2f(s[k]);
         bf16x8 ph, pl;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            ph[k] = (__bf16)p[k];
-            pl[k] = (__bf16)(p[k] - (float)ph[k]);
-        }
+        split_p(p, ph, pl);
+        osum = mfma_a(ones, ph, osum);
+        osum = mfma_a(ones, pl, osum);
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
             const int vc = u * 16 + c16;
@@ -190,8 +238,6 @@ __device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
             const bf16x4 l1 = *reinterpret_cast<const bf16x4*>(vl_row + 16);
             const bf16x8 vh = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
             const bf16x8 vl = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) o[u][r] *= alpha;
             o[u] = mfma_a(vh, ph, o[u]);
             o[u] = mfma_a(vl, ph, o[u]);
             o[u] = mfma_a(vh, pl, o[u]);
@@ -199,7 +245,7 @@ __device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
     }
     if (iq >= lo && iq < N) {
         float* dst = orow(iq);
-        const float inv = 1.0f / lrow;
+        const float inv = 1.0f / osum[0];
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
             float4 v;
