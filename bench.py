@@ -23,6 +23,13 @@ METRIC = ("local-energy evals/sec, VQ-dedup vs plain on 1 MI355X, at "
 UNIT = "local-energy evals/s"
 PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}     # TFLOP/s, dense
 HBM_PEAK = 8000.0                                         # GB/s
+# Attention at head width 16-32 is bound by the vector unit, not the matrix
+# core: every (query, key) pair needs one exponential, a quarter-rate
+# transcendental.  256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz / 4 = 9.83e12
+# exponentials per second bound the pair rate; the attention peak is that
+# rate times the algorithmic FLOPs of a pair (4 d_head: q.k and p.v).
+EXP_RATE = 256 * 4 * 16 * 2.4e9 / 4
+TRAFFIC_FILE = "profiles/attention_dedup_16x16_bf16__hbm_traffic.json"
 
 
 def flops_model(mc, ctr, base_samples):
@@ -42,6 +49,33 @@ def flops_model(mc, ctr, base_samples):
         "attention_dedup": 4.0 * max(pairs_total - pairs_base, 0) * dh,
         "head": 2.0 * ctr["head_rows"] * d * 2,
     }
+
+
+def kernel_source_digest():
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                       "paper_2212_11296_amd", "csrc", "kernels_attn.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, mc):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated),
+    or None when the summary is absent, covers another kernel or workload,
+    or was taken from a different kernel source."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        TRAFFIC_FILE)
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("kernel") != kernel or t.get("L") != mc.L
+            or t.get("batch") != mc.batch
+            or t.get("source_sha256") != kernel_source_digest()):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def counters_dict(vq, arr, nl):
@@ -108,6 +142,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the steps, copy a buffer of this many MiB "
+                         "once (a kernel of known traffic that calibrates "
+                         "hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -148,6 +186,14 @@ def main():
         vq.local_energy(cfg, p, sp, mode, ratios=True, counters=True, ws=w,
                         check=False, out=out)
 
+    if args.copy_probe_mib > 0:
+        n_el = args.copy_probe_mib << 18
+        src = torch.ones(n_el, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(vq.DEDUP, ws)
     torch.cuda.synchronize()
@@ -184,12 +230,13 @@ def main():
         avg_ms = dom_total_ms / dom_launches
         achieved = flop_per_launch / (avg_ms / 1e3) / 1e12
         if dom.startswith("attention"):
-            bound, peak = "alu", PEAK["fp32"]
+            bound, peak = "alu", 4.0 * mc.d_head * EXP_RATE / 1e12
         else:
             bound, peak = "mfma", PEAK["bf16"]
         roof = {"bound": bound, "kernel": dom, "achieved": achieved,
                 "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "flop_per_launch": flop_per_launch,
+                "traffic": measured_traffic(dom, mc),
+                "flop_per_launch": flop_per_launch,
                 "avg_launch_ms": avg_ms}
     else:
         roof = {"bound": None, "kernel": dom, "achieved": None, "peak": None,
