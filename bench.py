@@ -128,12 +128,119 @@ def cpu_baseline(mc, theta, spins, gpu_ratios, n_nb0, budget_s):
             }, err
 
 
+def grad_flops(mc):
+    """Algorithmic FLOPs of the gradient's products per sample (2 per
+    multiply-add): the recomputed MLP input product and the backward
+    products of every layer (MLP, output projection, quantizer, QKV)."""
+    N, d, F, Q = mc.N, mc.d_model, mc.d_ff, mc.codebook_size
+    per_layer = 10 * N * d * F + 16 * N * d * d + 6 * N * Q * d
+    return {"grad_gemm": float(mc.n_layers * per_layer),
+            "grad_attention": float(mc.n_layers * 8 * N * N * mc.d_head
+                                    * mc.n_heads)}
+
+
+def bench_grad(args, vq, torch, np, mc, make_params, make_spins):
+    """Weighted straight-through gradient sum_i w_i d log psi_i / d theta of
+    the 20x20 gradient workload; prints one JSON line."""
+    B = mc.batch
+    dev = torch.device("cuda:0")
+    theta = make_params(mc)
+    spins = make_spins(mc)
+    p = torch.tensor(theta, dtype=torch.float32, device=dev)
+    sp = torch.tensor(spins, device=dev)
+    w = torch.tensor(np.random.default_rng(77).standard_normal(B),
+                     dtype=torch.float64, device=dev)
+    cfg = vq.make_config(mc)
+    need = vq.workspace_size(cfg, B, vq.WS_GRAD, 0)
+    ws = torch.empty(min(need, int(args.ws_gb * (1 << 30))),
+                     dtype=torch.uint8, device=dev)
+    g = torch.empty(p.numel(), dtype=torch.float32, device=dev)
+
+    def step():
+        vq.grad_logpsi(cfg, p, sp, weights=w, ws=ws, check=False, out=g)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    vq.profile_reset()
+    vq.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    vq.profile_enable(False)
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = vq.profile_read()
+    vq.api._check_status(ws)
+    per_kernel = {k: {"ms_per_step": v[0] / args.steps,
+                      "launches_per_step": v[1] / args.steps}
+                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    dom = next(iter(per_kernel))
+    fl = {k: v * B for k, v in grad_flops(mc).items()}
+    roof = {"bound": None, "kernel": dom, "achieved": None, "peak": None,
+            "unit": None, "frac": None, "traffic": None}
+    if dom in fl:
+        launches = prof[dom][1]
+        per_launch = fl[dom] * args.steps / launches
+        avg = prof[dom][0] / launches
+        ach = per_launch / (avg / 1e3) / 1e12
+        if dom == "grad_attention":
+            peak = 4.0 * mc.d_head * EXP_RATE / 1e12
+        else:
+            peak = PEAK["fp32"]
+        roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "flop_per_launch": per_launch, "avg_launch_ms": avg}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import grad as og
+        t0 = time.perf_counter()
+        k = 0
+        while k < 1 or (time.perf_counter() - t0 < args.cpu_seconds and k < 4):
+            og.grad_logpsi(mc, theta, spins[k:k + 1])
+            k += 1
+        dt = time.perf_counter() - t0
+        try:
+            cores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            cores = os.cpu_count()
+        cpu = {"value": k / dt, "unit": "samples/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"per-sample gradients of the first {k} samples, "
+                         f"torch float64 autograd on the CPU, {dt:.1f} s"}
+    res = {
+        "metric": "straight-through gradient samples/sec (weighted sum of "
+                  "d log psi / d theta), 1 MI355X",
+        "value": B / (ms / 1000.0), "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": (f"{mc.L}x{mc.L} periodic Heisenberg, VQ "
+                                f"transformer d={mc.d_model} L={mc.n_layers} "
+                                f"heads={mc.n_heads} mlp={mc.d_ff} "
+                                f"Q={mc.codebook_size}, {B} seeded Sz=0 "
+                                f"samples, weighted gradient"),
+                   "L": mc.L, "batch": B, "precision": mc.precision},
+        "roofline": roof, "cpu_baseline": cpu,
+        "algorithmic_tflop_per_step": sum(fl.values()) / 1e12,
+        "kernels": per_kernel,
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="large")
+    ap.add_argument("--workload", default="eloc", choices=["eloc", "grad"],
+                    help="eloc: local energy (default); grad: weighted "
+                         "straight-through gradient of the 20x20 workload")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--flags", type=int, default=0,
@@ -161,6 +268,12 @@ def main():
     import paper_2212_11296_amd as vq
     from workloads import config_by_name, make_params, make_spins, with_batch
 
+    if args.workload == "grad":
+        mc = config_by_name("grad")
+        if args.batch:
+            mc = with_batch(mc, args.batch)
+        bench_grad(args, vq, torch, np, mc, make_params, make_spins)
+        return
     mc = config_by_name(args.config)
     if args.batch:
         mc = with_batch(mc, args.batch)

@@ -127,8 +127,11 @@ int64_t vqnqs_param_count(const vqnqs_config* cfg);
 
 /* Workspace bytes needed to evaluate `batch` samples in `mode` processing
  * `chunk` samples at a time (chunk <= 0 means the whole batch at once).
- * mode is a vqnqs_mode for vqnqs_local_energy, or -1 for
- * vqnqs_forward_logpsi / vqnqs_neighbours. */
+ * mode is a vqnqs_mode for vqnqs_local_energy, VQNQS_WS_FORWARD for
+ * vqnqs_forward_logpsi / vqnqs_neighbours, or VQNQS_WS_GRAD for
+ * vqnqs_grad_logpsi. */
+#define VQNQS_WS_FORWARD (-1)
+#define VQNQS_WS_GRAD (-3)
 vqnqs_status vqnqs_workspace_size(const vqnqs_config* cfg, int64_t batch,
                                   int32_t mode, int64_t chunk, size_t* bytes);
 
@@ -167,6 +170,33 @@ vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
                                 int32_t mode, double* eloc, double* stats,
                                 double* ratios, int64_t* counters, void* ws,
                                 size_t ws_bytes, void* stream);
+
+/* Gradient of log psi with respect to the flat parameters, with the
+ * straight-through quantizer of eqs. (7)-(8): the forward value is the
+ * nearest codeword; the backward passes the gradient g reaching the
+ * quantized vector to the chosen codeword (one-hot term) and through
+ * p = softmax(-||u - W_j||) over all codewords of that quantizer head to the
+ * codewords and to the attention output u (softmax term).  Everything else
+ * is differentiated exactly (log psi = 1/2 log P, Sec. 2).  The forward
+ * keeps only every layer's input; each layer is recomputed with the forward
+ * kernels (same codes) before its backward (layer checkpointing).
+ *   weights [batch] double DEVICE in, nullable:
+ *       non-NULL: grad[P] = sum_i weights[i] d log psi(s_i)/d theta
+ *                 (the form a variational gradient step needs, Sec. 2)
+ *       NULL:     grad[batch][P], one gradient per sample
+ *   grad    DEVICE out, the parameters' element type (double for VQNQS_F64,
+ *           float otherwise); P = vqnqs_param_count(cfg)
+ *   logpsi  [batch] double DEVICE out, nullable: log psi of every sample
+ * In the BF16 mode the forward and its recompute run on the matrix core at
+ * the bfloat16-rounded parameters, the backward in FP32.  Workspace:
+ * vqnqs_workspace_size(cfg, batch, VQNQS_WS_GRAD, chunk, &bytes); the
+ * per-sample gradients of a chunk are held in it (P values per sample).
+ * The weighted sum is accumulated over samples in a fixed order. */
+vqnqs_status vqnqs_grad_logpsi(const vqnqs_config* cfg, const void* params,
+                               const int8_t* spins, int64_t batch,
+                               const double* weights, void* grad,
+                               double* logpsi, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* Reads the device status word of a workspace used by a previous call:
  * synchronises `stream`, then returns VQNQS_OK or VQNQS_ERR_BAD_SPIN. */

@@ -8,11 +8,13 @@ library; the first call does, and fails loudly if it has not been built.
 from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
                   NCOUNTERS, CTR, VQNQSError, library_path, load_library,
                   exported_symbols, param_count, workspace_size, neighbours,
-                  forward_logpsi, local_energy, make_config, profile_enable,
-                  profile_reset, profile_read)
+                  forward_logpsi, local_energy, grad_logpsi, logpsi,
+                  make_config, profile_enable, profile_reset, profile_read,
+                  WS_FORWARD, WS_GRAD)
 
 __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "FLAG_CERTIFIED_VQ", "NCOUNTERS", "CTR", "VQNQSError",
            "library_path", "load_library", "exported_symbols", "param_count",
            "workspace_size", "neighbours", "forward_logpsi", "local_energy",
-           "make_config", "profile_enable", "profile_reset", "profile_read"]
+           "grad_logpsi", "logpsi", "make_config", "profile_enable",
+           "profile_reset", "profile_read", "WS_FORWARD", "WS_GRAD"]

@@ -15,8 +15,9 @@ _STATUS = {0: "ok", 1: "null pointer", 2: "invalid config", 3: "invalid shape",
            4: "workspace too small", 5: "unsupported configuration",
            6: "spin value other than +1/-1", 7: "HIP runtime error"}
 
+WS_FORWARD, WS_GRAD = -1, -3
 EXPORTS = ["vqnqs_param_count", "vqnqs_workspace_size", "vqnqs_neighbours",
-           "vqnqs_forward_logpsi", "vqnqs_local_energy",
+           "vqnqs_forward_logpsi", "vqnqs_local_energy", "vqnqs_grad_logpsi",
            "vqnqs_workspace_status", "vqnqs_status_string",
            "vqnqs_profile_enable", "vqnqs_profile_reset", "vqnqs_profile_read"]
 
@@ -77,6 +78,8 @@ def load_library():
     lib.vqnqs_local_energy.argtypes = [C, P, P, I64, I32, P, P, P, P, P, SZ,
                                        P]
     lib.vqnqs_local_energy.restype = ctypes.c_int
+    lib.vqnqs_grad_logpsi.argtypes = [C, P, P, I64, P, P, P, P, SZ, P]
+    lib.vqnqs_grad_logpsi.restype = ctypes.c_int
     lib.vqnqs_workspace_status.argtypes = [P, P]
     lib.vqnqs_workspace_status.restype = ctypes.c_int
     lib.vqnqs_status_string.argtypes = [ctypes.c_int]
@@ -226,3 +229,58 @@ def local_energy(cfg, params, spins, mode=DEDUP, stats=True, ratios=False,
     if check:
         _check_status(ws)
     return o
+
+
+def grad_logpsi(cfg, params, spins, weights=None, logpsi=False, ws=None,
+                budget=8 << 30, check=True, out=None):
+    """Straight-through gradient of log psi (device tensor, params' dtype):
+    [P] weighted by ``weights`` (device float64 [B]) if given, else [B][P]."""
+    import torch
+    B = spins.shape[0]
+    P = param_count(cfg)
+    ws = _workspace(cfg, B, WS_GRAD, ws, budget)
+    shape = (P,) if weights is not None else (B, P)
+    g = (out if out is not None
+         else torch.empty(shape, dtype=params.dtype, device="cuda"))
+    lp = torch.empty(B, dtype=torch.float64, device="cuda") if logpsi else None
+    w = None
+    if weights is not None:
+        w = weights.to(device="cuda", dtype=torch.float64).contiguous()
+        if w.numel() == 0:
+            # an empty tensor has no address; the weighted form is selected
+            # by a non-NULL pointer
+            w = torch.zeros(1, dtype=torch.float64, device="cuda")
+    _check("vqnqs_grad_logpsi", load_library().vqnqs_grad_logpsi(
+        ctypes.byref(cfg), _ptr(params), _ptr(spins), B, _ptr(w), _ptr(g),
+        _ptr(lp), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)
+    return (g, lp) if logpsi else g
+
+
+def _logpsi_function():
+    import torch
+
+    class LogPsi(torch.autograd.Function):
+        """log psi(spins) as a differentiable function of the parameters:
+        forward by vqnqs_forward_logpsi, backward by vqnqs_grad_logpsi with
+        the incoming gradient as the sample weights."""
+
+        @staticmethod
+        def forward(ctx, params, spins, cfg):
+            ctx.save_for_backward(params, spins)
+            ctx.cfg = cfg
+            return forward_logpsi(cfg, params, spins)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            params, spins = ctx.saved_tensors
+            g = grad_logpsi(ctx.cfg, params, spins, weights=grad_out)
+            return g, None, None
+
+    return LogPsi
+
+
+def logpsi(cfg, params, spins):
+    """Differentiable log psi [B] (autograd through the HIP backward)."""
+    return _logpsi_function().apply(params, spins, cfg)

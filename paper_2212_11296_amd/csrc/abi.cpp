@@ -74,7 +74,8 @@ vqnqs_status vqnqs_workspace_size(const vqnqs_config* cfg, int64_t batch,
     if (!dims_from(cfg, &m, &e)) return e;
     if (!bytes) return VQNQS_ERR_NULL_POINTER;
     if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
-    if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP && mode != -1)
+    if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP &&
+        mode != VQNQS_WS_FORWARD && mode != VQNQS_WS_GRAD)
         return VQNQS_ERR_INVALID_CONFIG;
     if (chunk <= 0 || chunk > batch) chunk = batch > 0 ? batch : 1;
     *bytes = vq::workspace_bytes(m, mode, chunk);
@@ -123,6 +124,21 @@ vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
         return VQNQS_ERR_NULL_POINTER;
     return vq::local_energy(m, params, spins, batch, mode, eloc, stats, ratios,
                             counters, ws, ws_bytes, (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_grad_logpsi(const vqnqs_config* cfg, const void* params,
+                               const int8_t* spins, int64_t batch,
+                               const double* weights, void* grad,
+                               double* logpsi, void* ws, size_t ws_bytes,
+                               void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (!ws || !grad || (batch > 0 && (!params || !spins)))
+        return VQNQS_ERR_NULL_POINTER;
+    return vq::grad_logpsi(m, params, spins, batch, weights, grad, logpsi, ws,
+                           ws_bytes, (hipStream_t)stream);
 }
 
 vqnqs_status vqnqs_workspace_status(const void* ws, void* stream) {

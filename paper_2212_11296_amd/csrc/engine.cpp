@@ -81,10 +81,24 @@ struct Workspace {
     int16_t* crow;
     uint64_t* mask;
     int64_t *list, *vq_list;
+    // gradient of log psi: layer inputs (checkpoints), one layer's
+    // recomputed activations and the backward's row buffers
+    acc* gx;                  // [nl+1][n][N][d]
+    act *gq, *gk, *gv, *ga;   // [n][N][d]
+    int32_t* gcode;           // [n][N][H]
+    double* glogpsi;          // [n]
+    acc *h1, *xh1, *rs1, *xp, *zq, *h2, *xh2, *rs2;
+    acc *gu, *gg, *dF;        // [n][N][d_ff]
+    acc *dX, *dXp, *dT, *da;  // [n][N][d]
+    acc* dqkv;                // [n][N][3d]
+    acc *lse, *Dd;            // [n][N][heads]
+    acc *S, *E;               // [n][N][Q]
+    acc *rowG, *colG, *dz2, *coef;
+    acc* part;                // [n][P] per-sample gradients (weighted form)
     size_t bytes;
 };
 
-enum class Job { Forward, Plain, Dedup, Neighbours };
+enum class Job { Forward, Plain, Dedup, Neighbours, Grad };
 
 template <class P>
 static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
@@ -119,6 +133,43 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     w.list_n = c.take<int32_t>(1);
     w.vq_n = c.take<int32_t>(1);
     if (job == Job::Neighbours) {
+        w.bytes = c.off;
+        return w;
+    }
+    if (job == Job::Grad) {
+        const int64_t R = n * N, F = m.dff, Q = m.Q;
+        w.gx = c.take<acc>((size_t)(m.nl + 1) * R * d);
+        w.gq = c.take<act>(R * d);
+        w.gk = c.take<act>(R * d);
+        w.gv = c.take<act>(R * d);
+        w.ga = c.take<act>(R * d);
+        w.gcode = c.take<int32_t>(R * H);
+        w.glogpsi = c.take<double>(n);
+        w.h1 = c.take<acc>(R * d);
+        w.xh1 = c.take<acc>(R * d);
+        w.rs1 = c.take<acc>(R);
+        w.xp = c.take<acc>(R * d);
+        w.zq = c.take<acc>(R * d);
+        w.h2 = c.take<acc>(R * d);
+        w.xh2 = c.take<acc>(R * d);
+        w.rs2 = c.take<acc>(R);
+        w.gu = c.take<acc>(R * F);
+        w.gg = c.take<acc>(R * F);
+        w.dF = c.take<acc>(R * F);
+        w.dX = c.take<acc>(R * d);
+        w.dXp = c.take<acc>(R * d);
+        w.dT = c.take<acc>(R * d);
+        w.da = c.take<acc>(R * d);
+        w.dqkv = c.take<acc>(R * 3 * d);
+        w.lse = c.take<acc>(R * m.nh);
+        w.Dd = c.take<acc>(R * m.nh);
+        w.S = c.take<acc>(R * Q);
+        w.E = c.take<acc>(R * Q);
+        w.rowG = c.take<acc>(R);
+        w.colG = c.take<acc>(n * Q);
+        w.dz2 = c.take<acc>(2 * R);
+        w.coef = c.take<acc>(n);
+        w.part = c.take<acc>((size_t)n * param_count(m));
         w.bytes = c.off;
         return w;
     }
@@ -172,6 +223,7 @@ size_t workspace_bytes(const ModelDims& m, int mode, int64_t chunk) {
     const Job job = mode == VQNQS_PLAIN   ? Job::Plain
                     : mode == VQNQS_DEDUP ? Job::Dedup
                     : mode == -2          ? Job::Neighbours
+                    : mode == -3          ? Job::Grad
                                           : Job::Forward;
     switch (m.precision) {
         case VQNQS_F64: return carve<PrecF64>(m, job, chunk, nullptr).bytes;
@@ -194,6 +246,8 @@ int64_t pick_chunk(const ModelDims& m, int mode, int64_t batch, size_t ws) {
     const int64_t rows1 = std::max<int64_t>(1, max_overlay_rows(m));
     hi = std::min<int64_t>(hi, ((int64_t)1 << 30) / rows1);
     hi = std::min<int64_t>(hi, ((int64_t)1 << 30) / (2 * m.N));
+    // gradient products tile rows by 64 with at most 65535 row tiles
+    if (mode == -3) hi = std::min<int64_t>(hi, (int64_t)65535 * 64 / m.N);
     if (hi < 1) hi = 1;
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo + 1) / 2;
@@ -265,6 +319,29 @@ int64_t param_count(const ModelDims& m) {
         if (pf_.enabled()) pf_.end(st);                     \
         if (e_ != hipSuccess) return VQNQS_ERR_HIP;         \
     } while (0)
+
+// Element offsets of every tensor of layer l (and of the head) in the flat
+// parameter vector: the layout of include/vqnqs.h.
+static LayerOffsets layer_offsets(const ModelDims& m, int l) {
+    const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
+    const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
+                        d * F + F + F * d + d;
+    LayerOffsets o;
+    o.ln1_g = 3 * d + N * d + per * l;
+    o.ln1_b = o.ln1_g + d;
+    o.W_qkv = o.ln1_b + d;
+    o.b_qkv = o.W_qkv + d * 3 * d;
+    o.codebook = o.b_qkv + 3 * d;
+    o.W_o = o.codebook + Q * d;
+    o.b_o = o.W_o + d * d;
+    o.ln2_g = o.b_o + d;
+    o.ln2_b = o.ln2_g + d;
+    o.W1 = o.ln2_b + d;
+    o.b1 = o.W1 + d * F;
+    o.W2 = o.b1 + F;
+    o.b2 = o.W2 + F * d;
+    return o;
+}
 
 template <class P>
 struct Runner {
@@ -353,6 +430,7 @@ struct Runner {
         double* logpsi;
         bool cache;
         int32_t* codes_out;   // nullable [n][nl][N][H]
+        bool keep_x = false;  // block inputs per layer only (checkpoints)
     };
 
     vqnqs_status forward(const SeqBufs& b, const int32_t* n_dev, int64_t n,
@@ -361,9 +439,10 @@ struct Runner {
         LK("embed", launch_embed<P>(m, head(), b.spins, n_dev, n, b.x, st));
         for (int l = 0; l < m.nl; ++l) {
             const int64_t cl = b.cache ? l : 0;
+            const bool per_layer_x = b.cache || b.keep_x;
             BlockIO<P> io{};
-            io.x = b.x + (b.cache ? (int64_t)(l + 1) * sd : 0);
-            io.x_in = b.x + (b.cache ? (int64_t)l * sd : 0);
+            io.x = b.x + (per_layer_x ? (int64_t)(l + 1) * sd : 0);
+            io.x_in = b.x + (per_layer_x ? (int64_t)l * sd : 0);
             io.q = b.q + cl * sd;
             io.k = b.k + cl * sd;
             io.v = b.v + cl * sd;
@@ -380,7 +459,7 @@ struct Runner {
             if (b.codes_out)
                 LK("copy_codes", launch_copy_codes(io.codes, n, m.N, m.H, m.nl, l, b.codes_out, st));
         }
-        const acc* xf = b.x + (b.cache ? (int64_t)m.nl * sd : 0);
+        const acc* xf = b.x + (b.cache || b.keep_x ? (int64_t)m.nl * sd : 0);
         LK("head_seq", launch_head_seq<P>(m, head(), b.spins, n_dev, n, xf, b.lp, b.logpsi, st));
         if (count_rows && ctr) {
             if (n_dev) {
@@ -395,6 +474,145 @@ struct Runner {
                 CK(launch_counter_add_const(ctr, VQNQS_CTR_HEAD_ROWS, rows, st));
             }
         }
+        return VQNQS_OK;
+    }
+
+    // ------------------------------------------------ gradient of log psi
+    hipError_t gemm(int64_t M, int64_t Nn, int64_t K, const acc* A, int64_t lda,
+                    int64_t sA, int tA, const acc* B, int64_t ldb, int64_t sB,
+                    int tB, acc* C, int64_t ldc, int64_t sC, int beta,
+                    int64_t groups) {
+        GemmDesc g{M, Nn, K, A, lda, sA, tA, B, ldb, sB, tB, C, ldc, sC, beta,
+                   groups};
+        return launch_gemm<acc>(g, st);
+    }
+    hipError_t colsum(int64_t n, int cols, const acc* A, int64_t lda,
+                      const acc* B, int64_t ldb, acc* out, int64_t os) {
+        return launch_colsum<acc>(n, m.N, cols, A, lda, B, ldb, out, os, 0, st);
+    }
+
+    // Per-sample straight-through gradients of n samples into gout[n][P]
+    // (upstream 1/2 * weight of every position's log-probability).  The
+    // forward keeps only the layer inputs; each layer is recomputed with the
+    // forward's own kernels (so its codes are the forward's) before its
+    // backward.
+    vqnqs_status grad_chunk(const int8_t* sp, int64_t n, const double* wts,
+                            acc* gout, double* lp_out) {
+        const int64_t N = m.N, d = m.d, F = m.dff, Q = m.Q, ds = m.dseg;
+        const int64_t R = n * N, sd = R * d, NP = param_count(m);
+        LK("neighbours", launch_neighbours(sp, n, m, w.bonds, w.count, nullptr,
+                                           nullptr, w.status, st));
+        SeqBufs sb{sp, w.gx, w.gq, w.gk, w.gv, w.ga, w.gcode, nullptr, nullptr,
+                   lp_out ? lp_out : w.glogpsi, false, nullptr, true};
+        vqnqs_status s = forward(sb, nullptr, n, false);
+        if (s) return s;
+        LK("grad_coef", launch_coef<acc>(n, wts, w.coef, st));
+        const HeadW<acc> hw = head();
+        const int64_t off_lnf = layer_offsets(m, m.nl).ln1_g;
+        const int64_t off_Wh = off_lnf + 2 * d, off_bh = off_Wh + 2 * d;
+        // head: d log psi / d x_L
+        LK("grad_head", launch_head_bwd<acc>(n, (int)N, (int)d, hw, sp,
+                                             w.gx + (int64_t)m.nl * sd, w.coef,
+                                             w.h1, w.xh1, w.rs1, w.dz2, w.dT,
+                                             w.dX, st));
+        LK("grad_gemm", gemm(d, 2, N, w.h1, d, N * d, 1, w.dz2, 2, 2 * N, 0,
+                             gout + off_Wh, 2, NP, 0, n));
+        LK("grad_colsum", colsum(n, 2, w.dz2, 2, nullptr, 0, gout + off_bh, NP));
+        LK("grad_colsum", colsum(n, d, w.dT, d, w.xh1, d, gout + off_lnf, NP));
+        LK("grad_colsum", colsum(n, d, w.dT, d, nullptr, 0, gout + off_lnf + d, NP));
+        for (int l = m.nl - 1; l >= 0; --l) {
+            const LayerW<acc> lw = layer(l);
+            const LayerOffsets o = layer_offsets(m, l);
+            const acc* xl = w.gx + (int64_t)l * sd;
+            // recompute q, k, v, a and the codes
+            BlockIO<P> io{};
+            io.x = const_cast<acc*>(xl);
+            io.x_in = xl;
+            io.q = w.gq;
+            io.k = w.gk;
+            io.v = w.gv;
+            io.a = w.ga;
+            io.codes = w.gcode;
+            io.margin = nullptr;
+            const RowSet rs{nullptr, nullptr, R, (int32_t)N};
+            LK("qkv", qkv(lw, rs, io));
+            LK("attention_seq", attn_seq(nullptr, n, io, nullptr));
+            LK("vq", vqs(lw, rs, io));
+            LK("grad_ln", launch_ln_save<acc>(R, (int)d, xl, lw.ln1_g, lw.ln1_b,
+                                              w.h1, w.xh1, w.rs1, st));
+            LK("grad_xprime", launch_xprime<acc>(R, m, xl, w.gcode, lw.table,
+                                                 lw.b_o, lw.codebook, w.xp,
+                                                 w.zq, st));
+            LK("grad_ln", launch_ln_save<acc>(R, (int)d, w.xp, lw.ln2_g,
+                                              lw.ln2_b, w.h2, w.xh2, w.rs2, st));
+            LK("grad_gemm", gemm(R, F, d, w.h2, d, 0, 0, lw.W1, F, 0, 0, w.gu,
+                                 F, 0, 0, 1));
+            LK("grad_gelu", launch_bias_gelu<acc>(R, (int)F, w.gu, lw.b1, w.gg, st));
+            // MLP: x = x' + GELU(LN2(x') W1 + b1) W2 + b2
+            LK("grad_gemm", gemm(F, d, N, w.gg, F, N * F, 1, w.dX, d, N * d, 0,
+                                 gout + o.W2, d, NP, 0, n));
+            LK("grad_colsum", colsum(n, d, w.dX, d, nullptr, 0, gout + o.b2, NP));
+            LK("grad_gemm", gemm(R, F, d, w.dX, d, 0, 0, lw.W2, d, 0, 1, w.dF,
+                                 F, 0, 0, 1));
+            LK("grad_gelu", launch_gelu_bwd<acc>(R * F, w.gu, w.dF, st));
+            LK("grad_gemm", gemm(d, F, N, w.h2, d, N * d, 1, w.dF, F, N * F, 0,
+                                 gout + o.W1, F, NP, 0, n));
+            LK("grad_colsum", colsum(n, F, w.dF, F, nullptr, 0, gout + o.b1, NP));
+            LK("grad_gemm", gemm(R, d, F, w.dF, F, 0, 0, lw.W1, F, 0, 1, w.dT,
+                                 d, 0, 0, 1));
+            LK("grad_colsum", colsum(n, d, w.dT, d, w.xh2, d, gout + o.ln2_g, NP));
+            LK("grad_colsum", colsum(n, d, w.dT, d, nullptr, 0, gout + o.ln2_b, NP));
+            LK("grad_ln", launch_ln_bwd<acc>(R, (int)d, w.xh2, w.rs2, lw.ln2_g,
+                                             w.dT, w.dX, w.dXp, st));
+            // output projection: x' = x + z W_o + b_o
+            LK("grad_gemm", gemm(d, d, N, w.zq, d, N * d, 1, w.dXp, d, N * d, 0,
+                                 gout + o.W_o, d, NP, 0, n));
+            LK("grad_colsum", colsum(n, d, w.dXp, d, nullptr, 0, gout + o.b_o, NP));
+            LK("grad_gemm", gemm(R, d, d, w.dXp, d, 0, 0, lw.W_o, d, 0, 1, w.dT,
+                                 d, 0, 0, 1));
+            // straight-through quantizer (eqs. 7-8), head by head
+            for (int h = 0; h < m.H; ++h) {
+                const acc* cb = lw.codebook + (int64_t)h * Q * ds;
+                acc* dcb = gout + o.codebook + (int64_t)h * Q * ds;
+                const acc* ah = w.ga + h * ds;
+                LK("grad_gemm", gemm(R, Q, ds, ah, d, 0, 0, cb, ds, 0, 1, w.S,
+                                     Q, 0, 0, 1));
+                LK("grad_gemm", gemm(R, Q, ds, w.dT + h * ds, d, 0, 0, cb, ds,
+                                     0, 1, w.E, Q, 0, 0, 1));
+                LK("grad_vq", launch_vq_bwd_rows<acc>(R, (int)Q, (int)ds, m.H,
+                                                      h, ah, (int)d, w.gcode,
+                                                      lw.cnorm + (int64_t)h * Q,
+                                                      w.S, w.E, w.rowG, st));
+                LK("grad_gemm", gemm(R, ds, Q, w.S, Q, 0, 0, cb, ds, 0, 0,
+                                     w.da + h * ds, d, 0, 0, 1));
+                LK("grad_vq", launch_da_fix<acc>(R, (int)ds, (int)d, ah, w.rowG,
+                                                 w.da + h * ds, st));
+                LK("grad_gemm", gemm(Q, ds, N, w.E, Q, N * Q, 1, w.dT + h * ds,
+                                     d, N * d, 0, dcb, ds, NP, 0, n));
+                LK("grad_gemm", gemm(Q, ds, N, w.S, Q, N * Q, 1, ah, d, N * d, 0,
+                                     dcb, ds, NP, 1, n));
+                LK("grad_colsum", colsum(n, (int)Q, w.S, Q, nullptr, 0, w.colG, Q));
+                LK("grad_vq", launch_cb_fix<acc>(n, (int)Q, (int)ds, w.colG, cb,
+                                                 dcb, NP, st));
+            }
+            // causal attention
+            LK("grad_attention", launch_attn_bwd<acc>(n, m, w.gq, w.gk, w.gv,
+                                                      w.ga, w.da, w.lse, w.Dd,
+                                                      w.dqkv, st));
+            // LN1 + QKV projection
+            LK("grad_gemm", gemm(d, 3 * d, N, w.h1, d, N * d, 1, w.dqkv, 3 * d,
+                                 N * 3 * d, 0, gout + o.W_qkv, 3 * d, NP, 0, n));
+            LK("grad_colsum", colsum(n, 3 * (int)d, w.dqkv, 3 * d, nullptr, 0,
+                                     gout + o.b_qkv, NP));
+            LK("grad_gemm", gemm(R, d, 3 * d, w.dqkv, 3 * d, 0, 0, lw.W_qkv,
+                                 3 * d, 0, 1, w.dT, d, 0, 0, 1));
+            LK("grad_colsum", colsum(n, d, w.dT, d, w.xh1, d, gout + o.ln1_g, NP));
+            LK("grad_colsum", colsum(n, d, w.dT, d, nullptr, 0, gout + o.ln1_b, NP));
+            LK("grad_ln", launch_ln_bwd<acc>(R, (int)d, w.xh1, w.rs1, lw.ln1_g,
+                                             w.dT, w.dXp, w.dX, st));
+        }
+        LK("grad_embed", launch_embed_bwd<acc>(n, (int)N, (int)d, sp, w.dX, gout,
+                                               NP, 0, 3 * d, st));
         return VQNQS_OK;
     }
 
@@ -611,6 +829,58 @@ vqnqs_status forward_logpsi(const ModelDims& m, const void* params,
         default:
             return run_forward<PrecBF16>(m, params, spins, batch, logpsi, codes,
                                          ws, ws_bytes, st);
+    }
+}
+
+template <class P>
+static vqnqs_status run_grad(const ModelDims& m, const void* params,
+                             const int8_t* spins, int64_t batch,
+                             const double* weights, void* grad, double* logpsi,
+                             void* ws, size_t ws_bytes, hipStream_t st) {
+    using acc = typename P::acc;
+    const int64_t chunk = pick_chunk(m, -3, batch, ws_bytes);
+    if (batch > 0 && chunk <= 0) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
+    if (batch == 0 && ws_bytes < workspace_bytes(m, -3, 1))
+        return VQNQS_ERR_WORKSPACE_TOO_SMALL;
+    Runner<P> r{m, static_cast<const acc*>(params),
+                carve<P>(m, Job::Grad, std::max<int64_t>(chunk, 1), ws), st,
+                nullptr};
+    const int64_t Pn = param_count(m);
+    acc* g = static_cast<acc*>(grad);
+    CK(launch_fill_i32(r.w.status, 1, 0, st));
+    if (batch == 0) {
+        if (weights) CK(launch_fill_t<acc>(g, Pn, (acc)0, st));
+        return VQNQS_OK;
+    }
+    vqnqs_status s = r.prepare();
+    if (s) return s;
+    for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
+        const int64_t n = std::min(chunk, batch - c0);
+        acc* gout = weights ? r.w.part : g + c0 * Pn;
+        s = r.grad_chunk(spins + c0 * m.N, n, weights ? weights + c0 : nullptr,
+                         gout, logpsi ? logpsi + c0 : nullptr);
+        if (s) return s;
+        if (weights)
+            LK("grad_reduce", launch_reduce_samples<acc>(n, Pn, r.w.part, g,
+                                                         c0 > 0 ? 1 : 0, st));
+    }
+    return VQNQS_OK;
+}
+
+vqnqs_status grad_logpsi(const ModelDims& m, const void* params,
+                         const int8_t* spins, int64_t batch,
+                         const double* weights, void* grad, double* logpsi,
+                         void* ws, size_t ws_bytes, hipStream_t st) {
+    switch (m.precision) {
+        case VQNQS_F64:
+            return run_grad<PrecF64>(m, params, spins, batch, weights, grad,
+                                     logpsi, ws, ws_bytes, st);
+        case VQNQS_F32:
+            return run_grad<PrecF32>(m, params, spins, batch, weights, grad,
+                                     logpsi, ws, ws_bytes, st);
+        default:
+            return run_grad<PrecBF16>(m, params, spins, batch, weights, grad,
+                                      logpsi, ws, ws_bytes, st);
     }
 }
 

@@ -18,6 +18,10 @@ vqnqs_status forward_logpsi(const ModelDims& m, const void* params,
                             const int8_t* spins, int64_t batch, double* logpsi,
                             int32_t* codes, void* ws, size_t ws_bytes,
                             hipStream_t st);
+vqnqs_status grad_logpsi(const ModelDims& m, const void* params,
+                         const int8_t* spins, int64_t batch,
+                         const double* weights, void* grad, double* logpsi,
+                         void* ws, size_t ws_bytes, hipStream_t st);
 vqnqs_status neighbours(const ModelDims& m, const int8_t* spins, int64_t batch,
                         int16_t* bonds, int32_t* count, double* diag, void* ws,
                         size_t ws_bytes, hipStream_t st);

@@ -167,4 +167,71 @@ hipError_t launch_ratio_plain(const double* logpsi_nb, const double* logpsi_s,
                               const NbDesc* desc, const int32_t* n_dev,
                               int64_t n_max, double* ratio, hipStream_t st);
 
+// ---- backward of log psi (straight-through quantizer, eqs. 7-8)
+// C[g] = beta*C[g] + op(A[g]) op(B[g]), g < groups; op(A) M x K, op(B) K x N.
+struct GemmDesc {
+    int64_t M, N, K;
+    const void* A;
+    int64_t lda, sA;
+    int tA;
+    const void* B;
+    int64_t ldb, sB;
+    int tB;
+    void* C;
+    int64_t ldc, sC;
+    int beta;
+    int64_t groups;
+};
+template <typename T>
+hipError_t launch_gemm(const GemmDesc& g, hipStream_t st);
+template <typename T>
+hipError_t launch_colsum(int64_t groups, int64_t rows, int cols, const T* A,
+                         int64_t lda, const T* B, int64_t ldb, T* out,
+                         int64_t os, int beta, hipStream_t st);
+template <typename T>
+hipError_t launch_reduce_samples(int64_t n, int64_t P, const T* part, T* grad,
+                                 int beta, hipStream_t st);
+template <typename T>
+hipError_t launch_coef(int64_t n, const double* w, T* coef, hipStream_t st);
+template <typename T>
+hipError_t launch_fill_t(T* p, int64_t n, T v, hipStream_t st);
+template <typename T>
+hipError_t launch_ln_save(int64_t R, int d, const T* x, const T* g, const T* b,
+                          T* y, T* xh, T* rstd, hipStream_t st);
+template <typename T>
+hipError_t launch_ln_bwd(int64_t R, int d, const T* xh, const T* rstd,
+                         const T* g, const T* dy, const T* base, T* out,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_xprime(int64_t R, const ModelDims& m, const T* x,
+                         const int32_t* codes, const T* table, const T* b_o,
+                         const T* codebook, T* xp, T* z, hipStream_t st);
+template <typename T>
+hipError_t launch_bias_gelu(int64_t R, int F, T* u, const T* b1, T* g,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_gelu_bwd(int64_t n, const T* u, T* dg, hipStream_t st);
+template <typename T>
+hipError_t launch_head_bwd(int64_t n, int N, int d, const HeadW<T>& hw,
+                           const int8_t* spins, const T* x, const T* coef, T* f,
+                           T* xh, T* rstd, T* dz, T* df, T* dx, hipStream_t st);
+template <typename T>
+hipError_t launch_embed_bwd(int64_t n, int N, int d, const int8_t* spins,
+                            const T* dx, T* grad, int64_t P, int64_t tok_off,
+                            int64_t pos_off, hipStream_t st);
+template <typename T>
+hipError_t launch_vq_bwd_rows(int64_t R, int Q, int dseg, int H, int h,
+                              const T* a, int lda, const int32_t* codes,
+                              const T* w2, T* S, T* E, T* rowG, hipStream_t st);
+template <typename T>
+hipError_t launch_da_fix(int64_t R, int dseg, int ld, const T* a,
+                         const T* rowG, T* da, hipStream_t st);
+template <typename T>
+hipError_t launch_cb_fix(int64_t n, int Q, int dseg, const T* colG, const T* cb,
+                         T* dcb, int64_t P, hipStream_t st);
+template <typename T>
+hipError_t launch_attn_bwd(int64_t n, const ModelDims& m, const T* q,
+                           const T* k, const T* v, const T* o, const T* dO,
+                           T* lse, T* Dd, T* dqkv, hipStream_t st);
+
 }  // namespace vq

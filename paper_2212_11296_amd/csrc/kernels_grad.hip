@@ -1,0 +1,852 @@
+// Backward pass of log psi with the straight-through quantizer (paper
+// eqs. 7-8; chain-rule log psi of Sec. 2; network of Sec. 3.1).
+//
+// The forward of one layer is recomputed from its checkpointed input (layer
+// checkpointing) and differentiated in reverse: output projection + MLP,
+// the quantizer, causal attention, LN1 + QKV; then the head and the
+// embeddings.  The quantizer passes the gradient through a softmax over the
+// negative unsquared distances to all codewords (eq. 8):
+//   p = softmax(-delta), delta_j = ||u - W_j||, e_j = g . W_j,
+//   t_j = p_j (e_j - p.e),  G_j = t_j / delta_j,
+//   dL/du   = -(sum_j G_j) u + sum_j G_j W_j,
+//   dL/dW_j = (p_j + [j == code]) g + G_j u - G_j W_j,
+// where g is the gradient reaching the quantized vector (eq. 7: the
+// one-hot term carries g to the chosen codeword, the softmax term to all).
+//
+// Every parameter gradient is formed per sample (one group of N rows) into
+// a [sample][P] array, so per-sample gradients need no extra pass and the
+// weighted sum is a fixed-order reduction over samples (deterministic).
+// Products are tiled VALU kernels in the arithmetic type T (double in the
+// FP64 mode, float otherwise).
+#include "kernels.h"
+
+namespace vq {
+
+constexpr int kGT = 256;          // threads per workgroup
+constexpr int kGridMax = 65535;
+
+static inline unsigned cap_grid(int64_t u) {
+    if (u <= 0) return 1;
+    return (unsigned)(u < 8192 ? u : 8192);
+}
+
+// ------------------------------------------------------------------- GEMM
+// C[g] = beta * C[g] + op(A[g]) op(B[g]) for g < groups; op(A) is M x K
+// (A[m*lda + k], or A[k*lda + m] when tA), op(B) is K x N (B[k*ldb + n],
+// or B[n*ldb + k] when tB).  64 x 64 tiles, K steps of 16 through LDS.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_gemm(GemmDesc g) {
+    constexpr int BM = 64, BN = 64, BK = 16;
+    __shared__ T As[BK][BM + 1];
+    __shared__ T Bs[BK][BN + 1];
+    const int64_t grp = blockIdx.z;
+    const T* A = static_cast<const T*>(g.A) + grp * g.sA;
+    const T* B = static_cast<const T*>(g.B) + grp * g.sB;
+    T* C = static_cast<T*>(g.C) + grp * g.sC;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + kGT * r;
+            int mm, kk;
+            if (g.tA) { kk = e >> 6; mm = e & 63; }
+            else { mm = e >> 4; kk = e & 15; }
+            const int64_t gm = m0 + mm, gk = k0 + kk;
+            T v = 0;
+            if (gm < g.M && gk < g.K)
+                v = g.tA ? A[gk * g.lda + gm] : A[gm * g.lda + gk];
+            As[kk][mm] = v;
+            int nn;
+            if (g.tB) { nn = e >> 4; kk = e & 15; }
+            else { kk = e >> 6; nn = e & 63; }
+            const int64_t gn = n0 + nn, gk2 = k0 + kk;
+            T w = 0;
+            if (gn < g.N && gk2 < g.K)
+                w = g.tB ? B[gn * g.ldb + gk2] : B[gk2 * g.ldb + gn];
+            Bs[kk][nn] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t gm = m0 + ty + 16 * i;
+        if (gm >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t gn = n0 + tx + 16 * j;
+            if (gn >= g.N) continue;
+            T* c = C + gm * g.ldc + gn;
+            *c = g.beta ? *c + acc[i][j] : acc[i][j];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_gemm(const GemmDesc& g, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0 || g.groups <= 0) return hipSuccess;
+    const int64_t gx = (g.N + 63) / 64, gy = (g.M + 63) / 64;
+    if (gx > kGridMax || gy > kGridMax || g.groups > kGridMax)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gemm<T>), dim3((unsigned)gx, (unsigned)gy,
+                                        (unsigned)g.groups),
+                       dim3(kGT), 0, st, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- column reductions
+// out[g*os + c] = beta*out + sum_{r < rows} A[(g*rows + r)*lda + c]
+//                                         (* B[(g*rows + r)*ldb + c])
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_colsum(int64_t groups, int64_t rows,
+                                                int cols, const T* A,
+                                                int64_t lda, const T* B,
+                                                int64_t ldb, T* out,
+                                                int64_t os, int beta) {
+    const int64_t total = groups * cols;
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kGT) {
+        const int64_t g = e / cols;
+        const int c = (int)(e - g * cols);
+        T s = 0;
+        for (int64_t r = 0; r < rows; ++r) {
+            const int64_t row = g * rows + r;
+            T v = A[row * lda + c];
+            if (B) v *= B[row * ldb + c];
+            s += v;
+        }
+        T* o = out + g * os + c;
+        *o = beta ? *o + s : s;
+    }
+}
+
+template <typename T>
+hipError_t launch_colsum(int64_t groups, int64_t rows, int cols, const T* A,
+                         int64_t lda, const T* B, int64_t ldb, T* out,
+                         int64_t os, int beta, hipStream_t st) {
+    const int64_t total = groups * cols;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_colsum<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
+                       dim3(kGT), 0, st, groups, rows, cols, A, lda, B, ldb,
+                       out, os, beta);
+    return hipGetLastError();
+}
+
+// grad[p] = beta*grad[p] + sum_{s < n} part[s*P + p], samples in order.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_reduce_samples(int64_t n, int64_t P,
+                                                        const T* part, T* grad,
+                                                        int beta) {
+    for (int64_t p = (int64_t)blockIdx.x * kGT + threadIdx.x; p < P;
+         p += (int64_t)gridDim.x * kGT) {
+        T s = beta ? grad[p] : (T)0;
+        for (int64_t i = 0; i < n; ++i) s += part[i * P + p];
+        grad[p] = s;
+    }
+}
+
+template <typename T>
+hipError_t launch_reduce_samples(int64_t n, int64_t P, const T* part, T* grad,
+                                 int beta, hipStream_t st) {
+    hipLaunchKernelGGL((k_reduce_samples<T>), dim3(cap_grid((P + kGT - 1) / kGT)),
+                       dim3(kGT), 0, st, n, P, part, grad, beta);
+    return hipGetLastError();
+}
+
+// coef[s] = 1/2 * (w ? w[s] : 1): the upstream of every position's
+// log-probability (log psi = 1/2 sum_i l_i).
+template <typename T>
+__global__ void k_coef(int64_t n, const double* w, T* coef) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) coef[s] = (T)(0.5 * (w ? w[s] : 1.0));
+}
+
+template <typename T>
+hipError_t launch_coef(int64_t n, const double* w, T* coef, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_coef<T>), dim3((unsigned)((n + 255) / 256)), dim3(256),
+                       0, st, n, w, coef);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_fill_t(T* p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * kGT + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kGT)
+        p[i] = v;
+}
+
+template <typename T>
+hipError_t launch_fill_t(T* p, int64_t n, T v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill_t<T>), dim3(cap_grid((n + kGT - 1) / kGT)), dim3(kGT),
+                       0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- LayerNorm
+// One wave per row: y = xh * g + b with xh = (x - mean) * rstd (biased
+// variance, eps 1e-5); xh and rstd are kept for the backward.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_ln_save(int64_t R, int d, const T* x,
+                                                 const T* g, const T* b, T* y,
+                                                 T* xh, T* rstd) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = kGT / 64;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
+         r += (int64_t)gridDim.x * wpb) {
+        const T* xr = x + r * d;
+        T s = 0;
+        for (int k = lane; k < d; k += 64) s += xr[k];
+        const T mean = wave_sum(s) / (T)d;
+        T v = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T t = xr[k] - mean;
+            v += t * t;
+        }
+        v = wave_sum(v) / (T)d;
+        const T rs = (T)1 / dsqrt(v + (T)1e-5);
+        for (int k = lane; k < d; k += 64) {
+            const T h = (xr[k] - mean) * rs;
+            xh[r * d + k] = h;
+            y[r * d + k] = h * g[k] + b[k];
+        }
+        if (lane == 0) rstd[r] = rs;
+    }
+}
+
+template <typename T>
+hipError_t launch_ln_save(int64_t R, int d, const T* x, const T* g, const T* b,
+                          T* y, T* xh, T* rstd, hipStream_t st) {
+    if (R <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ln_save<T>), dim3(cap_grid((R + 3) / 4)), dim3(kGT), 0, st,
+                       R, d, x, g, b, y, xh, rstd);
+    return hipGetLastError();
+}
+
+// out = (base ? base : 0) + LN backward of dy: with e = g * dy,
+// dx = rstd * (e - mean(e) - xh * mean(e * xh)).
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_ln_bwd(int64_t R, int d, const T* xh,
+                                                const T* rstd, const T* g,
+                                                const T* dy, const T* base,
+                                                T* out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = kGT / 64;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
+         r += (int64_t)gridDim.x * wpb) {
+        T s1 = 0, s2 = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T e = g[k] * dy[r * d + k];
+            s1 += e;
+            s2 += e * xh[r * d + k];
+        }
+        s1 = wave_sum(s1) / (T)d;
+        s2 = wave_sum(s2) / (T)d;
+        const T rs = rstd[r];
+        for (int k = lane; k < d; k += 64) {
+            const T e = g[k] * dy[r * d + k];
+            const T v = rs * (e - s1 - xh[r * d + k] * s2);
+            out[r * d + k] = base ? base[r * d + k] + v : v;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_ln_bwd(int64_t R, int d, const T* xh, const T* rstd,
+                         const T* g, const T* dy, const T* base, T* out,
+                         hipStream_t st) {
+    if (R <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_ln_bwd<T>), dim3(cap_grid((R + 3) / 4)), dim3(kGT), 0, st,
+                       R, d, xh, rstd, g, dy, base, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- recomputed block pieces
+// x' = x + b_o + sum_h table[h][code_h] (the forward's order), and the
+// quantized vector z = concat_h codebook[h][code_h].
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_xprime(int64_t R, ModelDims m,
+                                                const T* x, const int32_t* codes,
+                                                const T* table, const T* b_o,
+                                                const T* codebook, T* xp, T* z) {
+    const int d = m.d;
+    const int64_t total = R * d;
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kGT) {
+        const int64_t r = e / d;
+        const int k = (int)(e - r * d);
+        const int32_t* cd = codes + r * m.H;
+        T zz = b_o[k];
+        for (int h = 0; h < m.H; ++h)
+            zz += table[((int64_t)h * m.Q + cd[h]) * d + k];
+        xp[e] = x[e] + zz;
+        const int h = k / m.dseg;
+        z[e] = codebook[((int64_t)h * m.Q + cd[h]) * m.dseg + (k - h * m.dseg)];
+    }
+}
+
+template <typename T>
+hipError_t launch_xprime(int64_t R, const ModelDims& m, const T* x,
+                         const int32_t* codes, const T* table, const T* b_o,
+                         const T* codebook, T* xp, T* z, hipStream_t st) {
+    const int64_t total = R * m.d;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_xprime<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
+                       dim3(kGT), 0, st, R, m, x, codes, table, b_o, codebook, xp, z);
+    return hipGetLastError();
+}
+
+// u += b1 (in place), g = GELU(u) with the exact erf form.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_bias_gelu(int64_t R, int F, T* u,
+                                                   const T* b1, T* g) {
+    const int64_t total = R * F;
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kGT) {
+        const T v = u[e] + b1[e % F];
+        u[e] = v;
+        g[e] = gelu_exact(v);
+    }
+}
+
+template <typename T>
+hipError_t launch_bias_gelu(int64_t R, int F, T* u, const T* b1, T* g,
+                            hipStream_t st) {
+    const int64_t total = R * F;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_bias_gelu<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
+                       dim3(kGT), 0, st, R, F, u, b1, g);
+    return hipGetLastError();
+}
+
+// dg *= GELU'(u) = Phi(u) + u phi(u).
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_gelu_bwd(int64_t n, const T* u, T* dg) {
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kGT) {
+        const T x = u[e];
+        const T cdf = (T)0.5 * ((T)1 + derf(x * (T)0.70710678118654752440));
+        const T pdf = dexp((T)-0.5 * x * x) * (T)0.39894228040143267794;
+        dg[e] *= cdf + x * pdf;
+    }
+}
+
+template <typename T>
+hipError_t launch_gelu_bwd(int64_t n, const T* u, T* dg, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gelu_bwd<T>), dim3(cap_grid((n + kGT - 1) / kGT)), dim3(kGT),
+                       0, st, n, u, dg);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- head
+// One wave per row: f = LNf(x), logits = f W_head + b_head, target y from
+// the spin; dlogit_c = coef * ([c == y] - softmax_c); df = W_head dlogit;
+// dx = LN backward of df.  Keeps f, xh, rstd, dlogit, df for the parameter
+// gradients.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_head_bwd(int64_t n, int N, int d,
+                                                  HeadW<T> hw,
+                                                  const int8_t* spins,
+                                                  const T* x, const T* coef,
+                                                  T* f, T* xh, T* rstd, T* dz,
+                                                  T* df, T* dx) {
+    const int lane = threadIdx.x & 63;
+    const int64_t R = n * N, wpb = kGT / 64;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
+         r += (int64_t)gridDim.x * wpb) {
+        const T* xr = x + r * d;
+        T s = 0;
+        for (int k = lane; k < d; k += 64) s += xr[k];
+        const T mean = wave_sum(s) / (T)d;
+        T v = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T t = xr[k] - mean;
+            v += t * t;
+        }
+        v = wave_sum(v) / (T)d;
+        const T rs = (T)1 / dsqrt(v + (T)1e-5);
+        T z0 = 0, z1 = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T h = (xr[k] - mean) * rs;
+            const T fk = h * hw.lnf_g[k] + hw.lnf_b[k];
+            xh[r * d + k] = h;
+            f[r * d + k] = fk;
+            z0 += fk * hw.W_head[2 * k];
+            z1 += fk * hw.W_head[2 * k + 1];
+        }
+        z0 = wave_sum(z0) + hw.b_head[0];
+        z1 = wave_sum(z1) + hw.b_head[1];
+        const T mx = z0 > z1 ? z0 : z1;
+        const T e0 = dexp(z0 - mx), e1 = dexp(z1 - mx);
+        const T p0 = e0 / (e0 + e1), p1 = e1 / (e0 + e1);
+        const int y = spins[r] < 0 ? 1 : 0;
+        const T c = coef[r / N];
+        const T g0 = c * ((y == 0 ? (T)1 : (T)0) - p0);
+        const T g1 = c * ((y == 1 ? (T)1 : (T)0) - p1);
+        if (lane == 0) {
+            dz[2 * r] = g0;
+            dz[2 * r + 1] = g1;
+            rstd[r] = rs;
+        }
+        T s1 = 0, s2 = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T dfk = g0 * hw.W_head[2 * k] + g1 * hw.W_head[2 * k + 1];
+            df[r * d + k] = dfk;
+            const T e = hw.lnf_g[k] * dfk;
+            s1 += e;
+            s2 += e * xh[r * d + k];
+        }
+        s1 = wave_sum(s1) / (T)d;
+        s2 = wave_sum(s2) / (T)d;
+        for (int k = lane; k < d; k += 64) {
+            const T e = hw.lnf_g[k] * df[r * d + k];
+            dx[r * d + k] = rs * (e - s1 - xh[r * d + k] * s2);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_head_bwd(int64_t n, int N, int d, const HeadW<T>& hw,
+                           const int8_t* spins, const T* x, const T* coef, T* f,
+                           T* xh, T* rstd, T* dz, T* df, T* dx, hipStream_t st) {
+    const int64_t R = n * N;
+    if (R <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_head_bwd<T>), dim3(cap_grid((R + 3) / 4)), dim3(kGT), 0,
+                       st, n, N, d, hw, spins, x, coef, f, xh, rstd, dz, df, dx);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- embedding
+// x0_i = tok[u_i] + pos[i] with u_0 = BOS (2), u_i = token of spin i-1.
+// Per sample s: dpos = dx0, dtok[t] = sum over positions with input t.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_embed_bwd(int64_t n, int N, int d,
+                                                   const int8_t* spins,
+                                                   const T* dx, T* grad,
+                                                   int64_t P, int64_t tok_off,
+                                                   int64_t pos_off) {
+    const int64_t total = n * d;
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kGT) {
+        const int64_t s = e / d;
+        const int c = (int)(e - s * d);
+        T t0 = 0, t1 = 0, t2 = 0;
+        T* g = grad + s * P;
+        for (int i = 0; i < N; ++i) {
+            const T v = dx[(s * N + i) * d + c];
+            g[pos_off + (int64_t)i * d + c] = v;
+            if (i == 0) t2 += v;
+            else if (spins[s * N + i - 1] < 0) t1 += v;
+            else t0 += v;
+        }
+        g[tok_off + c] = t0;
+        g[tok_off + d + c] = t1;
+        g[tok_off + 2 * d + c] = t2;
+    }
+}
+
+template <typename T>
+hipError_t launch_embed_bwd(int64_t n, int N, int d, const int8_t* spins,
+                            const T* dx, T* grad, int64_t P, int64_t tok_off,
+                            int64_t pos_off, hipStream_t st) {
+    const int64_t total = n * d;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_embed_bwd<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
+                       dim3(kGT), 0, st, n, N, d, spins, dx, grad, P, tok_off,
+                       pos_off);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- quantizer
+// One wave per row, quantizer head h: S holds a_h . W_j and E holds
+// g_h . W_j on entry; on exit S holds G_j = t_j / delta_j and E holds
+// p_j + [j == code]; rowG[r] = sum_j G_j.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_vq_bwd_rows(int64_t R, int Q, int dseg,
+                                                     int H, int h, const T* a,
+                                                     int lda,
+                                                     const int32_t* codes,
+                                                     const T* w2, T* S, T* E,
+                                                     T* rowG) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = kGT / 64;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
+         r += (int64_t)gridDim.x * wpb) {
+        const T* ar = a + r * lda;
+        T a2 = 0;
+        for (int c = lane; c < dseg; c += 64) a2 += ar[c] * ar[c];
+        a2 = wave_sum(a2);
+        T* Sr = S + r * Q;
+        T* Er = E + r * Q;
+        // distances (kept in S) and their minimum
+        T dmin = -neg_inf<T>();
+        for (int j = lane; j < Q; j += 64) {
+            T q2 = a2 - (T)2 * Sr[j] + w2[j];
+            q2 = q2 > (T)0 ? q2 : (T)0;
+            const T dl = dsqrt(q2);
+            Sr[j] = dl;
+            dmin = dl < dmin ? dl : dmin;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const T other = __shfl_xor(dmin, o, 64);
+            dmin = other < dmin ? other : dmin;
+        }
+        T l = 0, pe = 0;
+        for (int j = lane; j < Q; j += 64) {
+            const T pt = dexp(dmin - Sr[j]);
+            l += pt;
+            pe += pt * Er[j];
+        }
+        l = wave_sum(l);
+        pe = wave_sum(pe) / l;
+        const int code = codes[r * H + h];
+        T gs = 0;
+        for (int j = lane; j < Q; j += 64) {
+            const T dl = Sr[j];
+            const T p = dexp(dmin - dl) / l;
+            const T t = p * (Er[j] - pe);
+            const T G = dl > (T)0 ? t / dl : (T)0;
+            Sr[j] = G;
+            Er[j] = p + (j == code ? (T)1 : (T)0);
+            gs += G;
+        }
+        gs = wave_sum(gs);
+        if (lane == 0) rowG[r] = gs;
+    }
+}
+
+template <typename T>
+hipError_t launch_vq_bwd_rows(int64_t R, int Q, int dseg, int H, int h,
+                              const T* a, int lda, const int32_t* codes,
+                              const T* w2, T* S, T* E, T* rowG, hipStream_t st) {
+    if (R <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_vq_bwd_rows<T>), dim3(cap_grid((R + 3) / 4)), dim3(kGT), 0,
+                       st, R, Q, dseg, H, h, a, lda, codes, w2, S, E, rowG);
+    return hipGetLastError();
+}
+
+// da[r][c] -= rowG[r] * a[r][c] over the columns of one quantizer head.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_da_fix(int64_t R, int dseg, int ld,
+                                                const T* a, const T* rowG,
+                                                T* da) {
+    const int64_t total = R * dseg;
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kGT) {
+        const int64_t r = e / dseg;
+        const int c = (int)(e - r * dseg);
+        da[r * ld + c] -= rowG[r] * a[r * ld + c];
+    }
+}
+
+template <typename T>
+hipError_t launch_da_fix(int64_t R, int dseg, int ld, const T* a,
+                         const T* rowG, T* da, hipStream_t st) {
+    const int64_t total = R * dseg;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_da_fix<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
+                       dim3(kGT), 0, st, R, dseg, ld, a, rowG, da);
+    return hipGetLastError();
+}
+
+// dcb[g][j][c] -= colG[g][j] * cb[j][c] (per sample g; dcb stride P).
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_cb_fix(int64_t n, int Q, int dseg,
+                                                const T* colG, const T* cb,
+                                                T* dcb, int64_t P) {
+    const int64_t per = (int64_t)Q * dseg, total = n * per;
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kGT) {
+        const int64_t g = e / per;
+        const int64_t jc = e - g * per;
+        const int j = (int)(jc / dseg);
+        dcb[g * P + jc] -= colG[g * Q + j] * cb[jc];
+    }
+}
+
+template <typename T>
+hipError_t launch_cb_fix(int64_t n, int Q, int dseg, const T* colG, const T* cb,
+                         T* dcb, int64_t P, hipStream_t st) {
+    const int64_t total = n * (int64_t)Q * dseg;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_cb_fix<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
+                       dim3(kGT), 0, st, n, Q, dseg, colG, cb, dcb, P);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- attention
+// One workgroup per (sample, head).  Scores s_ij = q_i . k_j / sqrt(d_head)
+// for j <= i; P = softmax_j(s).  lse_i = log sum_j exp(s_ij), and
+// Dd_i = dO_i . O_i (O = the forward attention output).
+template <typename T, int DH>
+__global__ void __launch_bounds__(kGT) k_attn_stats(int64_t n, ModelDims m,
+                                                    const T* q, const T* k,
+                                                    const T* o, const T* dO,
+                                                    T* lse, T* Dd) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Ks = reinterpret_cast<T*>(smem_raw);
+    const int N = m.N, d = m.d, nh = m.nh;
+    const T scale = (T)1 / dsqrt((T)DH);
+    for (int64_t u = blockIdx.x; u < n * nh; u += gridDim.x) {
+        const int64_t s = u / nh;
+        const int h = (int)(u - s * nh);
+        const int64_t base = s * N * d + h * DH;
+        __syncthreads();
+        for (int e = threadIdx.x; e < N * DH; e += kGT)
+            Ks[e] = k[base + (int64_t)(e / DH) * d + e % DH];
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += kGT) {
+            T qi[DH];
+            T dd = 0;
+#pragma unroll
+            for (int c = 0; c < DH; ++c) {
+                qi[c] = q[base + (int64_t)i * d + c];
+                dd += dO[base + (int64_t)i * d + c] * o[base + (int64_t)i * d + c];
+            }
+            T mx = neg_inf<T>(), l = 0;
+            for (int j = 0; j <= i; ++j) {
+                T sc = 0;
+#pragma unroll
+                for (int c = 0; c < DH; ++c) sc += qi[c] * Ks[j * DH + c];
+                sc *= scale;
+                if (sc > mx) {
+                    l = l * dexp(mx - sc) + (T)1;
+                    mx = sc;
+                } else {
+                    l += dexp(sc - mx);
+                }
+            }
+            lse[(s * N + i) * nh + h] = mx + dlog(l);
+            Dd[(s * N + i) * nh + h] = dd;
+        }
+    }
+}
+
+// dq_i = scale * sum_{j <= i} dS_ij k_j with dS_ij = P_ij (dO_i . v_j - Dd_i).
+template <typename T, int DH>
+__global__ void __launch_bounds__(kGT) k_attn_bwd_q(int64_t n, ModelDims m,
+                                                    const T* q, const T* k,
+                                                    const T* v, const T* dO,
+                                                    const T* lse, const T* Dd,
+                                                    T* dqkv) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Ks = reinterpret_cast<T*>(smem_raw);
+    T* Vs = Ks + m.N * DH;
+    const int N = m.N, d = m.d, nh = m.nh;
+    const T scale = (T)1 / dsqrt((T)DH);
+    for (int64_t u = blockIdx.x; u < n * nh; u += gridDim.x) {
+        const int64_t s = u / nh;
+        const int h = (int)(u - s * nh);
+        const int64_t base = s * N * d + h * DH;
+        __syncthreads();
+        for (int e = threadIdx.x; e < N * DH; e += kGT) {
+            const int64_t o = base + (int64_t)(e / DH) * d + e % DH;
+            Ks[e] = k[o];
+            Vs[e] = v[o];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += kGT) {
+            T qi[DH], gi[DH], acc[DH];
+#pragma unroll
+            for (int c = 0; c < DH; ++c) {
+                qi[c] = q[base + (int64_t)i * d + c];
+                gi[c] = dO[base + (int64_t)i * d + c];
+                acc[c] = 0;
+            }
+            const T ls = lse[(s * N + i) * nh + h], dd = Dd[(s * N + i) * nh + h];
+            for (int j = 0; j <= i; ++j) {
+                T sc = 0, dp = 0;
+#pragma unroll
+                for (int c = 0; c < DH; ++c) {
+                    sc += qi[c] * Ks[j * DH + c];
+                    dp += gi[c] * Vs[j * DH + c];
+                }
+                const T p = dexp(sc * scale - ls);
+                const T ds = p * (dp - dd);
+#pragma unroll
+                for (int c = 0; c < DH; ++c) acc[c] += ds * Ks[j * DH + c];
+            }
+            T* out = dqkv + (s * N + i) * 3 * d + h * DH;
+#pragma unroll
+            for (int c = 0; c < DH; ++c) out[c] = acc[c] * scale;
+        }
+    }
+}
+
+// dk_j = scale * sum_{i >= j} dS_ij q_i,  dv_j = sum_{i >= j} P_ij dO_i.
+template <typename T, int DH>
+__global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
+                                                     const T* q, const T* k,
+                                                     const T* v, const T* dO,
+                                                     const T* lse, const T* Dd,
+                                                     T* dqkv) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Qs = reinterpret_cast<T*>(smem_raw);
+    T* Gs = Qs + m.N * DH;
+    T* Ls = Gs + m.N * DH;
+    T* Ds = Ls + m.N;
+    const int N = m.N, d = m.d, nh = m.nh;
+    const T scale = (T)1 / dsqrt((T)DH);
+    for (int64_t u = blockIdx.x; u < n * nh; u += gridDim.x) {
+        const int64_t s = u / nh;
+        const int h = (int)(u - s * nh);
+        const int64_t base = s * N * d + h * DH;
+        __syncthreads();
+        for (int e = threadIdx.x; e < N * DH; e += kGT) {
+            const int64_t o = base + (int64_t)(e / DH) * d + e % DH;
+            Qs[e] = q[o];
+            Gs[e] = dO[o];
+        }
+        for (int i = threadIdx.x; i < N; i += kGT) {
+            Ls[i] = lse[(s * N + i) * nh + h];
+            Ds[i] = Dd[(s * N + i) * nh + h];
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < N; j += kGT) {
+            T kj[DH], vj[DH], dk[DH], dv[DH];
+#pragma unroll
+            for (int c = 0; c < DH; ++c) {
+                kj[c] = k[base + (int64_t)j * d + c];
+                vj[c] = v[base + (int64_t)j * d + c];
+                dk[c] = 0;
+                dv[c] = 0;
+            }
+            for (int i = j; i < N; ++i) {
+                T sc = 0, dp = 0;
+#pragma unroll
+                for (int c = 0; c < DH; ++c) {
+                    sc += Qs[i * DH + c] * kj[c];
+                    dp += Gs[i * DH + c] * vj[c];
+                }
+                const T p = dexp(sc * scale - Ls[i]);
+                const T ds = p * (dp - Ds[i]);
+#pragma unroll
+                for (int c = 0; c < DH; ++c) {
+                    dv[c] += p * Gs[i * DH + c];
+                    dk[c] += ds * Qs[i * DH + c];
+                }
+            }
+            T* out = dqkv + (s * N + j) * 3 * d + h * DH;
+#pragma unroll
+            for (int c = 0; c < DH; ++c) {
+                out[d + c] = dk[c] * scale;
+                out[2 * d + c] = dv[c];
+            }
+        }
+    }
+}
+
+// Kernels whose dynamic LDS exceeds 64 KiB must opt in before launch.
+template <typename F>
+static hipError_t lds_attr(F f, size_t sm) {
+    if (sm > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)sm);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, int DH>
+static hipError_t attn_bwd_dh(int64_t n, const ModelDims& m, const T* q,
+                              const T* k, const T* v, const T* o, const T* dO,
+                              T* lse, T* Dd, T* dqkv, hipStream_t st) {
+    const unsigned g = cap_grid(n * m.nh);
+    const size_t s1 = sizeof(T) * (size_t)m.N * DH;
+    const size_t s2 = 2 * s1;
+    const size_t s3 = 2 * s1 + 2 * sizeof(T) * (size_t)m.N;
+    hipError_t e;
+    if ((e = lds_attr(k_attn_stats<T, DH>, s1))) return e;
+    hipLaunchKernelGGL((k_attn_stats<T, DH>), dim3(g), dim3(kGT), s1, st, n, m, q, k,
+                       o, dO, lse, Dd);
+    if ((e = hipGetLastError())) return e;
+    if ((e = lds_attr(k_attn_bwd_q<T, DH>, s2))) return e;
+    hipLaunchKernelGGL((k_attn_bwd_q<T, DH>), dim3(g), dim3(kGT), s2, st, n, m, q, k,
+                       v, dO, lse, Dd, dqkv);
+    if ((e = hipGetLastError())) return e;
+    if ((e = lds_attr(k_attn_bwd_kv<T, DH>, s3))) return e;
+    hipLaunchKernelGGL((k_attn_bwd_kv<T, DH>), dim3(g), dim3(kGT), s3, st, n, m, q, k,
+                       v, dO, lse, Dd, dqkv);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_attn_bwd(int64_t n, const ModelDims& m, const T* q,
+                           const T* k, const T* v, const T* o, const T* dO,
+                           T* lse, T* Dd, T* dqkv, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    switch (m.dh) {
+        case 4: return attn_bwd_dh<T, 4>(n, m, q, k, v, o, dO, lse, Dd, dqkv, st);
+        case 8: return attn_bwd_dh<T, 8>(n, m, q, k, v, o, dO, lse, Dd, dqkv, st);
+        case 16: return attn_bwd_dh<T, 16>(n, m, q, k, v, o, dO, lse, Dd, dqkv, st);
+        case 32: return attn_bwd_dh<T, 32>(n, m, q, k, v, o, dO, lse, Dd, dqkv, st);
+        case 64: return attn_bwd_dh<T, 64>(n, m, q, k, v, o, dO, lse, Dd, dqkv, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------- instantiations
+#define VQ_GRAD_INST(T)                                                          \
+    template hipError_t launch_gemm<T>(const GemmDesc&, hipStream_t);           \
+    template hipError_t launch_colsum<T>(int64_t, int64_t, int, const T*,       \
+                                         int64_t, const T*, int64_t, T*,        \
+                                         int64_t, int, hipStream_t);            \
+    template hipError_t launch_reduce_samples<T>(int64_t, int64_t, const T*,    \
+                                                 T*, int, hipStream_t);         \
+    template hipError_t launch_coef<T>(int64_t, const double*, T*, hipStream_t); \
+    template hipError_t launch_fill_t<T>(T*, int64_t, T, hipStream_t);          \
+    template hipError_t launch_ln_save<T>(int64_t, int, const T*, const T*,     \
+                                          const T*, T*, T*, T*, hipStream_t);   \
+    template hipError_t launch_ln_bwd<T>(int64_t, int, const T*, const T*,      \
+                                         const T*, const T*, const T*, T*,      \
+                                         hipStream_t);                          \
+    template hipError_t launch_xprime<T>(int64_t, const ModelDims&, const T*,   \
+                                         const int32_t*, const T*, const T*,    \
+                                         const T*, T*, T*, hipStream_t);        \
+    template hipError_t launch_bias_gelu<T>(int64_t, int, T*, const T*, T*,     \
+                                            hipStream_t);                       \
+    template hipError_t launch_gelu_bwd<T>(int64_t, const T*, T*, hipStream_t); \
+    template hipError_t launch_head_bwd<T>(int64_t, int, int, const HeadW<T>&,  \
+                                           const int8_t*, const T*, const T*,   \
+                                           T*, T*, T*, T*, T*, T*, hipStream_t); \
+    template hipError_t launch_embed_bwd<T>(int64_t, int, int, const int8_t*,   \
+                                            const T*, T*, int64_t, int64_t,     \
+                                            int64_t, hipStream_t);              \
+    template hipError_t launch_vq_bwd_rows<T>(int64_t, int, int, int, int,      \
+                                              const T*, int, const int32_t*,    \
+                                              const T*, T*, T*, T*,             \
+                                              hipStream_t);                     \
+    template hipError_t launch_da_fix<T>(int64_t, int, int, const T*, const T*, \
+                                         T*, hipStream_t);                      \
+    template hipError_t launch_cb_fix<T>(int64_t, int, int, const T*, const T*, \
+                                         T*, int64_t, hipStream_t);             \
+    template hipError_t launch_attn_bwd<T>(int64_t, const ModelDims&, const T*, \
+                                           const T*, const T*, const T*,        \
+                                           const T*, T*, T*, T*, hipStream_t);
+
+VQ_GRAD_INST(double)
+VQ_GRAD_INST(float)
+
+}  // namespace vq

@@ -1,0 +1,154 @@
+"""GPU parity of the straight-through gradient of log psi (eqs. 7-8)
+against the FP64 oracle, through the C ABI.
+
+FP64: per-sample and weighted gradients within 1e-9 of the largest entry
+(the two sides add in different orders; distances are expanded on the GPU
+and taken directly in the oracle).  FP32: within 1e-4 in norm.  BF16 at the
+20x20 shapes (d=256, 12 layers, Q=1024): the forward decides codes in its
+own precision; on samples whose codes all equal the oracle's, the gradient
+must agree within 2e-3 in norm; samples with a differing code must show a
+valid near-tie there (checked like the forward's codes)."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2212_11296_amd as vq
+from oracle import grad as og
+from oracle import network as net
+from workloads import CONFIGS, make_params, make_spins, with_batch
+
+from gpu_common import dev_params, dev_spins, host, needs_gpu, say
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+TWO_VQ = replace(CONFIGS["small"], name="two_vq", L=4, d_model=8,
+                 n_layers=2, n_heads=2, d_ff=16, codebook_size=6, vq_heads=2,
+                 batch=3, spin_seed=1701)
+
+
+def rel_max(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def rel_norm(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("mc", [with_batch(CONFIGS["small"], 4), TWO_VQ,
+                                with_batch(CONFIGS["medium"], 2,
+                                           precision="f64")],
+                         ids=["small", "two_vq", "medium"])
+def test_grad_f64_per_sample_and_weighted(mc):
+    say(f"grad f64 {mc.name} B={mc.batch}")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "f64"), dev_spins(s)
+    g, lp = vq.grad_logpsi(cfg, p, sp, logpsi=True)
+    ref = og.grad_logpsi(mc, theta, s)
+    assert rel_max(host(g), ref) < 1e-9
+    ref_lp = net.forward(mc, net.unpack(mc, theta), s)["logpsi"]
+    assert np.allclose(host(lp), ref_lp, rtol=1e-12, atol=1e-12)
+    w = np.linspace(-1.0, 2.0, mc.batch)
+    gw = vq.grad_logpsi(cfg, p, sp, weights=torch.tensor(w, device="cuda"))
+    assert rel_max(host(gw), w @ ref) < 1e-9
+
+
+def test_grad_f32_medium():
+    mc = with_batch(CONFIGS["medium"], 2)
+    say("grad f32 medium")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    g = vq.grad_logpsi(vq.make_config(mc), dev_params(theta, "f32"),
+                       dev_spins(s))
+    ref = og.grad_logpsi(mc, theta, s)
+    G = host(g).astype(np.float64)
+    for b in range(mc.batch):
+        assert rel_norm(G[b], ref[b]) < 1e-4
+
+
+def _codes_match_or_near_tie(mc, theta, s, gpu_codes):
+    """True where every code equals the oracle's; asserts that a sample with
+    a differing code has a valid near-tie at its first differing layer."""
+    ref = net.forward(mc, net.unpack(mc, theta), s, keep=True)
+    oc = np.transpose(ref["codes"], (1, 0, 2, 3))          # [B][nl][N][H]
+    same = []
+    for b in range(s.shape[0]):
+        diff = gpu_codes[b] != oc[b]
+        if not diff.any():
+            same.append(True)
+            continue
+        l = int(np.nonzero(diff.any(axis=(1, 2)))[0][0])
+        rows, heads = np.nonzero(diff[l])
+        c = ref["caches"][l]
+        gap = c["d2"][b, rows, heads] - c["d1"][b, rows, heads]
+        assert (gap < 1e-3 * (1 + c["d1"][b, rows, heads])).all(), (b, l)
+        same.append(False)
+    return np.array(same)
+
+
+def test_grad_bf16_grad_shapes_sampled():
+    """The 20x20 gradient workload's model (d=256, 12 layers, 8 heads, MLP
+    1024, Q=1024) on a few seeded samples, recomputed one by one by the
+    oracle."""
+    mc = with_batch(CONFIGS["grad"], 6)
+    say("grad bf16 20x20 sampled")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    g = host(vq.grad_logpsi(cfg, p, sp)).astype(np.float64)
+    _, codes = vq.forward_logpsi(cfg, p, sp, codes=True)
+    same = _codes_match_or_near_tie(mc, theta, s, host(codes))
+    idx = np.nonzero(same)[0][:2]
+    assert len(idx) >= 1
+    ref = og.grad_logpsi(mc, theta, s[idx])
+    for j, b in enumerate(idx):
+        assert rel_norm(g[b], ref[j]) < 2e-3, b
+
+
+def test_grad_autograd_function_matches_weighted():
+    mc = with_batch(CONFIGS["small"], 5)
+    say("grad autograd function")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p = dev_params(theta, "f64").requires_grad_(True)
+    w = torch.linspace(0.5, -1.5, mc.batch, dtype=torch.float64, device="cuda")
+    (w * vq.logpsi(cfg, p, dev_spins(s))).sum().backward()
+    gw = vq.grad_logpsi(cfg, p.detach(), dev_spins(s), weights=w)
+    assert np.array_equal(host(p.grad), host(gw))
+
+
+def test_grad_chunking_and_repeat_bitwise():
+    mc = with_batch(CONFIGS["small"], 7)
+    say("grad chunking")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "f64"), dev_spins(s)
+    w = torch.linspace(-1.0, 1.0, mc.batch, dtype=torch.float64, device="cuda")
+    full = host(vq.grad_logpsi(cfg, p, sp, weights=w))
+    again = host(vq.grad_logpsi(cfg, p, sp, weights=w))
+    small = torch.empty(vq.workspace_size(cfg, mc.batch, vq.WS_GRAD, 3),
+                        dtype=torch.uint8, device="cuda")
+    chunked = host(vq.grad_logpsi(cfg, p, sp, weights=w, ws=small))
+    assert np.array_equal(full, again)
+    assert np.array_equal(full, chunked)
+    per = host(vq.grad_logpsi(cfg, p, sp))
+    per_c = host(vq.grad_logpsi(cfg, p, sp, ws=small))
+    assert np.array_equal(per, per_c)
+
+
+def test_grad_empty_batch_weighted_is_zero():
+    mc = CONFIGS["small"]
+    cfg = vq.make_config(mc)
+    theta = make_params(mc)
+    p = dev_params(theta, "f64")
+    sp = torch.empty((0, mc.N), dtype=torch.int8, device="cuda")
+    g = vq.grad_logpsi(cfg, p, sp, weights=torch.empty(0, dtype=torch.float64,
+                                                       device="cuda"))
+    assert g.shape == (p.numel(),)
+    assert not host(g).any()
