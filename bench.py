@@ -232,15 +232,99 @@ def bench_grad(args, vq, torch, np, mc, make_params, make_spins):
     print(json.dumps(res))
 
 
+def bench_multi(args, vq, torch, np, make_params, make_spins):
+    """Mixed-lattice batch (6x6 .. 20x20, one model each, 512 .. 8192
+    samples): one vqnqs_local_energy_multi call per step, replayed as a
+    captured graph, against one vqnqs_local_energy call per lattice."""
+    from workloads import MULTI_LATTICE
+    dev = torch.device("cuda:0")
+    jobs = []
+    for mc in MULTI_LATTICE:
+        jobs.append((vq.make_config(mc),
+                     torch.tensor(make_params(mc), dtype=torch.float32,
+                                  device=dev),
+                     torch.tensor(make_spins(mc), device=dev)))
+    total = sum(int(s.shape[0]) for _, _, s in jobs)
+    need = vq.workspace_size_multi(jobs)
+    ws = torch.empty(min(need, int(args.ws_gb * (1 << 30))),
+                     dtype=torch.uint8, device=dev)
+    # launch choices for this model width, tuned on the 16x16 lattice
+    cfg16, p16, s16 = jobs[3]
+    tune_ws = torch.empty(vq.workspace_size(cfg16, 512, vq.DEDUP, 0)
+                          + 8 * 512 + 256, dtype=torch.uint8, device=dev)
+    choices = vq.autotune(cfg16, p16, s16[:512], ws=tune_ws)
+    del tune_ws
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    flags = vq.MULTI_CONCURRENT | vq.MULTI_GRAPH
+    outs = vq.local_energy_multi(jobs, flags=flags, ws=ws, check=False)
+    for _ in range(args.warmup):
+        vq.local_energy_multi(jobs, flags=flags, ws=ws, outs=outs, check=False)
+    torch.cuda.synchronize()
+    times = []
+    e_all0, e_all1 = ev(), ev()
+    e_all0.record(stream)
+    for _ in range(args.steps):
+        a, b = ev(), ev()
+        a.record(stream)
+        vq.local_energy_multi(jobs, flags=flags, ws=ws, outs=outs, check=False)
+        b.record(stream)
+        times.append((a, b))
+    e_all1.record(stream)
+    torch.cuda.synchronize()
+    vq.api._check_status(ws)
+    ms = e_all0.elapsed_time(e_all1) / args.steps
+    lat = sorted(a.elapsed_time(b) for a, b in times)
+    pct = lambda q: lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+    # the same lattices one call at a time on one stream
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    per = []
+    for cfg, p, s in jobs:
+        a, b = ev(), ev()
+        a.record(stream)
+        vq.local_energy(cfg, p, s, vq.DEDUP, ws=ws, check=False)
+        b.record(stream)
+        per.append((a, b))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    res = {
+        "metric": "local-energy evals/sec, mixed-lattice batch (6x6..20x20) "
+                  "in one graph-replayed multi-lattice call, 1 MI355X",
+        "value": total / (ms / 1000.0), "unit": "local-energy evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "lattices 6x6/8x8/12x12/16x16/20x20 with "
+                               "512/1024/2048/4096/8192 seeded Sz=0 samples, "
+                               "one VQ transformer each (d=128, 6 layers, "
+                               "8 heads, MLP 512, Q=512), dedup local energy",
+                   "samples": total, "flags": flags},
+        "latency_ms": {"p50": pct(0.5), "p99": pct(0.99), "all": lat},
+        "sequential_single_calls": {
+            "value": total / (ms_seq / 1000.0), "ms": ms_seq,
+            "per_lattice_ms": {f"{cfg.L}x{cfg.L}": a.elapsed_time(b)
+                               for (cfg, _, _), (a, b) in zip(jobs, per)}},
+        "speedup_vs_sequential": ms_seq / ms,
+        "tuning": {"qkv_mb": choices[0], "mlp_mb": choices[1],
+                   "vq_mb": choices[2]},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="large")
-    ap.add_argument("--workload", default="eloc", choices=["eloc", "grad"],
+    ap.add_argument("--workload", default="eloc",
+                    choices=["eloc", "grad", "multi"],
                     help="eloc: local energy (default); grad: weighted "
-                         "straight-through gradient of the 20x20 workload")
+                         "straight-through gradient of the 20x20 workload; "
+                         "multi: mixed-lattice batch in one call")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--flags", type=int, default=0,
@@ -268,6 +352,9 @@ def main():
     import paper_2212_11296_amd as vq
     from workloads import config_by_name, make_params, make_spins, with_batch
 
+    if args.workload == "multi":
+        bench_multi(args, vq, torch, np, make_params, make_spins)
+        return
     if args.workload == "grad":
         mc = config_by_name("grad")
         if args.batch:

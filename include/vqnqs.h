@@ -198,6 +198,66 @@ vqnqs_status vqnqs_grad_logpsi(const vqnqs_config* cfg, const void* params,
                                double* logpsi, void* ws, size_t ws_bytes,
                                void* stream);
 
+/* One lattice of a multi-lattice batch: its own model, parameters and
+ * samples, with the outputs of vqnqs_local_energy (same meanings). */
+typedef struct {
+    vqnqs_config cfg;
+    const void* params;     /* DEVICE, flat parameters of this model        */
+    const int8_t* spins;    /* DEVICE [batch][N]                            */
+    int64_t batch;
+    double* eloc;           /* DEVICE out [batch]                           */
+    double* stats;          /* DEVICE out [2], nullable                     */
+    double* ratios;         /* DEVICE out [batch][2N], nullable             */
+    int64_t* counters;      /* DEVICE out [VQNQS_NCOUNTERS], nullable       */
+} vqnqs_job;
+
+/* flags of vqnqs_local_energy_multi */
+#define VQNQS_MULTI_CONCURRENT 1   /* each job on its own internal stream   */
+#define VQNQS_MULTI_GRAPH 2        /* capture once, replay as a HIP graph   */
+
+/* Workspace for vqnqs_local_energy_multi to hold every job's whole batch;
+ * any smaller workspace that holds every job's one-sample minimum also
+ * works (the jobs are then chunked). */
+vqnqs_status vqnqs_workspace_size_multi(const vqnqs_job* jobs, int32_t njobs,
+                                        int32_t mode, size_t* bytes);
+
+/* Local energies (eq. 2) of several lattices in one call: the batched
+ * launch of a mixed-lattice sample set.  The workspace is split between
+ * the jobs in proportion to their needs.  With VQNQS_MULTI_CONCURRENT every
+ * job's kernels run on an internal stream (created on first use, default
+ * priority, kept until the process ends) forked from and joined back to
+ * `stream`, so small lattices fill the device beside large ones.  With
+ * VQNQS_MULTI_GRAPH the whole sequence is captured into a HIP graph on the
+ * first call and replayed by later calls with identical arguments (same
+ * pointers, sizes, stream and tuning), one launch in place of thousands;
+ * the graph reads the buffers' current contents at every replay.  The
+ * legacy NULL stream cannot be captured: the call then runs directly.
+ * Results equal those of one vqnqs_local_energy call per job, bit for bit.
+ * Calls that overlap on one device must not share a workspace; the internal
+ * streams are shared, so such calls also serialise. */
+vqnqs_status vqnqs_local_energy_multi(const vqnqs_job* jobs, int32_t njobs,
+                                      int32_t mode, int32_t flags, void* ws,
+                                      size_t ws_bytes, void* stream);
+
+/* Autotuner (measurement, not part of the method): times the rows-per-wave
+ * variants of the BF16 matrix-core products (QKV projection, MLP, codebook
+ * search) with one local-energy evaluation of the given samples per
+ * variant, and keeps the fastest for every later call on a model of this
+ * width (process-wide).  Results never depend on these choices.  The call
+ * synchronises `stream` and clears the totals of vqnqs_profile_*.
+ * Needs the workspace of vqnqs_local_energy plus 8 bytes per sample.
+ *   choices [3] int32 HOST out, nullable: rows per wave / 16 of the QKV,
+ *           MLP and codebook-search kernels now in force */
+vqnqs_status vqnqs_autotune(const vqnqs_config* cfg, const void* params,
+                            const int8_t* spins, int64_t batch, int32_t mode,
+                            void* ws, size_t ws_bytes, void* stream,
+                            int32_t* choices);
+
+/* Sets the rows-per-wave choices (as returned by vqnqs_autotune) for
+ * models of this width; VQNQS_ERR_INVALID_CONFIG for a choice the width
+ * does not allow (1 or 2 below width 256, 1 at 256). */
+vqnqs_status vqnqs_set_tuning(const vqnqs_config* cfg, const int32_t* choices);
+
 /* Reads the device status word of a workspace used by a previous call:
  * synchronises `stream`, then returns VQNQS_OK or VQNQS_ERR_BAD_SPIN. */
 vqnqs_status vqnqs_workspace_status(const void* ws, void* stream);

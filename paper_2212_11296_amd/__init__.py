@@ -10,11 +10,15 @@ from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
                   exported_symbols, param_count, workspace_size, neighbours,
                   forward_logpsi, local_energy, grad_logpsi, logpsi,
                   make_config, profile_enable, profile_reset, profile_read,
-                  WS_FORWARD, WS_GRAD)
+                  WS_FORWARD, WS_GRAD, MULTI_CONCURRENT, MULTI_GRAPH,
+                  local_energy_multi, workspace_size_multi, autotune,
+                  set_tuning)
 
 __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "FLAG_CERTIFIED_VQ", "NCOUNTERS", "CTR", "VQNQSError",
            "library_path", "load_library", "exported_symbols", "param_count",
            "workspace_size", "neighbours", "forward_logpsi", "local_energy",
            "grad_logpsi", "logpsi", "make_config", "profile_enable",
-           "profile_reset", "profile_read", "WS_FORWARD", "WS_GRAD"]
+           "profile_reset", "profile_read", "WS_FORWARD", "WS_GRAD",
+           "MULTI_CONCURRENT", "MULTI_GRAPH", "local_energy_multi",
+           "workspace_size_multi", "autotune", "set_tuning"]

@@ -16,8 +16,11 @@ _STATUS = {0: "ok", 1: "null pointer", 2: "invalid config", 3: "invalid shape",
            6: "spin value other than +1/-1", 7: "HIP runtime error"}
 
 WS_FORWARD, WS_GRAD = -1, -3
+MULTI_CONCURRENT, MULTI_GRAPH = 1, 2
 EXPORTS = ["vqnqs_param_count", "vqnqs_workspace_size", "vqnqs_neighbours",
            "vqnqs_forward_logpsi", "vqnqs_local_energy", "vqnqs_grad_logpsi",
+           "vqnqs_workspace_size_multi", "vqnqs_local_energy_multi",
+           "vqnqs_autotune", "vqnqs_set_tuning",
            "vqnqs_workspace_status", "vqnqs_status_string",
            "vqnqs_profile_enable", "vqnqs_profile_reset", "vqnqs_profile_read"]
 
@@ -35,6 +38,13 @@ class Config(ctypes.Structure):
                 ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
                 ("codebook_size", ctypes.c_int32), ("vq_heads", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("cfg", Config), ("params", ctypes.c_void_p),
+                ("spins", ctypes.c_void_p), ("batch", ctypes.c_int64),
+                ("eloc", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("ratios", ctypes.c_void_p), ("counters", ctypes.c_void_p)]
 
 
 def make_config(mc, precision=None, flags=0):
@@ -80,6 +90,16 @@ def load_library():
     lib.vqnqs_local_energy.restype = ctypes.c_int
     lib.vqnqs_grad_logpsi.argtypes = [C, P, P, I64, P, P, P, P, SZ, P]
     lib.vqnqs_grad_logpsi.restype = ctypes.c_int
+    J = ctypes.POINTER(Job)
+    lib.vqnqs_workspace_size_multi.argtypes = [J, I32, I32, ctypes.POINTER(SZ)]
+    lib.vqnqs_workspace_size_multi.restype = ctypes.c_int
+    lib.vqnqs_local_energy_multi.argtypes = [J, I32, I32, I32, P, SZ, P]
+    lib.vqnqs_local_energy_multi.restype = ctypes.c_int
+    lib.vqnqs_autotune.argtypes = [C, P, P, I64, I32, P, SZ, P,
+                                   ctypes.POINTER(I32)]
+    lib.vqnqs_autotune.restype = ctypes.c_int
+    lib.vqnqs_set_tuning.argtypes = [C, ctypes.POINTER(I32)]
+    lib.vqnqs_set_tuning.restype = ctypes.c_int
     lib.vqnqs_workspace_status.argtypes = [P, P]
     lib.vqnqs_workspace_status.restype = ctypes.c_int
     lib.vqnqs_status_string.argtypes = [ctypes.c_int]
@@ -284,3 +304,81 @@ def _logpsi_function():
 def logpsi(cfg, params, spins):
     """Differentiable log psi [B] (autograd through the HIP backward)."""
     return _logpsi_function().apply(params, spins, cfg)
+
+
+def _jobs_array(jobs, outs):
+    arr = (Job * len(jobs))()
+    for i, ((cfg, params, spins), o) in enumerate(zip(jobs, outs)):
+        arr[i].cfg = cfg
+        arr[i].params = params.data_ptr()
+        arr[i].spins = spins.data_ptr()
+        arr[i].batch = spins.shape[0]
+        arr[i].eloc = o["eloc"].data_ptr()
+        arr[i].stats = o["stats"].data_ptr() if "stats" in o else None
+        arr[i].ratios = o["ratios"].data_ptr() if "ratios" in o else None
+        arr[i].counters = (o["counters"].data_ptr() if "counters" in o
+                           else None)
+    return arr
+
+
+def workspace_size_multi(jobs, mode=DEDUP):
+    """jobs: list of (cfg, params, spins)."""
+    out = ctypes.c_size_t(0)
+    arr = (Job * len(jobs))()
+    for i, (cfg, params, spins) in enumerate(jobs):
+        arr[i].cfg = cfg
+        arr[i].batch = spins.shape[0]
+    _check("vqnqs_workspace_size_multi", load_library().vqnqs_workspace_size_multi(
+        arr, len(jobs), mode, ctypes.byref(out)))
+    return out.value
+
+
+def local_energy_multi(jobs, mode=DEDUP, flags=MULTI_CONCURRENT | MULTI_GRAPH,
+                       ws=None, budget=8 << 30, ratios=False, stats=True,
+                       outs=None, check=True):
+    """Local energies of several lattices in one call.  jobs: list of
+    (cfg, params, spins).  Returns one dict of device outputs per job; pass
+    the same ``outs`` (and ``ws``) back to replay the captured graph."""
+    import torch
+    if outs is None:
+        outs = []
+        for cfg, params, spins in jobs:
+            B, N = spins.shape[0], cfg.L * cfg.L
+            o = {"eloc": torch.empty(B, dtype=torch.float64, device="cuda")}
+            if stats:
+                o["stats"] = torch.empty(2, dtype=torch.float64, device="cuda")
+            if ratios:
+                o["ratios"] = torch.empty((B, 2 * N), dtype=torch.float64,
+                                          device="cuda")
+            outs.append(o)
+    if ws is None:
+        need = workspace_size_multi(jobs, mode)
+        ws = torch.empty(min(need, budget), dtype=torch.uint8, device="cuda")
+    arr = _jobs_array(jobs, outs)
+    _check("vqnqs_local_energy_multi", load_library().vqnqs_local_energy_multi(
+        arr, len(jobs), mode, flags, _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)      # the OR of every job's status word
+    return outs
+
+
+def autotune(cfg, params, spins, mode=DEDUP, ws=None, budget=8 << 30):
+    """Times the matrix-core launch variants on these samples and keeps the
+    fastest for this model width; returns the choices [qkv, mlp, vq]."""
+    import torch
+    B = spins.shape[0]
+    if ws is None:
+        need = workspace_size(cfg, max(B, 1), mode, 0) + 8 * B + 256
+        ws = torch.empty(min(need, budget + 8 * B + 256), dtype=torch.uint8,
+                         device="cuda")
+    ch = (ctypes.c_int32 * 3)()
+    _check("vqnqs_autotune", load_library().vqnqs_autotune(
+        ctypes.byref(cfg), _ptr(params), _ptr(spins), B, mode, _ptr(ws),
+        ws.numel(), _stream(), ch))
+    return list(ch)
+
+
+def set_tuning(cfg, choices):
+    ch = (ctypes.c_int32 * 3)(*choices)
+    _check("vqnqs_set_tuning",
+           load_library().vqnqs_set_tuning(ctypes.byref(cfg), ch))

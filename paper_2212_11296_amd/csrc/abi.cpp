@@ -1,6 +1,7 @@
 // C ABI entry points: argument validation (host only, before any HIP call)
 // and dispatch to the engine.
 #include <cmath>
+#include <vector>
 
 #include "engine.h"
 #include "kernels.h"
@@ -139,6 +140,75 @@ vqnqs_status vqnqs_grad_logpsi(const vqnqs_config* cfg, const void* params,
         return VQNQS_ERR_NULL_POINTER;
     return vq::grad_logpsi(m, params, spins, batch, weights, grad, logpsi, ws,
                            ws_bytes, (hipStream_t)stream);
+}
+
+static vqnqs_status multi_dims(const vqnqs_job* jobs, int32_t njobs,
+                               int32_t mode, std::vector<vq::ModelDims>& ms) {
+    if (!jobs) return VQNQS_ERR_NULL_POINTER;
+    if (njobs < 1 || njobs > 64) return VQNQS_ERR_INVALID_SHAPE;
+    if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP) return VQNQS_ERR_INVALID_CONFIG;
+    ms.resize(njobs);
+    for (int i = 0; i < njobs; ++i) {
+        vqnqs_status e;
+        if (!dims_from(&jobs[i].cfg, &ms[i], &e)) return e;
+        if (jobs[i].batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    }
+    return VQNQS_OK;
+}
+
+vqnqs_status vqnqs_workspace_size_multi(const vqnqs_job* jobs, int32_t njobs,
+                                        int32_t mode, size_t* bytes) {
+    std::vector<vq::ModelDims> ms;
+    vqnqs_status e = multi_dims(jobs, njobs, mode, ms);
+    if (e) return e;
+    if (!bytes) return VQNQS_ERR_NULL_POINTER;
+    *bytes = vq::workspace_bytes_multi(ms.data(), jobs, njobs, mode);
+    return VQNQS_OK;
+}
+
+vqnqs_status vqnqs_local_energy_multi(const vqnqs_job* jobs, int32_t njobs,
+                                      int32_t mode, int32_t flags, void* ws,
+                                      size_t ws_bytes, void* stream) {
+    std::vector<vq::ModelDims> ms;
+    vqnqs_status e = multi_dims(jobs, njobs, mode, ms);
+    if (e) return e;
+    if (flags & ~(VQNQS_MULTI_CONCURRENT | VQNQS_MULTI_GRAPH))
+        return VQNQS_ERR_INVALID_CONFIG;
+    if (!ws) return VQNQS_ERR_NULL_POINTER;
+    for (int i = 0; i < njobs; ++i)
+        if (jobs[i].batch > 0 &&
+            (!jobs[i].params || !jobs[i].spins || !jobs[i].eloc))
+            return VQNQS_ERR_NULL_POINTER;
+    return vq::local_energy_multi(ms.data(), jobs, njobs, mode, flags, ws,
+                                  ws_bytes, (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_autotune(const vqnqs_config* cfg, const void* params,
+                            const int8_t* spins, int64_t batch, int32_t mode,
+                            void* ws, size_t ws_bytes, void* stream,
+                            int32_t* choices) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP) return VQNQS_ERR_INVALID_CONFIG;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (!ws || (batch > 0 && (!params || !spins))) return VQNQS_ERR_NULL_POINTER;
+    return vq::autotune(m, params, spins, batch, mode, ws, ws_bytes,
+                        (hipStream_t)stream, choices);
+}
+
+vqnqs_status vqnqs_set_tuning(const vqnqs_config* cfg, const int32_t* choices) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (!choices) return VQNQS_ERR_NULL_POINTER;
+    vq::Tuning t;
+    t.qkv_mb = choices[0];
+    t.mlp_mb = choices[1];
+    t.vq_mb = choices[2];
+    if (!vq::tuning_valid(m, t)) return VQNQS_ERR_INVALID_CONFIG;
+    vq::tuning_set(m, t);
+    return VQNQS_OK;
 }
 
 vqnqs_status vqnqs_workspace_status(const void* ws, void* stream) {

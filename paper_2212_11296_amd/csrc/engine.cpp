@@ -3,7 +3,11 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "kernels.h"
 #include "profiler.h"
@@ -892,6 +896,297 @@ vqnqs_status neighbours(const ModelDims& m, const int8_t* spins, int64_t batch,
     CK(launch_fill_i32(w.status, 1, 0, st));
     LK("neighbours", launch_neighbours(spins, batch, m, bonds, count, diag, nullptr, w.status,
                          st));
+    return VQNQS_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+// Times the rows-per-wave variants of the three matrix-core products on the
+// caller's inputs (one local-energy evaluation per variant, after a warm-up
+// run) and keeps the fastest, per model width.  Results never depend on
+// these choices; only speed does.
+static double class_ms(const char* cls) {
+    constexpr int kMax = 64, kLen = 48;
+    static char names[kMax * kLen];
+    double ms[kMax];
+    long long cnt[kMax];
+    const int n = std::min(Profiler::get().read(names, kLen, ms, cnt, kMax), kMax);
+    for (int i = 0; i < n; ++i)
+        if (std::strncmp(names + i * kLen, cls, kLen) == 0) return ms[i];
+    return 0.0;
+}
+
+vqnqs_status autotune(const ModelDims& m, const void* params,
+                      const int8_t* spins, int64_t batch, int mode, void* ws,
+                      size_t ws_bytes, hipStream_t st, int32_t* choices) {
+    Tuning best = tuning_get(m);
+    if (m.mfma && batch > 0) {
+        const size_t eb = al256((size_t)batch * sizeof(double));
+        if (ws_bytes <= eb) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
+        double* eloc = reinterpret_cast<double*>(static_cast<char*>(ws) +
+                                                 ws_bytes - eb);
+        const size_t usable = ws_bytes - eb;
+        Profiler& pf = Profiler::get();
+        const bool was_on = pf.enabled();
+        pf.enable(false);
+        auto run = [&]() {
+            return local_energy(m, params, spins, batch, mode, eloc, nullptr,
+                                nullptr, nullptr, ws, usable, st);
+        };
+        vqnqs_status s = run();                    // warm-up
+        if (s) return s;
+        const char* cls[3] = {"qkv", "mlp", "vq"};
+        for (int c = 0; c < 3; ++c) {
+            double best_ms = -1.0;
+            Tuning pick = best;
+            for (int mb = 1; mb <= 2; ++mb) {
+                Tuning t = best;
+                (c == 0 ? t.qkv_mb : c == 1 ? t.mlp_mb : t.vq_mb) = mb;
+                if (!tuning_valid(m, t)) continue;
+                tuning_set(m, t);
+                pf.reset();
+                pf.enable(true);
+                s = run();
+                pf.enable(false);
+                if (s) return s;
+                if (hipStreamSynchronize(st) != hipSuccess) return VQNQS_ERR_HIP;
+                const double ms = class_ms(cls[c]);
+                if (best_ms < 0 || ms < best_ms) {
+                    best_ms = ms;
+                    pick = t;
+                }
+            }
+            best = pick;
+        }
+        tuning_set(m, best);
+        pf.reset();
+        pf.enable(was_on);
+    }
+    if (choices) {
+        choices[0] = best.qkv_mb;
+        choices[1] = best.mlp_mb;
+        choices[2] = best.vq_mb;
+    }
+    return VQNQS_OK;
+}
+
+// ---------------------------------------------------- multi-lattice batch
+// Several lattices (each its own model and parameters) in one call.  Each
+// job's kernel sequence goes to an internal stream forked from the caller's
+// stream, so small lattices run beside large ones, and the whole fork/join
+// sequence is captured once into a HIP graph that later identical calls
+// replay (one launch instead of thousands).
+namespace {
+
+constexpr int kMaxJobStreams = 8;
+constexpr size_t kStatusBytes = 256;   // combined status word of the call
+constexpr size_t kMaxGraphs = 16;
+
+struct Pools {
+    std::mutex mu;
+    std::map<int, std::vector<hipStream_t>> streams;
+    std::map<int, std::vector<hipEvent_t>> events;
+    struct Graph {
+        std::vector<int64_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+};
+
+Pools& pools() {
+    static Pools p;
+    return p;
+}
+
+// Internal streams (default priority, non-blocking) and events of the
+// current device, created on first use and kept until the process ends.
+hipError_t job_streams(int ns, std::vector<hipStream_t>& st,
+                       std::vector<hipEvent_t>& ev) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    Pools& p = pools();
+    std::lock_guard<std::mutex> lk(p.mu);
+    auto& sv = p.streams[dev];
+    while ((int)sv.size() < ns) {
+        hipStream_t s;
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking))) return e;
+        sv.push_back(s);
+    }
+    auto& evv = p.events[dev];
+    while ((int)evv.size() < ns + 1) {
+        hipEvent_t x;
+        if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming))) return e;
+        evv.push_back(x);
+    }
+    st.assign(sv.begin(), sv.begin() + ns);
+    ev.assign(evv.begin(), evv.begin() + ns + 1);
+    return hipSuccess;
+}
+
+}  // namespace
+
+size_t workspace_bytes_multi(const ModelDims* ms, const vqnqs_job* jobs,
+                             int njobs, int mode) {
+    size_t tot = kStatusBytes;
+    for (int i = 0; i < njobs; ++i)
+        tot += al256(workspace_bytes(ms[i], mode, std::max<int64_t>(jobs[i].batch, 1)));
+    return tot;
+}
+
+// Workspace slices: every job gets its full need when the total fits, else
+// its minimum plus a share of the rest proportional to what it lacks.
+static bool split_workspace(const ModelDims* ms, const vqnqs_job* jobs,
+                            int njobs, int mode, size_t ws_bytes,
+                            std::vector<size_t>& off, std::vector<size_t>& len) {
+    std::vector<size_t> need(njobs), mn(njobs);
+    size_t tn = 0, tm = 0;
+    for (int i = 0; i < njobs; ++i) {
+        const int64_t b = std::max<int64_t>(jobs[i].batch, 1);
+        need[i] = al256(workspace_bytes(ms[i], mode, b));
+        mn[i] = al256(workspace_bytes(ms[i], mode, 1));
+        tn += need[i];
+        tm += mn[i];
+    }
+    if (ws_bytes < kStatusBytes || tm > ws_bytes - kStatusBytes) return false;
+    ws_bytes -= kStatusBytes;
+    const size_t extra = ws_bytes - tm, want = tn - tm;
+    off.assign(njobs, 0);
+    len.assign(njobs, 0);
+    size_t o = kStatusBytes;
+    for (int i = 0; i < njobs; ++i) {
+        size_t l = need[i];
+        if (tn > ws_bytes) {
+            const double frac = want ? (double)(need[i] - mn[i]) / (double)want : 0.0;
+            l = mn[i] + ((size_t)(frac * (double)extra) & ~(size_t)255);
+            l = std::min(l, need[i]);
+        }
+        off[i] = o;
+        len[i] = l;
+        o += l;
+    }
+    return true;
+}
+
+static vqnqs_status run_jobs(const ModelDims* ms, const vqnqs_job* jobs,
+                             int njobs, int mode, void* ws,
+                             const std::vector<size_t>& off,
+                             const std::vector<size_t>& len, bool concurrent,
+                             hipStream_t st) {
+    char* base = static_cast<char*>(ws);
+    StatusOffsets so{};
+    so.n = njobs;
+    for (int i = 0; i < njobs; ++i) so.off[i] = (int64_t)off[i];
+    if (!concurrent || njobs == 1) {
+        for (int i = 0; i < njobs; ++i) {
+            const vqnqs_job& j = jobs[i];
+            vqnqs_status s = local_energy(ms[i], j.params, j.spins, j.batch,
+                                          mode, j.eloc, j.stats, j.ratios,
+                                          j.counters, base + off[i], len[i], st);
+            if (s) return s;
+        }
+        CK(launch_or_status(base, so, st));
+        return VQNQS_OK;
+    }
+    const int ns = std::min(njobs, kMaxJobStreams);
+    std::vector<hipStream_t> js;
+    std::vector<hipEvent_t> ev;
+    CK(job_streams(ns, js, ev));
+    CK(hipEventRecord(ev[ns], st));                  // fork
+    for (int k = 0; k < ns; ++k) CK(hipStreamWaitEvent(js[k], ev[ns], 0));
+    for (int i = 0; i < njobs; ++i) {
+        const vqnqs_job& j = jobs[i];
+        vqnqs_status s = local_energy(ms[i], j.params, j.spins, j.batch, mode,
+                                      j.eloc, j.stats, j.ratios, j.counters,
+                                      base + off[i], len[i], js[i % ns]);
+        if (s) return s;
+    }
+    for (int k = 0; k < ns; ++k) {                   // join
+        CK(hipEventRecord(ev[k], js[k]));
+        CK(hipStreamWaitEvent(st, ev[k], 0));
+    }
+    CK(launch_or_status(base, so, st));
+    return VQNQS_OK;
+}
+
+static std::vector<int64_t> graph_key(const ModelDims* ms, const vqnqs_job* jobs,
+                                      int njobs, int mode, int flags, void* ws,
+                                      size_t ws_bytes, hipStream_t st) {
+    std::vector<int64_t> k = {mode, flags, (int64_t)(intptr_t)ws,
+                              (int64_t)ws_bytes, (int64_t)(intptr_t)st, njobs};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    k.push_back(dev);
+    for (int i = 0; i < njobs; ++i) {
+        const vqnqs_job& j = jobs[i];
+        const vqnqs_config& c = j.cfg;
+        const Tuning t = tuning_get(ms[i]);
+        int64_t jb;
+        std::memcpy(&jb, &c.J, sizeof jb);
+        const int64_t f[] = {c.L, c.periodic, c.marshall, jb, c.d_model,
+                             c.n_layers, c.n_heads, c.d_ff, c.codebook_size,
+                             c.vq_heads, c.precision, c.flags,
+                             (int64_t)(intptr_t)j.params,
+                             (int64_t)(intptr_t)j.spins, j.batch,
+                             (int64_t)(intptr_t)j.eloc, (int64_t)(intptr_t)j.stats,
+                             (int64_t)(intptr_t)j.ratios,
+                             (int64_t)(intptr_t)j.counters, t.qkv_mb, t.mlp_mb,
+                             t.vq_mb};
+        k.insert(k.end(), std::begin(f), std::end(f));
+    }
+    return k;
+}
+
+vqnqs_status local_energy_multi(const ModelDims* ms, const vqnqs_job* jobs,
+                                int njobs, int mode, int flags, void* ws,
+                                size_t ws_bytes, hipStream_t st) {
+    std::vector<size_t> off, len;
+    if (!split_workspace(ms, jobs, njobs, mode, ws_bytes, off, len))
+        return VQNQS_ERR_WORKSPACE_TOO_SMALL;
+    const bool concurrent = (flags & VQNQS_MULTI_CONCURRENT) != 0;
+    // the legacy default stream cannot be captured
+    if (!(flags & VQNQS_MULTI_GRAPH) || st == nullptr)
+        return run_jobs(ms, jobs, njobs, mode, ws, off, len, concurrent, st);
+    const std::vector<int64_t> key =
+        graph_key(ms, jobs, njobs, mode, flags, ws, ws_bytes, st);
+    Pools& p = pools();
+    {
+        std::lock_guard<std::mutex> lk(p.mu);
+        for (auto& g : p.graphs)
+            if (g.key == key) {
+                CK(hipGraphLaunch(g.exec, st));
+                return VQNQS_OK;
+            }
+    }
+    Profiler& pf = Profiler::get();
+    const bool was_on = pf.enabled();
+    pf.enable(false);                 // no timing events inside a graph
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        pf.enable(was_on);
+        return VQNQS_ERR_HIP;
+    }
+    vqnqs_status s = run_jobs(ms, jobs, njobs, mode, ws, off, len, concurrent, st);
+    e = hipStreamEndCapture(st, &graph);
+    pf.enable(was_on);
+    if (s) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess || !graph) return VQNQS_ERR_HIP;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return VQNQS_ERR_HIP;
+    {
+        std::lock_guard<std::mutex> lk(p.mu);
+        if (p.graphs.size() >= kMaxGraphs) {
+            (void)hipGraphExecDestroy(p.graphs.front().exec);
+            p.graphs.erase(p.graphs.begin());
+        }
+        p.graphs.push_back({key, exec});
+    }
+    CK(hipGraphLaunch(exec, st));
     return VQNQS_OK;
 }
 

@@ -22,6 +22,14 @@ vqnqs_status grad_logpsi(const ModelDims& m, const void* params,
                          const int8_t* spins, int64_t batch,
                          const double* weights, void* grad, double* logpsi,
                          void* ws, size_t ws_bytes, hipStream_t st);
+vqnqs_status autotune(const ModelDims& m, const void* params,
+                      const int8_t* spins, int64_t batch, int mode, void* ws,
+                      size_t ws_bytes, hipStream_t st, int32_t* choices);
+size_t workspace_bytes_multi(const ModelDims* ms, const vqnqs_job* jobs,
+                             int njobs, int mode);
+vqnqs_status local_energy_multi(const ModelDims* ms, const vqnqs_job* jobs,
+                                int njobs, int mode, int flags, void* ws,
+                                size_t ws_bytes, hipStream_t st);
 vqnqs_status neighbours(const ModelDims& m, const int8_t* spins, int64_t batch,
                         int16_t* bonds, int32_t* count, double* diag, void* ws,
                         size_t ws_bytes, hipStream_t st);

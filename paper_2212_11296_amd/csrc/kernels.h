@@ -49,6 +49,12 @@ hipError_t launch_counter_add(int64_t* ctr, int slot, const int32_t* v,
                               int64_t scale, hipStream_t st);
 hipError_t launch_counter_add_const(int64_t* ctr, int slot, int64_t v,
                                     hipStream_t st);
+struct StatusOffsets {
+    int n;
+    int64_t off[64];
+};
+hipError_t launch_or_status(char* base, const StatusOffsets& so,
+                            hipStream_t st);
 hipError_t launch_copy_codes(const int32_t* src, int64_t n, int N, int H,
                              int nl, int l, int32_t* dst, hipStream_t st);
 
@@ -60,6 +66,15 @@ hipError_t launch_prepare(const ModelDims& m, const LayerW<typename P::acc>& w,
                           hipStream_t st);
 
 // ---- BF16 matrix-core path
+// Rows per wave (16 * mb) of the QKV, MLP and quantizer products; results
+// do not depend on them.  Process-wide, per model width.
+struct Tuning {
+    int qkv_mb, mlp_mb, vq_mb;
+};
+Tuning tuning_default(const ModelDims& m);
+Tuning tuning_get(const ModelDims& m);
+void tuning_set(const ModelDims& m, const Tuning& t);
+bool tuning_valid(const ModelDims& m, const Tuning& t);
 bool mfma_shapes_ok(const ModelDims& m);
 hipError_t launch_round_bf16(const float* src, int64_t n, float* dst,
                              hipStream_t st);

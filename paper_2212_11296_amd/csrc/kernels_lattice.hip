@@ -326,4 +326,21 @@ hipError_t launch_counter_add(int64_t* ctr, int slot, const int32_t* v,
     return hipGetLastError();
 }
 
+// Status word of a multi-lattice call: the OR of its jobs' status words
+// (each at the start of the job's workspace slice).
+__global__ void k_or_status(char* base, StatusOffsets so) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int32_t v = 0;
+        for (int i = 0; i < so.n; ++i)
+            v |= *reinterpret_cast<const int32_t*>(base + so.off[i]);
+        *reinterpret_cast<int32_t*>(base) = v;
+    }
+}
+
+hipError_t launch_or_status(char* base, const StatusOffsets& so,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_or_status, dim3(1), dim3(64), 0, st, base, so);
+    return hipGetLastError();
+}
+
 }  // namespace vq

@@ -16,6 +16,9 @@
 // Weight matrices W[K][Nout] are packed once per call into fragments
 // frag(nb, kb) = 64 lanes x 8 bf16, stored contiguously so one fragment is
 // one 16-byte load per lane.
+#include <map>
+#include <mutex>
+
 #include "kernels.h"
 
 namespace vq {
@@ -671,17 +674,72 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
 }
 
 // ------------------------------------------------------------ launchers
+// Launch choices per model width (rows per wave of the three products).
+// Every row's arithmetic is the same whichever is chosen: the choices trade
+// register pressure against weight reuse, never results.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, Tuning> g_tune;
+}  // namespace
+
+Tuning tuning_default(const ModelDims& m) {
+    Tuning t;
+    t.qkv_mb = m.d >= 256 ? 1 : 2;
+    t.mlp_mb = m.d >= 256 ? 1 : 2;
+    t.vq_mb = m.dseg >= 256 ? 1 : 2;
+    return t;
+}
+
+Tuning tuning_get(const ModelDims& m) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find({m.d, m.dseg});
+    return it == g_tune.end() ? tuning_default(m) : it->second;
+}
+
+void tuning_set(const ModelDims& m, const Tuning& t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[{m.d, m.dseg}] = t;
+}
+
+bool tuning_valid(const ModelDims& m, const Tuning& t) {
+    auto ok = [](int mb, int width) {
+        return mb == 1 || (mb == 2 && width < 256);
+    };
+    return ok(t.qkv_mb, m.d) && ok(t.mlp_mb, m.d) && ok(t.vq_mb, m.dseg);
+}
+
+template <int KB, int MB>
+static void qkv_go(const ModelDims& m, const LayerW<float>& w, RowSet rows,
+                   const BlockIO<PrecBF16>& io, const bf16x8* B,
+                   hipStream_t st) {
+    constexpr int R = 64 * MB;    // rows per workgroup (4 waves)
+    hipLaunchKernelGGL((k_qkv_mfma<KB, MB>), dim3(mgrid((rows.n_host + R - 1) / R)),
+                       dim3(kMT), 0, st, m, w, rows, io, B);
+}
+
 hipError_t launch_qkv_mfma(const ModelDims& m, const LayerW<float>& w,
                            RowSet rows, const BlockIO<PrecBF16>& io,
                            hipStream_t st) {
     const bf16x8* B = reinterpret_cast<const bf16x8*>(w.Wqkv_p);
-    switch (m.d / 32) {
-        case 2: hipLaunchKernelGGL((k_qkv_mfma<2, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B); break;
-        case 4: hipLaunchKernelGGL((k_qkv_mfma<4, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B); break;
-        case 8: hipLaunchKernelGGL((k_qkv_mfma<8, 1>), dim3(mgrid((rows.n_host + 63) / 64)), dim3(kMT), 0, st, m, w, rows, io, B); break;
+    const int mb = tuning_get(m).qkv_mb;
+    switch (m.d / 32 * 10 + mb) {
+        case 21: qkv_go<2, 1>(m, w, rows, io, B, st); break;
+        case 22: qkv_go<2, 2>(m, w, rows, io, B, st); break;
+        case 41: qkv_go<4, 1>(m, w, rows, io, B, st); break;
+        case 42: qkv_go<4, 2>(m, w, rows, io, B, st); break;
+        case 81: qkv_go<8, 1>(m, w, rows, io, B, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int KB, int MB>
+static void mlp_go(const ModelDims& m, const LayerW<float>& w, RowSet rows,
+                   const BlockIO<PrecBF16>& io, const bf16x8* B1,
+                   const bf16x8* B2, hipStream_t st) {
+    constexpr int R = 64 * MB;
+    hipLaunchKernelGGL((k_mlp_mfma<KB, MB>), dim3(mgrid((rows.n_host + R - 1) / R)),
+                       dim3(kMT), 0, st, m, w, rows, io, B1, B2);
 }
 
 hipError_t launch_mlp_mfma(const ModelDims& m, const LayerW<float>& w,
@@ -689,28 +747,40 @@ hipError_t launch_mlp_mfma(const ModelDims& m, const LayerW<float>& w,
                            hipStream_t st) {
     const bf16x8* B1 = reinterpret_cast<const bf16x8*>(w.W1_p);
     const bf16x8* B2 = reinterpret_cast<const bf16x8*>(w.W2_p);
-    switch (m.d / 32) {
-        case 2: hipLaunchKernelGGL((k_mlp_mfma<2, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
-        case 4: hipLaunchKernelGGL((k_mlp_mfma<4, 2>), dim3(mgrid((rows.n_host + 127) / 128)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
-        case 8: hipLaunchKernelGGL((k_mlp_mfma<8, 1>), dim3(mgrid((rows.n_host + 63) / 64)), dim3(kMT), 0, st, m, w, rows, io, B1, B2); break;
+    const int mb = tuning_get(m).mlp_mb;
+    switch (m.d / 32 * 10 + mb) {
+        case 21: mlp_go<2, 1>(m, w, rows, io, B1, B2, st); break;
+        case 22: mlp_go<2, 2>(m, w, rows, io, B1, B2, st); break;
+        case 41: mlp_go<4, 1>(m, w, rows, io, B1, B2, st); break;
+        case 42: mlp_go<4, 2>(m, w, rows, io, B1, B2, st); break;
+        case 81: mlp_go<8, 1>(m, w, rows, io, B1, B2, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int KBS, int MB>
+static void vq_go(const ModelDims& m, const LayerW<float>& w, RowSet rows,
+                  const BlockIO<PrecBF16>& io, const bf16x8* cb,
+                  hipStream_t st) {
+    constexpr int R = 64 * MB;    // 16*MB rows per wave, 4 waves
+    hipLaunchKernelGGL((k_vq_mfma<KBS, MB>), dim3(mgrid((rows.n_host + R - 1) / R)),
+                       dim3(kMT), 0, st, m, w, rows, io, cb);
 }
 
 hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
                           RowSet rows, const BlockIO<PrecBF16>& io,
                           hipStream_t st) {
     const bf16x8* cb = reinterpret_cast<const bf16x8*>(w.cb_p);
-    const int KBS = m.dseg / 32;
-    // 32 rows per wave (16 when the segment is 256 wide), 4 waves per group
-    const int WR = KBS == 8 ? 16 : 32;
-    const unsigned g = mgrid((rows.n_host + 4 * WR - 1) / (4 * WR));
-    switch (KBS) {
-        case 1: hipLaunchKernelGGL((k_vq_mfma<1, 2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
-        case 2: hipLaunchKernelGGL((k_vq_mfma<2, 2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
-        case 4: hipLaunchKernelGGL((k_vq_mfma<4, 2>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
-        case 8: hipLaunchKernelGGL((k_vq_mfma<8, 1>), dim3(g), dim3(kMT), 0, st, m, w, rows, io, cb); break;
+    const int mb = tuning_get(m).vq_mb;
+    switch (m.dseg / 32 * 10 + mb) {
+        case 11: vq_go<1, 1>(m, w, rows, io, cb, st); break;
+        case 12: vq_go<1, 2>(m, w, rows, io, cb, st); break;
+        case 21: vq_go<2, 1>(m, w, rows, io, cb, st); break;
+        case 22: vq_go<2, 2>(m, w, rows, io, cb, st); break;
+        case 41: vq_go<4, 1>(m, w, rows, io, cb, st); break;
+        case 42: vq_go<4, 2>(m, w, rows, io, cb, st); break;
+        case 81: vq_go<8, 1>(m, w, rows, io, cb, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
