@@ -333,6 +333,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch choices instead of timing "
+                         "the variants on the first 512 samples")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB "
                          "once (a kernel of known traffic that calibrates "
@@ -385,6 +388,11 @@ def main():
     def step(mode, w):
         vq.local_energy(cfg, p, sp, mode, ratios=True, counters=True, ws=w,
                         check=False, out=out)
+
+    choices = None
+    if not args.no_autotune:
+        nt = min(B, 512)
+        choices = vq.autotune(cfg, p, sp[:nt], vq.DEDUP, ws=ws)
 
     if args.copy_probe_mib > 0:
         n_el = args.copy_probe_mib << 18
@@ -492,6 +500,9 @@ def main():
         "achieved_tflops_overall": sum(flops.values()) / (ms / 1e3) / 1e12,
         "mean_energy": stats[0], "energy_variance": stats[1],
         "oracle_spot_max_rel_err_ratio": spot_err,
+        "tuning": (None if choices is None else
+                   {"qkv_mb": choices[0], "mlp_mb": choices[1],
+                    "vq_mb": choices[2]}),
         "counters_per_step": ctr_d,
         "kernels": per_kernel,
     }

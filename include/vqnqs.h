@@ -255,7 +255,9 @@ vqnqs_status vqnqs_autotune(const vqnqs_config* cfg, const void* params,
 
 /* Sets the rows-per-wave choices (as returned by vqnqs_autotune) for
  * models of this width; VQNQS_ERR_INVALID_CONFIG for a choice the width
- * does not allow (1 or 2 below width 256, 1 at 256). */
+ * does not allow (QKV and MLP: 1 or 2 below model width 256, 1 at 256;
+ * codebook search: 1, 2 or 4 up to segment width 128, 1 or 2 below 256,
+ * 1 at 256). */
 vqnqs_status vqnqs_set_tuning(const vqnqs_config* cfg, const int32_t* choices);
 
 /* Reads the device status word of a workspace used by a previous call:

@@ -655,7 +655,10 @@ struct Runner {
         if (s) return s;
         const int64_t N = m.N, d = m.d, H = m.H;
         const int64_t sd = n * N * d, sh = n * N * H;
-        SeqBufs sb{spins, w.bx, w.bq, w.bk, w.bv, w.ba, w.bcode, w.bmargin,
+        // margins only feed the certified-reuse test
+        const bool cert = (m.flags & VQNQS_FLAG_CERTIFIED_VQ) != 0;
+        SeqBufs sb{spins, w.bx, w.bq, w.bk, w.bv, w.ba, w.bcode,
+                   cert ? w.bmargin : nullptr,
                    w.blp, w.logpsi_s, true, nullptr};
         s = forward(sb, nullptr, n, true);
         if (s) return s;
@@ -938,7 +941,7 @@ vqnqs_status autotune(const ModelDims& m, const void* params,
         for (int c = 0; c < 3; ++c) {
             double best_ms = -1.0;
             Tuning pick = best;
-            for (int mb = 1; mb <= 2; ++mb) {
+            for (int mb = 1; mb <= 4; mb *= 2) {
                 Tuning t = best;
                 (c == 0 ? t.qkv_mb : c == 1 ? t.mlp_mb : t.vq_mb) = mb;
                 if (!tuning_valid(m, t)) continue;

@@ -519,7 +519,10 @@ __device__ inline float score_err_split(int n, float na, float wmax) {
 // four waves of a workgroup stream the codes of the quantizer head through
 // a double-buffered LDS stage (CBK code blocks of 16 codes per chunk), the
 // next chunk's global loads in flight while the current one is searched.
-template <int KBS, int MB>
+// Every codebook fragment read from LDS feeds 2*MB MFMAs.  The second-best
+// distance (for the certified-reuse margins) is tracked only when MARGIN;
+// the chosen code is the same either way.
+template <int KBS, int MB, bool MARGIN>
 __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
                                                 RowSet rows, BlockIO<PrecBF16> io,
                                                 const bf16x8* __restrict__ cbp) {
@@ -620,12 +623,18 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const float sc = cnv - 2.0f * acc[i][r];
-                            if (sc < best[i][r].b) {
-                                best[i][r].s = best[i][r].b;
-                                best[i][r].b = sc;
-                                best[i][r].i = code;
-                            } else if (sc < best[i][r].s) {
-                                best[i][r].s = sc;
+                            if (MARGIN) {
+                                if (sc < best[i][r].b) {
+                                    best[i][r].s = best[i][r].b;
+                                    best[i][r].b = sc;
+                                    best[i][r].i = code;
+                                } else if (sc < best[i][r].s) {
+                                    best[i][r].s = sc;
+                                }
+                            } else {
+                                const bool lt = sc < best[i][r].b;
+                                best[i][r].b = lt ? sc : best[i][r].b;
+                                best[i][r].i = lt ? code : best[i][r].i;
                             }
                         }
                 }
@@ -644,7 +653,7 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
                         T2 y;
                         y.b = __shfl_xor(v.b, o, 64);
                         y.i = __shfl_xor(v.i, o, 64);
-                        y.s = __shfl_xor(v.s, o, 64);
+                        y.s = MARGIN ? __shfl_xor(v.s, o, 64) : inf;
                         v = t2_merge(v, y);
                     }
                     best[i][r] = v;
@@ -659,7 +668,7 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
                     const int64_t s = __shfl(myslot[i], rw, 64);
                     if ((lane & 15) == 0 && s >= 0) {
                         io.codes[s * m.H + hq] = best[i][r].i;
-                        if (io.margin) {
+                        if (MARGIN) {
                             const float na = sqrtf(a2);
                             const float E = score_err_split(2 * DS, na, wmax);
                             const float u1 = best[i][r].b + a2 + E;
@@ -705,7 +714,9 @@ bool tuning_valid(const ModelDims& m, const Tuning& t) {
     auto ok = [](int mb, int width) {
         return mb == 1 || (mb == 2 && width < 256);
     };
-    return ok(t.qkv_mb, m.d) && ok(t.mlp_mb, m.d) && ok(t.vq_mb, m.dseg);
+    const bool vq_ok = t.vq_mb == 1 || (t.vq_mb == 2 && m.dseg < 256) ||
+                       (t.vq_mb == 4 && m.dseg <= 128);
+    return ok(t.qkv_mb, m.d) && ok(t.mlp_mb, m.d) && vq_ok;
 }
 
 template <int KB, int MB>
@@ -764,8 +775,13 @@ static void vq_go(const ModelDims& m, const LayerW<float>& w, RowSet rows,
                   const BlockIO<PrecBF16>& io, const bf16x8* cb,
                   hipStream_t st) {
     constexpr int R = 64 * MB;    // 16*MB rows per wave, 4 waves
-    hipLaunchKernelGGL((k_vq_mfma<KBS, MB>), dim3(mgrid((rows.n_host + R - 1) / R)),
-                       dim3(kMT), 0, st, m, w, rows, io, cb);
+    const dim3 g(mgrid((rows.n_host + R - 1) / R));
+    if (io.margin)
+        hipLaunchKernelGGL((k_vq_mfma<KBS, MB, true>), g, dim3(kMT), 0, st, m, w,
+                           rows, io, cb);
+    else
+        hipLaunchKernelGGL((k_vq_mfma<KBS, MB, false>), g, dim3(kMT), 0, st, m,
+                           w, rows, io, cb);
 }
 
 hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
@@ -778,8 +794,11 @@ hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
         case 12: vq_go<1, 2>(m, w, rows, io, cb, st); break;
         case 21: vq_go<2, 1>(m, w, rows, io, cb, st); break;
         case 22: vq_go<2, 2>(m, w, rows, io, cb, st); break;
+        case 14: vq_go<1, 4>(m, w, rows, io, cb, st); break;
+        case 24: vq_go<2, 4>(m, w, rows, io, cb, st); break;
         case 41: vq_go<4, 1>(m, w, rows, io, cb, st); break;
         case 42: vq_go<4, 2>(m, w, rows, io, cb, st); break;
+        case 44: vq_go<4, 4>(m, w, rows, io, cb, st); break;
         case 81: vq_go<8, 1>(m, w, rows, io, cb, st); break;
         default: return hipErrorInvalidValue;
     }
