@@ -134,99 +134,147 @@ __device__ inline void split_p(const float* p, bf16x8& ph, bf16x8& pl) {
     for (int k = 0; k < 8; ++k) pl[k] = (__bf16)r[k];
 }
 
-// One 16-query tile t against keys 0..16t+15 held in LDS; writes rows
-// i >= lo (and < N) through orow(i).
-template <int DH, class OF>
-__device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
-                                 OF orow) {
+// Online-softmax state of one 16-query tile (this lane: query iq).
+template <int DH>
+struct QTile {
+    bf16x8 b0, b1, b2;                // query fragments
+    f32x4 o[DH / 16];                 // output accumulators
+    f32x4 osum;                       // normaliser (all-ones operand)
+    f32x4 negm;                       // -reference, the score MFMA's input
+    float mref;
+    int t, iq, nblk;
+};
+
+template <int DH>
+__device__ inline void qtile_init(QTile<DH>& q, const Tiles<DH>& T, int t) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c16 = lane & 15;
-    const int iq = t * 16 + c16;              // the query of this lane
-    const __bf16* qr = T.Qc + iq * 2 * DH;
-    bf16x8 b0, b1, b2;
+    q.t = t;
+    q.iq = t * 16 + c16;
+    q.nblk = (t * 16 + 15) / 32 + 1;
+    const __bf16* qr = T.Qc + q.iq * 2 * DH;
     if (DH == 16) {
         // [kh(16) | kl(16)] x [qh ; qh]  and  [kh | kl] x [ql ; ql]
-        b0 = *reinterpret_cast<const bf16x8*>(qr + 8 * (g & 1));
-        b1 = *reinterpret_cast<const bf16x8*>(qr + DH + 8 * (g & 1));
-        b2 = b1;
+        q.b0 = *reinterpret_cast<const bf16x8*>(qr + 8 * (g & 1));
+        q.b1 = *reinterpret_cast<const bf16x8*>(qr + DH + 8 * (g & 1));
+        q.b2 = q.b1;
     } else {
         // [kh(32)] x [qh], [kl(32)] x [qh], [kh(32)] x [ql]
-        b0 = *reinterpret_cast<const bf16x8*>(qr + 8 * g);
-        b1 = b0;
-        b2 = *reinterpret_cast<const bf16x8*>(qr + DH + 8 * g);
+        q.b0 = *reinterpret_cast<const bf16x8*>(qr + 8 * g);
+        q.b1 = q.b0;
+        q.b2 = *reinterpret_cast<const bf16x8*>(qr + DH + 8 * g);
     }
-    constexpr int NT = DH / 16;
-    f32x4 o[NT];
 #pragma unroll
-    for (int u = 0; u < NT; ++u) o[u] = f32x4{0, 0, 0, 0};
-    f32x4 osum = f32x4{0, 0, 0, 0};
+    for (int u = 0; u < DH / 16; ++u) q.o[u] = f32x4{0, 0, 0, 0};
+    q.osum = f32x4{0, 0, 0, 0};
+    q.negm = f32x4{0, 0, 0, 0};
+    q.mref = 0.0f;
+}
+
+// One 32-key block (keys j0..j0+31) for one query tile, from the block's K
+// fragments ka/kb (per 16-key sub-tile) and V fragments vh/vl.
+template <int DH>
+__device__ inline void qtile_block(QTile<DH>& q, int N, int blk,
+                                   const bf16x8 (&ka)[2], const bf16x8 (&kb)[2],
+                                   const bf16x8 (&vh)[DH / 16],
+                                   const bf16x8 (&vl)[DH / 16],
+                                   const bf16x8& ones) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    const int j0 = blk * 32;
+    float s[8];
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+        f32x4 acc;
+        if (DH == 16) {
+            acc = mfma_a(ka[sub], q.b0, q.negm);
+            acc = mfma_a(ka[sub], q.b1, acc);
+        } else {
+            acc = mfma_a(ka[sub], q.b0, q.negm);
+            acc = mfma_a(kb[sub], q.b1, acc);
+            acc = mfma_a(ka[sub], q.b2, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s[sub * 4 + r] = acc[r];
+    }
+    // keys beyond the query (or the sequence) only in the last blocks
+    if (j0 + 31 > q.t * 16 || j0 + 31 >= N) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int key = j0 + (k >> 2) * 16 + 4 * g + (k & 3);
+            if (key > q.iq || key >= N) s[k] = -__builtin_inff();
+        }
+    }
+    float lm = s[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) lm = __builtin_fmaxf(lm, s[k]);
+    const bool first = blk == 0;
+    if (first || __builtin_amdgcn_ballot_w64(lm > kTau) != 0) {
+        float dm = __builtin_fmaxf(lm, __shfl_xor(lm, 16, 64));
+        dm = __builtin_fmaxf(dm, __shfl_xor(dm, 32, 64));
+        // the first block sets the reference to its maximum; later blocks
+        // raise it only past kTau
+        const float delta = first ? dm : (dm > kTau ? dm : 0.0f);
+        if (delta != 0.0f) {
+            if (!first) {
+                const float alpha = __builtin_amdgcn_exp2f(-delta);
+#pragma unroll
+                for (int u = 0; u < DH / 16; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) q.o[u][r] *= alpha;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) q.osum[r] *= alpha;
+            }
+            q.mref += delta;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s[k] -= delta;
+            q.negm = f32x4{-q.mref, -q.mref, -q.mref, -q.mref};
+        }
+    }
+    float p[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] = __builtin_amdgcn_exp2f(s[k]);
+    bf16x8 ph, pl;
+    split_p(p, ph, pl);
+    q.osum = mfma_a(ones, ph, q.osum);
+    q.osum = mfma_a(ones, pl, q.osum);
+#pragma unroll
+    for (int u = 0; u < DH / 16; ++u) {
+        q.o[u] = mfma_a(vh[u], ph, q.o[u]);
+        q.o[u] = mfma_a(vl[u], ph, q.o[u]);
+        q.o[u] = mfma_a(vh[u], pl, q.o[u]);
+    }
+}
+
+// NQ query tiles tq[0] > tq[1] > ... of one wave against keys 0..16t+15 held
+// in LDS: the tiles share every K and V fragment read and their softmax
+// chains are independent, so the vector unit and the matrix core see NQ
+// times the independent work of one tile.  Writes rows i >= lo (and < N)
+// through orow(i).  Each tile's arithmetic is the same as on its own.
+template <int DH, int NQ, class OF>
+__device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ],
+                                  int lo, OF orow) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    constexpr int NT = DH / 16;
+    QTile<DH> q[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) qtile_init<DH>(q[i], T, tq[i]);
     bf16x8 ones;
 #pragma unroll
     for (int k = 0; k < 8; ++k) ones[k] = (__bf16)1.0f;
-    float mref = 0.0f;                        // reference of this query
-    f32x4 negm = f32x4{0, 0, 0, 0};
-    const int nblk = (t * 16 + 15) / 32 + 1;
+    const int nblk = q[0].nblk;
     for (int blk = 0; blk < nblk; ++blk) {
         const int j0 = blk * 32;
-        float s[8];
+        bf16x8 ka[2], kb[2];
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
             const __bf16* kr = T.Kc + (j0 + sub * 16 + c16) * 2 * DH;
-            f32x4 acc;
-            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(kr + 8 * g);
-            if (DH == 16) {
-                acc = mfma_a(a0, b0, negm);
-                acc = mfma_a(a0, b1, acc);
-            } else {
-                const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(kr + DH + 8 * g);
-                acc = mfma_a(a0, b0, negm);
-                acc = mfma_a(a1, b1, acc);
-                acc = mfma_a(a0, b2, acc);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) s[sub * 4 + r] = acc[r];
+            ka[sub] = *reinterpret_cast<const bf16x8*>(kr + 8 * g);
+            kb[sub] = DH == 16 ? ka[sub]
+                               : *reinterpret_cast<const bf16x8*>(kr + DH + 8 * g);
         }
-        // keys beyond the query (or the sequence) only in the last blocks
-        if (j0 + 31 > t * 16 || j0 + 31 >= N) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int key = j0 + (k >> 2) * 16 + 4 * g + (k & 3);
-                if (key > iq || key >= N) s[k] = -__builtin_inff();
-            }
-        }
-        float lm = s[0];
-#pragma unroll
-        for (int k = 1; k < 8; ++k) lm = __builtin_fmaxf(lm, s[k]);
-        const bool first = blk == 0;
-        if (first || __builtin_amdgcn_ballot_w64(lm > kTau) != 0) {
-            float dm = __builtin_fmaxf(lm, __shfl_xor(lm, 16, 64));
-            dm = __builtin_fmaxf(dm, __shfl_xor(dm, 32, 64));
-            // the first block sets the reference to its maximum; later
-            // blocks raise it only past kTau
-            const float delta = first ? dm : (dm > kTau ? dm : 0.0f);
-            if (delta != 0.0f) {
-                if (!first) {
-                    const float alpha = __builtin_amdgcn_exp2f(-delta);
-#pragma unroll
-                    for (int u = 0; u < NT; ++u)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) o[u][r] *= alpha;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) osum[r] *= alpha;
-                }
-                mref += delta;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) s[k] -= delta;
-                negm = f32x4{-mref, -mref, -mref, -mref};
-            }
-        }
-        float p[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) p[k] = __builtin_amdgcn_exp2f(s[k]);
-        bf16x8 ph, pl;
-        split_p(p, ph, pl);
-        osum = mfma_a(ones, ph, osum);
-        osum = mfma_a(ones, pl, osum);
+        bf16x8 vh[NT], vl[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
             const int vc = u * 16 + c16;
@@ -236,25 +284,46 @@ __device__ inline void attn_tile(const Tiles<DH>& T, int N, int t, int lo,
             const bf16x4 h1 = *reinterpret_cast<const bf16x4*>(vh_row + 16);
             const bf16x4 l0 = *reinterpret_cast<const bf16x4*>(vl_row);
             const bf16x4 l1 = *reinterpret_cast<const bf16x4*>(vl_row + 16);
-            const bf16x8 vh = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
-            const bf16x8 vl = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
-            o[u] = mfma_a(vh, ph, o[u]);
-            o[u] = mfma_a(vl, ph, o[u]);
-            o[u] = mfma_a(vh, pl, o[u]);
+            vh[u] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+            vl[u] = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+        }
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (blk < q[i].nblk)
+                qtile_block<DH>(q[i], N, blk, ka, kb, vh, vl, ones);
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        if (q[i].iq >= lo && q[i].iq < N) {
+            float* dst = orow(q[i].iq);
+            const float inv = 1.0f / q[i].osum[0];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                float4 v;
+                v.x = q[i].o[u][0] * inv;
+                v.y = q[i].o[u][1] * inv;
+                v.z = q[i].o[u][2] * inv;
+                v.w = q[i].o[u][3] * inv;
+                *reinterpret_cast<float4*>(dst + u * 16 + 4 * g) = v;
+            }
         }
     }
-    if (iq >= lo && iq < N) {
-        float* dst = orow(iq);
-        const float inv = 1.0f / osum[0];
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            float4 v;
-            v.x = o[u][0] * inv;
-            v.y = o[u][1] * inv;
-            v.z = o[u][2] * inv;
-            v.w = o[u][3] * inv;
-            *reinterpret_cast<float4*>(dst + u * 16 + 4 * g) = v;
-        }
+}
+
+// The query tiles of wave w, from the last down in steps of 4, two at a
+// time (the last one alone when their number is odd); tiles below tmin are
+// not computed.
+template <int DH, class OF>
+__device__ inline void wave_tiles(const Tiles<DH>& T, int N, int NTQ, int w,
+                                  int tmin, int lo, OF orow) {
+    int t = NTQ - 1 - w;
+    for (; t - 4 >= tmin; t -= 8) {
+        const int tq[2] = {t, t - 4};
+        attn_tiles<DH, 2>(T, N, tq, lo, orow);
+    }
+    if (t >= tmin) {
+        const int tq[1] = {t};
+        attn_tiles<DH, 1>(T, N, tq, lo, orow);
     }
 }
 
@@ -271,7 +340,7 @@ __global__ void __launch_bounds__(kAT) k_attn_seq_mfma(ModelDims m,
     const float qs = kLog2e / sqrtf((float)DH);
     const int64_t n = n_dev ? (int64_t)*n_dev : n_seq;
     const int64_t units = n * m.nh;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NTQ = (N + 15) / 16;
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
         const int64_t s = u / m.nh;
@@ -280,9 +349,8 @@ __global__ void __launch_bounds__(kAT) k_attn_seq_mfma(ModelDims m,
         __syncthreads();
         load_all<DH>(T, N, io.q, io.k, io.v, sb, d, qs);
         __syncthreads();
-        for (int t = NTQ - 1 - wave; t >= 0; t -= 4)
-            attn_tile<DH>(T, N, t, 0,
-                          [&](int i) { return io.a + sb + (int64_t)i * d; });
+        wave_tiles<DH>(T, N, NTQ, wave, 0, 0,
+                       [&](int i) { return io.a + sb + (int64_t)i * d; });
     }
     if (ctr && blockIdx.x == 0 && threadIdx.x == 0) {
         atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
@@ -304,7 +372,7 @@ __global__ void __launch_bounds__(kAT) k_attn_dedup_mfma(ModelDims m,
     const Tiles<DH> T = carve_tiles<DH>(smem_raw, N);
     const float qs = kLog2e / sqrtf((float)DH);
     const int64_t units = dd.n_samples * m.nh;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NTQ = (N + 15) / 16;
     int64_t my_rows = 0, my_pairs = 0;
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
@@ -341,9 +409,8 @@ __global__ void __launch_bounds__(kAT) k_attn_dedup_mfma(ModelDims m,
                 T.put(j, c, dd.ok[o], dd.oq[o], qs, dd.ov[o]);
             }
             __syncthreads();
-            for (int t = NTQ - 1 - wave; t >= pmin / 16; t -= 4)
-                attn_tile<DH>(T, N, t, pmin,
-                              [&](int i) { return dd.oa + ob0 + (int64_t)i * d; });
+            wave_tiles<DH>(T, N, NTQ, wave, pmin / 16, pmin,
+                           [&](int i) { return dd.oa + ob0 + (int64_t)i * d; });
             if (h == 0 && threadIdx.x == 0) {
                 my_rows += N - pmin;
                 my_pairs += ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2;
