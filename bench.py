@@ -189,10 +189,12 @@ def bench_grad(args, vq, torch, np, mc, make_params, make_spins):
         avg = prof[dom][0] / launches
         ach = per_launch / (avg / 1e3) / 1e12
         if dom == "grad_attention":
-            peak = 4.0 * mc.d_head * EXP_RATE / 1e12
+            bound, peak = "alu", 4.0 * mc.d_head * EXP_RATE / 1e12
         else:
-            peak = PEAK["fp32"]
-        roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": peak,
+            # FP32-accurate products (three bf16 matrix-core passes): the
+            # FP32 dense matrix peak
+            bound, peak = "mfma", PEAK["fp32"]
+        roof = {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak,
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                 "flop_per_launch": per_launch, "avg_launch_ms": avg}
     cpu = None

@@ -488,6 +488,9 @@ struct Runner {
                     int64_t groups) {
         GemmDesc g{M, Nn, K, A, lda, sA, tA, B, ldb, sB, tB, C, ldc, sC, beta,
                    groups};
+        // the BF16 mode runs its products on the matrix core
+        if constexpr (std::is_same<P, PrecBF16>::value)
+            if (m.mfma) return launch_gemm_mfma(g, st);
         return launch_gemm<acc>(g, st);
     }
     hipError_t colsum(int64_t n, int cols, const acc* A, int64_t lda,

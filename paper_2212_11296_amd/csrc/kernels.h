@@ -199,6 +199,8 @@ struct GemmDesc {
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& g, hipStream_t st);
+// FP32 operands on the bf16 matrix core (hi/lo split, three passes)
+hipError_t launch_gemm_mfma(const GemmDesc& g, hipStream_t st);
 template <typename T>
 hipError_t launch_colsum(int64_t groups, int64_t rows, int cols, const T* A,
                          int64_t lda, const T* B, int64_t ldb, T* out,

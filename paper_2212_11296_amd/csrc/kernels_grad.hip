@@ -112,6 +112,126 @@ hipError_t launch_gemm(const GemmDesc& g, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------ GEMM on the matrix core
+// FP32 operands enter the bf16 matrix core as hi + lo pairs; three passes
+// hi.hi + hi.lo + lo.hi accumulate in FP32 (about 16 significant bits per
+// product; the lo.lo term is below that).  Workgroup tile 128 x 128, each of
+// the four waves 64 x 64 (4 x 4 tiles of 16 x 16), K steps of 32.  The
+// operands are staged in LDS as [row][k] (A) and [col][k] (B), so every
+// MFMA fragment is one 16-byte read per lane whatever the transposition.
+typedef __attribute__((ext_vector_type(8))) __bf16 gbf16x8;
+typedef __attribute__((ext_vector_type(4))) float gf32x4;
+
+__global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
+    constexpr int BM = 128, BN = 128, BK = 32, LD = BK + 8;
+    __shared__ __align__(16) __bf16 Ah[BM * LD], Al[BM * LD];
+    __shared__ __align__(16) __bf16 Bh[BN * LD], Bl[BN * LD];
+    const int64_t grp = blockIdx.z;
+    const float* A = static_cast<const float*>(g.A) + grp * g.sA;
+    const float* B = static_cast<const float*>(g.B) + grp * g.sB;
+    float* C = static_cast<float*>(g.C) + grp * g.sC;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    gf32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = gf32x4{0, 0, 0, 0};
+    // Global loads of the next K step are issued before this step's MFMAs
+    // (register prefetch) and stored to LDS after them.
+    constexpr int PER = (BM * BK) / kGT;
+    float pa[PER], pb[PER];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int e = tid + kGT * r;
+            int mm, kk;
+            if (g.tA) { kk = e / BM; mm = e % BM; }
+            else { mm = e / BK; kk = e % BK; }
+            const int64_t gm = m0 + mm, gk = k0 + kk;
+            pa[r] = (gm < g.M && gk < g.K)
+                        ? (g.tA ? A[gk * g.lda + gm] : A[gm * g.lda + gk]) : 0.0f;
+            int nn;
+            if (g.tB) { nn = e / BK; kk = e % BK; }
+            else { kk = e / BN; nn = e % BN; }
+            const int64_t gn = n0 + nn, gk2 = k0 + kk;
+            pb[r] = (gn < g.N && gk2 < g.K)
+                        ? (g.tB ? B[gn * g.ldb + gk2] : B[gk2 * g.ldb + gn]) : 0.0f;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int e = tid + kGT * r;
+            int mm, kk;
+            if (g.tA) { kk = e / BM; mm = e % BM; }
+            else { mm = e / BK; kk = e % BK; }
+            const __bf16 h = (__bf16)pa[r];
+            Ah[mm * LD + kk] = h;
+            Al[mm * LD + kk] = (__bf16)(pa[r] - (float)h);
+            int nn;
+            if (g.tB) { nn = e / BK; kk = e % BK; }
+            else { kk = e / BN; nn = e % BN; }
+            const __bf16 wh = (__bf16)pb[r];
+            Bh[nn * LD + kk] = wh;
+            Bl[nn * LD + kk] = (__bf16)(pb[r] - (float)wh);
+        }
+    };
+    fetch(0);
+    for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+        stash();
+        __syncthreads();
+        if (k0 + BK < g.K) fetch(k0 + BK);
+        gbf16x8 bh[4], bl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int nn = wn * 64 + j * 16 + (lane & 15);
+            bh[j] = *reinterpret_cast<const gbf16x8*>(Bh + nn * LD + 8 * (lane >> 4));
+            bl[j] = *reinterpret_cast<const gbf16x8*>(Bl + nn * LD + 8 * (lane >> 4));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int mm = wm * 64 + i * 16 + (lane & 15);
+            const gbf16x8 ah = *reinterpret_cast<const gbf16x8*>(Ah + mm * LD + 8 * (lane >> 4));
+            const gbf16x8 al = *reinterpret_cast<const gbf16x8*>(Al + mm * LD + 8 * (lane >> 4));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D layout: lane holds rows 4*(lane/16) + r of column lane%16
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gm = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const int64_t gn = n0 + wn * 64 + j * 16 + (lane & 15);
+                if (gm < g.M && gn < g.N) {
+                    float* c = C + gm * g.ldc + gn;
+                    *c = g.beta ? *c + acc[i][j][r] : acc[i][j][r];
+                }
+            }
+}
+
+hipError_t launch_gemm_mfma(const GemmDesc& g, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0 || g.groups <= 0) return hipSuccess;
+    const int64_t gx = (g.N + 127) / 128, gy = (g.M + 127) / 128;
+    if (gx > kGridMax || gy > kGridMax || g.groups > kGridMax)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)gx, (unsigned)gy,
+                                        (unsigned)g.groups),
+                       dim3(kGT), 0, st, g);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- column reductions
 // out[g*os + c] = beta*out + sum_{r < rows} A[(g*rows + r)*lda + c]
 //                                         (* B[(g*rows + r)*ldb + c])
