@@ -235,14 +235,17 @@ __device__ inline void ln_frags_v(const float (&v)[MB][KB][8], const float* g,
 }
 
 // Cooperative copy of `cnt` fragment lanes (16 B each) into an LDS stage.
+// The loads are unconditional (indices past cnt are clamped to the last
+// lane; those entries are never used), so nothing consumes a loaded value
+// before the stage is stored: the loads stay in flight over the caller's
+// work between fetch and store.
 template <int PER>
 __device__ inline void stage_fetch(bf16x8 (&pre)[PER], const bf16x8* src,
                                    int64_t cnt) {
-    const bf16x8 z = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int64_t e = threadIdx.x + k * kMT;
-        pre[k] = e < cnt ? src[e] : z;
+        pre[k] = src[e < cnt ? e : cnt - 1];
     }
 }
 template <int PER>
@@ -332,6 +335,21 @@ __global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
 // GELU(A W1[:, chunk] + b1) is transposed through a per-wave LDS scratch into
 // A fragments and multiplied into the output accumulators with W2[chunk, :].
 // The W1/W2 fragments of a chunk are staged in LDS for the four waves.
+// GELU with erf from Abramowitz & Stegun 7.1.26 (absolute error of erf at
+// most 1.5e-7): with y = |x|/sqrt(2), t = 1/(1 + p y) and
+// q = (a1 t + ... + a5 t^5) exp(-y^2) ~ erfc(y), 1 + erf(x/sqrt(2)) is q for
+// x < 0 (no cancellation) and 2 - q otherwise.  Branch-free.
+__device__ inline float gelu_as(float x) {
+    const float y = __builtin_fabsf(x) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * y);
+    const float poly =
+        t * (0.254829592f +
+             t * (-0.284496736f +
+                  t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+    const float q = poly * __builtin_amdgcn_exp2f(-(y * y) * 1.4426950408889634f);
+    return 0.5f * x * (x >= 0.0f ? 2.0f - q : q);
+}
+
 template <int KB1, int MB>
 __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_mfma(ModelDims m, LayerW<float> w,
                                                  RowSet rows, BlockIO<PrecBF16> io,
@@ -351,6 +369,21 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
     const int gq = lane >> 4, c16 = lane & 15;
     const int64_t n = rs_n(rows);
     const int64_t ntile = (n + 4 * WR - 1) / (4 * WR);
+    // W1 columns and W2 rows of one hidden chunk, fetched into registers
+    bf16x8 p1[PER1], p2[PER2];
+    auto fetch_w = [&](int hc) {
+        stage_fetch<PER1>(p1, B1 + (int64_t)hc * C1, C1);
+        // W2 rows of the chunk: k-blocks hc*KB2C .. +KB2C of every output
+        // block nb; packed index (nb*KB2 + kb)*64 + lane
+#pragma unroll
+        for (int k = 0; k < PER2; ++k) {
+            const int e = threadIdx.x + k * kMT;
+            const int ln = e & 63, f = e >> 6;
+            const int kbl = f % KB2C, nb = f / KB2C;
+            p2[k] = B2[((int64_t)nb * KB2 + hc * KB2C + kbl) * 64 + ln];
+        }
+    };
+    fetch_w(0);
     for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
         int64_t slot[MB];
 #pragma unroll
@@ -391,31 +424,23 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
         __bf16* hl = hs[wave][1];
         for (int hc = 0; hc < F / HC; ++hc) {
             __syncthreads();                       // stages free
-            {
-                bf16x8 p1[PER1];
-                stage_fetch<PER1>(p1, B1 + (int64_t)hc * C1, C1);
-                stage_store<PER1>(p1, s1);
-                // W2 rows of the chunk: k-blocks hc*KB2C .. +KB2C of every
-                // output block nb; packed index (nb*KB2 + kb)*64 + lane
-#pragma unroll
-                for (int k = 0; k < PER2; ++k) {
-                    const int e = threadIdx.x + k * kMT;
-                    const int ln = e & 63, f = e >> 6;
-                    const int kbl = f % KB2C, nb = f / KB2C;
-                    s2[e] = B2[((int64_t)nb * KB2 + hc * KB2C + kbl) * 64 + ln];
-                }
-            }
+            stage_store<PER1>(p1, s1);
+            stage_store<PER2>(p2, s2);
             __syncthreads();
-            // hidden chunk = GELU(A W1[:, chunk] + b1)
+            // the next chunk's weights (chunk 0 again after the last: the
+            // next tile's) load while this chunk is computed
+            fetch_w(hc + 1 < F / HC ? hc + 1 : 0);
+            // hidden chunk = GELU(A W1[:, chunk] + b1); the K loop is
+            // outermost so the NB1C accumulators are independent MFMA chains
             f32x4 hacc[MB][NB1C];
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
                 for (int nb = 0; nb < NB1C; ++nb) hacc[i][nb] = f32x4{0, 0, 0, 0};
 #pragma unroll
-            for (int nb = 0; nb < NB1C; ++nb)
+            for (int kb = 0; kb < KB1; ++kb)
 #pragma unroll
-                for (int kb = 0; kb < KB1; ++kb) {
+                for (int nb = 0; nb < NB1C; ++nb) {
                     const bf16x8 b = s1[(nb * KB1 + kb) * 64 + lane];
 #pragma unroll
                     for (int i = 0; i < MB; ++i) {
@@ -433,7 +458,7 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = i * 16 + 4 * gq + r;
-                        const float h = gelu_exact(hacc[i][nb][r] + bias);
+                        const float h = gelu_as(hacc[i][nb][r] + bias);
                         split1(h, hh[row * LDH + col], hl[row * LDH + col]);
                     }
             }
@@ -588,16 +613,20 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int e = threadIdx.x + k * kMT;
-                stage[0][e] = e < cbtot ? cbh[e] : zero8;
+                stage[0][e] = cbh[e < cbtot ? e : cbtot - 1];
             }
             __syncthreads();
             for (int c = 0; c < nchunk; ++c) {
                 bf16x8 pre[PER];
                 const int64_t nb = (int64_t)(c + 1) * CHUNK;
+                if (c + 1 < nchunk) {
+                    // clamped, unconditional loads (lanes past the codebook
+                    // are never read): in flight during this chunk's search
 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int64_t e = nb + threadIdx.x + k * kMT;
-                    pre[k] = (c + 1 < nchunk && e < cbtot) ? cbh[e] : zero8;
+                    for (int k = 0; k < PER; ++k) {
+                        const int64_t e = nb + threadIdx.x + k * kMT;
+                        pre[k] = cbh[e < cbtot ? e : cbtot - 1];
+                    }
                 }
                 const bf16x8* sb = stage[c & 1];
 #pragma unroll
@@ -638,8 +667,10 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
                             }
                         }
                 }
+                if (c + 1 < nchunk)
 #pragma unroll
-                for (int k = 0; k < PER; ++k) stage[(c + 1) & 1][threadIdx.x + k * kMT] = pre[k];
+                    for (int k = 0; k < PER; ++k)
+                        stage[(c + 1) & 1][threadIdx.x + k * kMT] = pre[k];
                 __syncthreads();
             }
             // combine the 16 column lanes of each row group

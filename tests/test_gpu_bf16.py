@@ -10,7 +10,8 @@ percentile below 1e-3; neighbour ratios with median relative error below
 error, amplified through the layers and the exponential of the log-psi
 difference), and at most 1% of them beyond 1e-3: those are quantizer
 near-ties resolved to the other, equally valid, code, which moves a ratio by
-a finite, unbounded step; log psi within 1e-3 absolute.  VQ
+a finite, unbounded step; log psi within 1e-3 absolute on the samples
+whose codes all agree with the oracle's (at least half of them).  VQ
 codes are integers decided in floating point: they must equal the oracle's
 except where the oracle's best and second-best distances are within the
 BF16 path's error bound (a valid near-tie), checked at the first differing
@@ -32,6 +33,9 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 
 
 def check_codes(mc, theta, s, gpu_codes):
+    """Fraction of codes differing from the oracle's; asserts that every
+    sample's first differing layer shows only valid near-ties.  Also returns
+    the mask of samples whose codes all agree."""
     ref = net.forward(mc, net.unpack(mc, theta), s, keep=True)
     oc = np.transpose(ref["codes"], (1, 0, 2, 3))          # [B][nl][N][H]
     diff = gpu_codes != oc
@@ -43,7 +47,7 @@ def check_codes(mc, theta, s, gpu_codes):
         c = ref["caches"][l]
         gap = c["d2"][b, rows, heads] - c["d1"][b, rows, heads]
         assert (gap < 1e-3 * (1 + c["d1"][b, rows, heads])).all(), (b, l)
-    return diff.mean()
+    return diff.mean(), ~diff.reshape(diff.shape[0], -1).any(axis=1)
 
 
 @pytest.mark.parametrize("name,batch", [("medium", 64), ("large", 8),
@@ -56,9 +60,12 @@ def test_forward_bf16(name, batch):
     lp, codes = vq.forward_logpsi(vq.make_config(mc), dev_params(theta, "bf16"),
                                   dev_spins(s), codes=True)
     ref = net.forward(mc, net.unpack(mc, theta), s)
-    assert np.abs(host(lp) - ref["logpsi"]).max() < 1e-3
-    rate = check_codes(mc, theta, s, host(codes))
+    rate, same = check_codes(mc, theta, s, host(codes))
     assert rate < 1e-3
+    # log psi where every code agrees (a valid near-tie flip elsewhere moves
+    # log psi by a finite step)
+    assert same.sum() >= max(1, batch // 2)
+    assert np.abs(host(lp)[same] - ref["logpsi"][same]).max() < 1e-3
 
 
 @pytest.mark.parametrize("flags", [0, vq.FLAG_CERTIFIED_VQ])
