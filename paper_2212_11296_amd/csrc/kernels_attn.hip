@@ -425,12 +425,16 @@ __global__ void __launch_bounds__(kAT) k_attn_dedup_mfma(ModelDims m,
     }
 }
 
-bool attn_mfma_ok(const ModelDims& m) { return m.dh == 16 || m.dh == 32; }
-
 static size_t attn_lds(const ModelDims& m) {
     const int Np = (m.N + 31) & ~31;
     return sizeof(__bf16) *
            ((size_t)2 * Np * 2 * m.dh + (size_t)2 * m.dh * (Np + 8));
+}
+
+// The matrix-core kernels hold K, Q and V of a whole sequence in LDS; longer
+// sequences use the vector-unit attention (K and V only).
+bool attn_mfma_ok(const ModelDims& m) {
+    return (m.dh == 16 || m.dh == 32) && attn_lds(m) <= 160 * 1024;
 }
 
 static unsigned agrid(int64_t units) {

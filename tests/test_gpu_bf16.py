@@ -17,6 +17,8 @@ except where the oracle's best and second-best distances are within the
 BF16 path's error bound (a valid near-tie), checked at the first differing
 layer of each sequence.
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import torch
@@ -136,3 +138,37 @@ def test_plain_equals_dedup_large_bitwise_rows():
                               ratios=True)["ratios"])
     assert np.allclose(rb, ra, rtol=1e-12, atol=0)
     assert np.array_equal(rb, rc)
+
+
+def test_max_lattice_32x32_bf16():
+    """The largest lattice the library admits (32x32, 1024 sites): the
+    matrix-core attention tiles would not fit in LDS, so the vector-unit
+    attention serves.  Forward against the oracle, dedup equal to plain, and
+    sampled ratios recomputed by the oracle."""
+    mc = replace(CONFIGS["small"], name="max32", L=32, d_model=32, n_layers=1,
+                 n_heads=2, d_ff=128, codebook_size=32, precision="bf16",
+                 batch=2, spin_seed=1777)
+    say("bf16 32x32")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    lp, codes = vq.forward_logpsi(cfg, p, sp, codes=True)
+    P = net.unpack(mc, theta)
+    ref = net.forward(mc, P, s)
+    rate, same = check_codes(mc, theta, s, host(codes))
+    assert rate < 1e-3
+    assert np.abs(host(lp)[same] - ref["logpsi"][same]).max(initial=0) < 1e-3
+    ra = host(vq.local_energy(cfg, p, sp, vq.PLAIN, ratios=True)["ratios"])
+    rb = host(vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)["ratios"])
+    assert np.allclose(rb, ra, rtol=1e-12, atol=0)
+    bl = lattice.bonds(mc.L, True)
+    nb = lattice.neighbours(s[0], bl)
+    assert np.count_nonzero(rb[0]) == len(nb)
+    ks = [0, len(nb) // 3, 2 * len(nb) // 3, len(nb) - 1]
+    seqs = np.stack([s[0]] + [lattice.swap(s[0], nb[k][1], nb[k][2])
+                              for k in ks])
+    lps = net.forward(mc, P, seqs)["logpsi"]
+    rel = [abs(rb[0, k] / np.exp(lps[j + 1] - lps[0]) - 1)
+           for j, k in enumerate(ks)]
+    assert sorted(rel)[len(rel) // 2] < 1e-3      # median (near-ties aside)
