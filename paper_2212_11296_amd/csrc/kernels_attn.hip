@@ -54,21 +54,40 @@ struct Tiles {
     __bf16* Qc;   // [Np][2DH]  q hi | q lo (q pre-scaled)
     __bf16* Vt;   // [2DH][ldv] v hi rows then v lo rows, transposed
     int ldv;
-    // Stores row j, column c: k, q*qs and v as hi+lo bfloat16 pairs.  The
-    // scaling and the split are kept free of FMA contraction so that a row
-    // gets the same bits whichever loop stores it (the compiler decides
-    // contraction per inlined copy otherwise).
-    __device__ void put(int j, int c, float k, float qraw, float qs,
-                        float v) const {
+    // Stores columns c4..c4+3 of row j: k, q*qs and v as hi+lo bfloat16
+    // pairs (a row past the sequence, !live, stores zeros).  The scaling and
+    // the split are kept free of FMA contraction so that a row gets the same
+    // bits whichever loop stores it (the compiler decides contraction per
+    // inlined copy otherwise).
+    __device__ void put4(int j, int c4, bool live, float4 k, float4 qraw,
+                         float qs, float4 v) const {
 #pragma clang fp contract(off)
-        const float q = qraw * qs;
-        const __bf16 kh = (__bf16)k, qh = (__bf16)q, vh = (__bf16)v;
-        Kc[j * 2 * DH + c] = kh;
-        Kc[j * 2 * DH + DH + c] = (__bf16)(k - (float)kh);
-        Qc[j * 2 * DH + c] = qh;
-        Qc[j * 2 * DH + DH + c] = (__bf16)(q - (float)qh);
-        Vt[c * ldv + j] = vh;
-        Vt[(DH + c) * ldv + j] = (__bf16)(v - (float)vh);
+        const float kk[4] = {k.x, k.y, k.z, k.w};
+        const float qq[4] = {qraw.x * qs, qraw.y * qs, qraw.z * qs, qraw.w * qs};
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+        bf16x4 kh, kl, qh, ql;
+        __bf16 vh[4], vl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float a = live ? kk[i] : 0.0f;
+            const float b = live ? qq[i] : 0.0f;
+            const float c = live ? vv[i] : 0.0f;
+            kh[i] = (__bf16)a;
+            kl[i] = (__bf16)(a - (float)kh[i]);
+            qh[i] = (__bf16)b;
+            ql[i] = (__bf16)(b - (float)qh[i]);
+            vh[i] = (__bf16)c;
+            vl[i] = (__bf16)(c - (float)vh[i]);
+        }
+        *reinterpret_cast<bf16x4*>(Kc + j * 2 * DH + c4) = kh;
+        *reinterpret_cast<bf16x4*>(Kc + j * 2 * DH + DH + c4) = kl;
+        *reinterpret_cast<bf16x4*>(Qc + j * 2 * DH + c4) = qh;
+        *reinterpret_cast<bf16x4*>(Qc + j * 2 * DH + DH + c4) = ql;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            Vt[(c4 + i) * ldv + j] = vh[i];
+            Vt[(DH + c4 + i) * ldv + j] = vl[i];
+        }
     }
 };
 
@@ -84,22 +103,34 @@ __device__ inline Tiles<DH> carve_tiles(unsigned char* smem, int N) {
 }
 
 // All rows of the sequence at row offset sb (row j at sb + j*d), padded with
-// zero rows to a multiple of 32.
+// zero rows to a multiple of 32.  Four columns per 16-byte load; each
+// thread issues all its loads before the first store (rows past the
+// sequence load row N-1 and store zeros), so the tile costs one round trip
+// to HBM, not one per element.
 template <int DH>
 __device__ inline void load_all(const Tiles<DH>& T, int N, const float* Q,
                                 const float* K, const float* V, int64_t sb,
                                 int d, float qs) {
-    const int Np = npad32(N);
-    for (int e = threadIdx.x; e < Np * DH; e += kAT) {
-        const int j = e / DH, c = e - (e / DH) * DH;
-        float k = 0.0f, q = 0.0f, v = 0.0f;
-        if (j < N) {
-            const int64_t o = sb + (int64_t)j * d + c;
-            k = K[o];
-            q = Q[o];
-            v = V[o];
+    constexpr int G = DH / 4;                 // 4-column groups per row
+    constexpr int UNR = 4;
+    const int tot = npad32(N) * G;
+    for (int e0 = 0; e0 < tot; e0 += kAT * UNR) {
+        float4 k[UNR], q[UNR], v[UNR];
+#pragma unroll
+        for (int i = 0; i < UNR; ++i) {
+            const int e = e0 + kAT * i + threadIdx.x;
+            const int j = e / G, c4 = (e % G) * 4;
+            const int jr = j < N ? j : N - 1;
+            const int64_t o = sb + (int64_t)jr * d + c4;
+            k[i] = *reinterpret_cast<const float4*>(K + o);
+            q[i] = *reinterpret_cast<const float4*>(Q + o);
+            v[i] = *reinterpret_cast<const float4*>(V + o);
         }
-        T.put(j, c, k, q, qs, v);
+#pragma unroll
+        for (int i = 0; i < UNR; ++i) {
+            const int e = e0 + kAT * i + threadIdx.x;
+            if (e < tot) T.put4(e / G, (e % G) * 4, e / G < N, k[i], q[i], qs, v[i]);
+        }
     }
 }
 
@@ -362,12 +393,18 @@ __global__ void __launch_bounds__(kAT) k_attn_seq_mfma(ModelDims m,
 
 // Overlay form: one workgroup per (sample, head) walks the sample's
 // neighbours.  Between two neighbours only rows in either changed set are
-// rewritten, as (row, element) pairs spread over the workgroup.
+// rewritten: the previous neighbour's rows go back to the sample's values
+// (unless the next one changes them too) and the next neighbour's rows take
+// its overlay values.  The next neighbour's row mask is fetched during the
+// current neighbour's compute and kept in LDS; a step then costs two
+// batched round trips to HBM (row indices, then 16-byte value loads).
 template <int DH>
 __global__ void __launch_bounds__(kAT) k_attn_dedup_mfma(ModelDims m,
                                                         DedupIO<PrecBF16> dd,
                                                         int64_t* ctr) {
+    constexpr int G = DH / 4, UNR = 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ uint64_t msk[VQ_MAX_MASK_WORDS];
     const int N = m.N, d = m.d, W = dd.mask_words;
     const Tiles<DH> T = carve_tiles<DH>(smem_raw, N);
     const float qs = kLog2e / sqrtf((float)DH);
@@ -379,35 +416,60 @@ __global__ void __launch_bounds__(kAT) k_attn_dedup_mfma(ModelDims m,
         const int64_t sg = u / m.nh;
         const int h = (int)(u - sg * m.nh);
         const int64_t sb = sg * N * d + h * DH;
+        const int k0 = dd.nb_off[sg], k1 = dd.nb_off[sg + 1];
         __syncthreads();
         load_all<DH>(T, N, dd.bq, dd.bk, dd.bv, sb, d, qs);
-        const int k0 = dd.nb_off[sg], k1 = dd.nb_off[sg + 1];
-        for (int k = k0; k <= k1; ++k) {
+        uint64_t mnext = 0;
+        if (k0 < k1 && threadIdx.x < W) mnext = dd.mask[(int64_t)k0 * W + threadIdx.x];
+        for (int k = k0; k < k1; ++k) {
+            __syncthreads();             // LDS free: load_all or last compute
+            if (threadIdx.x < W) msk[threadIdx.x] = mnext;
             __syncthreads();
-            // the previous neighbour's rows go back to the sample's values
-            // (unless this neighbour changes them too) ...
-            if (k > k0) {
-                const NbDesc P = dd.desc[k - 1];
-                const int cp = dd.ccnt[k - 1];
-                const uint64_t* cur = k < k1 ? dd.mask + (int64_t)k * W : nullptr;
-                for (int e = threadIdx.x; e < cp * DH; e += kAT) {
-                    const int j = dd.crow[P.ov + e / DH], c = e % DH;
-                    if (cur && mbit(cur, j)) continue;
-                    const int64_t o = sb + (int64_t)j * d + c;
-                    T.put(j, c, dd.bk[o], dd.bq[o], qs, dd.bv[o]);
-                }
-            }
-            if (k == k1) break;
-            // ... and this neighbour's changed rows take its overlay values
+            // step (k-1 -> k): restore rows of C_{k-1} not in C_k, patch C_k
+            const int cp = k > k0 ? dd.ccnt[k - 1] : 0;
+            const int64_t pov = k > k0 ? dd.desc[k - 1].ov : 0;
             const NbDesc D = dd.desc[k];
             const int pmin = D.p1 + 1;
             const int cc = dd.ccnt[k];
             const int64_t ob0 = (D.ov - pmin) * (int64_t)d + h * DH;
-            for (int e = threadIdx.x; e < cc * DH; e += kAT) {
-                const int j = dd.crow[D.ov + e / DH], c = e % DH;
-                const int64_t o = ob0 + (int64_t)j * d + c;
-                T.put(j, c, dd.ok[o], dd.oq[o], qs, dd.ov[o]);
+            const int np = cp * G, tot = (cp + cc) * G;
+            for (int e0 = 0; e0 < tot; e0 += kAT * UNR) {
+                int jj[UNR];
+#pragma unroll
+                for (int i = 0; i < UNR; ++i) {
+                    const int e = e0 + kAT * i + threadIdx.x;
+                    const int ec = e < tot ? e : tot - 1;
+                    const int64_t ix = ec < np ? pov + ec / G : D.ov + (ec - np) / G;
+                    jj[i] = dd.crow[ix];
+                }
+                float4 kv[UNR], qv[UNR], vv[UNR];
+                bool use[UNR];
+#pragma unroll
+                for (int i = 0; i < UNR; ++i) {
+                    const int e = e0 + kAT * i + threadIdx.x;
+                    const int ec = e < tot ? e : tot - 1;
+                    const bool restore = ec < np;
+                    const int c4 = ((restore ? ec : ec - np) % G) * 4;
+                    const int j = jj[i];
+                    use[i] = e < tot && !(restore && mbit(msk, j));
+                    const int64_t o = (restore ? sb : ob0) + (int64_t)j * d + c4;
+                    const float* K = restore ? dd.bk : dd.ok;
+                    const float* Q = restore ? dd.bq : dd.oq;
+                    const float* V = restore ? dd.bv : dd.ov;
+                    kv[i] = *reinterpret_cast<const float4*>(K + o);
+                    qv[i] = *reinterpret_cast<const float4*>(Q + o);
+                    vv[i] = *reinterpret_cast<const float4*>(V + o);
+                }
+#pragma unroll
+                for (int i = 0; i < UNR; ++i) {
+                    const int e = e0 + kAT * i + threadIdx.x;
+                    const int ec = e < tot ? e : tot - 1;
+                    const int c4 = ((ec < np ? ec : ec - np) % G) * 4;
+                    if (use[i]) T.put4(jj[i], c4, true, kv[i], qv[i], qs, vv[i]);
+                }
             }
+            if (k + 1 < k1 && threadIdx.x < W)
+                mnext = dd.mask[(int64_t)(k + 1) * W + threadIdx.x];
             __syncthreads();
             wave_tiles<DH>(T, N, NTQ, wave, pmin / 16, pmin,
                            [&](int i) { return dd.oa + ob0 + (int64_t)i * d; });

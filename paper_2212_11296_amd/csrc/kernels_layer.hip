@@ -492,7 +492,10 @@ __global__ void __launch_bounds__(kThreads) k_vq(ModelDims m,
             __syncthreads();
             Top2<acc> best[TR];
 #pragma unroll
-            for (int rr = 0; rr < TR; ++rr) best[rr] = Top2<acc>{inf, 0x7fffffff, inf};
+            // start from code 0: any finite distance replaces it (so results
+            // are unchanged), and a row whose distances are all non-finite
+            // still gets a valid code for the table lookups that follow
+            for (int rr = 0; rr < TR; ++rr) best[rr] = Top2<acc>{inf, 0, inf};
             const acc* cb = w.codebook + (int64_t)hq * m.Q * ds;
             const acc* cn = w.cnorm + (int64_t)hq * m.Q;
             for (int c = threadIdx.x; c < m.Q; c += kThreads) {

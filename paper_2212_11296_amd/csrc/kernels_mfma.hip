@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) best[i][r] = T2{inf, 0x7fffffff, inf};
+                for (int r = 0; r < 4; ++r) best[i][r] = T2{inf, 0, inf};   // see k_vq
             const bf16x8* cbh = cbp + (int64_t)hq * cbtot;
             const float* cn = w.cnorm + (int64_t)hq * m.Q;
             __syncthreads();                 // stage free from the last head

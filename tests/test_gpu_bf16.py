@@ -172,3 +172,34 @@ def test_max_lattice_32x32_bf16():
     rel = [abs(rb[0, k] / np.exp(lps[j + 1] - lps[0]) - 1)
            for j, k in enumerate(ks)]
     assert sorted(rel)[len(rel) // 2] < 1e-3      # median (near-ties aside)
+
+
+@pytest.mark.parametrize("periodic,vq_heads", [(True, 4), (False, 1)],
+                         ids=["periodic_H4", "open_H1"])
+def test_bf16_quantizer_heads_and_open_boundary(periodic, vq_heads):
+    """Matrix-core path with several quantizer heads (segment width 32) and
+    with open boundaries: forward and local energies against the oracle,
+    dedup equal to plain."""
+    mc = replace(CONFIGS["small"], name="h4", L=6, d_model=128, n_layers=2,
+                 n_heads=8, d_ff=512, codebook_size=64, vq_heads=vq_heads,
+                 periodic=periodic, precision="bf16", batch=12,
+                 spin_seed=1781)
+    say(f"bf16 L6 periodic={periodic} H={vq_heads}")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    lp, codes = vq.forward_logpsi(cfg, p, sp, codes=True)
+    ref = net.forward(mc, net.unpack(mc, theta), s)
+    rate, same = check_codes(mc, theta, s, host(codes))
+    assert rate < 1e-3
+    assert same.sum() >= mc.batch // 2
+    assert np.abs(host(lp)[same] - ref["logpsi"][same]).max() < 1e-3
+    a = vq.local_energy(cfg, p, sp, vq.PLAIN, ratios=True)
+    b = vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)
+    assert np.allclose(host(b["ratios"]), host(a["ratios"]), rtol=1e-12, atol=0)
+    E_ref = oeloc.eloc_network_naive(mc, theta, s)
+    E = host(b["eloc"])
+    assert abs(E.mean() - E_ref.mean()) / abs(E_ref.mean()) < 1e-3
+    per = np.abs(E - E_ref) / np.abs(E_ref)
+    assert np.median(per) < 1e-4
