@@ -331,7 +331,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--flags", type=int, default=0,
                     help="1 = certified VQ code reuse")
-    ap.add_argument("--ws-gb", type=float, default=64.0)
+    ap.add_argument("--ws-gb", type=float, default=192.0,
+                    help="workspace cap in GiB (of 288 GB HBM; larger chunks "
+                         "mean fewer, fuller launches)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
