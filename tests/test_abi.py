@@ -98,3 +98,79 @@ def test_workspace_size_grows_with_chunk():
             s8 = vq.workspace_size(c, 64, mode, 8)
             sall = vq.workspace_size(c, 64, mode, 0)
             assert 0 < s1 < s8 < sall
+
+
+def test_gradient_multi_and_tuning_errors_on_host():
+    """Argument errors of the gradient, multi-lattice and tuning entry points
+    are detected on the host, before any HIP call."""
+    lib = vq.load_library()
+    c = _cfg()
+    dummy = ctypes.c_void_p(16)           # never dereferenced: errors first
+    ws = 1 << 20
+    # gradient: null grad, negative batch, null params
+    assert lib.vqnqs_grad_logpsi(ctypes.byref(c), dummy, dummy, 4, None, None,
+                                 None, dummy, ws, None) == 1
+    assert lib.vqnqs_grad_logpsi(ctypes.byref(c), dummy, dummy, -1, None, dummy,
+                                 None, dummy, ws, None) == 3
+    assert lib.vqnqs_grad_logpsi(ctypes.byref(c), None, dummy, 4, None, dummy,
+                                 None, dummy, ws, None) == 1
+    bad = _cfg(d_model=17)
+    assert lib.vqnqs_grad_logpsi(ctypes.byref(bad), dummy, dummy, 4, None,
+                                 dummy, None, dummy, ws, None) == 2
+    # multi-lattice: no jobs, too many jobs, bad mode, bad flags, null eloc
+    jobs = (vq.api.Job * 2)()
+    for j in jobs:
+        j.cfg = c
+        j.params = 16
+        j.spins = 16
+        j.batch = 4
+        j.eloc = 16
+    assert lib.vqnqs_local_energy_multi(jobs, 0, 1, 0, dummy, ws, None) == 3
+    assert lib.vqnqs_local_energy_multi(jobs, 65, 1, 0, dummy, ws, None) == 3
+    assert lib.vqnqs_local_energy_multi(jobs, 2, 7, 0, dummy, ws, None) == 2
+    assert lib.vqnqs_local_energy_multi(jobs, 2, 1, 8, dummy, ws, None) == 2
+    assert lib.vqnqs_local_energy_multi(jobs, 2, 1, 0, None, ws, None) == 1
+    jobs[1].eloc = None
+    assert lib.vqnqs_local_energy_multi(jobs, 2, 1, 0, dummy, ws, None) == 1
+    jobs[1].eloc = 16
+    jobs[0].batch = -1
+    assert lib.vqnqs_local_energy_multi(jobs, 2, 1, 0, dummy, ws, None) == 3
+    jobs[0].batch = 4
+    jobs[0].cfg = bad
+    assert lib.vqnqs_local_energy_multi(jobs, 2, 1, 0, dummy, ws, None) == 2
+    # a workspace that cannot hold every job's minimum
+    jobs[0].cfg = c
+    assert lib.vqnqs_local_energy_multi(jobs, 2, 1, 0, dummy, 1024, None) == 4
+    # tuning: choices the width does not allow, null choices
+    ch = (ctypes.c_int32 * 3)(3, 1, 1)
+    assert lib.vqnqs_set_tuning(ctypes.byref(c), ch) == 2
+    assert lib.vqnqs_set_tuning(ctypes.byref(c), None) == 1
+    large = vq.make_config(CONFIGS["large"])
+    assert lib.vqnqs_set_tuning(ctypes.byref(large),
+                                (ctypes.c_int32 * 3)(2, 1, 4)) == 0
+    assert lib.vqnqs_set_tuning(ctypes.byref(large),
+                                (ctypes.c_int32 * 3)(2, 2, 2)) == 0
+    assert lib.vqnqs_autotune(ctypes.byref(c), dummy, dummy, 4, 5, dummy, ws,
+                              None, None) == 2
+
+
+def test_gradient_and_multi_workspace_sizes():
+    for name in ["small", "medium", "grad"]:
+        c = vq.make_config(CONFIGS[name])
+        s1 = vq.workspace_size(c, 16, vq.WS_GRAD, 1)
+        s4 = vq.workspace_size(c, 16, vq.WS_GRAD, 4)
+        assert 0 < s1 < s4
+        # per-sample gradients of a chunk are held in the workspace
+        assert s4 - s1 >= 3 * vq.param_count(c) * (8 if name == "small" else 4)
+    jobs = [(vq.make_config(m), _Shape(m.batch), _Shape(m.batch))
+            for m in (CONFIGS["small"], CONFIGS["medium"])]
+    total = vq.workspace_size_multi(jobs)
+    parts = sum(vq.workspace_size(cfg, s.shape[0], vq.DEDUP, 0)
+                for cfg, s, _ in jobs)
+    assert parts <= total <= parts + 256 * (len(jobs) + 1)
+
+
+class _Shape:
+    """Stand-in with only a shape, for workspace queries."""
+    def __init__(self, b):
+        self.shape = (b,)
