@@ -486,8 +486,13 @@ struct Runner {
                     int64_t sA, int tA, const acc* B, int64_t ldb, int64_t sB,
                     int tB, acc* C, int64_t ldc, int64_t sC, int beta,
                     int64_t groups) {
+        // B is bf16-exact when it is one of the (rounded) parameters
+        const uintptr_t b = reinterpret_cast<uintptr_t>(B);
+        const uintptr_t p0 = reinterpret_cast<uintptr_t>(params);
+        const int b_exact =
+            m.mfma && b >= p0 && b < p0 + sizeof(acc) * (uintptr_t)param_count(m);
         GemmDesc g{M, Nn, K, A, lda, sA, tA, B, ldb, sB, tB, C, ldc, sC, beta,
-                   groups};
+                   groups, b_exact};
         // the BF16 mode runs its products on the matrix core
         if constexpr (std::is_same<P, PrecBF16>::value)
             if (m.mfma) return launch_gemm_mfma(g, st);

@@ -196,6 +196,7 @@ struct GemmDesc {
     int64_t ldc, sC;
     int beta;
     int64_t groups;
+    int b_exact;   // matrix-core form: B is bf16-exact (its lo part is zero)
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& g, hipStream_t st);

@@ -115,7 +115,8 @@ hipError_t launch_gemm(const GemmDesc& g, hipStream_t st) {
 // ------------------------------------------------ GEMM on the matrix core
 // FP32 operands enter the bf16 matrix core as hi + lo pairs; three passes
 // hi.hi + hi.lo + lo.hi accumulate in FP32 (about 16 significant bits per
-// product; the lo.lo term is below that).  Workgroup tile 128 x 128, each of
+// product; the lo.lo term is below that).  When B is bf16-exact (the
+// BF16 mode's weights) its lo part is zero and the hi.lo pass is skipped.  Workgroup tile 128 x 128, each of
 // the four waves 64 x 64 (4 x 4 tiles of 16 x 16), K steps of 32.  The
 // operands are staged in LDS as [row][k] (A) and [col][k] (B), so every
 // MFMA fragment is one 16-byte read per lane whatever the transposition.
@@ -199,7 +200,8 @@ __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+                if (!g.b_exact)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
             }
         }
