@@ -146,6 +146,13 @@ constexpr float kTau = 8.0f;
 
 typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 
+// Maximum of two scores, NaN-propagating: it maps to v_maximum3_f32 and
+// needs no quieting of the matrix-core results it reads (the maximum only
+// decides when and by how much a reference is raised).
+__device__ inline float vmax(float a, float b) {
+    return __builtin_elementwise_maximum(a, b);
+}
+
 // p as hi+lo bfloat16: hi is p truncated to its upper 16 bits, lo the exact
 // remainder rounded to bfloat16 (relative error of hi+lo at most 2^-16).
 __device__ inline void split_p(const float* p, bf16x8& ph, bf16x8& pl) {
@@ -238,11 +245,11 @@ __device__ inline void qtile_block(QTile<DH>& q, int N, int blk,
     }
     float lm = s[0];
 #pragma unroll
-    for (int k = 1; k < 8; ++k) lm = __builtin_fmaxf(lm, s[k]);
+    for (int k = 1; k < 8; ++k) lm = vmax(lm, s[k]);
     const bool first = blk == 0;
     if (first || __builtin_amdgcn_ballot_w64(lm > kTau) != 0) {
-        float dm = __builtin_fmaxf(lm, __shfl_xor(lm, 16, 64));
-        dm = __builtin_fmaxf(dm, __shfl_xor(dm, 32, 64));
+        float dm = vmax(lm, __shfl_xor(lm, 16, 64));
+        dm = vmax(dm, __shfl_xor(dm, 32, 64));
         // the first block sets the reference to its maximum; later blocks
         // raise it only past kTau
         const float delta = first ? dm : (dm > kTau ? dm : 0.0f);
@@ -277,6 +284,85 @@ __device__ inline void qtile_block(QTile<DH>& q, int N, int blk,
     }
 }
 
+// An interior block (not the first; every key of it at or before every
+// query of the tiles, and inside the sequence) for NQ tiles in lock step:
+// no masking, and one wave-uniform branch that is taken only when some
+// tile's reference must be raised.  The tiles' chains are independent and
+// straight-line, so the scheduler can interleave one tile's exponentials with
+// another's matrix-core work.  Per query the operations, their order and
+// their operands are those of qtile_block.
+template <int DH, int NQ>
+__device__ inline void qtiles_block_interior(QTile<DH> (&q)[NQ],
+                                             const bf16x8 (&ka)[2],
+                                             const bf16x8 (&kb)[2],
+                                             const bf16x8 (&vh)[DH / 16],
+                                             const bf16x8 (&vl)[DH / 16],
+                                             const bf16x8& ones) {
+    float s[NQ][8], lm[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            f32x4 acc;
+            if (DH == 16) {
+                acc = mfma_a(ka[sub], q[i].b0, q[i].negm);
+                acc = mfma_a(ka[sub], q[i].b1, acc);
+            } else {
+                acc = mfma_a(ka[sub], q[i].b0, q[i].negm);
+                acc = mfma_a(kb[sub], q[i].b1, acc);
+                acc = mfma_a(ka[sub], q[i].b2, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s[i][sub * 4 + r] = acc[r];
+        }
+    }
+    bool raise = false;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        lm[i] = s[i][0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) lm[i] = vmax(lm[i], s[i][k]);
+        raise = raise || lm[i] > kTau;
+    }
+    if (__builtin_amdgcn_ballot_w64(raise) != 0) {
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            float dm = vmax(lm[i], __shfl_xor(lm[i], 16, 64));
+            dm = vmax(dm, __shfl_xor(dm, 32, 64));
+            const float delta = dm > kTau ? dm : 0.0f;
+            if (delta != 0.0f) {
+                const float alpha = __builtin_amdgcn_exp2f(-delta);
+#pragma unroll
+                for (int u = 0; u < DH / 16; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) q[i].o[u][r] *= alpha;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) q[i].osum[r] *= alpha;
+                q[i].mref += delta;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) s[i][k] -= delta;
+                q[i].negm = f32x4{-q[i].mref, -q[i].mref, -q[i].mref, -q[i].mref};
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        float p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] = __builtin_amdgcn_exp2f(s[i][k]);
+        bf16x8 ph, pl;
+        split_p(p, ph, pl);
+        q[i].osum = mfma_a(ones, ph, q[i].osum);
+        q[i].osum = mfma_a(ones, pl, q[i].osum);
+#pragma unroll
+        for (int u = 0; u < DH / 16; ++u) {
+            q[i].o[u] = mfma_a(vh[u], ph, q[i].o[u]);
+            q[i].o[u] = mfma_a(vl[u], ph, q[i].o[u]);
+            q[i].o[u] = mfma_a(vh[u], pl, q[i].o[u]);
+        }
+    }
+}
+
 // NQ query tiles tq[0] > tq[1] > ... of one wave against keys 0..16t+15 held
 // in LDS: the tiles share every K and V fragment read and their softmax
 // chains are independent, so the vector unit and the matrix core see NQ
@@ -294,10 +380,10 @@ __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ]
     bf16x8 ones;
 #pragma unroll
     for (int k = 0; k < 8; ++k) ones[k] = (__bf16)1.0f;
-    const int nblk = q[0].nblk;
-    for (int blk = 0; blk < nblk; ++blk) {
+    // K and V fragments of the 32-key block blk
+    auto frags = [&](int blk, bf16x8(&ka)[2], bf16x8(&kb)[2], bf16x8(&vh)[NT],
+                     bf16x8(&vl)[NT]) {
         const int j0 = blk * 32;
-        bf16x8 ka[2], kb[2];
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
             const __bf16* kr = T.Kc + (j0 + sub * 16 + c16) * 2 * DH;
@@ -305,7 +391,6 @@ __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ]
             kb[sub] = DH == 16 ? ka[sub]
                                : *reinterpret_cast<const bf16x8*>(kr + DH + 8 * g);
         }
-        bf16x8 vh[NT], vl[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
             const int vc = u * 16 + c16;
@@ -318,11 +403,27 @@ __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ]
             vh[u] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
             vl[u] = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
         }
+    };
+    auto general = [&](int blk) {
+        bf16x8 ka[2], kb[2], vh[NT], vl[NT];
+        frags(blk, ka, kb, vh, vl);
 #pragma unroll
         for (int i = 0; i < NQ; ++i)
             if (blk < q[i].nblk)
                 qtile_block<DH>(q[i], N, blk, ka, kb, vh, vl, ones);
+    };
+    const int nblk = q[0].nblk;
+    // blocks 1..last are interior for every tile: 32 blk + 31 <= 16 t_min
+    // and 32 blk + 31 < N
+    const int jl = min(16 * tq[NQ - 1] - 31, N - 32);
+    const int last = jl >= 0 ? jl / 32 : 0;
+    general(0);
+    for (int blk = 1; blk <= last; ++blk) {
+        bf16x8 ka[2], kb[2], vh[NT], vl[NT];
+        frags(blk, ka, kb, vh, vl);
+        qtiles_block_interior<DH, NQ>(q, ka, kb, vh, vl, ones);
     }
+    for (int blk = last + 1; blk < nblk; ++blk) general(blk);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         if (q[i].iq >= lo && q[i].iq < N) {
@@ -358,9 +459,17 @@ __device__ inline void wave_tiles(const Tiles<DH>& T, int N, int NTQ, int w,
     }
 }
 
+// WPE: waves per SIMD the register allocation must allow (1: no cap).  Where
+// the LDS tiles leave room for three workgroups per CU (head width 16 up to
+// 16x16 lattices), the capped instance runs a third wave per SIMD, which
+// hides much of the latency of the per-block chain (score MFMAs, maximum,
+// exponentials, output MFMAs); the cap costs a few spills of loop-invariant
+// values.  Elsewhere the uncapped instance runs.
+
 // Full sequences (the samples themselves, or materialised neighbours).
-template <int DH>
-__global__ void __launch_bounds__(kAT) k_attn_seq_mfma(ModelDims m,
+template <int DH, int WPE>
+__global__ void __launch_bounds__(kAT) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_attn_seq_mfma(ModelDims m,
                                                       const int32_t* n_dev,
                                                       int64_t n_seq,
                                                       BlockIO<PrecBF16> io,
@@ -398,8 +507,9 @@ __global__ void __launch_bounds__(kAT) k_attn_seq_mfma(ModelDims m,
 // its overlay values.  The next neighbour's row mask is fetched during the
 // current neighbour's compute and kept in LDS; a step then costs two
 // batched round trips to HBM (row indices, then 16-byte value loads).
-template <int DH>
-__global__ void __launch_bounds__(kAT) k_attn_dedup_mfma(ModelDims m,
+template <int DH, int WPE>
+__global__ void __launch_bounds__(kAT) __attribute__((amdgpu_waves_per_eu(WPE)))
+k_attn_dedup_mfma(ModelDims m,
                                                         DedupIO<PrecBF16> dd,
                                                         int64_t* ctr) {
     constexpr int G = DH / 4, UNR = 2;
@@ -512,22 +622,30 @@ static void big_lds(F f, size_t sm) {
                                   (int)sm);
 }
 
+// Workgroups per CU that the LDS of one (sequence, head) allows.
+static int attn_wg_per_cu(const ModelDims& m) {
+    return (int)((160 * 1024) /
+                 (attn_lds(m) + sizeof(uint64_t) * VQ_MAX_MASK_WORDS));
+}
+
 hipError_t launch_attn_seq_mfma(const ModelDims& m, const int32_t* n_dev,
                                 int64_t n_seq, const BlockIO<PrecBF16>& io,
                                 int64_t* ctr, hipStream_t st) {
     const size_t sm = attn_lds(m);
     const unsigned g = agrid(n_seq * m.nh);
-    if (m.dh == 16) {
-        big_lds(k_attn_seq_mfma<16>, sm);
-        hipLaunchKernelGGL(k_attn_seq_mfma<16>, dim3(g), dim3(kAT), sm, st, m,
-                           n_dev, n_seq, io, ctr);
-    } else if (m.dh == 32) {
-        big_lds(k_attn_seq_mfma<32>, sm);
-        hipLaunchKernelGGL(k_attn_seq_mfma<32>, dim3(g), dim3(kAT), sm, st, m,
-                           n_dev, n_seq, io, ctr);
-    } else {
+    auto go = [&](auto kern) {
+        big_lds(kern, sm);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kAT), sm, st, m, n_dev, n_seq,
+                           io, ctr);
+    };
+    if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
+        go(k_attn_seq_mfma<16, 3>);
+    else if (m.dh == 16)
+        go(k_attn_seq_mfma<16, 1>);
+    else if (m.dh == 32)
+        go(k_attn_seq_mfma<32, 1>);
+    else
         return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
@@ -536,17 +654,18 @@ hipError_t launch_attn_dedup_mfma(const ModelDims& m,
                                   hipStream_t st) {
     const size_t sm = attn_lds(m);
     const unsigned g = agrid(d.n_samples * m.nh);
-    if (m.dh == 16) {
-        big_lds(k_attn_dedup_mfma<16>, sm);
-        hipLaunchKernelGGL(k_attn_dedup_mfma<16>, dim3(g), dim3(kAT), sm, st,
-                           m, d, ctr);
-    } else if (m.dh == 32) {
-        big_lds(k_attn_dedup_mfma<32>, sm);
-        hipLaunchKernelGGL(k_attn_dedup_mfma<32>, dim3(g), dim3(kAT), sm, st,
-                           m, d, ctr);
-    } else {
+    auto go = [&](auto kern) {
+        big_lds(kern, sm);
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kAT), sm, st, m, d, ctr);
+    };
+    if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
+        go(k_attn_dedup_mfma<16, 3>);
+    else if (m.dh == 16)
+        go(k_attn_dedup_mfma<16, 1>);
+    else if (m.dh == 32)
+        go(k_attn_dedup_mfma<32, 1>);
+    else
         return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
