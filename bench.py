@@ -23,12 +23,15 @@ METRIC = ("local-energy evals/sec, VQ-dedup vs plain on 1 MI355X, at "
 UNIT = "local-energy evals/s"
 PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}     # TFLOP/s, dense
 HBM_PEAK = 8000.0                                         # GB/s
-# Attention at head width 16-32 is bound by the vector unit, not the matrix
-# core: every (query, key) pair needs one exponential, a quarter-rate
-# transcendental.  256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz / 4 = 9.83e12
+# Attention at head width 16-32 is bound by the vector unit, not by the
+# algorithmic matrix-core work: every (query, key) pair needs one
+# exponential, and v_exp_f32 issues at half the rate of plain FP32 VALU
+# instructions on gfx950 (8 lanes per SIMD per cycle; a timing probe of
+# independent exponential chains gives 7.47 lane-ops per SIMD-cycle against
+# 14.7 for additions).  256 CUs x 4 SIMDs x 8 x 2.4 GHz = 1.97e13
 # exponentials per second bound the pair rate; the attention peak is that
 # rate times the algorithmic FLOPs of a pair (4 d_head: q.k and p.v).
-EXP_RATE = 256 * 4 * 16 * 2.4e9 / 4
+EXP_RATE = 256 * 4 * 8 * 2.4e9
 TRAFFIC_FILE = "profiles/attention_dedup_16x16_bf16__hbm_traffic.json"
 
 

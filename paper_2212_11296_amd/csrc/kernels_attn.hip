@@ -209,95 +209,24 @@ __device__ inline void qtile_init(QTile<DH>& q, const Tiles<DH>& T, int t) {
     q.mref = 0.0f;
 }
 
-// One 32-key block (keys j0..j0+31) for one query tile, from the block's K
-// fragments ka/kb (per 16-key sub-tile) and V fragments vh/vl.
-template <int DH>
-__device__ inline void qtile_block(QTile<DH>& q, int N, int blk,
-                                   const bf16x8 (&ka)[2], const bf16x8 (&kb)[2],
-                                   const bf16x8 (&vh)[DH / 16],
-                                   const bf16x8 (&vl)[DH / 16],
-                                   const bf16x8& ones) {
+// One 32-key block (keys j0..j0+31) for NQ query tiles in lock step, from
+// the block's K fragments ka/kb (per 16-key sub-tile) and V fragments
+// vh/vl.  EDGE: the block may hold keys after a tile's queries or past the
+// sequence (they are masked), or be the first block (it sets the
+// references).  Otherwise the block is straight-line code apart from one
+// wave-uniform branch, taken only when some reference must be raised; the
+// tiles' chains are independent, so the scheduler interleaves one tile's
+// exponentials with another's matrix-core work.  Per query the operations
+// and their order do not depend on NQ or on which tiles share the block.
+template <int DH, int NQ, bool EDGE>
+__device__ inline void qtiles_block(QTile<DH> (&q)[NQ], int N, int blk,
+                                    const bf16x8 (&ka)[2], const bf16x8 (&kb)[2],
+                                    const bf16x8 (&vh)[DH / 16],
+                                    const bf16x8 (&vl)[DH / 16],
+                                    const bf16x8& ones) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
     const int j0 = blk * 32;
-    float s[8];
-#pragma unroll
-    for (int sub = 0; sub < 2; ++sub) {
-        f32x4 acc;
-        if (DH == 16) {
-            acc = mfma_a(ka[sub], q.b0, q.negm);
-            acc = mfma_a(ka[sub], q.b1, acc);
-        } else {
-            acc = mfma_a(ka[sub], q.b0, q.negm);
-            acc = mfma_a(kb[sub], q.b1, acc);
-            acc = mfma_a(ka[sub], q.b2, acc);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) s[sub * 4 + r] = acc[r];
-    }
-    // keys beyond the query (or the sequence) only in the last blocks
-    if (j0 + 31 > q.t * 16 || j0 + 31 >= N) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int key = j0 + (k >> 2) * 16 + 4 * g + (k & 3);
-            if (key > q.iq || key >= N) s[k] = -__builtin_inff();
-        }
-    }
-    float lm = s[0];
-#pragma unroll
-    for (int k = 1; k < 8; ++k) lm = vmax(lm, s[k]);
-    const bool first = blk == 0;
-    if (first || __builtin_amdgcn_ballot_w64(lm > kTau) != 0) {
-        float dm = vmax(lm, __shfl_xor(lm, 16, 64));
-        dm = vmax(dm, __shfl_xor(dm, 32, 64));
-        // the first block sets the reference to its maximum; later blocks
-        // raise it only past kTau
-        const float delta = first ? dm : (dm > kTau ? dm : 0.0f);
-        if (delta != 0.0f) {
-            if (!first) {
-                const float alpha = __builtin_amdgcn_exp2f(-delta);
-#pragma unroll
-                for (int u = 0; u < DH / 16; ++u)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) q.o[u][r] *= alpha;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) q.osum[r] *= alpha;
-            }
-            q.mref += delta;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s[k] -= delta;
-            q.negm = f32x4{-q.mref, -q.mref, -q.mref, -q.mref};
-        }
-    }
-    float p[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) p[k] = __builtin_amdgcn_exp2f(s[k]);
-    bf16x8 ph, pl;
-    split_p(p, ph, pl);
-    q.osum = mfma_a(ones, ph, q.osum);
-    q.osum = mfma_a(ones, pl, q.osum);
-#pragma unroll
-    for (int u = 0; u < DH / 16; ++u) {
-        q.o[u] = mfma_a(vh[u], ph, q.o[u]);
-        q.o[u] = mfma_a(vl[u], ph, q.o[u]);
-        q.o[u] = mfma_a(vh[u], pl, q.o[u]);
-    }
-}
-
-// An interior block (not the first; every key of it at or before every
-// query of the tiles, and inside the sequence) for NQ tiles in lock step:
-// no masking, and one wave-uniform branch that is taken only when some
-// tile's reference must be raised.  The tiles' chains are independent and
-// straight-line, so the scheduler can interleave one tile's exponentials with
-// another's matrix-core work.  Per query the operations, their order and
-// their operands are those of qtile_block.
-template <int DH, int NQ>
-__device__ inline void qtiles_block_interior(QTile<DH> (&q)[NQ],
-                                             const bf16x8 (&ka)[2],
-                                             const bf16x8 (&kb)[2],
-                                             const bf16x8 (&vh)[DH / 16],
-                                             const bf16x8 (&vl)[DH / 16],
-                                             const bf16x8& ones) {
     float s[NQ][8], lm[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -316,7 +245,21 @@ __device__ inline void qtiles_block_interior(QTile<DH> (&q)[NQ],
             for (int r = 0; r < 4; ++r) s[i][sub * 4 + r] = acc[r];
         }
     }
-    bool raise = false;
+    if (EDGE) {
+        // keys beyond the query (or the sequence)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            if (j0 + 31 > q[i].t * 16 || j0 + 31 >= N) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int key = j0 + (k >> 2) * 16 + 4 * g + (k & 3);
+                    if (key > q[i].iq || key >= N) s[i][k] = -__builtin_inff();
+                }
+            }
+        }
+    }
+    const bool first = EDGE && blk == 0;
+    bool raise = first;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         lm[i] = s[i][0];
@@ -329,15 +272,19 @@ __device__ inline void qtiles_block_interior(QTile<DH> (&q)[NQ],
         for (int i = 0; i < NQ; ++i) {
             float dm = vmax(lm[i], __shfl_xor(lm[i], 16, 64));
             dm = vmax(dm, __shfl_xor(dm, 32, 64));
-            const float delta = dm > kTau ? dm : 0.0f;
+            // the first block sets the reference to its maximum; later
+            // blocks raise it only past kTau
+            const float delta = first ? dm : (dm > kTau ? dm : 0.0f);
             if (delta != 0.0f) {
-                const float alpha = __builtin_amdgcn_exp2f(-delta);
+                if (!first) {
+                    const float alpha = __builtin_amdgcn_exp2f(-delta);
 #pragma unroll
-                for (int u = 0; u < DH / 16; ++u)
+                    for (int u = 0; u < DH / 16; ++u)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) q[i].o[u][r] *= alpha;
+                        for (int r = 0; r < 4; ++r) q[i].o[u][r] *= alpha;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) q[i].osum[r] *= alpha;
+                    for (int r = 0; r < 4; ++r) q[i].osum[r] *= alpha;
+                }
                 q[i].mref += delta;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) s[i][k] -= delta;
@@ -363,16 +310,71 @@ __device__ inline void qtiles_block_interior(QTile<DH> (&q)[NQ],
     }
 }
 
-// NQ query tiles tq[0] > tq[1] > ... of one wave against keys 0..16t+15 held
-// in LDS: the tiles share every K and V fragment read and their softmax
-// chains are independent, so the vector unit and the matrix core see NQ
-// times the independent work of one tile.  Writes rows i >= lo (and < N)
-// through orow(i).  Each tile's arithmetic is the same as on its own.
+// K and V fragments of the 32-key block blk.
+template <int DH>
+__device__ inline void block_frags(const Tiles<DH>& T, int blk, bf16x8 (&ka)[2],
+                                   bf16x8 (&kb)[2], bf16x8 (&vh)[DH / 16],
+                                   bf16x8 (&vl)[DH / 16]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    const int j0 = blk * 32;
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+        const __bf16* kr = T.Kc + (j0 + sub * 16 + c16) * 2 * DH;
+        ka[sub] = *reinterpret_cast<const bf16x8*>(kr + 8 * g);
+        kb[sub] = DH == 16 ? ka[sub]
+                           : *reinterpret_cast<const bf16x8*>(kr + DH + 8 * g);
+    }
+#pragma unroll
+    for (int u = 0; u < DH / 16; ++u) {
+        const int vc = u * 16 + c16;
+        const __bf16* vh_row = T.Vt + vc * T.ldv + j0 + 4 * g;
+        const __bf16* vl_row = T.Vt + (DH + vc) * T.ldv + j0 + 4 * g;
+        const bf16x4 h0 = *reinterpret_cast<const bf16x4*>(vh_row);
+        const bf16x4 h1 = *reinterpret_cast<const bf16x4*>(vh_row + 16);
+        const bf16x4 l0 = *reinterpret_cast<const bf16x4*>(vl_row);
+        const bf16x4 l1 = *reinterpret_cast<const bf16x4*>(vl_row + 16);
+        vh[u] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+        vl[u] = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
+}
+
+// Blocks [b0, b1) for NQ tiles, all of which have at least b1 blocks; the
+// smallest tile is tq_min.  Blocks 1..last need no mask for any tile
+// (32 blk + 31 <= 16 tq_min and 32 blk + 31 < N): they run the straight-line
+// form, the others the edge form.
+template <int DH, int NQ>
+__device__ inline void run_blocks(const Tiles<DH>& T, QTile<DH> (&q)[NQ], int N,
+                                  int tq_min, int b0, int b1,
+                                  const bf16x8& ones) {
+    constexpr int NT = DH / 16;
+    const int jl = min(16 * tq_min - 31, N - 32);
+    const int last = jl >= 0 ? jl / 32 : 0;
+    const int i0 = max(b0, 1), i1 = min(b1, last + 1);
+    auto edge = [&](int blk) {
+        bf16x8 ka[2], kb[2], vh[NT], vl[NT];
+        block_frags<DH>(T, blk, ka, kb, vh, vl);
+        qtiles_block<DH, NQ, true>(q, N, blk, ka, kb, vh, vl, ones);
+    };
+    if (b0 == 0 && b1 > 0) edge(0);
+    for (int blk = i0; blk < i1; ++blk) {
+        bf16x8 ka[2], kb[2], vh[NT], vl[NT];
+        block_frags<DH>(T, blk, ka, kb, vh, vl);
+        qtiles_block<DH, NQ, false>(q, N, blk, ka, kb, vh, vl, ones);
+    }
+    for (int blk = max(i0, i1); blk < b1; ++blk) edge(blk);
+}
+
+// Query tiles tq[0] >= tq[1] (NQ = 2) or tq[0] of one wave against the keys
+// held in LDS.  The tiles advance in lock step, sharing every K and V
+// fragment read, over the blocks they both have; the larger tile then runs
+// its remaining blocks alone.  Writes rows i >= lo (and < N) through
+// orow(i).
 template <int DH, int NQ, class OF>
 __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ],
                                   int lo, OF orow) {
     const int lane = threadIdx.x & 63;
-    const int g = lane >> 4, c16 = lane & 15;
+    const int g = lane >> 4;
     constexpr int NT = DH / 16;
     QTile<DH> q[NQ];
 #pragma unroll
@@ -380,50 +382,13 @@ __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ]
     bf16x8 ones;
 #pragma unroll
     for (int k = 0; k < 8; ++k) ones[k] = (__bf16)1.0f;
-    // K and V fragments of the 32-key block blk
-    auto frags = [&](int blk, bf16x8(&ka)[2], bf16x8(&kb)[2], bf16x8(&vh)[NT],
-                     bf16x8(&vl)[NT]) {
-        const int j0 = blk * 32;
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-            const __bf16* kr = T.Kc + (j0 + sub * 16 + c16) * 2 * DH;
-            ka[sub] = *reinterpret_cast<const bf16x8*>(kr + 8 * g);
-            kb[sub] = DH == 16 ? ka[sub]
-                               : *reinterpret_cast<const bf16x8*>(kr + DH + 8 * g);
-        }
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            const int vc = u * 16 + c16;
-            const __bf16* vh_row = T.Vt + vc * T.ldv + j0 + 4 * g;
-            const __bf16* vl_row = T.Vt + (DH + vc) * T.ldv + j0 + 4 * g;
-            const bf16x4 h0 = *reinterpret_cast<const bf16x4*>(vh_row);
-            const bf16x4 h1 = *reinterpret_cast<const bf16x4*>(vh_row + 16);
-            const bf16x4 l0 = *reinterpret_cast<const bf16x4*>(vl_row);
-            const bf16x4 l1 = *reinterpret_cast<const bf16x4*>(vl_row + 16);
-            vh[u] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
-            vl[u] = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
-        }
-    };
-    auto general = [&](int blk) {
-        bf16x8 ka[2], kb[2], vh[NT], vl[NT];
-        frags(blk, ka, kb, vh, vl);
-#pragma unroll
-        for (int i = 0; i < NQ; ++i)
-            if (blk < q[i].nblk)
-                qtile_block<DH>(q[i], N, blk, ka, kb, vh, vl, ones);
-    };
-    const int nblk = q[0].nblk;
-    // blocks 1..last are interior for every tile: 32 blk + 31 <= 16 t_min
-    // and 32 blk + 31 < N
-    const int jl = min(16 * tq[NQ - 1] - 31, N - 32);
-    const int last = jl >= 0 ? jl / 32 : 0;
-    general(0);
-    for (int blk = 1; blk <= last; ++blk) {
-        bf16x8 ka[2], kb[2], vh[NT], vl[NT];
-        frags(blk, ka, kb, vh, vl);
-        qtiles_block_interior<DH, NQ>(q, ka, kb, vh, vl, ones);
+    QTile<DH>(&q0)[1] = *reinterpret_cast<QTile<DH>(*)[1]>(&q[0]);
+    if (NQ == 2) {
+        run_blocks<DH, NQ>(T, q, N, tq[NQ - 1], 0, q[NQ - 1].nblk, ones);
+        run_blocks<DH, 1>(T, q0, N, tq[0], q[NQ - 1].nblk, q[0].nblk, ones);
+    } else {
+        run_blocks<DH, 1>(T, q0, N, tq[0], 0, q[0].nblk, ones);
     }
-    for (int blk = last + 1; blk < nblk; ++blk) general(blk);
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         if (q[i].iq >= lo && q[i].iq < N) {
@@ -442,12 +407,36 @@ __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ]
     }
 }
 
-// The query tiles of wave w, from the last down in steps of 4, two at a
-// time (the last one alone when their number is odd); tiles below tmin are
-// not computed.
+// Active tiles (tmin..NTQ-1) from which adjacent tiles are paired.
+constexpr int kPairTiles = 12;
+
+// The query tiles of wave w (of 4), tiles below tmin not computed.  With at
+// least kPairTiles active tiles, tiles are paired as (2k+1, 2k), which have
+// the same k+1 key blocks, and the pairs, from the largest k down, are dealt
+// to the waves in snake order (0 1 2 3 3 2 1 0 ...), which evens out the
+// blocks per wave.  With fewer, wave w takes tiles NTQ-1-w, NTQ-5-w, ...,
+// two at a time, so that every wave has work.
 template <int DH, class OF>
 __device__ inline void wave_tiles(const Tiles<DH>& T, int N, int NTQ, int w,
                                   int tmin, int lo, OF orow) {
+    if (NTQ - tmin >= kPairTiles) {
+        const int K = (NTQ + 1) / 2;          // pairs
+        const int kmin = tmin / 2;
+        for (int i = 0; i < K - kmin; ++i) {
+            const int r = i & 7;
+            if ((r < 4 ? r : 7 - r) != w) continue;
+            const int k = K - 1 - i;
+            const int hi = 2 * k + 1, lo2 = 2 * k;
+            if (hi < NTQ && lo2 >= tmin) {
+                const int tq[2] = {hi, lo2};
+                attn_tiles<DH, 2>(T, N, tq, lo, orow);
+            } else {
+                const int tq[1] = {hi < NTQ ? hi : lo2};
+                attn_tiles<DH, 1>(T, N, tq, lo, orow);
+            }
+        }
+        return;
+    }
     int t = NTQ - 1 - w;
     for (; t - 4 >= tmin; t -= 8) {
         const int tq[2] = {t, t - 4};
@@ -544,9 +533,14 @@ k_attn_dedup_mfma(ModelDims m,
             const int64_t ob0 = (D.ov - pmin) * (int64_t)d + h * DH;
             const int np = cp * G, tot = (cp + cc) * G;
             for (int e0 = 0; e0 < tot; e0 += kAT * UNR) {
+                // a wave skips the elements none of its lanes has
+                bool act[UNR];
+#pragma unroll
+                for (int i = 0; i < UNR; ++i) act[i] = e0 + kAT * i + 64 * wave < tot;
                 int jj[UNR];
 #pragma unroll
                 for (int i = 0; i < UNR; ++i) {
+                    if (!act[i]) continue;
                     const int e = e0 + kAT * i + threadIdx.x;
                     const int ec = e < tot ? e : tot - 1;
                     const int64_t ix = ec < np ? pov + ec / G : D.ov + (ec - np) / G;
@@ -556,6 +550,7 @@ k_attn_dedup_mfma(ModelDims m,
                 bool use[UNR];
 #pragma unroll
                 for (int i = 0; i < UNR; ++i) {
+                    if (!act[i]) continue;
                     const int e = e0 + kAT * i + threadIdx.x;
                     const int ec = e < tot ? e : tot - 1;
                     const bool restore = ec < np;
@@ -572,6 +567,7 @@ k_attn_dedup_mfma(ModelDims m,
                 }
 #pragma unroll
                 for (int i = 0; i < UNR; ++i) {
+                    if (!act[i]) continue;
                     const int e = e0 + kAT * i + threadIdx.x;
                     const int ec = e < tot ? e : tot - 1;
                     const int c4 = ((ec < np ? ec : ec - np) % G) * 4;

@@ -392,26 +392,50 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
             slot[i] = r < n ? rs_slot(rows, r) : -1;
         }
         // x' = x_in + (b_o + sum_h table) in A-fragment positions, kept in
-        // registers (never written and re-read through global memory)
+        // registers (never written and re-read through global memory).  A
+        // lane's 8 columns per k-block are contiguous: 16-byte loads, all of
+        // one quantizer head issued together, the next head's code loading
+        // meanwhile (one round trip per head, not one per element).
         float xv[MB][KB1][8];
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
-            const float* x = slot[i] >= 0 ? io.x_in + slot[i] * D : nullptr;
-            const int32_t* cd = slot[i] >= 0 ? io.codes + slot[i] * m.H : nullptr;
+            const bool live = slot[i] >= 0;
+            const int64_t sl = live ? slot[i] : 0;
+            const float* x = io.x_in + sl * D;
+            const int32_t* cd = io.codes + sl * m.H;
+            float z[KB1][8], xin[KB1][8];
+            int cnext = live ? cd[0] : 0;
 #pragma unroll
             for (int kb = 0; kb < KB1; ++kb)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int k = kb * 32 + 8 * gq + j;
-                    float val = 0.0f;
-                    if (x) {
-                        float z = w.b_o[k];
-                        for (int hq = 0; hq < m.H; ++hq)
-                            z += w.table[((int64_t)hq * m.Q + cd[hq]) * D + k];
-                        val = x[k] + z;
-                    }
-                    xv[i][kb][j] = val;
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const int k = kb * 32 + 8 * gq + 4 * h2;
+                    const float4 xa = *reinterpret_cast<const float4*>(x + k);
+                    const float4 ba = *reinterpret_cast<const float4*>(w.b_o + k);
+                    xin[kb][4 * h2 + 0] = xa.x; xin[kb][4 * h2 + 1] = xa.y;
+                    xin[kb][4 * h2 + 2] = xa.z; xin[kb][4 * h2 + 3] = xa.w;
+                    z[kb][4 * h2 + 0] = ba.x; z[kb][4 * h2 + 1] = ba.y;
+                    z[kb][4 * h2 + 2] = ba.z; z[kb][4 * h2 + 3] = ba.w;
                 }
+            for (int hq = 0; hq < m.H; ++hq) {
+                const int c = cnext;
+                if (hq + 1 < m.H) cnext = live ? cd[hq + 1] : 0;
+                const float* tr = w.table + ((int64_t)hq * m.Q + c) * D;
+#pragma unroll
+                for (int kb = 0; kb < KB1; ++kb)
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int k = kb * 32 + 8 * gq + 4 * h2;
+                        const float4 ta = *reinterpret_cast<const float4*>(tr + k);
+                        z[kb][4 * h2 + 0] += ta.x; z[kb][4 * h2 + 1] += ta.y;
+                        z[kb][4 * h2 + 2] += ta.z; z[kb][4 * h2 + 3] += ta.w;
+                    }
+            }
+#pragma unroll
+            for (int kb = 0; kb < KB1; ++kb)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    xv[i][kb][j] = live ? xin[kb][j] + z[kb][j] : 0.0f;
         }
         bf16x8 ah[MB][KB1], al[MB][KB1];
         ln_frags_v<KB1, MB>(xv, w.ln2_g, w.ln2_b, ah, al);
@@ -486,26 +510,58 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
         }
         // x = x' + hidden W2 + b2, with x' recomputed for this lane's
         // elements in the prologue's addition order: every element is read
-        // and written by one lane only, also when x_in and x coincide
+        // and written by one lane only, also when x_in and x coincide.  All
+        // loads of a fragment's four rows are issued before its first store.
 #pragma unroll
-        for (int i = 0; i < MB; ++i)
+        for (int i = 0; i < MB; ++i) {
+            int64_t s4[4];
+            bool v4[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t s = __shfl(slot[i], 4 * gq + r, 64);
-                if (s < 0) continue;
-                const float* x = io.x_in + s * D;
-                const int32_t* cd = io.codes + s * m.H;
-                float* xo = io.x + s * D;
+                const int64_t sr = __shfl(slot[i], 4 * gq + r, 64);
+                v4[r] = sr >= 0;
+                s4[r] = v4[r] ? sr : 0;
+            }
+            float z[4][NBO], xin[4][NBO], b2v[NBO];
+            int cn[4];
 #pragma unroll
-                for (int nb = 0; nb < NBO; ++nb) {
-                    const int col = nb * 16 + c16;
-                    float z = w.b_o[col];
-                    for (int hq = 0; hq < m.H; ++hq)
-                        z += w.table[((int64_t)hq * m.Q + cd[hq]) * D + col];
-                    const float xp = x[col] + z;
-                    xo[col] = xp + (out[i][nb][r] + w.b2[col]);
+            for (int r = 0; r < 4; ++r) cn[r] = v4[r] ? io.codes[s4[r] * m.H] : 0;
+#pragma unroll
+            for (int nb = 0; nb < NBO; ++nb) {
+                const int col = nb * 16 + c16;
+                const float bo = w.b_o[col];
+                b2v[nb] = w.b2[col];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    z[r][nb] = bo;
+                    xin[r][nb] = io.x_in[s4[r] * D + col];
                 }
             }
+            for (int hq = 0; hq < m.H; ++hq) {
+                int c[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    c[r] = cn[r];
+                    if (hq + 1 < m.H) cn[r] = v4[r] ? io.codes[s4[r] * m.H + hq + 1] : 0;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float* tr = w.table + ((int64_t)hq * m.Q + c[r]) * D;
+#pragma unroll
+                    for (int nb = 0; nb < NBO; ++nb) z[r][nb] += tr[nb * 16 + c16];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!v4[r]) continue;
+                float* xo = io.x + s4[r] * D;
+#pragma unroll
+                for (int nb = 0; nb < NBO; ++nb) {
+                    const float xp = xin[r][nb] + z[r][nb];
+                    xo[nb * 16 + c16] = xp + (out[i][nb][r] + b2v[nb]);
+                }
+            }
+        }
     }
 }
 
