@@ -254,6 +254,21 @@ __device__ inline void stage_store(const bf16x8 (&pre)[PER], bf16x8* dst) {
     for (int k = 0; k < PER; ++k) dst[threadIdx.x + k * kMT] = pre[k];
 }
 
+// Global-to-LDS loads (gfx950): lane l's 16 (4) bytes at gsrc land at
+// lds + 16 l (4 l); lds is the wave's base address, the same in every lane.
+// They complete in order with the vector memory loads (vmcnt).
+__device__ inline void lds_dma16(const void* gsrc, void* lds) {
+    __builtin_amdgcn_global_load_lds(
+        gsrc, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+__device__ inline void lds_dma4(const void* gsrc, void* lds) {
+    __builtin_amdgcn_global_load_lds(
+        gsrc, (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+// s_waitcnt vmcnt(0): this wave's vector memory loads, global-to-LDS loads
+// included, have completed (expcnt and lgkmcnt left at their maxima).
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // --------------------------------------------------------------- LN1 + QKV
 // Each wave: 16*MB rows (LN1 output as register A fragments).  The 3d/16
 // output column blocks stream through a double-buffered LDS stage, NBC
@@ -598,27 +613,55 @@ __device__ inline float score_err_split(int n, float na, float wmax) {
 
 // Each wave owns 16*MB rows kept in registers as hi/lo A fragments; the
 // four waves of a workgroup stream the codes of the quantizer head through
-// a double-buffered LDS stage (CBK code blocks of 16 codes per chunk), the
-// next chunk's global loads in flight while the current one is searched.
+// a double-buffered LDS stage (CBK code blocks of 16 codes per chunk, with
+// their squared norms).  The stages are filled by global-to-LDS loads (no
+// registers, no store instructions), issued one chunk ahead: the next chunk
+// of the head, or after a head's last chunk the first chunk of the next head
+// (or of the next tile's first head) when the chunk count is even.  A chunk
+// starts with this wave's loads complete and a barrier, after which every
+// wave has also finished reading the other stage, which then takes the next
+// chunk.
 // Every codebook fragment read from LDS feeds 2*MB MFMAs.  The second-best
 // distance (for the certified-reuse margins) is tracked only when MARGIN;
-// the chosen code is the same either way.
+// the chosen code is the same either way.  The register cap applies where
+// it costs no spills.
 template <int KBS, int MB, bool MARGIN>
-__global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
-                                                RowSet rows, BlockIO<PrecBF16> io,
-                                                const bf16x8* __restrict__ cbp) {
+__global__ void __launch_bounds__(kMT)
+    __attribute__((amdgpu_waves_per_eu(MB <= 2 && !MARGIN ? 3 : 1)))
+    k_vq_mfma(ModelDims m, LayerW<float> w, RowSet rows, BlockIO<PrecBF16> io,
+              const bf16x8* __restrict__ cbp) {
     constexpr int DS = KBS * 32, WR = MB * 16, CBK = 4;
     constexpr int CHUNK = CBK * KBS * 64;       // fragment lanes per chunk
     constexpr int PER = CHUNK / kMT;             // per thread
-    __shared__ bf16x8 stage[2][CHUNK];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int CN = CBK * 16;                 // code norms per chunk
+    static_assert(CN == 64, "one wave loads a chunk's code norms");
+    __shared__ bf16x8 stage0[CHUNK], stage1[CHUNK];
+    __shared__ float cn0[CN], cn1[CN];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int64_t n = rs_n(rows);
     const int64_t ntile = (n + 4 * WR - 1) / (4 * WR);
     const int QB = m.Q / 16;
     const int64_t cbtot = (int64_t)QB * KBS * 64;
     const int nchunk = (QB + CBK - 1) / CBK;
     const float inf = __builtin_inff();
-    const bf16x8 zero8 = bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    // chunk c of head hq into (st, cs): clamped addresses (entries past the
+    // codebook are never read)
+    auto fetch = [&](int hq, int c, bf16x8* st, float* cs) {
+        const bf16x8* cbh = cbp + (int64_t)hq * cbtot;
+        const int64_t e0 = (int64_t)c * CHUNK;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t e = e0 + threadIdx.x + k * kMT;
+            lds_dma16(cbh + (e < cbtot ? e : cbtot - 1), st + wave * 64 + k * kMT);
+        }
+        if (wave == 0) {
+            const int code = c * CN + lane;
+            lds_dma4(w.cnorm + (int64_t)hq * m.Q + (code < m.Q ? code : m.Q - 1),
+                     cs);
+        }
+    };
+    bool ahead = false;      // this head's first chunk is in stage0
     for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
         int64_t myslot[MB];
 #pragma unroll
@@ -663,28 +706,26 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
             for (int i = 0; i < MB; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) best[i][r] = T2{inf, 0, inf};   // see k_vq
-            const bf16x8* cbh = cbp + (int64_t)hq * cbtot;
-            const float* cn = w.cnorm + (int64_t)hq * m.Q;
-            __syncthreads();                 // stage free from the last head
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int e = threadIdx.x + k * kMT;
-                stage[0][e] = cbh[e < cbtot ? e : cbtot - 1];
+            if (!ahead) {
+                // the first chunk was not fetched ahead (start, or odd
+                // chunk count): both stages are free after the barrier
+                __syncthreads();
+                fetch(hq, 0, stage0, cn0);
             }
-            __syncthreads();
-            for (int c = 0; c < nchunk; ++c) {
-                bf16x8 pre[PER];
-                const int64_t nb = (int64_t)(c + 1) * CHUNK;
+            // chunk c from (sb, cs), the next one into (nsb, ncs).  A head's
+            // last chunk fetches the next head's first one (the next tile's
+            // first head after the last) into stage0 when it reads stage1.
+            auto chunk = [&](int c, const bf16x8* sb, const float* cs,
+                             bf16x8* nsb, float* ncs, bool into0) {
+                wait_vmem();
+                __syncthreads();
+                // in flight during this chunk's search
                 if (c + 1 < nchunk) {
-                    // clamped, unconditional loads (lanes past the codebook
-                    // are never read): in flight during this chunk's search
-#pragma unroll
-                    for (int k = 0; k < PER; ++k) {
-                        const int64_t e = nb + threadIdx.x + k * kMT;
-                        pre[k] = cbh[e < cbtot ? e : cbtot - 1];
-                    }
+                    fetch(hq, c + 1, nsb, ncs);
+                } else {
+                    ahead = into0 && (hq + 1 < m.H || t + gridDim.x < ntile);
+                    if (ahead) fetch(hq + 1 < m.H ? hq + 1 : 0, 0, nsb, ncs);
                 }
-                const bf16x8* sb = stage[c & 1];
 #pragma unroll
                 for (int cbl = 0; cbl < CBK; ++cbl) {
                     const int cb = c * CBK + cbl;
@@ -702,7 +743,7 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
                         }
                     }
                     const int code = cb * 16 + (lane & 15);
-                    const float cnv = cn[code];
+                    const float cnv = cs[cbl * 16 + (lane & 15)];
 #pragma unroll
                     for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -723,11 +764,14 @@ __global__ void __launch_bounds__(kMT) k_vq_mfma(ModelDims m, LayerW<float> w,
                             }
                         }
                 }
-                if (c + 1 < nchunk)
-#pragma unroll
-                    for (int k = 0; k < PER; ++k)
-                        stage[(c + 1) & 1][threadIdx.x + k * kMT] = pre[k];
-                __syncthreads();
+            };
+            // the two stages are distinct arrays, each named statically in
+            // its copy of the chunk body: the compiler then sees that the
+            // global-to-LDS loads into one never feed the reads of the other
+            // and does not wait for them before the search
+            for (int c = 0; c < nchunk; c += 2) {
+                chunk(c, stage0, cn0, stage1, cn1, false);
+                if (c + 1 < nchunk) chunk(c + 1, stage1, cn1, stage0, cn0, true);
             }
             // combine the 16 column lanes of each row group
 #pragma unroll
