@@ -268,24 +268,41 @@ __device__ inline void lds_dma4(const void* gsrc, void* lds) {
 // s_waitcnt vmcnt(0): this wave's vector memory loads, global-to-LDS loads
 // included, have completed (expcnt and lgkmcnt left at their maxima).
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt lgkmcnt(0) alone (vector memory loads stay in flight).
+__device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
 // --------------------------------------------------------------- LN1 + QKV
 // Each wave: 16*MB rows (LN1 output as register A fragments).  The 3d/16
-// output column blocks stream through a double-buffered LDS stage, NBC
-// blocks per chunk, shared by the four waves.
+// output column blocks stream through two LDS stages, NBC blocks (64
+// columns) per chunk with their biases, shared by the four waves and filled
+// like the VQ search's: global-to-LDS loads one chunk ahead (the next tile's
+// first chunk after the last), a wait for them and a barrier at each chunk
+// start.  A chunk's outputs stay in registers and are stored after the next
+// chunk's loads have been issued, so that wait never covers fresh stores.
 template <int KB, int MB>
 __global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
                                                  RowSet rows, BlockIO<PrecBF16> io,
                                                  const bf16x8* __restrict__ Bp) {
     constexpr int D = KB * 32, WR = MB * 16, NBC = 4;
     constexpr int CHUNK = NBC * KB * 64, PER = CHUNK / kMT;
-    __shared__ bf16x8 stage[2][CHUNK];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int NBT = 3 * D / 16;
+    constexpr int nchunk = NBT / NBC;
+    static_assert(NBT % NBC == 0, "whole chunks");
+    __shared__ bf16x8 stage0[CHUNK], stage1[CHUNK];
+    __shared__ float bias0[NBC * 16], bias1[NBC * 16];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int gq = lane >> 4, c16 = lane & 15;
     const int64_t n = rs_n(rows);
     const int64_t ntile = (n + 4 * WR - 1) / (4 * WR);
-    constexpr int NBT = 3 * D / 16;
-    constexpr int nchunk = NBT / NBC;
+    auto fetch = [&](int c, bf16x8* st, float* bs) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            lds_dma16(Bp + (int64_t)c * CHUNK + threadIdx.x + k * kMT,
+                      st + wave * 64 + k * kMT);
+        if (wave == 0) lds_dma4(w.b_qkv + c * NBC * 16 + lane, bs);
+    };
+    bool ahead = false;      // the tile's first chunk is in stage0
     for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
         int64_t slot[MB];
         const float* xr[MB];
@@ -302,17 +319,35 @@ __global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
         for (int i = 0; i < MB; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) oslot[i][r] = __shfl(slot[i], 4 * gq + r, 64);
-        __syncthreads();
-        {
-            bf16x8 pre[PER];
-            stage_fetch<PER>(pre, Bp, CHUNK);
-            stage_store<PER>(pre, stage[0]);
+        if (!ahead) {
+            __syncthreads();                 // both stages free
+            fetch(0, stage0, bias0);
         }
-        __syncthreads();
-        for (int c = 0; c < nchunk; ++c) {
-            bf16x8 pre[PER];
-            if (c + 1 < nchunk) stage_fetch<PER>(pre, Bp + (int64_t)(c + 1) * CHUNK, CHUNK);
-            const bf16x8* sb = stage[c & 1];
+        float ov[MB][NBC][4];                // outputs of the pending chunk
+        auto flush = [&](int c) {
+#pragma unroll
+            for (int nbl = 0; nbl < NBC; ++nbl) {
+                const int col = (c * NBC + nbl) * 16 + c16;
+                float* dst = col < D ? io.q : (col < 2 * D ? io.k : io.v);
+                const int cc = col < D ? col : (col < 2 * D ? col - D : col - 2 * D);
+#pragma unroll
+                for (int i = 0; i < MB; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (oslot[i][r] >= 0) dst[oslot[i][r] * D + cc] = ov[i][nbl][r];
+            }
+        };
+        auto chunk = [&](int c, const bf16x8* sb, const float* bs, bf16x8* nsb,
+                         float* nbs, bool into0) {
+            wait_vmem();
+            __syncthreads();
+            if (c + 1 < nchunk) {
+                fetch(c + 1, nsb, nbs);
+            } else {
+                ahead = into0 && t + gridDim.x < ntile;
+                if (ahead) fetch(0, nsb, nbs);
+            }
+            if (c > 0) flush(c - 1);
 #pragma unroll
             for (int nbl = 0; nbl < NBC; ++nbl) {
                 f32x4 acc[MB];
@@ -327,19 +362,20 @@ __global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
                         acc[i] = mfma(al[i][kb], b, acc[i]);
                     }
                 }
-                const int col = (c * NBC + nbl) * 16 + c16;
-                float* dst = col < D ? io.q : (col < 2 * D ? io.k : io.v);
-                const int cc = col < D ? col : (col < 2 * D ? col - D : col - 2 * D);
-                const float bias = w.b_qkv[col];
+                const float bias = bs[nbl * 16 + c16];
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (oslot[i][r] >= 0) dst[oslot[i][r] * D + cc] = acc[i][r] + bias;
+                    for (int r = 0; r < 4; ++r) ov[i][nbl][r] = acc[i][r] + bias;
             }
-            if (c + 1 < nchunk) stage_store<PER>(pre, stage[(c + 1) & 1]);
-            __syncthreads();
+        };
+        // the two stages are distinct arrays named statically in each copy
+        // of the chunk body (see k_vq_mfma)
+        for (int c = 0; c < nchunk; c += 2) {
+            chunk(c, stage0, bias0, stage1, bias1, false);
+            if (c + 1 < nchunk) chunk(c + 1, stage1, bias1, stage0, bias0, true);
         }
+        flush(nchunk - 1);
     }
 }
 
@@ -501,7 +537,7 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
                         split1(h, hh[row * LDH + col], hl[row * LDH + col]);
                     }
             }
-            __builtin_amdgcn_s_waitcnt(0);
+            wait_lds();                    // this wave's transposes
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int kb = 0; kb < KB2C; ++kb) {
