@@ -860,76 +860,139 @@ hipError_t launch_certify(const ModelDims& m, const DedupIO<P>& d,
     return hipGetLastError();
 }
 
+// One wave copies rows sb + jl[p] of src to rows ob + jl[p] of dst
+// (p < nj), V units of T per row: batches of 4 units per lane, the batch's
+// loads issued before its stores (indices past the end are clamped; their
+// values are not stored).
+template <class T>
+__device__ inline void copy_rows(const T* __restrict__ src, T* __restrict__ dst,
+                                 int V, int64_t sb, int64_t ob, const int* jl,
+                                 int nj) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63;
+    const int tot = nj * V;
+    for (int e0 = 0; e0 < tot; e0 += 64 * U) {
+        T v[U];
+        int64_t off[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + 64 * u + lane;
+            const int ec = e < tot ? e : tot - 1;
+            const int p = ec / V;
+            off[u] = (int64_t)jl[p] * V + (ec - p * V);
+            v[u] = src[sb * V + off[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + 64 * u + lane < tot) dst[ob * V + off[u]] = v[u];
+    }
+}
+
 // C_l = C_{l-1} plus rows whose code differs from the sample's; rows that
 // join C get the sample's block input copied into their overlay row, and
 // all rows of C_l are listed for the MLP stage (and the next QKV stage).
+// A wave takes kCdBatch of its neighbours at a time and reserves their list
+// entries with one atomic on the shared counter (one per neighbour made the
+// counter's atomics the bottleneck); the order of the list does not matter,
+// every listed row is computed on its own.
+constexpr int kCdBatch = 8;
+
 template <class P>
 __global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
-    // The neighbour's mask words live in LDS while they change: global
+    using acc = typename P::acc;
+    // The neighbours' mask words live in LDS while they change: global
     // memory is read once at the start and written once at the end, so no
     // lane ever reads back a word another lane stored in this kernel.
-    __shared__ uint64_t smk[VQ_MAX_MASK_WORDS];
+    __shared__ uint64_t smk[kCdBatch][VQ_MAX_MASK_WORDS];
+    __shared__ int jl[64];
     const int64_t n = (int64_t)*dd.n_nb;
     const int lane = threadIdx.x;
     const int N = m.N, d = m.d, W = dd.mask_words;
-    for (int64_t nb = blockIdx.x; nb < n; nb += gridDim.x) {
-        const NbDesc D = dd.desc[nb];
-        const int pmin = D.p1 + 1;
-        uint64_t* mk = dd.mask + nb * W;
-        __syncthreads();
-        for (int wd = lane; wd < W; wd += 64) smk[wd] = mk[wd];
-        __syncthreads();
-        for (int i0 = pmin; i0 < N; i0 += 64) {
-            const int i = i0 + lane;
-            bool joins = false;
-            if (i < N && !mask_bit(smk, i)) {
-                const int64_t slot = D.ov + (i - pmin);
-                const int64_t brow = (int64_t)D.sigma * N + i;
-                for (int hq = 0; hq < m.H; ++hq)
-                    joins |= dd.ocode[slot * m.H + hq] != dd.bcode[brow * m.H + hq];
-            }
-            const uint64_t jm = __ballot(joins);
-            // copy the sample's block input into the overlay rows that join
-            uint64_t rem = jm;
-            while (rem) {
-                const int b = __ffsll((long long)rem) - 1;
-                rem &= rem - 1;
-                const int ii = i0 + b;
-                const int64_t slot = D.ov + (ii - pmin);
-                const int64_t brow = (int64_t)D.sigma * N + ii;
-                for (int k = lane; k < d; k += 64) dd.ox[slot * d + k] = dd.bx[brow * d + k];
-            }
-            // rows of this group occupy word i0/64 and possibly the next one
+    const int64_t stride = gridDim.x;
+    for (int64_t nb0 = blockIdx.x; nb0 < n; nb0 += stride * kCdBatch) {
+        int tot[kCdBatch];
+        int all = 0;
+#pragma unroll 1
+        for (int g = 0; g < kCdBatch; ++g) {
+            tot[g] = 0;
+            const int64_t nb = nb0 + g * stride;
+            if (nb >= n) continue;
+            const NbDesc D = dd.desc[nb];
+            const int pmin = D.p1 + 1;
+            const uint64_t* mk = dd.mask + nb * W;
+            uint64_t* sm = smk[g];
             __syncthreads();
-            if (lane == 0 && jm) {
-                const int w0 = i0 >> 6, sh = i0 & 63;
-                smk[w0] |= jm << sh;
-                if (sh && w0 + 1 < W) smk[w0 + 1] |= jm >> (64 - sh);
-            }
+            for (int wd = lane; wd < W; wd += 64) sm[wd] = mk[wd];
             __syncthreads();
+            for (int i0 = pmin; i0 < N; i0 += 64) {
+                const int i = i0 + lane;
+                bool joins = false;
+                if (i < N && !mask_bit(sm, i)) {
+                    const int64_t slot = D.ov + (i - pmin);
+                    const int64_t brow = (int64_t)D.sigma * N + i;
+                    for (int hq = 0; hq < m.H; ++hq)
+                        joins |= dd.ocode[slot * m.H + hq] != dd.bcode[brow * m.H + hq];
+                }
+                const uint64_t jm = __ballot(joins);
+                // copy the sample's block input into the overlay rows that
+                // join: the group's joined rows are listed in LDS, then
+                // copied in batches whose loads precede their stores
+                if (jm) {
+                    const uint64_t below = lane == 0 ? 0ull : (jm & (~0ull >> (64 - lane)));
+                    if ((jm >> lane) & 1) jl[__popcll(below)] = lane;
+                    __syncthreads();
+                    const int nj = __popcll(jm);
+                    const int64_t sb = (int64_t)D.sigma * N + i0;   // sample row i0
+                    const int64_t ob = D.ov + (i0 - pmin);           // its overlay row
+                    if ((d * (int)sizeof(acc)) % 16 == 0)
+                        copy_rows<uint4>(reinterpret_cast<const uint4*>(dd.bx),
+                                         reinterpret_cast<uint4*>(dd.ox),
+                                         d * (int)sizeof(acc) / 16, sb, ob, jl, nj);
+                    else
+                        copy_rows<acc>(dd.bx, dd.ox, d, sb, ob, jl, nj);
+                }
+                // rows of this group occupy word i0/64 and possibly the next one
+                __syncthreads();
+                if (lane == 0 && jm) {
+                    const int w0 = i0 >> 6, sh = i0 & 63;
+                    sm[w0] |= jm << sh;
+                    if (sh && w0 + 1 < W) sm[w0 + 1] |= jm >> (64 - sh);
+                }
+                __syncthreads();
+            }
+            for (int i0 = pmin; i0 < N; i0 += 64) {
+                const int i = i0 + lane;
+                tot[g] += __popcll(__ballot(i < N && mask_bit(sm, i)));
+            }
+            all += tot[g];
         }
         int64_t pos = 0;
-        int total = 0;
-        for (int i0 = pmin; i0 < N; i0 += 64) {
-            const int i = i0 + lane;
-            total += __popcll(__ballot(i < N && mask_bit(smk, i)));
-        }
-        if (lane == 0) pos = atomicAdd(dd.list_n, total);
+        if (lane == 0 && all) pos = atomicAdd(dd.list_n, all);
         pos = __shfl(pos, 0, 64);
-        int k = 0;
-        for (int i0 = pmin; i0 < N; i0 += 64) {
-            const int i = i0 + lane;
-            const bool inC = i < N && mask_bit(smk, i);
-            const uint64_t cm = __ballot(inC);
-            const uint64_t below = lane == 0 ? 0ull : (cm & (~0ull >> (64 - lane)));
-            if (inC) {
-                dd.list[pos + k + __popcll(below)] = D.ov + (i - pmin);
-                dd.crow[D.ov + k + __popcll(below)] = (int16_t)i;
+#pragma unroll 1
+        for (int g = 0; g < kCdBatch; ++g) {
+            const int64_t nb = nb0 + g * stride;
+            if (nb >= n) continue;
+            const NbDesc D = dd.desc[nb];
+            const int pmin = D.p1 + 1;
+            const uint64_t* sm = smk[g];
+            int k = 0;
+            for (int i0 = pmin; i0 < N; i0 += 64) {
+                const int i = i0 + lane;
+                const bool inC = i < N && mask_bit(sm, i);
+                const uint64_t cm = __ballot(inC);
+                const uint64_t below = lane == 0 ? 0ull : (cm & (~0ull >> (64 - lane)));
+                if (inC) {
+                    dd.list[pos + k + __popcll(below)] = D.ov + (i - pmin);
+                    dd.crow[D.ov + k + __popcll(below)] = (int16_t)i;
+                }
+                k += __popcll(cm);
             }
-            k += __popcll(cm);
+            pos += k;
+            if (lane == 0) dd.ccnt[nb] = k;
+            uint64_t* mk = dd.mask + nb * W;
+            for (int wd = lane; wd < W; wd += 64) mk[wd] = sm[wd];
         }
-        if (lane == 0) dd.ccnt[nb] = k;
-        for (int wd = lane; wd < W; wd += 64) mk[wd] = smk[wd];
     }
 }
 
