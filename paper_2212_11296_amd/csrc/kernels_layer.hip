@@ -654,26 +654,52 @@ hipError_t launch_mlp(const ModelDims& m, const LayerW<typename P::acc>& w,
 }
 
 // ------------------------------------------------------------------ head
-// Final LN, linear d -> 2 and log-softmax of one row, computed by one wave
-// (all lanes return the same values).
-template <typename C>
-__device__ inline void head_row(const C* x, int d, const HeadW<C>& hw, C& lp0,
-                                C& lp1) {
+// Final LN, linear d -> 2 and log-softmax of R rows, computed by one wave
+// (all lanes return the same values).  The rows' chains are interleaved so
+// their loads and reductions overlap; each row sees the same operations in
+// the same order whatever R is, and contraction is off, so a row's result
+// does not depend on which rows share the call.
+template <typename C, int R>
+__device__ inline void head_rows(const C* const (&x)[R], int d,
+                                 const HeadW<C>& hw, C (&lp0)[R], C (&lp1)[R]) {
+#pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
-    C mean, rstd;
-    ln_stats<C>(x, d, mean, rstd);
-    C z0 = 0, z1 = 0;
+    C s[R], v[R], mean[R], rstd[R], z0[R], z1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[r] = v[r] = z0[r] = z1[r] = 0;
+    for (int k = lane; k < d; k += 64)
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] += x[r][k];
+#pragma unroll
+    for (int r = 0; r < R; ++r) mean[r] = wave_sum(s[r]) / (C)d;
+    for (int k = lane; k < d; k += 64)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const C t = x[r][k] - mean[r];
+            v[r] += t * t;
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        rstd[r] = (C)1 / dsqrt(wave_sum(v[r]) / (C)d + (C)1e-5);
     for (int k = lane; k < d; k += 64) {
-        const C f = (x[k] - mean) * rstd * hw.lnf_g[k] + hw.lnf_b[k];
-        z0 += f * hw.W_head[2 * k];
-        z1 += f * hw.W_head[2 * k + 1];
+        const C g = hw.lnf_g[k], b = hw.lnf_b[k];
+        const C w0 = hw.W_head[2 * k], w1 = hw.W_head[2 * k + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const C f = (x[r][k] - mean[r]) * rstd[r] * g + b;
+            z0[r] += f * w0;
+            z1[r] += f * w1;
+        }
     }
-    z0 = wave_sum(z0) + hw.b_head[0];
-    z1 = wave_sum(z1) + hw.b_head[1];
-    const C mx = z0 > z1 ? z0 : z1;
-    const C lse = mx + dlog(dexp(z0 - mx) + dexp(z1 - mx));
-    lp0 = z0 - lse;
-    lp1 = z1 - lse;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const C a0 = wave_sum(z0[r]) + hw.b_head[0];
+        const C a1 = wave_sum(z1[r]) + hw.b_head[1];
+        const C mx = a0 > a1 ? a0 : a1;
+        const C lse = mx + dlog(dexp(a0 - mx) + dexp(a1 - mx));
+        lp0[r] = a0 - lse;
+        lp1[r] = a1 - lse;
+    }
 }
 
 template <class P>
@@ -689,13 +715,14 @@ __global__ void __launch_bounds__(kThreads) k_head_seq(
     for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
         for (int i = wave; i < m.N; i += kThreads / 64) {
             const int64_t row = s * m.N + i;
-            acc l0, l1;
-            head_row<acc>(x + row * m.d, m.d, hw, l0, l1);
+            const acc* xr[1] = {x + row * m.d};
+            acc l0[1], l1[1];
+            head_rows<acc, 1>(xr, m.d, hw, l0, l1);
             if (lane == 0) {
-                ell[i] = (double)(spins[row] < 0 ? l1 : l0);
+                ell[i] = (double)(spins[row] < 0 ? l1[0] : l0[0]);
                 if (lp) {
-                    lp[row * 2] = l0;
-                    lp[row * 2 + 1] = l1;
+                    lp[row * 2] = l0[0];
+                    lp[row * 2 + 1] = l1[0];
                 }
             }
         }
@@ -744,7 +771,10 @@ hipError_t launch_ratio_plain(const double* logpsi_nb, const double* logpsi_s,
 
 // ------------------------------------------------------------ dedup steps
 // C_0: the changed inputs p1+1 and p2+1 (when < N) get their new
-// embeddings; every overlay row records its neighbour.
+// embeddings; every overlay row records its neighbour.  A wave reserves the
+// list entries of kCdBatch neighbours with one atomic on the shared counter.
+constexpr int kCdBatch = 8;
+
 template <class P>
 __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
                                                    HeadW<typename P::acc> hw,
@@ -752,37 +782,55 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
     const int64_t n = (int64_t)*dd.n_nb;
     const int lane = threadIdx.x;
     const int N = m.N, d = m.d, W = dd.mask_words;
-    for (int64_t nb = blockIdx.x; nb < n; nb += gridDim.x) {
-        const NbDesc D = dd.desc[nb];
-        const int pmin = D.p1 + 1;
-        for (int i = lane; i < N - pmin; i += 64) dd.slot_nb[D.ov + i] = (int32_t)nb;
-        uint64_t* mk = dd.mask + nb * W;
-        const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
-        const int rowsC[2] = {D.p1 + 1, D.p2 + 1};
-        // spin moved into p1 is s[p2] and vice versa
-        const int tokC[2] = {sp[D.p2] < 0 ? 1 : 0, sp[D.p1] < 0 ? 1 : 0};
-        const int nC = rowsC[1] < N ? 2 : 1;
-        // every mask word written once, never read back within the kernel
-        for (int wd = lane; wd < W; wd += 64) {
-            uint64_t v = 0;
-            for (int c = 0; c < nC; ++c)
-                if ((rowsC[c] >> 6) == wd) v |= 1ull << (rowsC[c] & 63);
-            mk[wd] = v;
+    const int64_t stride = gridDim.x;
+    for (int64_t nb0 = blockIdx.x; nb0 < n; nb0 += stride * kCdBatch) {
+        int all = 0;
+#pragma unroll 1
+        for (int g = 0; g < kCdBatch; ++g) {
+            const int64_t nb = nb0 + g * stride;
+            if (nb >= n) continue;
+            const NbDesc D = dd.desc[nb];
+            const int pmin = D.p1 + 1;
+            for (int i = lane; i < N - pmin; i += 64) dd.slot_nb[D.ov + i] = (int32_t)nb;
+            uint64_t* mk = dd.mask + nb * W;
+            const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
+            const int rowsC[2] = {D.p1 + 1, D.p2 + 1};
+            // spin moved into p1 is s[p2] and vice versa
+            const int tokC[2] = {sp[D.p2] < 0 ? 1 : 0, sp[D.p1] < 0 ? 1 : 0};
+            const int nC = rowsC[1] < N ? 2 : 1;
+            // every mask word written once, never read back within the kernel
+            for (int wd = lane; wd < W; wd += 64) {
+                uint64_t v = 0;
+                for (int c = 0; c < nC; ++c)
+                    if ((rowsC[c] >> 6) == wd) v |= 1ull << (rowsC[c] & 63);
+                mk[wd] = v;
+            }
+            for (int c = 0; c < nC; ++c) {
+                const int i = rowsC[c];
+                const int64_t slot = D.ov + (i - pmin);
+                for (int k = lane; k < d; k += 64)
+                    dd.ox[slot * d + k] = hw.tok[tokC[c] * d + k] + hw.pos[(int64_t)i * d + k];
+                if (lane == 0) dd.crow[D.ov + c] = (int16_t)i;
+            }
+            if (lane == 0) dd.ccnt[nb] = nC;
+            all += nC;
         }
         int64_t pos = 0;
-        if (lane == 0) pos = atomicAdd(dd.list_n, nC);
+        if (lane == 0) pos = atomicAdd(dd.list_n, all);
         pos = __shfl(pos, 0, 64);
-        for (int c = 0; c < nC; ++c) {
-            const int i = rowsC[c];
-            const int64_t slot = D.ov + (i - pmin);
-            for (int k = lane; k < d; k += 64)
-                dd.ox[slot * d + k] = hw.tok[tokC[c] * d + k] + hw.pos[(int64_t)i * d + k];
-            if (lane == 0) {
-                dd.list[pos + c] = slot;
-                dd.crow[D.ov + c] = (int16_t)i;
+        if (lane == 0) {
+#pragma unroll 1
+            for (int g = 0; g < kCdBatch; ++g) {
+                const int64_t nb = nb0 + g * stride;
+                if (nb >= n) break;
+                const NbDesc D = dd.desc[nb];
+                const int pmin = D.p1 + 1;
+                const int nC = D.p2 + 1 < N ? 2 : 1;
+                dd.list[pos] = D.ov + (D.p1 + 1 - pmin);
+                if (nC == 2) dd.list[pos + 1] = D.ov + (D.p2 + 1 - pmin);
+                pos += nC;
             }
         }
-        if (lane == 0) dd.ccnt[nb] = nC;
     }
 }
 
@@ -895,7 +943,6 @@ __device__ inline void copy_rows(const T* __restrict__ src, T* __restrict__ dst,
 // entries with one atomic on the shared counter (one per neighbour made the
 // counter's atomics the bottleneck); the order of the list does not matter,
 // every listed row is computed on its own.
-constexpr int kCdBatch = 8;
 
 template <class P>
 __global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
@@ -1006,13 +1053,19 @@ hipError_t launch_code_diff(const ModelDims& m, const DedupIO<P>& d,
 
 // Delta log psi of each neighbour: rows of C_L get new head outputs, the
 // exchanged sites p1, p2 (new targets) use the sample's cached log-probs
-// when their hidden state is unchanged.  Sums in FP64, row order.
+// when their hidden state is unchanged.  The rows of C_L are listed in LDS
+// and evaluated four at a time, their new log-probs kept in LDS; the
+// differences are summed in FP64 in row order.
 template <class P>
 __global__ void __launch_bounds__(64) k_head_dedup(
     ModelDims m, HeadW<typename P::acc> hw, DedupIO<P> dd,
     const typename P::acc* __restrict__ blp, double* __restrict__ ratio,
     int64_t* ctr) {
     using acc = typename P::acc;
+    constexpr int R = 4;
+    __shared__ uint64_t sm[VQ_MAX_MASK_WORDS];
+    __shared__ int16_t rl[VQ_MAX_MASK_WORDS * 64];
+    __shared__ typename P::acc lnw[VQ_MAX_MASK_WORDS * 64];   // by list position
     const int64_t n = (int64_t)*dd.n_nb;
     const int lane = threadIdx.x;
     const int N = m.N, W = dd.mask_words;
@@ -1022,28 +1075,58 @@ __global__ void __launch_bounds__(64) k_head_dedup(
         const int pmin = D.p1 + 1;
         const uint64_t* mk = dd.mask + nb * W;
         const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
-        double delta = 0.0;
-        for (int i = D.p1; i < N; ++i) {
-            const bool inC = i >= pmin && mask_bit(mk, i);
-            const bool ex = i == D.p1 || i == D.p2;
-            if (!inC && !ex) continue;
-            // target of s' at i: exchanged sites swap spins
-            const int8_t snew = i == D.p1 ? sp[D.p2] : (i == D.p2 ? sp[D.p1] : sp[i]);
-            const int tnew = snew < 0 ? 1 : 0, told = sp[i] < 0 ? 1 : 0;
-            const int64_t brow = (int64_t)D.sigma * N + i;
-            const acc lold = blp[brow * 2 + told];
-            acc lnew;
-            if (inC) {
-                acc l0, l1;
-                head_row<acc>(dd.ox + (D.ov + (i - pmin)) * (int64_t)m.d, m.d, hw, l0, l1);
-                lnew = tnew ? l1 : l0;
-                my_rows++;
-            } else {
-                lnew = blp[brow * 2 + tnew];
-            }
-            delta += (double)lnew - (double)lold;
+        __syncthreads();
+        for (int wd = lane; wd < W; wd += 64) sm[wd] = mk[wd];
+        __syncthreads();
+        // rows of C_L in order
+        int nc = 0;
+        for (int i0 = pmin; i0 < N; i0 += 64) {
+            const int i = i0 + lane;
+            const bool inC = i < N && mask_bit(sm, i);
+            const uint64_t cm = __ballot(inC);
+            const uint64_t below = lane == 0 ? 0ull : (cm & (~0ull >> (64 - lane)));
+            if (inC) rl[nc + __popcll(below)] = (int16_t)i;
+            nc += __popcll(cm);
         }
-        if (lane == 0) ratio[nb] = exp(0.5 * delta);
+        __syncthreads();
+        // target of s' at i: exchanged sites swap spins
+        auto snew = [&](int i) {
+            return i == D.p1 ? sp[D.p2] : (i == D.p2 ? sp[D.p1] : sp[i]);
+        };
+        for (int c0 = 0; c0 < nc; c0 += R) {
+            const acc* xr[R];
+            int ir[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ir[r] = rl[c0 + r < nc ? c0 + r : nc - 1];
+                xr[r] = dd.ox + (D.ov + (ir[r] - pmin)) * (int64_t)m.d;
+            }
+            acc l0[R], l1[R];
+            head_rows<acc, R>(xr, m.d, hw, l0, l1);
+            if (lane < R && c0 + lane < nc) {
+                int i = ir[0];
+                acc a0 = l0[0], a1 = l1[0];
+#pragma unroll
+                for (int r = 1; r < R; ++r)
+                    if (lane == r) { i = ir[r]; a0 = l0[r]; a1 = l1[r]; }
+                lnw[c0 + lane] = snew(i) < 0 ? a1 : a0;
+            }
+        }
+        my_rows += nc;
+        __syncthreads();
+        if (lane == 0) {
+            double delta = 0.0;
+            int c = 0;
+            for (int i = D.p1; i < N; ++i) {
+                const bool inC = c < nc && rl[c] == i;
+                if (!inC && i != D.p1 && i != D.p2) continue;
+                const int tnew = snew(i) < 0 ? 1 : 0, told = sp[i] < 0 ? 1 : 0;
+                const int64_t brow = (int64_t)D.sigma * N + i;
+                const acc lnew = inC ? lnw[c++] : blp[brow * 2 + tnew];
+                delta += (double)lnew - (double)blp[brow * 2 + told];
+            }
+            ratio[nb] = exp(0.5 * delta);
+        }
     }
     if (ctr && lane == 0 && my_rows)
         atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_HEAD_ROWS),
