@@ -62,11 +62,12 @@ def kernel_source_digest():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel, mc):
+def measured_traffic(kernel, mc, launches_per_call):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated),
     or None when the summary is absent, covers another kernel or workload,
-    or was taken from a different kernel source."""
+    was taken with another split of the batch into launches (the bytes of
+    one launch depend on it), or from a different kernel source."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                         TRAFFIC_FILE)
     try:
@@ -76,6 +77,7 @@ def measured_traffic(kernel, mc):
         return None
     if (t.get("kernel") != kernel or t.get("L") != mc.L
             or t.get("batch") != mc.batch
+            or t.get("launches_per_call") != launches_per_call
             or t.get("source_sha256") != kernel_source_digest()):
         return None
     return t.get("bytes_per_launch")
@@ -450,7 +452,8 @@ def main():
             bound, peak = "mfma", PEAK["bf16"]
         roof = {"bound": bound, "kernel": dom, "achieved": achieved,
                 "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(dom, mc),
+                "traffic": measured_traffic(dom, mc,
+                                            round(dom_launches / args.steps)),
                 "flop_per_launch": flop_per_launch,
                 "avg_launch_ms": avg_ms}
     else:
