@@ -448,6 +448,22 @@ __device__ inline void wave_tiles(const Tiles<DH>& T, int N, int NTQ, int w,
     }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b % 8),
+// and every XCD has its own L2.  A (sample, head) unit reads 64-byte pieces
+// of rows whose 128-byte lines it shares with the other heads of the same
+// sample, so unit indices are permuted to send the heads of one sample to
+// consecutive workgroups of one XCD (the grid is a multiple of 8 whenever it
+// strides).  Within each full block of 8 nh indices, index 8k + x maps to
+// sample 8 blk + x, head k; a last partial block maps to itself, so the map
+// is a bijection on [0, units).
+__device__ inline int64_t xcd_unit(int64_t v, int64_t units, int nh) {
+    const int64_t B = 8 * (int64_t)nh;
+    const int64_t blk = v / B;
+    if ((blk + 1) * B > units) return v;
+    const int r = (int)(v - blk * B);
+    return blk * B + (int64_t)(r & 7) * nh + (r >> 3);
+}
+
 // WPE: waves per SIMD the register allocation must allow (1: no cap).  Where
 // the LDS tiles leave room for three workgroups per CU (head width 16 up to
 // 16x16 lattices), the capped instance runs a third wave per SIMD, which
@@ -471,7 +487,8 @@ k_attn_seq_mfma(ModelDims m,
     const int64_t units = n * m.nh;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NTQ = (N + 15) / 16;
-    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    for (int64_t v = blockIdx.x; v < units; v += gridDim.x) {
+        const int64_t u = xcd_unit(v, units, m.nh);
         const int64_t s = u / m.nh;
         const int h = (int)(u - s * m.nh);
         const int64_t sb = s * N * d + h * DH;
@@ -511,7 +528,8 @@ k_attn_dedup_mfma(ModelDims m,
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int NTQ = (N + 15) / 16;
     int64_t my_rows = 0, my_pairs = 0;
-    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    for (int64_t v = blockIdx.x; v < units; v += gridDim.x) {
+        const int64_t u = xcd_unit(v, units, m.nh);
         const int64_t sg = u / m.nh;
         const int h = (int)(u - sg * m.nh);
         const int64_t sb = sg * N * d + h * DH;
