@@ -536,18 +536,42 @@ k_attn_dedup_mfma(ModelDims m,
         const int k0 = dd.nb_off[sg], k1 = dd.nb_off[sg + 1];
         __syncthreads();
         load_all<DH>(T, N, dd.bq, dd.bk, dd.bv, sb, d, qs);
+        // The next neighbour's mask words, descriptor, changed-row count and
+        // first batch of row indices are loaded during the current one's
+        // compute, so a step starts with only its value loads outstanding.
         uint64_t mnext = 0;
-        if (k0 < k1 && threadIdx.x < W) mnext = dd.mask[(int64_t)k0 * W + threadIdx.x];
+        NbDesc Dn{};
+        int ccn = 0;
+        int jjn[UNR];
+        // row indices of the first batch of the step into the neighbour with
+        // descriptor Dx and count ccx, after cpx rows of the one at povx
+        auto first_rows = [&](int cpx, int64_t povx, const NbDesc& Dx, int ccx) {
+            const int npx = cpx * G, totx = (cpx + ccx) * G;
+            if (totx == 0) return;
+#pragma unroll
+            for (int i = 0; i < UNR; ++i) {
+                const int e = kAT * i + threadIdx.x;
+                const int ec = e < totx ? e : totx - 1;
+                const int64_t ix = ec < npx ? povx + ec / G : Dx.ov + (ec - npx) / G;
+                jjn[i] = dd.crow[ix];
+            }
+        };
+        if (k0 < k1) {
+            if (threadIdx.x < W) mnext = dd.mask[(int64_t)k0 * W + threadIdx.x];
+            Dn = dd.desc[k0];
+            ccn = dd.ccnt[k0];
+            first_rows(0, 0, Dn, ccn);
+        }
+        int cp = 0;
+        int64_t pov = 0;
         for (int k = k0; k < k1; ++k) {
             __syncthreads();             // LDS free: load_all or last compute
             if (threadIdx.x < W) msk[threadIdx.x] = mnext;
             __syncthreads();
             // step (k-1 -> k): restore rows of C_{k-1} not in C_k, patch C_k
-            const int cp = k > k0 ? dd.ccnt[k - 1] : 0;
-            const int64_t pov = k > k0 ? dd.desc[k - 1].ov : 0;
-            const NbDesc D = dd.desc[k];
+            const NbDesc D = Dn;
             const int pmin = D.p1 + 1;
-            const int cc = dd.ccnt[k];
+            const int cc = ccn;
             const int64_t ob0 = (D.ov - pmin) * (int64_t)d + h * DH;
             const int np = cp * G, tot = (cp + cc) * G;
             for (int e0 = 0; e0 < tot; e0 += kAT * UNR) {
@@ -559,6 +583,10 @@ k_attn_dedup_mfma(ModelDims m,
 #pragma unroll
                 for (int i = 0; i < UNR; ++i) {
                     if (!act[i]) continue;
+                    if (e0 == 0) {
+                        jj[i] = jjn[i];
+                        continue;
+                    }
                     const int e = e0 + kAT * i + threadIdx.x;
                     const int ec = e < tot ? e : tot - 1;
                     const int64_t ix = ec < np ? pov + ec / G : D.ov + (ec - np) / G;
@@ -592,8 +620,14 @@ k_attn_dedup_mfma(ModelDims m,
                     if (use[i]) T.put4(jj[i], c4, true, kv[i], qv[i], qs, vv[i]);
                 }
             }
-            if (k + 1 < k1 && threadIdx.x < W)
-                mnext = dd.mask[(int64_t)(k + 1) * W + threadIdx.x];
+            if (k + 1 < k1) {
+                if (threadIdx.x < W) mnext = dd.mask[(int64_t)(k + 1) * W + threadIdx.x];
+                Dn = dd.desc[k + 1];
+                ccn = dd.ccnt[k + 1];
+                first_rows(cc, D.ov, Dn, ccn);
+            }
+            cp = cc;
+            pov = D.ov;
             __syncthreads();
             wave_tiles<DH>(T, N, NTQ, wave, pmin / 16, pmin,
                            [&](int i) { return dd.oa + ob0 + (int64_t)i * d; });
