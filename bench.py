@@ -110,7 +110,12 @@ def cpu_baseline(mc, theta, spins, gpu_ratios, n_nb0, budget_s):
     lps = onet.logpsi_fn(mc, P, chunk=32)(sub)
     dt = time.perf_counter() - t0 + per
     r_ref = np.exp(lps - lp0)
-    err = float(np.max(np.abs(gpu_ratios[:k] / r_ref - 1.0)))
+    rel = np.abs(gpu_ratios[:k] / r_ref - 1.0)
+    # a quantizer near-tie resolved to the other code moves a ratio by a
+    # finite step: the maximum alone does not describe the accuracy
+    err = {"n": int(k), "median": float(np.median(rel)),
+           "p99": float(np.quantile(rel, 0.99)), "max": float(np.max(rel)),
+           "n_above_1e-3": int((rel > 1e-3).sum())}
     evals_per_eloc = 1 + n_nb0
     rate = (k + 1) / dt / evals_per_eloc
     try:
@@ -509,7 +514,7 @@ def main():
         "algorithmic_tflop_per_step": sum(flops.values()) / 1e12,
         "achieved_tflops_overall": sum(flops.values()) / (ms / 1e3) / 1e12,
         "mean_energy": stats[0], "energy_variance": stats[1],
-        "oracle_spot_max_rel_err_ratio": spot_err,
+        "oracle_spot_rel_err_ratio": spot_err,
         "tuning": (None if choices is None else
                    {"qkv_mb": choices[0], "mlp_mb": choices[1],
                     "vq_mb": choices[2]}),
