@@ -8,8 +8,8 @@
   every replay, and every replay is checked.
 * A workspace smaller than the whole batch (chunked jobs) changes nothing.
 * A bad spin in any job shows in the call's status word.
-* Launch choices (rows per wave) never change results; the autotuner picks
-  valid ones.
+* Launch choices (rows per wave, including four rows per wave in the
+  codebook search) never change results; the autotuner picks valid ones.
 """
 import numpy as np
 import pytest
@@ -112,7 +112,8 @@ def test_launch_choices_do_not_change_results(mc):
     cfg = vq.make_config(mc)
     p, s = dev_params(make_params(mc), "bf16"), dev_spins(make_spins(mc))
     outs = []
-    for ch in ([1, 1, 1], [2, 2, 2], [1, 2, 1], [2, 1, 2]):
+    for ch in ([1, 1, 1], [2, 2, 2], [1, 2, 1], [2, 1, 2], [1, 1, 4],
+               [2, 2, 4]):
         vq.set_tuning(cfg, ch)
         o = vq.local_energy(cfg, p, s, vq.DEDUP, ratios=True)
         outs.append((host(o["eloc"]), host(o["ratios"])))
@@ -120,7 +121,7 @@ def test_launch_choices_do_not_change_results(mc):
         assert np.array_equal(e, outs[0][0])
         assert np.array_equal(r, outs[0][1])
     ch = vq.autotune(cfg, p, s)
-    assert all(c in (1, 2) for c in ch)
+    assert ch[0] in (1, 2) and ch[1] in (1, 2) and ch[2] in (1, 2, 4)
     o = vq.local_energy(cfg, p, s, vq.DEDUP, ratios=True)
     assert np.array_equal(host(o["eloc"]), outs[0][0])
     with pytest.raises(vq.VQNQSError):
