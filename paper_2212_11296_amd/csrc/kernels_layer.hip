@@ -843,15 +843,28 @@ hipError_t launch_dedup_init(const ModelDims& m, const HeadW<typename P::acc>& h
 }
 
 // Certified reuse test for every overlay row (or, without the flag, plain
-// listing of every row for the codebook search).
+// listing of every row for the codebook search).  One wave per row; rows
+// that need the search collect in an LDS list of 64 and are appended to the
+// shared list with one atomic per 64 rows.
 template <class P>
 __global__ void __launch_bounds__(64) k_certify(ModelDims m, DedupIO<P> dd,
                                                 int certified, int64_t* ctr) {
     using acc = typename P::acc;
+    __shared__ int64_t pend[64];
     const int64_t R = (int64_t)*dd.n_rows;
     const int lane = threadIdx.x;
     const int ds = m.dseg;
     int64_t n_cert = 0;
+    int npend = 0;                 // the same in every lane
+    auto flush = [&]() {
+        __syncthreads();
+        int64_t base = 0;
+        if (lane == 0) base = atomicAdd(dd.vq_n, npend);
+        base = __shfl(base, 0, 64);
+        if (lane < npend) dd.vq_list[base + lane] = pend[lane];
+        npend = 0;
+        __syncthreads();
+    };
     for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
         const int32_t nb = dd.slot_nb[r];
         const NbDesc D = dd.desc[nb];
@@ -890,11 +903,12 @@ __global__ void __launch_bounds__(64) k_certify(ModelDims m, DedupIO<P> dd,
             for (int hq = lane; hq < m.H; hq += 64)
                 dd.ocode[r * m.H + hq] = dd.bcode[brow * m.H + hq];
             n_cert++;
-        } else if (lane == 0) {
-            const int32_t p = atomicAdd(dd.vq_n, 1);
-            dd.vq_list[p] = r;
+        } else {
+            if (lane == 0) pend[npend] = r;
+            if (++npend == 64) flush();
         }
     }
+    if (npend) flush();
     if (ctr && lane == 0 && n_cert)
         atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_VQ_CERTIFIED),
                   (unsigned long long)n_cert);
