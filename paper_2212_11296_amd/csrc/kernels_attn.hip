@@ -153,6 +153,21 @@ __device__ inline float vmax(float a, float b) {
     return __builtin_elementwise_maximum(a, b);
 }
 
+// x of lane l ^ 16 and of lane l ^ 32, by the gfx950 lane-swap instructions
+// (VALU, no LDS round trip).  Given the same register twice, permlane16_swap
+// returns rows (0,0,2,2) and (1,1,3,3) of 16 lanes, permlane32_swap the
+// halves (lo,lo) and (hi,hi).
+__device__ inline float lane_xor16(float x) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x),
+                                                    __float_as_uint(x), false, false);
+    return __uint_as_float(((threadIdx.x >> 4) & 1) ? r[0] : r[1]);
+}
+__device__ inline float lane_xor32(float x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x),
+                                                    __float_as_uint(x), false, false);
+    return __uint_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+}
+
 // p as hi+lo bfloat16: hi is p truncated to its upper 16 bits, lo the exact
 // remainder rounded to bfloat16 (relative error of hi+lo at most 2^-16).
 __device__ inline void split_p(const float* p, bf16x8& ph, bf16x8& pl) {
@@ -270,8 +285,8 @@ __device__ inline void qtiles_block(QTile<DH> (&q)[NQ], int N, int blk,
     if (__builtin_amdgcn_ballot_w64(raise) != 0) {
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            float dm = vmax(lm[i], __shfl_xor(lm[i], 16, 64));
-            dm = vmax(dm, __shfl_xor(dm, 32, 64));
+            float dm = vmax(lm[i], lane_xor16(lm[i]));
+            dm = vmax(dm, lane_xor32(dm));
             // the first block sets the reference to its maximum; later
             // blocks raise it only past kTau
             const float delta = first ? dm : (dm > kTau ? dm : 0.0f);
