@@ -116,17 +116,66 @@ hipError_t launch_gemm(const GemmDesc& g, hipStream_t st) {
 // FP32 operands enter the bf16 matrix core as hi + lo pairs; three passes
 // hi.hi + hi.lo + lo.hi accumulate in FP32 (about 16 significant bits per
 // product; the lo.lo term is below that).  When B is bf16-exact (the
-// BF16 mode's weights) its lo part is zero and the hi.lo pass is skipped.  Workgroup tile 128 x 128, each of
-// the four waves 64 x 64 (4 x 4 tiles of 16 x 16), K steps of 32.  The
-// operands are staged in LDS as [row][k] (A) and [col][k] (B), so every
-// MFMA fragment is one 16-byte read per lane whatever the transposition.
+// BF16 mode's weights) its lo part is zero and the hi.lo pass is skipped.
+// Workgroup tile 128 x 128, each of the four waves 64 x 64 (4 x 4 tiles of
+// 16 x 16), K steps of 32.  The operands are staged in LDS as [row][k] (A)
+// and [col][k] (B), so every MFMA fragment is one 16-byte read per lane
+// whatever the transposition.
 typedef __attribute__((ext_vector_type(8))) __bf16 gbf16x8;
+typedef __attribute__((ext_vector_type(4))) __bf16 gbf16x4;
 typedef __attribute__((ext_vector_type(4))) float gf32x4;
+
+// Four consecutive elements of one row of a matrix (0 past lim), one
+// 16-byte load when vec (aligned rows) and all four are in range.
+__device__ inline void load4(const float* base, int64_t lim, bool vec, float (&v)[4]) {
+    if (vec && lim >= 4) {
+        const float4 t = *reinterpret_cast<const float4*>(base);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = c < lim ? base[c] : 0.0f;
+    }
+}
+
+// The 4 x 4 block (rows r0..r0+3, k k0..k0+3) of an operand read as
+// X[row][k]: rows with k contiguous (kc) or k-major with rows contiguous.
+__device__ inline void load_block(const float* X, int64_t ld, bool kc, bool vec,
+                                  int64_t r0, int64_t nr, int64_t k0, int64_t nk,
+                                  float (&v)[4][4]) {
+    if (kc) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r0 + r < nr) {
+                load4(X + (r0 + r) * ld + k0, nk - k0, vec, v[r]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[r][c] = 0.0f;
+            }
+        }
+    } else {
+        float w[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (k0 + c < nk) {
+                load4(X + (k0 + c) * ld + r0, nr - r0, vec, w[c]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) w[c][r] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[r][c] = w[c][r];
+    }
+}
 
 __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
     constexpr int BM = 128, BN = 128, BK = 32, LD = BK + 8;
-    __shared__ __align__(16) __bf16 Ah[BM * LD], Al[BM * LD];
-    __shared__ __align__(16) __bf16 Bh[BN * LD], Bl[BN * LD];
+    // two stages: a K step's MFMAs read one while the next step is
+    // converted into the other
+    __shared__ __align__(16) __bf16 Ah[2][BM * LD], Al[2][BM * LD];
+    __shared__ __align__(16) __bf16 Bh[2][BN * LD], Bl[2][BN * LD];
     const int64_t grp = blockIdx.z;
     const float* A = static_cast<const float*>(g.A) + grp * g.sA;
     const float* B = static_cast<const float*>(g.B) + grp * g.sB;
@@ -140,63 +189,69 @@ __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = gf32x4{0, 0, 0, 0};
-    // Global loads of the next K step are issued before this step's MFMAs
-    // (register prefetch) and stored to LDS after them.
-    constexpr int PER = (BM * BK) / kGT;
-    float pa[PER], pb[PER];
+    // Each thread converts one 4 x 4 block (4 rows x 4 k) of each operand
+    // per K step.  Along a contiguous k the blocks of consecutive threads
+    // are consecutive in k, otherwise in rows, so the 16-byte loads of a
+    // wave are contiguous.
+    const bool akc = !g.tA, bkc = g.tB != 0;
+    const bool avec = g.lda % 4 == 0 && g.sA % 4 == 0 &&
+                      (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
+    const bool bvec = g.ldb % 4 == 0 && g.sB % 4 == 0 &&
+                      (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
+    const int abr = akc ? tid >> 3 : tid & 31, abk = akc ? tid & 7 : tid >> 5;
+    const int bbr = bkc ? tid >> 3 : tid & 31, bbk = bkc ? tid & 7 : tid >> 5;
+    float va[4][4], vb[4][4];
     auto fetch = [&](int64_t k0) {
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const int e = tid + kGT * r;
-            int mm, kk;
-            if (g.tA) { kk = e / BM; mm = e % BM; }
-            else { mm = e / BK; kk = e % BK; }
-            const int64_t gm = m0 + mm, gk = k0 + kk;
-            pa[r] = (gm < g.M && gk < g.K)
-                        ? (g.tA ? A[gk * g.lda + gm] : A[gm * g.lda + gk]) : 0.0f;
-            int nn;
-            if (g.tB) { nn = e / BK; kk = e % BK; }
-            else { kk = e / BN; nn = e % BN; }
-            const int64_t gn = n0 + nn, gk2 = k0 + kk;
-            pb[r] = (gn < g.N && gk2 < g.K)
-                        ? (g.tB ? B[gn * g.ldb + gk2] : B[gk2 * g.ldb + gn]) : 0.0f;
-        }
+        load_block(A, g.lda, akc, avec, m0 + 4 * abr, g.M, k0 + 4 * abk, g.K, va);
+        load_block(B, g.ldb, bkc, bvec, n0 + 4 * bbr, g.N, k0 + 4 * bbk, g.K, vb);
     };
-    auto stash = [&]() {
+    // hi = bf16(x), lo = bf16(x - hi); a row's four k go to LDS as 8 bytes
+    auto stash = [&](int buf) {
 #pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            const int e = tid + kGT * r;
-            int mm, kk;
-            if (g.tA) { kk = e / BM; mm = e % BM; }
-            else { mm = e / BK; kk = e % BK; }
-            const __bf16 h = (__bf16)pa[r];
-            Ah[mm * LD + kk] = h;
-            Al[mm * LD + kk] = (__bf16)(pa[r] - (float)h);
-            int nn;
-            if (g.tB) { nn = e / BK; kk = e % BK; }
-            else { kk = e / BN; nn = e % BN; }
-            const __bf16 wh = (__bf16)pb[r];
-            Bh[nn * LD + kk] = wh;
-            Bl[nn * LD + kk] = (__bf16)(pb[r] - (float)wh);
+        for (int r = 0; r < 4; ++r) {
+            gbf16x4 h, l;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                h[c] = (__bf16)va[r][c];
+                l[c] = (__bf16)(va[r][c] - (float)h[c]);
+            }
+            const int o = (4 * abr + r) * LD + 4 * abk;
+            *reinterpret_cast<gbf16x4*>(&Ah[buf][o]) = h;
+            *reinterpret_cast<gbf16x4*>(&Al[buf][o]) = l;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            gbf16x4 h, l;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                h[c] = (__bf16)vb[r][c];
+                l[c] = (__bf16)(vb[r][c] - (float)h[c]);
+            }
+            const int o = (4 * bbr + r) * LD + 4 * bbk;
+            *reinterpret_cast<gbf16x4*>(&Bh[buf][o]) = h;
+            if (!g.b_exact) *reinterpret_cast<gbf16x4*>(&Bl[buf][o]) = l;
         }
     };
     fetch(0);
+    stash(0);
+    __syncthreads();
+    int cur = 0;
     for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
-        stash();
-        __syncthreads();
-        if (k0 + BK < g.K) fetch(k0 + BK);
+        const bool more = k0 + BK < g.K;
+        if (more) fetch(k0 + BK);
         gbf16x8 bh[4], bl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int nn = wn * 64 + j * 16 + (lane & 15);
-            bh[j] = *reinterpret_cast<const gbf16x8*>(Bh + nn * LD + 8 * (lane >> 4));
-            bl[j] = *reinterpret_cast<const gbf16x8*>(Bl + nn * LD + 8 * (lane >> 4));
+            bh[j] = *reinterpret_cast<const gbf16x8*>(&Bh[cur][nn * LD + 8 * (lane >> 4)]);
+            if (!g.b_exact)
+                bl[j] = *reinterpret_cast<const gbf16x8*>(&Bl[cur][nn * LD + 8 * (lane >> 4)]);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int mm = wm * 64 + i * 16 + (lane & 15);
-            const gbf16x8 ah = *reinterpret_cast<const gbf16x8*>(Ah + mm * LD + 8 * (lane >> 4));
-            const gbf16x8 al = *reinterpret_cast<const gbf16x8*>(Al + mm * LD + 8 * (lane >> 4));
+            const gbf16x8 ah = *reinterpret_cast<const gbf16x8*>(&Ah[cur][mm * LD + 8 * (lane >> 4)]);
+            const gbf16x8 al = *reinterpret_cast<const gbf16x8*>(&Al[cur][mm * LD + 8 * (lane >> 4)]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
@@ -205,7 +260,9 @@ __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
             }
         }
+        if (more) stash(cur ^ 1);
         __syncthreads();
+        cur ^= 1;
     }
     // D layout: lane holds rows 4*(lane/16) + r of column lane%16
 #pragma unroll
