@@ -902,23 +902,32 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
             Ds[i] = Dd[(s * N + i) * nh + h];
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < N; j += kGT) {
+        // The lanes of a wave walk the same query i from the wave's first
+        // key, so every LDS read is a broadcast; a lane's terms for queries
+        // before its own key are exact zeros, which leave its sums as they
+        // would be without them.
+        for (int jb = 0; jb < N; jb += kGT) {
+            const int jw = jb + (threadIdx.x & ~63);     // the wave's first key
+            if (jw >= N) continue;
+            const int j = jb + threadIdx.x;
+            const bool live = j < N;
+            const int jr = live ? j : N - 1;
             T kj[DH], vj[DH], dk[DH], dv[DH];
 #pragma unroll
             for (int c = 0; c < DH; ++c) {
-                kj[c] = k[base + (int64_t)j * d + c];
-                vj[c] = v[base + (int64_t)j * d + c];
+                kj[c] = k[base + (int64_t)jr * d + c];
+                vj[c] = v[base + (int64_t)jr * d + c];
                 dk[c] = 0;
                 dv[c] = 0;
             }
-            for (int i = j; i < N; ++i) {
+            for (int i = jw; i < N; ++i) {
                 T sc = 0, dp = 0;
 #pragma unroll
                 for (int c = 0; c < DH; ++c) {
                     sc += Qs[i * DH + c] * kj[c];
                     dp += Gs[i * DH + c] * vj[c];
                 }
-                const T p = dexp(sc * scale - Ls[i]);
+                const T p = i >= j ? dexp(sc * scale - Ls[i]) : (T)0;
                 const T ds = p * (dp - Ds[i]);
 #pragma unroll
                 for (int c = 0; c < DH; ++c) {
@@ -926,11 +935,13 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
                     dk[c] += ds * Qs[i * DH + c];
                 }
             }
-            T* out = dqkv + (s * N + j) * 3 * d + h * DH;
+            if (live) {
+                T* out = dqkv + (s * N + j) * 3 * d + h * DH;
 #pragma unroll
-            for (int c = 0; c < DH; ++c) {
-                out[d + c] = dk[c] * scale;
-                out[2 * d + c] = dv[c];
+                for (int c = 0; c < DH; ++c) {
+                    out[d + c] = dk[c] * scale;
+                    out[2 * d + c] = dv[c];
+                }
             }
         }
     }
