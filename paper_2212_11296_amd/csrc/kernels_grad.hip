@@ -775,6 +775,50 @@ hipError_t launch_cb_fix(int64_t n, int Q, int dseg, const T* colG, const T* cb,
 }
 
 // --------------------------------------------------------------- attention
+// a . b over DH terms as four interleaved partial sums (c mod 4), added as
+// (s0 + s1) + (s2 + s3): four independent FMA chains instead of one.
+template <typename T, int DH>
+__device__ inline T dot4(const T* a, const T* b) {
+    static_assert(DH % 4 == 0, "head width a multiple of 4");
+    T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+    for (int c = 0; c < DH; c += 4) {
+        s0 += a[c] * b[c];
+        s1 += a[c + 1] * b[c + 1];
+        s2 += a[c + 2] * b[c + 2];
+        s3 += a[c + 3] * b[c + 3];
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Rows 0..N-1 of one head (DH columns at base + row * d) into an LDS tile
+// [N][DH]: 16-byte loads, four per thread issued before their stores.
+template <typename T, int DH>
+__device__ inline void fill_tile(T* dst, const T* src, int64_t base, int N,
+                                 int d) {
+    constexpr int V = 16 / (int)sizeof(T);       // elements per 16 bytes
+    static_assert(DH % V == 0, "whole 16-byte pieces per row");
+    constexpr int G = DH / V, U = 4;
+    typedef __attribute__((ext_vector_type(V))) T vec;
+    const int tot = N * G;
+    for (int e0 = 0; e0 < tot; e0 += kGT * U) {
+        vec v[U];
+        int row[U], c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + kGT * u + (int)threadIdx.x;
+            const int ec = e < tot ? e : tot - 1;
+            row[u] = ec / G;
+            c[u] = (ec % G) * V;
+            v[u] = *reinterpret_cast<const vec*>(src + base + (int64_t)row[u] * d + c[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + kGT * u + (int)threadIdx.x < tot)
+                *reinterpret_cast<vec*>(dst + row[u] * DH + c[u]) = v[u];
+    }
+}
+
 // One workgroup per (sample, head).  Scores s_ij = q_i . k_j / sqrt(d_head)
 // for j <= i; P = softmax_j(s).  lse_i = log sum_j exp(s_ij), and
 // Dd_i = dO_i . O_i (O = the forward attention output).
@@ -792,8 +836,7 @@ __global__ void __launch_bounds__(kGT) k_attn_stats(int64_t n, ModelDims m,
         const int h = (int)(u - s * nh);
         const int64_t base = s * N * d + h * DH;
         __syncthreads();
-        for (int e = threadIdx.x; e < N * DH; e += kGT)
-            Ks[e] = k[base + (int64_t)(e / DH) * d + e % DH];
+        fill_tile<T, DH>(Ks, k, base, N, d);
         __syncthreads();
         for (int i = threadIdx.x; i < N; i += kGT) {
             T qi[DH];
@@ -805,9 +848,7 @@ __global__ void __launch_bounds__(kGT) k_attn_stats(int64_t n, ModelDims m,
             }
             T mx = neg_inf<T>(), l = 0;
             for (int j = 0; j <= i; ++j) {
-                T sc = 0;
-#pragma unroll
-                for (int c = 0; c < DH; ++c) sc += qi[c] * Ks[j * DH + c];
+                T sc = dot4<T, DH>(qi, Ks + j * DH);
                 sc *= scale;
                 if (sc > mx) {
                     l = l * dexp(mx - sc) + (T)1;
@@ -839,11 +880,8 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_q(int64_t n, ModelDims m,
         const int h = (int)(u - s * nh);
         const int64_t base = s * N * d + h * DH;
         __syncthreads();
-        for (int e = threadIdx.x; e < N * DH; e += kGT) {
-            const int64_t o = base + (int64_t)(e / DH) * d + e % DH;
-            Ks[e] = k[o];
-            Vs[e] = v[o];
-        }
+        fill_tile<T, DH>(Ks, k, base, N, d);
+        fill_tile<T, DH>(Vs, v, base, N, d);
         __syncthreads();
         for (int i = threadIdx.x; i < N; i += kGT) {
             T qi[DH], gi[DH], acc[DH];
@@ -855,12 +893,8 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_q(int64_t n, ModelDims m,
             }
             const T ls = lse[(s * N + i) * nh + h], dd = Dd[(s * N + i) * nh + h];
             for (int j = 0; j <= i; ++j) {
-                T sc = 0, dp = 0;
-#pragma unroll
-                for (int c = 0; c < DH; ++c) {
-                    sc += qi[c] * Ks[j * DH + c];
-                    dp += gi[c] * Vs[j * DH + c];
-                }
+                const T sc = dot4<T, DH>(qi, Ks + j * DH);
+                const T dp = dot4<T, DH>(gi, Vs + j * DH);
                 const T p = dexp(sc * scale - ls);
                 const T ds = p * (dp - dd);
 #pragma unroll
@@ -892,11 +926,8 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
         const int h = (int)(u - s * nh);
         const int64_t base = s * N * d + h * DH;
         __syncthreads();
-        for (int e = threadIdx.x; e < N * DH; e += kGT) {
-            const int64_t o = base + (int64_t)(e / DH) * d + e % DH;
-            Qs[e] = q[o];
-            Gs[e] = dO[o];
-        }
+        fill_tile<T, DH>(Qs, q, base, N, d);
+        fill_tile<T, DH>(Gs, dO, base, N, d);
         for (int i = threadIdx.x; i < N; i += kGT) {
             Ls[i] = lse[(s * N + i) * nh + h];
             Ds[i] = Dd[(s * N + i) * nh + h];
@@ -921,12 +952,8 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
                 dv[c] = 0;
             }
             for (int i = jw; i < N; ++i) {
-                T sc = 0, dp = 0;
-#pragma unroll
-                for (int c = 0; c < DH; ++c) {
-                    sc += Qs[i * DH + c] * kj[c];
-                    dp += Gs[i * DH + c] * vj[c];
-                }
+                const T sc = dot4<T, DH>(kj, Qs + i * DH);
+                const T dp = dot4<T, DH>(vj, Gs + i * DH);
                 const T p = i >= j ? dexp(sc * scale - Ls[i]) : (T)0;
                 const T ds = p * (dp - Ds[i]);
 #pragma unroll
