@@ -49,6 +49,14 @@ __device__ inline void split1(float x, __bf16& hi, __bf16& lo) {
     hi = (__bf16)x;
     lo = (__bf16)(x - (float)hi);
 }
+// split1 of two values with paired conversions (the same per-value result).
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+__device__ inline void split2(float a, float b, bf16x2& hi, bf16x2& lo) {
+    hi = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    const f32x2 back = __builtin_convertvector(hi, f32x2);
+    lo = __builtin_convertvector(f32x2{a - back[0], b - back[1]}, bf16x2);
+}
 
 // ---------------------------------------------------------------- packing
 // out[((nb*KB + kb)*64 + l)*8 + j] = W[kb*32 + 8*(l/16) + j][nb*16 + l%16]
@@ -388,17 +396,20 @@ __global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
 // The W1/W2 fragments of a chunk are staged in LDS for the four waves.
 // GELU with erf from Abramowitz & Stegun 7.1.26 (absolute error of erf at
 // most 1.5e-7): with y = |x|/sqrt(2), t = 1/(1 + p y) and
-// q = (a1 t + ... + a5 t^5) exp(-y^2) ~ erfc(y), 1 + erf(x/sqrt(2)) is q for
-// x < 0 (no cancellation) and 2 - q otherwise.  Branch-free.
+// (a1 t + ... + a5 t^5) exp(-y^2) ~ erfc(y).  The constants are folded:
+// t = 1/(1 + (p/sqrt 2)|x|), the coefficients are halved so that
+// q = (a1/2 t + ... + a5/2 t^5) 2^(-(log2 e)/2 x^2) ~ erfc(y)/2 = Phi(-|x|),
+// and GELU(x) = x Phi(x) is x q for x < 0 (no cancellation) and x (1 - q)
+// otherwise.  Branch-free.
 __device__ inline float gelu_as(float x) {
-    const float y = __builtin_fabsf(x) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * y);
+    const float t =
+        __builtin_amdgcn_rcpf(__builtin_fmaf(__builtin_fabsf(x), 0.231641888f, 1.0f));
     const float poly =
-        t * (0.254829592f +
-             t * (-0.284496736f +
-                  t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-    const float q = poly * __builtin_amdgcn_exp2f(-(y * y) * 1.4426950408889634f);
-    return 0.5f * x * (x >= 0.0f ? 2.0f - q : q);
+        t * (0.127414796f +
+             t * (-0.142248368f +
+                  t * (0.710706871f + t * (-0.726576014f + t * 0.530702714f))));
+    const float q = poly * __builtin_amdgcn_exp2f(x * x * -0.72134752044448169f);
+    return x * (x >= 0.0f ? 1.0f - q : q);
 }
 
 template <int KB1, int MB>
@@ -531,10 +542,15 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
                 for (int i = 0; i < MB; ++i)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
+                    for (int r = 0; r < 4; r += 2) {
                         const int row = i * 16 + 4 * gq + r;
-                        const float h = gelu_as(hacc[i][nb][r] + bias);
-                        split1(h, hh[row * LDH + col], hl[row * LDH + col]);
+                        bf16x2 h2, l2;
+                        split2(gelu_as(hacc[i][nb][r] + bias),
+                               gelu_as(hacc[i][nb][r + 1] + bias), h2, l2);
+                        hh[row * LDH + col] = h2[0];
+                        hl[row * LDH + col] = l2[0];
+                        hh[(row + 1) * LDH + col] = h2[1];
+                        hl[(row + 1) * LDH + col] = l2[1];
                     }
             }
             wait_lds();                    // this wave's transposes
