@@ -109,6 +109,35 @@ def test_grad_bf16_grad_shapes_sampled():
         assert rel_norm(g[b], ref[j]) < 2e-3, b
 
 
+ODD_BF16 = replace(CONFIGS["medium"], name="odd_bf16", L=5, periodic=False,
+                   d_model=64, n_layers=2, n_heads=4, d_ff=256,
+                   codebook_size=64, precision="bf16", batch=3, spin_seed=2024)
+
+
+def test_grad_bf16_row_count_not_multiple_of_four():
+    """Open 5x5 lattice, 3 samples: 75 rows, so the matrix-core products see
+    row ranges that end inside a 4-row block (the guarded element loads)
+    besides the 16-byte ones; checked against the oracle like the 20x20
+    case."""
+    mc = ODD_BF16
+    say("grad bf16 odd rows")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    g = host(vq.grad_logpsi(cfg, p, sp)).astype(np.float64)
+    _, codes = vq.forward_logpsi(cfg, p, sp, codes=True)
+    same = _codes_match_or_near_tie(mc, theta, s, host(codes))
+    idx = np.nonzero(same)[0]
+    assert len(idx) >= 1
+    ref = og.grad_logpsi(mc, theta, s[idx])
+    for j, b in enumerate(idx):
+        assert rel_norm(g[b], ref[j]) < 2e-3, b
+    w = torch.linspace(-1.0, 1.0, mc.batch, dtype=torch.float64, device="cuda")
+    gw = host(vq.grad_logpsi(cfg, p, sp, weights=w)).astype(np.float64)
+    assert rel_norm(gw, host(w) @ g) < 1e-5
+
+
 def test_grad_autograd_function_matches_weighted():
     mc = with_batch(CONFIGS["small"], 5)
     say("grad autograd function")
