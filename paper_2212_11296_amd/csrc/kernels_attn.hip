@@ -526,8 +526,9 @@ k_attn_seq_mfma(ModelDims m,
 // rewritten: the previous neighbour's rows go back to the sample's values
 // (unless the next one changes them too) and the next neighbour's rows take
 // its overlay values.  The next neighbour's row mask is fetched during the
-// current neighbour's compute and kept in LDS; a step then costs two
-// batched round trips to HBM (row indices, then 16-byte value loads).
+// current neighbour's compute and kept in LDS (two buffers by parity, so a
+// neighbour costs two barriers); a step then waits for one batch of 16-byte
+// value loads.
 template <int DH, int WPE>
 __global__ void __launch_bounds__(kAT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_attn_dedup_mfma(ModelDims m,
@@ -535,7 +536,7 @@ k_attn_dedup_mfma(ModelDims m,
                                                         int64_t* ctr) {
     constexpr int G = DH / 4, UNR = 2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ uint64_t msk[VQ_MAX_MASK_WORDS];
+    __shared__ uint64_t msk[2][VQ_MAX_MASK_WORDS];   // by neighbour parity
     const int N = m.N, d = m.d, W = dd.mask_words;
     const Tiles<DH> T = carve_tiles<DH>(smem_raw, N);
     const float qs = kLog2e / sqrtf((float)DH);
@@ -579,10 +580,13 @@ k_attn_dedup_mfma(ModelDims m,
         }
         int cp = 0;
         int64_t pov = 0;
+        if (k0 < k1 && threadIdx.x < W) msk[0][threadIdx.x] = mnext;
         for (int k = k0; k < k1; ++k) {
-            __syncthreads();             // LDS free: load_all or last compute
-            if (threadIdx.x < W) msk[threadIdx.x] = mnext;
+            // LDS free (load_all or last compute done) and this neighbour's
+            // mask words in msk[par], written after the previous compute
+            const int par = (k - k0) & 1;
             __syncthreads();
+            const uint64_t* mk = msk[par];
             // step (k-1 -> k): restore rows of C_{k-1} not in C_k, patch C_k
             const NbDesc D = Dn;
             const int pmin = D.p1 + 1;
@@ -617,7 +621,7 @@ k_attn_dedup_mfma(ModelDims m,
                     const bool restore = ec < np;
                     const int c4 = ((restore ? ec : ec - np) % G) * 4;
                     const int j = jj[i];
-                    use[i] = e < tot && !(restore && mbit(msk, j));
+                    use[i] = e < tot && !(restore && mbit(mk, j));
                     const int64_t o = (restore ? sb : ob0) + (int64_t)j * d + c4;
                     const float* K = restore ? dd.bk : dd.ok;
                     const float* Q = restore ? dd.bq : dd.oq;
@@ -646,6 +650,10 @@ k_attn_dedup_mfma(ModelDims m,
             __syncthreads();
             wave_tiles<DH>(T, N, NTQ, wave, pmin / 16, pmin,
                            [&](int i) { return dd.oa + ob0 + (int64_t)i * d; });
+            // the next neighbour's mask into the other buffer (last read by
+            // the previous step, which every wave finished before this
+            // neighbour's compute)
+            if (k + 1 < k1 && threadIdx.x < W) msk[par ^ 1][threadIdx.x] = mnext;
             if (h == 0 && threadIdx.x == 0) {
                 my_rows += N - pmin;
                 my_pairs += ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2;
@@ -688,7 +696,7 @@ static void big_lds(F f, size_t sm) {
 // Workgroups per CU that the LDS of one (sequence, head) allows.
 static int attn_wg_per_cu(const ModelDims& m) {
     return (int)((160 * 1024) /
-                 (attn_lds(m) + sizeof(uint64_t) * VQ_MAX_MASK_WORDS));
+                 (attn_lds(m) + sizeof(uint64_t) * 2 * VQ_MAX_MASK_WORDS));
 }
 
 hipError_t launch_attn_seq_mfma(const ModelDims& m, const int32_t* n_dev,
