@@ -60,6 +60,7 @@ struct Workspace {
     acc* cnorm;   // [nl][H*Q + H]
     float* prm;   // BF16 mode: parameters rounded to bfloat16
     bf16 *wqkv_p, *w1_p, *w2_p, *cb_p;   // [nl] matrix-core fragment packs
+    float* cnh4;                         // [nl][H*Q*4] -cnorm/2, four copies
     // chunk neighbour bookkeeping
     int16_t* bonds;
     int32_t *count, *nb_off, *n_nb, *n_rows, *list_n, *vq_n;
@@ -124,6 +125,7 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
             w.w1_p = c.take<bf16>((size_t)m.nl * d * m.dff);
             w.w2_p = c.take<bf16>((size_t)m.nl * m.dff * d);
             w.cb_p = c.take<bf16>((size_t)m.nl * m.Q * d);
+            w.cnh4 = c.take<float>((size_t)m.nl * H * m.Q * 4);
         }
     }
     w.bonds = c.take<int16_t>(n * 2 * N);
@@ -366,6 +368,7 @@ struct Runner {
             lw.W1_p = w.w1_p + (int64_t)l * m.d * m.dff;
             lw.W2_p = w.w2_p + (int64_t)l * m.dff * m.d;
             lw.cb_p = w.cb_p + (int64_t)l * m.Q * m.d;
+            lw.cnh4 = w.cnh4 + (int64_t)l * m.H * m.Q * 4;
         }
         return lw;
     }
@@ -417,7 +420,8 @@ struct Runner {
                     LK("pack_layer", launch_pack_layer(m, lw, const_cast<bf16*>(lw.Wqkv_p),
                                          const_cast<bf16*>(lw.W1_p),
                                          const_cast<bf16*>(lw.W2_p),
-                                         const_cast<bf16*>(lw.cb_p), st));
+                                         const_cast<bf16*>(lw.cb_p),
+                                         const_cast<float*>(lw.cnh4), st));
         }
         return VQNQS_OK;
     }

@@ -80,7 +80,7 @@ hipError_t launch_round_bf16(const float* src, int64_t n, float* dst,
                              hipStream_t st);
 hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
                              bf16* Wqkv_p, bf16* W1_p, bf16* W2_p, bf16* cb_p,
-                             hipStream_t st);
+                             float* cnh4, hipStream_t st);
 hipError_t launch_qkv_mfma(const ModelDims& m, const LayerW<float>& w,
                            RowSet rows, const BlockIO<PrecBF16>& io,
                            hipStream_t st);

@@ -93,9 +93,20 @@ hipError_t launch_round_bf16(const float* src, int64_t n, float* dst,
     return hipGetLastError();
 }
 
+// out[e][0..3] = -cnorm[e]/2 (exact: halving a normal float), the quantizer
+// search's accumulator input.
+__global__ void k_pack_cnorm(const float* __restrict__ cnorm, int64_t n,
+                             f32x4* __restrict__ out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float v = -0.5f * cnorm[e];
+        out[e] = f32x4{v, v, v, v};
+    }
+}
+
 hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
                              bf16* Wqkv_p, bf16* W1_p, bf16* W2_p, bf16* cb_p,
-                             hipStream_t st) {
+                             float* cnh4, hipStream_t st) {
     const int d = m.d, F = m.dff;
     auto go = [&](const float* src, int K, int Nout, int64_t sk, int64_t sc,
                   bf16* out) {
@@ -111,6 +122,9 @@ hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
     for (int h = 0; h < m.H; ++h)
         go(w.codebook + (int64_t)h * m.Q * m.dseg, m.dseg, m.Q, 1, m.dseg,
            cb_p + (int64_t)h * m.Q * m.dseg);
+    const int64_t nc = (int64_t)m.H * m.Q;
+    hipLaunchKernelGGL(k_pack_cnorm, dim3(mgrid((nc + 255) / 256)), dim3(256),
+                       0, st, w.cnorm, nc, reinterpret_cast<f32x4*>(cnh4));
     return hipGetLastError();
 }
 
@@ -633,7 +647,8 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
 }
 
 // --------------------------------------------------------------- VQ search
-// Running best / second-best (score, code); ties go to the lower code.
+// Running best / second-best (value, code) of g = a.w - |w|^2/2, which the
+// nearest code maximises; equal values go to the lower code.
 struct T2 {
     float b;
     int i;
@@ -641,22 +656,22 @@ struct T2 {
 };
 __device__ inline T2 t2_merge(T2 x, T2 y) {
     T2 r;
-    if (y.b < x.b || (y.b == x.b && y.i < x.i)) {
+    if (y.b > x.b || (y.b == x.b && y.i < x.i)) {
         r.b = y.b;
         r.i = y.i;
-        r.s = x.b < y.s ? x.b : y.s;
+        r.s = x.b > y.s ? x.b : y.s;
     } else {
         r.b = x.b;
         r.i = x.i;
-        r.s = y.b < x.s ? y.b : x.s;
+        r.s = y.b > x.s ? y.b : x.s;
     }
     return r;
 }
 
-// Bound on the error of a computed score |w|^2 - 2 (hi + lo).w for a row of
-// norm na (length-n FP32 sums of exact products, any order), plus the
-// representation error |a - (hi + lo)| <= 2^-16 |a| in both the product and
-// the row norm that turns scores into distances.
+// Bound on the error of a computed score |w|^2 - 2 (hi + lo).w = -2 g for a
+// row of norm na (g an FP32 sum, in any order, of n exact products and the
+// exact -|w|^2/2), plus the representation error |a - (hi + lo)| <= 2^-16 |a|
+// in both the product and the row norm that turns scores into distances.
 __device__ inline float score_err_split(int n, float na, float wmax) {
     const float g = (float)(n + 4) * 5.9604645e-8f * 1.0625f;
     return g * (2.0f * na * wmax + wmax * wmax + na * na) +
@@ -666,15 +681,17 @@ __device__ inline float score_err_split(int n, float na, float wmax) {
 // Each wave owns 16*MB rows kept in registers as hi/lo A fragments; the
 // four waves of a workgroup stream the codes of the quantizer head through
 // a double-buffered LDS stage (CBK code blocks of 16 codes per chunk, with
-// their squared norms).  The stages are filled by global-to-LDS loads (no
-// registers, no store instructions), issued one chunk ahead: the next chunk
-// of the head, or after a head's last chunk the first chunk of the next head
-// (or of the next tile's first head) when the chunk count is even.  A chunk
-// starts with this wave's loads complete and a barrier, after which every
-// wave has also finished reading the other stage, which then takes the next
-// chunk.
+// -|w|^2/2 of each code four times over: the accumulator input of the
+// code's products, so the matrix core returns g = a.w - |w|^2/2 for every
+// row and the search only compares).  The stages are filled by
+// global-to-LDS loads (no registers, no store instructions), issued one
+// chunk ahead: the next chunk of the head, or after a head's last chunk the
+// first chunk of the next head (or of the next tile's first head) when the
+// chunk count is even.  A chunk starts with this wave's loads complete and a
+// barrier, after which every wave has also finished reading the other stage,
+// which then takes the next chunk.
 // Every codebook fragment read from LDS feeds 2*MB MFMAs.  The second-best
-// distance (for the certified-reuse margins) is tracked only when MARGIN;
+// value (for the certified-reuse margins) is tracked only when MARGIN;
 // the chosen code is the same either way.  The register cap applies where
 // it costs no spills.
 template <int KBS, int MB, bool MARGIN>
@@ -688,7 +705,7 @@ __global__ void __launch_bounds__(kMT)
     constexpr int CN = CBK * 16;                 // code norms per chunk
     static_assert(CN == 64, "one wave loads a chunk's code norms");
     __shared__ bf16x8 stage0[CHUNK], stage1[CHUNK];
-    __shared__ float cn0[CN], cn1[CN];
+    __shared__ f32x4 cn0[CN], cn1[CN];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t n = rs_n(rows);
@@ -699,7 +716,7 @@ __global__ void __launch_bounds__(kMT)
     const float inf = __builtin_inff();
     // chunk c of head hq into (st, cs): clamped addresses (entries past the
     // codebook are never read)
-    auto fetch = [&](int hq, int c, bf16x8* st, float* cs) {
+    auto fetch = [&](int hq, int c, bf16x8* st, f32x4* cs) {
         const bf16x8* cbh = cbp + (int64_t)hq * cbtot;
         const int64_t e0 = (int64_t)c * CHUNK;
 #pragma unroll
@@ -709,8 +726,8 @@ __global__ void __launch_bounds__(kMT)
         }
         if (wave == 0) {
             const int code = c * CN + lane;
-            lds_dma4(w.cnorm + (int64_t)hq * m.Q + (code < m.Q ? code : m.Q - 1),
-                     cs);
+            lds_dma16(w.cnh4 + ((int64_t)hq * m.Q + (code < m.Q ? code : m.Q - 1)) * 4,
+                      cs);
         }
     };
     bool ahead = false;      // this head's first chunk is in stage0
@@ -757,7 +774,7 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) best[i][r] = T2{inf, 0, inf};   // see k_vq
+                for (int r = 0; r < 4; ++r) best[i][r] = T2{-inf, 0, -inf};
             if (!ahead) {
                 // the first chunk was not fetched ahead (start, or odd
                 // chunk count): both stages are free after the barrier
@@ -767,8 +784,8 @@ __global__ void __launch_bounds__(kMT)
             // chunk c from (sb, cs), the next one into (nsb, ncs).  A head's
             // last chunk fetches the next head's first one (the next tile's
             // first head after the last) into stage0 when it reads stage1.
-            auto chunk = [&](int c, const bf16x8* sb, const float* cs,
-                             bf16x8* nsb, float* ncs, bool into0) {
+            auto chunk = [&](int c, const bf16x8* sb, const f32x4* cs,
+                             bf16x8* nsb, f32x4* ncs, bool into0) {
                 wait_vmem();
                 __syncthreads();
                 // in flight during this chunk's search
@@ -782,9 +799,11 @@ __global__ void __launch_bounds__(kMT)
                 for (int cbl = 0; cbl < CBK; ++cbl) {
                     const int cb = c * CBK + cbl;
                     if (cb >= QB) break;
+                    // -|w|^2/2 of this lane's code in all four rows
+                    const f32x4 cq = cs[cbl * 16 + (lane & 15)];
                     f32x4 acc[MB];
 #pragma unroll
-                    for (int i = 0; i < MB; ++i) acc[i] = f32x4{0, 0, 0, 0};
+                    for (int i = 0; i < MB; ++i) acc[i] = cq;
 #pragma unroll
                     for (int kb = 0; kb < KBS; ++kb) {
                         const bf16x8 b = sb[(cbl * KBS + kb) * 64 + lane];
@@ -795,24 +814,23 @@ __global__ void __launch_bounds__(kMT)
                         }
                     }
                     const int code = cb * 16 + (lane & 15);
-                    const float cnv = cs[cbl * 16 + (lane & 15)];
 #pragma unroll
                     for (int i = 0; i < MB; ++i)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const float sc = cnv - 2.0f * acc[i][r];
+                            const float g = acc[i][r];
                             if (MARGIN) {
-                                if (sc < best[i][r].b) {
+                                if (g > best[i][r].b) {
                                     best[i][r].s = best[i][r].b;
-                                    best[i][r].b = sc;
+                                    best[i][r].b = g;
                                     best[i][r].i = code;
-                                } else if (sc < best[i][r].s) {
-                                    best[i][r].s = sc;
+                                } else if (g > best[i][r].s) {
+                                    best[i][r].s = g;
                                 }
                             } else {
-                                const bool lt = sc < best[i][r].b;
-                                best[i][r].b = lt ? sc : best[i][r].b;
-                                best[i][r].i = lt ? code : best[i][r].i;
+                                const bool gt = g > best[i][r].b;
+                                best[i][r].b = gt ? g : best[i][r].b;
+                                best[i][r].i = gt ? code : best[i][r].i;
                             }
                         }
                 }
@@ -836,7 +854,7 @@ __global__ void __launch_bounds__(kMT)
                         T2 y;
                         y.b = __shfl_xor(v.b, o, 64);
                         y.i = __shfl_xor(v.i, o, 64);
-                        y.s = MARGIN ? __shfl_xor(v.s, o, 64) : inf;
+                        y.s = MARGIN ? __shfl_xor(v.s, o, 64) : -inf;
                         v = t2_merge(v, y);
                     }
                     best[i][r] = v;
@@ -854,8 +872,9 @@ __global__ void __launch_bounds__(kMT)
                         if (MARGIN) {
                             const float na = sqrtf(a2);
                             const float E = score_err_split(2 * DS, na, wmax);
-                            const float u1 = best[i][r].b + a2 + E;
-                            const float l2 = best[i][r].s + a2 - E;
+                            // scores |w|^2 - 2 a.w = -2 g (exact scaling)
+                            const float u1 = -2.0f * best[i][r].b + a2 + E;
+                            const float l2 = -2.0f * best[i][r].s + a2 - E;
                             io.margin[(s * m.H + hq) * 2 + 0] = sqrtf(u1 > 0 ? u1 : 0.0f);
                             io.margin[(s * m.H + hq) * 2 + 1] = sqrtf(l2 > 0 ? l2 : 0.0f);
                         }
