@@ -59,10 +59,14 @@ __device__ inline void split2(float a, float b, bf16x2& hi, bf16x2& lo) {
 }
 
 // ---------------------------------------------------------------- packing
-// out[((nb*KB + kb)*64 + l)*8 + j] = W[kb*32 + 8*(l/16) + j][nb*16 + l%16]
-// with W[k][c] read at src[k*sk + c*sc] (K x Nout logical matrix).
+// out[((nb*KB + kb)*64 + l)*8 + j] = W[kb*32 + kk(8*(l/16) + j)][nb*16 + l%16]
+// with W[k][c] read at src[k*sk + c*sc] (K x Nout logical matrix).  kk is
+// the identity, or with hperm the order in which a transposed product leaves
+// 32 rows in a lane's A fragment: 8g + j holds row 4g + j for j < 4 and row
+// 16 + 4g + (j - 4) otherwise (the 4 rows of each of two 16-row blocks).
 __global__ void k_pack_b(const float* __restrict__ src, int K, int Nout,
-                         int64_t sk, int64_t sc, __bf16* __restrict__ out) {
+                         int64_t sk, int64_t sc, int hperm,
+                         __bf16* __restrict__ out) {
     const int64_t total = (int64_t)K * Nout;
     const int KB = K / 32;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -72,7 +76,9 @@ __global__ void k_pack_b(const float* __restrict__ src, int K, int Nout,
         const int64_t f = e >> 9;             // fragment id nb*KB + kb
         const int kb = (int)(f % KB);
         const int nb = (int)(f / KB);
-        const int k = kb * 32 + 8 * (l >> 4) + j;
+        const int g = l >> 4;
+        const int k = kb * 32 + (hperm ? (j < 4 ? 4 * g + j : 12 + 4 * g + j)
+                                       : 8 * g + j);
         const int c = nb * 16 + (l & 15);
         out[e] = (__bf16)src[k * sk + (int64_t)c * sc];
     }
@@ -109,15 +115,15 @@ hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
                              float* cnh4, hipStream_t st) {
     const int d = m.d, F = m.dff;
     auto go = [&](const float* src, int K, int Nout, int64_t sk, int64_t sc,
-                  bf16* out) {
+                  bf16* out, int hperm = 0) {
         const int64_t total = (int64_t)K * Nout;
         hipLaunchKernelGGL(k_pack_b, dim3(mgrid((total + 255) / 256)),
-                           dim3(256), 0, st, src, K, Nout, sk, sc,
+                           dim3(256), 0, st, src, K, Nout, sk, sc, hperm,
                            reinterpret_cast<__bf16*>(out));
     };
     go(w.W_qkv, d, 3 * d, 3 * d, 1, Wqkv_p);
     go(w.W1, d, F, F, 1, W1_p);
-    go(w.W2, F, d, d, 1, W2_p);
+    go(w.W2, F, d, d, 1, W2_p, 1);    // rows in the hidden layer's lane order
     // codebook head h as B[k][c] = cb[h][c][k]
     for (int h = 0; h < m.H; ++h)
         go(w.codebook + (int64_t)h * m.Q * m.dseg, m.dseg, m.Q, 1, m.dseg,
@@ -404,9 +410,12 @@ __global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
 // ------------------------------------------ out-projection + residual + MLP
 // Each wave: 16*MB rows.  x' = x_in + b_o + sum_h table[h][code_h] is formed
 // in the A-fragment layout, written to the output rows, and LN2(x') kept as
-// register A fragments.  The hidden layer is produced 64 columns at a time:
-// GELU(A W1[:, chunk] + b1) is transposed through a per-wave LDS scratch into
-// A fragments and multiplied into the output accumulators with W2[chunk, :].
+// register fragments.  The hidden layer is produced 64 columns at a time and
+// transposed: with the W1 fragments as the left operand and the LN2 rows as
+// the right one the matrix core returns H^T, so a lane holds 4 consecutive
+// hidden units of one row of each 16-unit block.  Two such blocks, GELU'd
+// and split, are directly a lane's A fragment of the second product (the W2
+// rows are packed in that order), with no transposition through memory.
 // The W1/W2 fragments of a chunk are staged in LDS for the four waves.
 // GELU with erf from Abramowitz & Stegun 7.1.26 (absolute error of erf at
 // most 1.5e-7): with y = |x|/sqrt(2), t = 1/(1 + p y) and
@@ -437,10 +446,8 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
     constexpr int C1 = NB1C * KB1 * 64;            // W1 fragment lanes per chunk
     constexpr int C2 = KB2C * NBO * 64;            // W2 fragment lanes per chunk
     constexpr int PER1 = C1 / kMT, PER2 = C2 / kMT;
-    constexpr int LDH = HC + 8;
     __shared__ bf16x8 s1[C1];
     __shared__ bf16x8 s2[C2];
-    __shared__ __align__(16) __bf16 hs[4][2][WR * LDH];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gq = lane >> 4, c16 = lane & 15;
     const int64_t n = rs_n(rows);
@@ -520,8 +527,6 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
         for (int i = 0; i < MB; ++i)
 #pragma unroll
             for (int nb = 0; nb < NBO; ++nb) out[i][nb] = f32x4{0, 0, 0, 0};
-        __bf16* hh = hs[wave][0];
-        __bf16* hl = hs[wave][1];
         for (int hc = 0; hc < F / HC; ++hc) {
             __syncthreads();                       // stages free
             stage_store<PER1>(p1, s1);
@@ -530,8 +535,9 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
             // the next chunk's weights (chunk 0 again after the last: the
             // next tile's) load while this chunk is computed
             fetch_w(hc + 1 < F / HC ? hc + 1 : 0);
-            // hidden chunk = GELU(A W1[:, chunk] + b1); the K loop is
-            // outermost so the NB1C accumulators are independent MFMA chains
+            // hidden chunk transposed: H^T = W1[:, chunk]^T LN2(x')^T; the K
+            // loop is outermost so the NB1C accumulators are independent
+            // MFMA chains
             f32x4 hacc[MB][NB1C];
 #pragma unroll
             for (int i = 0; i < MB; ++i)
@@ -544,38 +550,36 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
                     const bf16x8 b = s1[(nb * KB1 + kb) * 64 + lane];
 #pragma unroll
                     for (int i = 0; i < MB; ++i) {
-                        hacc[i][nb] = mfma(ah[i][kb], b, hacc[i][nb]);
-                        hacc[i][nb] = mfma(al[i][kb], b, hacc[i][nb]);
+                        hacc[i][nb] = mfma(b, ah[i][kb], hacc[i][nb]);
+                        hacc[i][nb] = mfma(b, al[i][kb], hacc[i][nb]);
                     }
                 }
-            // D layout -> LDS (row-major [WR][HC]) -> A layout
-#pragma unroll
-            for (int nb = 0; nb < NB1C; ++nb) {
-                const int col = nb * 16 + c16;
-                const float bias = w.b1[hc * HC + col];
-#pragma unroll
-                for (int i = 0; i < MB; ++i)
-#pragma unroll
-                    for (int r = 0; r < 4; r += 2) {
-                        const int row = i * 16 + 4 * gq + r;
-                        bf16x2 h2, l2;
-                        split2(gelu_as(hacc[i][nb][r] + bias),
-                               gelu_as(hacc[i][nb][r + 1] + bias), h2, l2);
-                        hh[row * LDH + col] = h2[0];
-                        hl[row * LDH + col] = l2[0];
-                        hh[(row + 1) * LDH + col] = h2[1];
-                        hl[(row + 1) * LDH + col] = l2[1];
-                    }
-            }
-            wait_lds();                    // this wave's transposes
-            __builtin_amdgcn_wave_barrier();
+            // GELU(. + b1) of hidden units nb*16 + 4 gq + r of row c16, split
+            // hi/lo: blocks 2 kb and 2 kb + 1 form the A fragment of k-block kb
 #pragma unroll
             for (int kb = 0; kb < KB2C; ++kb) {
                 bf16x8 xh[MB], xl[MB];
 #pragma unroll
-                for (int i = 0; i < MB; ++i) {
-                    xh[i] = lds_frag(hh, LDH, i, kb, lane);
-                    xl[i] = lds_frag(hl, LDH, i, kb, lane);
+                for (int half = 0; half < 2; ++half) {
+                    const int nb = 2 * kb + half;
+                    const float4 bq = *reinterpret_cast<const float4*>(
+                        w.b1 + hc * HC + nb * 16 + 4 * gq);
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) {
+                        bf16x2 h01, l01, h23, l23;
+                        split2(gelu_as(hacc[i][nb][0] + bq.x),
+                               gelu_as(hacc[i][nb][1] + bq.y), h01, l01);
+                        split2(gelu_as(hacc[i][nb][2] + bq.z),
+                               gelu_as(hacc[i][nb][3] + bq.w), h23, l23);
+                        xh[i][4 * half + 0] = h01[0];
+                        xh[i][4 * half + 1] = h01[1];
+                        xh[i][4 * half + 2] = h23[0];
+                        xh[i][4 * half + 3] = h23[1];
+                        xl[i][4 * half + 0] = l01[0];
+                        xl[i][4 * half + 1] = l01[1];
+                        xl[i][4 * half + 2] = l23[0];
+                        xl[i][4 * half + 3] = l23[1];
+                    }
                 }
 #pragma unroll
                 for (int nb = 0; nb < NBO; ++nb) {
@@ -587,7 +591,6 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
                     }
                 }
             }
-            __builtin_amdgcn_wave_barrier();
         }
         // x = x' + hidden W2 + b2, with x' recomputed for this lane's
         // elements in the prologue's addition order: every element is read
