@@ -793,7 +793,7 @@ __device__ inline T dot4(const T* a, const T* b) {
 
 // Rows 0..N-1 of one head (DH columns at base + row * d) into an LDS tile
 // [N][DH]: 16-byte loads, four per thread issued before their stores.
-template <typename T, int DH>
+template <typename T, int DH, int NT>
 __device__ inline void fill_tile(T* dst, const T* src, int64_t base, int N,
                                  int d) {
     constexpr int V = 16 / (int)sizeof(T);       // elements per 16 bytes
@@ -801,12 +801,12 @@ __device__ inline void fill_tile(T* dst, const T* src, int64_t base, int N,
     constexpr int G = DH / V, U = 4;
     typedef __attribute__((ext_vector_type(V))) T vec;
     const int tot = N * G;
-    for (int e0 = 0; e0 < tot; e0 += kGT * U) {
+    for (int e0 = 0; e0 < tot; e0 += NT * U) {
         vec v[U];
         int row[U], c[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int e = e0 + kGT * u + (int)threadIdx.x;
+            const int e = e0 + NT * u + (int)threadIdx.x;
             const int ec = e < tot ? e : tot - 1;
             row[u] = ec / G;
             c[u] = (ec % G) * V;
@@ -814,7 +814,7 @@ __device__ inline void fill_tile(T* dst, const T* src, int64_t base, int N,
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (e0 + kGT * u + (int)threadIdx.x < tot)
+            if (e0 + NT * u + (int)threadIdx.x < tot)
                 *reinterpret_cast<vec*>(dst + row[u] * DH + c[u]) = v[u];
     }
 }
@@ -822,8 +822,8 @@ __device__ inline void fill_tile(T* dst, const T* src, int64_t base, int N,
 // One workgroup per (sample, head).  Scores s_ij = q_i . k_j / sqrt(d_head)
 // for j <= i; P = softmax_j(s).  lse_i = log sum_j exp(s_ij), and
 // Dd_i = dO_i . O_i (O = the forward attention output).
-template <typename T, int DH>
-__global__ void __launch_bounds__(kGT) k_attn_stats(int64_t n, ModelDims m,
+template <typename T, int DH, int NT>
+__global__ void __launch_bounds__(NT) k_attn_stats(int64_t n, ModelDims m,
                                                     const T* q, const T* k,
                                                     const T* o, const T* dO,
                                                     T* lse, T* Dd) {
@@ -836,9 +836,9 @@ __global__ void __launch_bounds__(kGT) k_attn_stats(int64_t n, ModelDims m,
         const int h = (int)(u - s * nh);
         const int64_t base = s * N * d + h * DH;
         __syncthreads();
-        fill_tile<T, DH>(Ks, k, base, N, d);
+        fill_tile<T, DH, NT>(Ks, k, base, N, d);
         __syncthreads();
-        for (int i = threadIdx.x; i < N; i += kGT) {
+        for (int i = threadIdx.x; i < N; i += NT) {
             T qi[DH];
             T dd = 0;
 #pragma unroll
@@ -864,8 +864,8 @@ __global__ void __launch_bounds__(kGT) k_attn_stats(int64_t n, ModelDims m,
 }
 
 // dq_i = scale * sum_{j <= i} dS_ij k_j with dS_ij = P_ij (dO_i . v_j - Dd_i).
-template <typename T, int DH>
-__global__ void __launch_bounds__(kGT) k_attn_bwd_q(int64_t n, ModelDims m,
+template <typename T, int DH, int NT>
+__global__ void __launch_bounds__(NT) k_attn_bwd_q(int64_t n, ModelDims m,
                                                     const T* q, const T* k,
                                                     const T* v, const T* dO,
                                                     const T* lse, const T* Dd,
@@ -880,10 +880,10 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_q(int64_t n, ModelDims m,
         const int h = (int)(u - s * nh);
         const int64_t base = s * N * d + h * DH;
         __syncthreads();
-        fill_tile<T, DH>(Ks, k, base, N, d);
-        fill_tile<T, DH>(Vs, v, base, N, d);
+        fill_tile<T, DH, NT>(Ks, k, base, N, d);
+        fill_tile<T, DH, NT>(Vs, v, base, N, d);
         __syncthreads();
-        for (int i = threadIdx.x; i < N; i += kGT) {
+        for (int i = threadIdx.x; i < N; i += NT) {
             T qi[DH], gi[DH], acc[DH];
 #pragma unroll
             for (int c = 0; c < DH; ++c) {
@@ -908,8 +908,8 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_q(int64_t n, ModelDims m,
 }
 
 // dk_j = scale * sum_{i >= j} dS_ij q_i,  dv_j = sum_{i >= j} P_ij dO_i.
-template <typename T, int DH>
-__global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
+template <typename T, int DH, int NT>
+__global__ void __launch_bounds__(NT) k_attn_bwd_kv(int64_t n, ModelDims m,
                                                      const T* q, const T* k,
                                                      const T* v, const T* dO,
                                                      const T* lse, const T* Dd,
@@ -926,9 +926,9 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
         const int h = (int)(u - s * nh);
         const int64_t base = s * N * d + h * DH;
         __syncthreads();
-        fill_tile<T, DH>(Qs, q, base, N, d);
-        fill_tile<T, DH>(Gs, dO, base, N, d);
-        for (int i = threadIdx.x; i < N; i += kGT) {
+        fill_tile<T, DH, NT>(Qs, q, base, N, d);
+        fill_tile<T, DH, NT>(Gs, dO, base, N, d);
+        for (int i = threadIdx.x; i < N; i += NT) {
             Ls[i] = lse[(s * N + i) * nh + h];
             Ds[i] = Dd[(s * N + i) * nh + h];
         }
@@ -937,7 +937,7 @@ __global__ void __launch_bounds__(kGT) k_attn_bwd_kv(int64_t n, ModelDims m,
         // key, so every LDS read is a broadcast; a lane's terms for queries
         // before its own key are exact zeros, which leave its sums as they
         // would be without them.
-        for (int jb = 0; jb < N; jb += kGT) {
+        for (int jb = 0; jb < N; jb += NT) {
             const int jw = jb + (threadIdx.x & ~63);     // the wave's first key
             if (jw >= N) continue;
             const int j = jb + threadIdx.x;
@@ -986,27 +986,42 @@ static hipError_t lds_attr(F f, size_t sm) {
     return hipSuccess;
 }
 
+template <typename T, int DH, int NT>
+static hipError_t attn_bwd_nt(int64_t n, const ModelDims& m, const T* q,
+                              const T* k, const T* v, const T* o, const T* dO,
+                              T* lse, T* Dd, T* dqkv, unsigned g, hipStream_t st) {
+    const size_t s1 = sizeof(T) * (size_t)m.N * DH;
+    const size_t s2 = 2 * s1;
+    const size_t s3 = 2 * s1 + 2 * sizeof(T) * (size_t)m.N;
+    hipError_t e;
+    if ((e = lds_attr(k_attn_stats<T, DH, NT>, s1))) return e;
+    hipLaunchKernelGGL((k_attn_stats<T, DH, NT>), dim3(g), dim3(NT), s1, st, n, m, q, k,
+                       o, dO, lse, Dd);
+    if ((e = hipGetLastError())) return e;
+    if ((e = lds_attr(k_attn_bwd_q<T, DH, NT>, s2))) return e;
+    hipLaunchKernelGGL((k_attn_bwd_q<T, DH, NT>), dim3(g), dim3(NT), s2, st, n, m, q, k,
+                       v, dO, lse, Dd, dqkv);
+    if ((e = hipGetLastError())) return e;
+    if ((e = lds_attr(k_attn_bwd_kv<T, DH, NT>, s3))) return e;
+    hipLaunchKernelGGL((k_attn_bwd_kv<T, DH, NT>), dim3(g), dim3(NT), s3, st, n, m, q, k,
+                       v, dO, lse, Dd, dqkv);
+    return hipGetLastError();
+}
+
 template <typename T, int DH>
 static hipError_t attn_bwd_dh(int64_t n, const ModelDims& m, const T* q,
                               const T* k, const T* v, const T* o, const T* dO,
                               T* lse, T* Dd, T* dqkv, hipStream_t st) {
     const unsigned g = cap_grid(n * m.nh);
-    const size_t s1 = sizeof(T) * (size_t)m.N * DH;
-    const size_t s2 = 2 * s1;
-    const size_t s3 = 2 * s1 + 2 * sizeof(T) * (size_t)m.N;
-    hipError_t e;
-    if ((e = lds_attr(k_attn_stats<T, DH>, s1))) return e;
-    hipLaunchKernelGGL((k_attn_stats<T, DH>), dim3(g), dim3(kGT), s1, st, n, m, q, k,
-                       o, dO, lse, Dd);
-    if ((e = hipGetLastError())) return e;
-    if ((e = lds_attr(k_attn_bwd_q<T, DH>, s2))) return e;
-    hipLaunchKernelGGL((k_attn_bwd_q<T, DH>), dim3(g), dim3(kGT), s2, st, n, m, q, k,
-                       v, dO, lse, Dd, dqkv);
-    if ((e = hipGetLastError())) return e;
-    if ((e = lds_attr(k_attn_bwd_kv<T, DH>, s3))) return e;
-    hipLaunchKernelGGL((k_attn_bwd_kv<T, DH>), dim3(g), dim3(kGT), s3, st, n, m, q, k,
-                       v, dO, lse, Dd, dqkv);
-    return hipGetLastError();
+    // One thread per query (per key in the key-side pass).  Past 256 rows,
+    // 512 threads take up to 512 rows in one round, two waves per SIMD where
+    // the tiles leave room for one workgroup per CU only; this where a
+    // thread's row vectors fit in the registers of two waves per SIMD.
+    if constexpr (sizeof(T) * DH <= 128)
+        if (m.N > kGT)
+            return attn_bwd_nt<T, DH, 2 * kGT>(n, m, q, k, v, o, dO, lse, Dd,
+                                               dqkv, g, st);
+    return attn_bwd_nt<T, DH, kGT>(n, m, q, k, v, o, dO, lse, Dd, dqkv, g, st);
 }
 
 template <typename T>
