@@ -180,7 +180,22 @@ __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
     const float* A = static_cast<const float*>(g.A) + grp * g.sA;
     const float* B = static_cast<const float*>(g.B) + grp * g.sB;
     float* C = static_cast<float*>(g.C) + grp * g.sC;
-    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    // Workgroups go to the 8 XCDs in turn, each with its own L2.  Where a
+    // group's tile count is a multiple of 8, XCD x takes the x-th eighth of
+    // the group's tiles in row-major order, so the column tiles of one row
+    // tile run on one XCD and share its A rows in that L2 (otherwise every
+    // XCD would fetch every A row tile from HBM).  A bijection on the tiles.
+    int64_t bx = blockIdx.x, by = blockIdx.y;
+    {
+        const int64_t tiles = (int64_t)gridDim.x * gridDim.y;
+        if (tiles % 8 == 0) {
+            const int64_t L = bx + (int64_t)gridDim.x * by;
+            const int64_t T = (L % 8) * (tiles / 8) + L / 8;
+            bx = T % gridDim.x;
+            by = T / gridDim.x;
+        }
+    }
+    const int64_t m0 = by * BM, n0 = bx * BN;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
