@@ -205,23 +205,29 @@ __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = gf32x4{0, 0, 0, 0};
     // Each thread converts one 4 x 4 block (4 rows x 4 k) of each operand
-    // per K step.  Along a contiguous k the blocks of consecutive threads
-    // are consecutive in k, otherwise in rows, so the 16-byte loads of a
-    // wave are contiguous.
+    // per K step.  Along a contiguous k the blocks of 8 consecutive threads
+    // are consecutive in k (128 contiguous bytes per row); otherwise 4
+    // consecutive threads take consecutive row blocks (64 contiguous bytes
+    // per k) and the next ones the next k blocks, so that the 8-byte LDS
+    // stores of 32 lanes fall on 64 distinct banks (consecutive row blocks
+    // alone are 320 bytes apart, 8 lanes to a bank).
     const bool akc = !g.tA, bkc = g.tB != 0;
     const bool avec = g.lda % 4 == 0 && g.sA % 4 == 0 &&
                       (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
     const bool bvec = g.ldb % 4 == 0 && g.sB % 4 == 0 &&
                       (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
-    const int abr = akc ? tid >> 3 : tid & 31, abk = akc ? tid & 7 : tid >> 5;
-    const int bbr = bkc ? tid >> 3 : tid & 31, bbk = bkc ? tid & 7 : tid >> 5;
-    float va[4][4], vb[4][4];
-    auto fetch = [&](int64_t k0) {
+    const int rr = (tid & 3) + 4 * (tid >> 5), rk = (tid >> 2) & 7;
+    const int abr = akc ? tid >> 3 : rr, abk = akc ? tid & 7 : rk;
+    const int bbr = bkc ? tid >> 3 : rr, bbk = bkc ? tid & 7 : rk;
+    // two register sets: the loads for K step s + 2 are issued while step s
+    // is multiplied and step s + 1 is converted into LDS
+    float va0[4][4], vb0[4][4], va1[4][4], vb1[4][4];
+    auto fetch = [&](int64_t k0, float (&va)[4][4], float (&vb)[4][4]) {
         load_block(A, g.lda, akc, avec, m0 + 4 * abr, g.M, k0 + 4 * abk, g.K, va);
         load_block(B, g.ldb, bkc, bvec, n0 + 4 * bbr, g.N, k0 + 4 * bbk, g.K, vb);
     };
     // hi = bf16(x), lo = bf16(x - hi); a row's four k go to LDS as 8 bytes
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf, const float (&va)[4][4], const float (&vb)[4][4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             gbf16x4 h, l;
@@ -247,26 +253,24 @@ __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
             if (!g.b_exact) *reinterpret_cast<gbf16x4*>(&Bl[buf][o]) = l;
         }
     };
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    int cur = 0;
-    for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
-        const bool more = k0 + BK < g.K;
-        if (more) fetch(k0 + BK);
+    // K step k from LDS stage b: loads for k + 2 BK into (fa, fb), the
+    // values of step k + BK from (sa, sb) into the other stage
+    auto step = [&](int64_t k0, int b, float (&fa)[4][4], float (&fb)[4][4],
+                    const float (&sa)[4][4], const float (&sb)[4][4]) {
+        if (k0 + 2 * BK < g.K) fetch(k0 + 2 * BK, fa, fb);
         gbf16x8 bh[4], bl[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int nn = wn * 64 + j * 16 + (lane & 15);
-            bh[j] = *reinterpret_cast<const gbf16x8*>(&Bh[cur][nn * LD + 8 * (lane >> 4)]);
+            bh[j] = *reinterpret_cast<const gbf16x8*>(&Bh[b][nn * LD + 8 * (lane >> 4)]);
             if (!g.b_exact)
-                bl[j] = *reinterpret_cast<const gbf16x8*>(&Bl[cur][nn * LD + 8 * (lane >> 4)]);
+                bl[j] = *reinterpret_cast<const gbf16x8*>(&Bl[b][nn * LD + 8 * (lane >> 4)]);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int mm = wm * 64 + i * 16 + (lane & 15);
-            const gbf16x8 ah = *reinterpret_cast<const gbf16x8*>(&Ah[cur][mm * LD + 8 * (lane >> 4)]);
-            const gbf16x8 al = *reinterpret_cast<const gbf16x8*>(&Al[cur][mm * LD + 8 * (lane >> 4)]);
+            const gbf16x8 ah = *reinterpret_cast<const gbf16x8*>(&Ah[b][mm * LD + 8 * (lane >> 4)]);
+            const gbf16x8 al = *reinterpret_cast<const gbf16x8*>(&Al[b][mm * LD + 8 * (lane >> 4)]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
@@ -275,9 +279,17 @@ __global__ void __launch_bounds__(kGT) k_gemm_mfma(GemmDesc g) {
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
             }
         }
-        if (more) stash(cur ^ 1);
+        if (k0 + BK < g.K) stash(b ^ 1, sa, sb);
         __syncthreads();
-        cur ^= 1;
+    };
+    fetch(0, va0, vb0);
+    stash(0, va0, vb0);
+    if (BK < g.K) fetch(BK, va1, vb1);
+    __syncthreads();
+    // the two sets are named statically in two copies of the step
+    for (int64_t k0 = 0; k0 < g.K; k0 += 2 * BK) {
+        step(k0, 0, va0, vb0, va1, vb1);
+        if (k0 + BK < g.K) step(k0 + BK, 1, va1, vb1, va0, vb0);
     }
     // D layout: lane holds rows 4*(lane/16) + r of column lane%16
 #pragma unroll
