@@ -846,6 +846,19 @@ __device__ inline void fill_tile(T* dst, const T* src, int64_t base, int N,
     }
 }
 
+// The dq pass holds the next key and value rows in registers (loaded from
+// LDS while the current ones are used) where they fit beside a thread's
+// other vectors.
+template <typename T, int DH>
+constexpr bool kPipeRows = sizeof(T) * DH <= 128 && (sizeof(T) == 4 || DH <= 8);
+
+// Row j of an LDS tile [N][DH] into registers.
+template <typename T, int DH>
+__device__ inline void lds_row(const T* tile, int j, T (&r)[DH]) {
+#pragma unroll
+    for (int c = 0; c < DH; ++c) r[c] = tile[j * DH + c];
+}
+
 // One workgroup per (sample, head).  Scores s_ij = q_i . k_j / sqrt(d_head)
 // for j <= i; P = softmax_j(s).  lse_i = log sum_j exp(s_ij), and
 // Dd_i = dO_i . O_i (O = the forward attention output).
@@ -910,26 +923,57 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_q(int64_t n, ModelDims m,
         fill_tile<T, DH, NT>(Ks, k, base, N, d);
         fill_tile<T, DH, NT>(Vs, v, base, N, d);
         __syncthreads();
-        for (int i = threadIdx.x; i < N; i += NT) {
+        // A wave walks the keys 0 .. (its last row) together; keys after a
+        // lane's own row add exact zeros (p = 0), which leave its sums as
+        // they are, so a lane's terms and their order are those of its row.
+        for (int i0 = 0; i0 < N; i0 += NT) {
+            const int wf = i0 + (int)(threadIdx.x & ~63);
+            if (wf >= N) continue;
+            const int i = i0 + (int)threadIdx.x;
+            const int ir = i < N ? i : N - 1;
+            const int jmax = min(wf + 63, N - 1);
             T qi[DH], gi[DH], acc[DH];
 #pragma unroll
             for (int c = 0; c < DH; ++c) {
-                qi[c] = q[base + (int64_t)i * d + c];
-                gi[c] = dO[base + (int64_t)i * d + c];
+                qi[c] = q[base + (int64_t)ir * d + c];
+                gi[c] = dO[base + (int64_t)ir * d + c];
                 acc[c] = 0;
             }
-            const T ls = lse[(s * N + i) * nh + h], dd = Dd[(s * N + i) * nh + h];
-            for (int j = 0; j <= i; ++j) {
-                const T sc = dot4<T, DH>(qi, Ks + j * DH);
-                const T dp = dot4<T, DH>(gi, Vs + j * DH);
-                const T p = dexp(sc * scale - ls);
+            const T ls = lse[(s * N + ir) * nh + h], dd = Dd[(s * N + ir) * nh + h];
+            auto term = [&](int j, const T* kc, const T* vc) {
+                const T sc = dot4<T, DH>(qi, kc);
+                const T dp = dot4<T, DH>(gi, vc);
+                const T e = dexp(sc * scale - ls);
+                const T p = j <= ir ? e : (T)0;
                 const T ds = p * (dp - dd);
 #pragma unroll
-                for (int c = 0; c < DH; ++c) acc[c] += ds * Ks[j * DH + c];
+                for (int c = 0; c < DH; ++c) acc[c] += ds * kc[c];
+            };
+            if constexpr (kPipeRows<T, DH>) {
+                T ka[DH], va[DH], kb[DH], vb[DH];
+                lds_row<T, DH>(Ks, 0, ka);
+                lds_row<T, DH>(Vs, 0, va);
+                for (int j = 0; j <= jmax; j += 2) {
+                    if (j + 1 <= jmax) {
+                        lds_row<T, DH>(Ks, j + 1, kb);
+                        lds_row<T, DH>(Vs, j + 1, vb);
+                    }
+                    term(j, ka, va);
+                    if (j + 1 > jmax) break;
+                    if (j + 2 <= jmax) {
+                        lds_row<T, DH>(Ks, j + 2, ka);
+                        lds_row<T, DH>(Vs, j + 2, va);
+                    }
+                    term(j + 1, kb, vb);
+                }
+            } else {
+                for (int j = 0; j <= jmax; ++j) term(j, Ks + j * DH, Vs + j * DH);
             }
-            T* out = dqkv + (s * N + i) * 3 * d + h * DH;
+            if (i < N) {
+                T* out = dqkv + (s * N + i) * 3 * d + h * DH;
 #pragma unroll
-            for (int c = 0; c < DH; ++c) out[c] = acc[c] * scale;
+                for (int c = 0; c < DH; ++c) out[c] = acc[c] * scale;
+            }
         }
     }
 }
