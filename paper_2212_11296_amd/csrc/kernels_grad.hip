@@ -1065,8 +1065,10 @@ static hipError_t attn_bwd_nt(int64_t n, const ModelDims& m, const T* q,
     const size_t s2 = 2 * s1;
     const size_t s3 = 2 * s1 + 2 * sizeof(T) * (size_t)m.N;
     hipError_t e;
-    if ((e = lds_attr(k_attn_stats<T, DH, NT>, s1))) return e;
-    hipLaunchKernelGGL((k_attn_stats<T, DH, NT>), dim3(g), dim3(NT), s1, st, n, m, q, k,
+    // the statistics pass keeps 256 threads: its tile leaves room for three
+    // workgroups per CU, which its registers allow at that size only
+    if ((e = lds_attr(k_attn_stats<T, DH, kGT>, s1))) return e;
+    hipLaunchKernelGGL((k_attn_stats<T, DH, kGT>), dim3(g), dim3(kGT), s1, st, n, m, q, k,
                        o, dO, lse, Dd);
     if ((e = hipGetLastError())) return e;
     if ((e = lds_attr(k_attn_bwd_q<T, DH, NT>, s2))) return e;
@@ -1084,10 +1086,11 @@ static hipError_t attn_bwd_dh(int64_t n, const ModelDims& m, const T* q,
                               const T* k, const T* v, const T* o, const T* dO,
                               T* lse, T* Dd, T* dqkv, hipStream_t st) {
     const unsigned g = cap_grid(n * m.nh);
-    // One thread per query (per key in the key-side pass).  Past 256 rows,
-    // 512 threads take up to 512 rows in one round, two waves per SIMD where
-    // the tiles leave room for one workgroup per CU only; this where a
-    // thread's row vectors fit in the registers of two waves per SIMD.
+    // One thread per query (per key in the key-side pass).  Past 256 rows
+    // the dq and key-side passes run 512 threads: up to 512 rows in one
+    // round, two waves per SIMD where their tiles leave room for one
+    // workgroup per CU only.  Only where a thread's row vectors fit the
+    // registers of two waves per SIMD.
     if constexpr (sizeof(T) * DH <= 128)
         if (m.N > kGT)
             return attn_bwd_nt<T, DH, 2 * kGT>(n, m, q, k, v, o, dO, lse, Dd,

@@ -543,17 +543,28 @@ __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k
             for (int i = 0; i < MB; ++i)
 #pragma unroll
                 for (int nb = 0; nb < NB1C; ++nb) hacc[i][nb] = f32x4{0, 0, 0, 0};
+            // a k-block's W1 fragments are read from LDS while the previous
+            // k-block is multiplied
+            bf16x8 w1f[2][NB1C];
 #pragma unroll
-            for (int kb = 0; kb < KB1; ++kb)
+            for (int nb = 0; nb < NB1C; ++nb) w1f[0][nb] = s1[nb * KB1 * 64 + lane];
+#pragma unroll
+            for (int kb = 0; kb < KB1; ++kb) {
+                if (kb + 1 < KB1) {
+#pragma unroll
+                    for (int nb = 0; nb < NB1C; ++nb)
+                        w1f[(kb + 1) & 1][nb] = s1[(nb * KB1 + kb + 1) * 64 + lane];
+                }
 #pragma unroll
                 for (int nb = 0; nb < NB1C; ++nb) {
-                    const bf16x8 b = s1[(nb * KB1 + kb) * 64 + lane];
+                    const bf16x8 b = w1f[kb & 1][nb];
 #pragma unroll
                     for (int i = 0; i < MB; ++i) {
                         hacc[i][nb] = mfma(b, ah[i][kb], hacc[i][nb]);
                         hacc[i][nb] = mfma(b, al[i][kb], hacc[i][nb]);
                     }
                 }
+            }
             // GELU(. + b1) of hidden units nb*16 + 4 gq + r of row c16, split
             // hi/lo: blocks 2 kb and 2 kb + 1 form the A fragment of k-block kb
 #pragma unroll
@@ -798,18 +809,30 @@ __global__ void __launch_bounds__(kMT)
                     ahead = into0 && (hq + 1 < m.H || t + gridDim.x < ntile);
                     if (ahead) fetch(hq + 1 < m.H ? hq + 1 : 0, 0, nsb, ncs);
                 }
+                // code blocks of this chunk; each block's fragments (and
+                // -|w|^2/2 of this lane's code in all four rows) are read
+                // from LDS while the previous block is searched
+                const int ncb = min(CBK, QB - c * CBK);
+                bf16x8 bf[2][KBS];
+                f32x4 cqs[2];
+                auto frags = [&](int cbl, bf16x8 (&b)[KBS], f32x4& cq) {
+#pragma unroll
+                    for (int kb = 0; kb < KBS; ++kb)
+                        b[kb] = sb[(cbl * KBS + kb) * 64 + lane];
+                    cq = cs[cbl * 16 + (lane & 15)];
+                };
+                frags(0, bf[0], cqs[0]);
 #pragma unroll
                 for (int cbl = 0; cbl < CBK; ++cbl) {
+                    if (cbl >= ncb) break;
                     const int cb = c * CBK + cbl;
-                    if (cb >= QB) break;
-                    // -|w|^2/2 of this lane's code in all four rows
-                    const f32x4 cq = cs[cbl * 16 + (lane & 15)];
+                    if (cbl + 1 < ncb) frags(cbl + 1, bf[(cbl + 1) & 1], cqs[(cbl + 1) & 1]);
                     f32x4 acc[MB];
 #pragma unroll
-                    for (int i = 0; i < MB; ++i) acc[i] = cq;
+                    for (int i = 0; i < MB; ++i) acc[i] = cqs[cbl & 1];
 #pragma unroll
                     for (int kb = 0; kb < KBS; ++kb) {
-                        const bf16x8 b = sb[(cbl * KBS + kb) * 64 + lane];
+                        const bf16x8 b = bf[cbl & 1][kb];
 #pragma unroll
                         for (int i = 0; i < MB; ++i) {
                             acc[i] = mfma(ah[i][kb], b, acc[i]);
