@@ -307,10 +307,13 @@ __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // first chunk after the last), a wait for them and a barrier at each chunk
 // start.  A chunk's outputs stay in registers and are stored after the next
 // chunk's loads have been issued, so that wait never covers fresh stores.
+// With one row tile per wave up to d = 128 the kernel fits 168 VGPRs (a few
+// spills at tile level), which allows three waves per SIMD.
 template <int KB, int MB>
-__global__ void __launch_bounds__(kMT) k_qkv_mfma(ModelDims m, LayerW<float> w,
-                                                 RowSet rows, BlockIO<PrecBF16> io,
-                                                 const bf16x8* __restrict__ Bp) {
+__global__ void __launch_bounds__(kMT)
+    __attribute__((amdgpu_waves_per_eu(MB == 1 && KB <= 4 ? 3 : 1)))
+    k_qkv_mfma(ModelDims m, LayerW<float> w, RowSet rows,
+               BlockIO<PrecBF16> io, const bf16x8* __restrict__ Bp) {
     constexpr int D = KB * 32, WR = MB * 16, NBC = 4;
     constexpr int CHUNK = NBC * KB * 64, PER = CHUNK / kMT;
     constexpr int NBT = 3 * D / 16;
