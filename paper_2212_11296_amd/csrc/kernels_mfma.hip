@@ -425,17 +425,17 @@ __global__ void __launch_bounds__(kMT)
 // (a1 t + ... + a5 t^5) exp(-y^2) ~ erfc(y).  The constants are folded:
 // t = 1/(1 + (p/sqrt 2)|x|), the coefficients are halved so that
 // q = (a1/2 t + ... + a5/2 t^5) 2^(-(log2 e)/2 x^2) ~ erfc(y)/2 = Phi(-|x|),
-// and GELU(x) = x Phi(x) is x q for x < 0 (no cancellation) and x (1 - q)
-// otherwise.  Branch-free.
+// and GELU(x) = x Phi(x) = max(x, 0) - |x| q: x q for x < 0 (no
+// cancellation) and x - x q otherwise, one FMA either way.  Branch-free.
 __device__ inline float gelu_as(float x) {
-    const float t =
-        __builtin_amdgcn_rcpf(__builtin_fmaf(__builtin_fabsf(x), 0.231641888f, 1.0f));
+    const float ax = __builtin_fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(ax, 0.231641888f, 1.0f));
     const float poly =
         t * (0.127414796f +
              t * (-0.142248368f +
                   t * (0.710706871f + t * (-0.726576014f + t * 0.530702714f))));
     const float q = poly * __builtin_amdgcn_exp2f(x * x * -0.72134752044448169f);
-    return x * (x >= 0.0f ? 1.0f - q : q);
+    return __builtin_fmaf(-ax, q, __builtin_elementwise_maximum(x, 0.0f));
 }
 
 template <int KB1, int MB>
