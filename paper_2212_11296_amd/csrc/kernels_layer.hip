@@ -1068,8 +1068,9 @@ hipError_t launch_code_diff(const ModelDims& m, const DedupIO<P>& d,
 // Delta log psi of each neighbour: rows of C_L get new head outputs, the
 // exchanged sites p1, p2 (new targets) use the sample's cached log-probs
 // when their hidden state is unchanged.  The rows of C_L are listed in LDS
-// and evaluated four at a time, their new log-probs kept in LDS; the
-// differences are summed in FP64 in row order.
+// and evaluated four at a time, their new log-probs kept in LDS beside the
+// sample's cached ones (loaded by all lanes at once); lane 0 sums the
+// differences in FP64 in row order from LDS.
 template <class P>
 __global__ void __launch_bounds__(64) k_head_dedup(
     ModelDims m, HeadW<typename P::acc> hw, DedupIO<P> dd,
@@ -1080,6 +1081,7 @@ __global__ void __launch_bounds__(64) k_head_dedup(
     __shared__ uint64_t sm[VQ_MAX_MASK_WORDS];
     __shared__ int16_t rl[VQ_MAX_MASK_WORDS * 64];
     __shared__ typename P::acc lnw[VQ_MAX_MASK_WORDS * 64];   // by list position
+    __shared__ typename P::acc lold[VQ_MAX_MASK_WORDS * 64];  // by list position
     const int64_t n = (int64_t)*dd.n_nb;
     const int lane = threadIdx.x;
     const int N = m.N, W = dd.mask_words;
@@ -1128,17 +1130,35 @@ __global__ void __launch_bounds__(64) k_head_dedup(
         }
         my_rows += nc;
         __syncthreads();
+        // the sample's log-prob of its own target at every listed row
+        bool p2in = false;
+        for (int c = lane; c < nc; c += 64) {
+            const int i = rl[c];
+            lold[c] = blp[((int64_t)D.sigma * N + i) * 2 + (sp[i] < 0 ? 1 : 0)];
+            p2in |= i == D.p2;
+        }
+        p2in = __ballot(p2in) != 0;
+        __syncthreads();
         if (lane == 0) {
-            double delta = 0.0;
-            int c = 0;
-            for (int i = D.p1; i < N; ++i) {
-                const bool inC = c < nc && rl[c] == i;
-                if (!inC && i != D.p1 && i != D.p2) continue;
+            // rows p1, then the listed rows (all after p1) with p2 in its
+            // place: the rows and the order of a walk over i = p1 .. N-1
+            auto unlisted = [&](int i) {
                 const int tnew = snew(i) < 0 ? 1 : 0, told = sp[i] < 0 ? 1 : 0;
                 const int64_t brow = (int64_t)D.sigma * N + i;
-                const acc lnew = inC ? lnw[c++] : blp[brow * 2 + tnew];
-                delta += (double)lnew - (double)blp[brow * 2 + told];
+                return (double)blp[brow * 2 + tnew] - (double)blp[brow * 2 + told];
+            };
+            const double t2 = p2in ? 0.0 : unlisted(D.p2);
+            double delta = 0.0;
+            delta += unlisted(D.p1);
+            bool p2done = p2in;
+            for (int c = 0; c < nc; ++c) {
+                if (!p2done && rl[c] > D.p2) {
+                    delta += t2;
+                    p2done = true;
+                }
+                delta += (double)lnw[c] - (double)lold[c];
             }
+            if (!p2done) delta += t2;
             ratio[nb] = exp(0.5 * delta);
         }
     }
