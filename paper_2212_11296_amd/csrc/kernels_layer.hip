@@ -654,19 +654,15 @@ hipError_t launch_mlp(const ModelDims& m, const LayerW<typename P::acc>& w,
 }
 
 // ------------------------------------------------------------------ head
-// Final LN, linear d -> 2 and log-softmax of R rows, computed by one wave
-// (all lanes return the same values).  The rows' chains are interleaved so
-// their loads and reductions overlap; each row sees the same operations in
-// the same order whatever R is, and contraction is off, so a row's result
-// does not depend on which rows share the call.
+// The three passes of head_rows over rows of any width, reading the rows
+// and the head parameters from memory in each.
 template <typename C, int R>
-__device__ inline void head_rows(const C* const (&x)[R], int d,
-                                 const HeadW<C>& hw, C (&lp0)[R], C (&lp1)[R]) {
+__device__ inline void head_passes(const C* const (&x)[R], int d,
+                                   const HeadW<C>& hw, C (&s)[R], C (&v)[R],
+                                   C (&mean)[R], C (&rstd)[R], C (&z0)[R],
+                                   C (&z1)[R]) {
 #pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
-    C s[R], v[R], mean[R], rstd[R], z0[R], z1[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) s[r] = v[r] = z0[r] = z1[r] = 0;
     for (int k = lane; k < d; k += 64)
 #pragma unroll
         for (int r = 0; r < R; ++r) s[r] += x[r][k];
@@ -690,6 +686,71 @@ __device__ inline void head_rows(const C* const (&x)[R], int d,
             z0[r] += f * w0;
             z1[r] += f * w1;
         }
+    }
+}
+
+// Final LN, linear d -> 2 and log-softmax of R rows, computed by one wave
+// (all lanes return the same values).  The rows' chains are interleaved so
+// their loads and reductions overlap; each row sees the same operations in
+// the same order whatever R is, and contraction is off, so a row's result
+// does not depend on which rows share the call.  Up to d = 64 kHeadCols a
+// lane loads its columns of the rows and of the head parameters once, all
+// before the first sum; wider rows are read in each of the three passes.
+constexpr int kHeadCols = 4;
+template <typename C, int R>
+__device__ inline void head_rows(const C* const (&x)[R], int d,
+                                 const HeadW<C>& hw, C (&lp0)[R], C (&lp1)[R]) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    C s[R], v[R], mean[R], rstd[R], z0[R], z1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[r] = v[r] = z0[r] = z1[r] = 0;
+    if (d <= 64 * kHeadCols) {
+        constexpr int KH = kHeadCols;
+        C xv[R][KH], g[KH], b[KH], w0[KH], w1[KH];
+#pragma unroll
+        for (int j = 0; j < KH; ++j) {
+            const int k = lane + 64 * j;
+            if (k < d) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) xv[r][j] = x[r][k];
+                g[j] = hw.lnf_g[k];
+                b[j] = hw.lnf_b[k];
+                w0[j] = hw.W_head[2 * k];
+                w1[j] = hw.W_head[2 * k + 1];
+            }
+        }
+        // the passes below take the columns k = lane, lane + 64, ... in
+        // order, as the loops of the general form do
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if (lane + 64 * j < d)
+#pragma unroll
+                for (int r = 0; r < R; ++r) s[r] += xv[r][j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) mean[r] = wave_sum(s[r]) / (C)d;
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if (lane + 64 * j < d)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const C t = xv[r][j] - mean[r];
+                    v[r] += t * t;
+                }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            rstd[r] = (C)1 / dsqrt(wave_sum(v[r]) / (C)d + (C)1e-5);
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if (lane + 64 * j < d)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const C f = (xv[r][j] - mean[r]) * rstd[r] * g[j] + b[j];
+                    z0[r] += f * w0[j];
+                    z1[r] += f * w1[j];
+                }
+    } else {
+        head_passes<C, R>(x, d, hw, s, v, mean, rstd, z0, z1);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
