@@ -687,6 +687,9 @@ hipError_t launch_embed_bwd(int64_t n, int N, int d, const int8_t* spins,
 // One wave per row, quantizer head h: S holds a_h . W_j and E holds
 // g_h . W_j on entry; on exit S holds G_j = t_j / delta_j and E holds
 // p_j + [j == code]; rowG[r] = sum_j G_j.
+// Codebooks up to 64 kVqBwdCols codes keep a row's values in registers.
+constexpr int kVqBwdCols = 16;
+
 template <typename T>
 __global__ void __launch_bounds__(kGT) k_vq_bwd_rows(int64_t R, int Q, int dseg,
                                                      int H, int h, const T* a,
@@ -704,6 +707,67 @@ __global__ void __launch_bounds__(kGT) k_vq_bwd_rows(int64_t R, int Q, int dseg,
         a2 = wave_sum(a2);
         T* Sr = S + r * Q;
         T* Er = E + r * Q;
+        const int code = codes[r * H + h];
+        if (Q <= 64 * kVqBwdCols) {
+            // the row's products and upstream values in registers: each is
+            // read once and written once (the general form below reads S
+            // three times), with the same operations in the same order
+            constexpr int U = kVqBwdCols;
+            T sv[U], ev[U], pt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = lane + 64 * u;
+                if (j < Q) {
+                    sv[u] = Sr[j];
+                    ev[u] = Er[j];
+                }
+            }
+            T dmin = -neg_inf<T>();
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = lane + 64 * u;
+                if (j < Q) {
+                    T q2 = a2 - (T)2 * sv[u] + w2[j];
+                    q2 = q2 > (T)0 ? q2 : (T)0;
+                    const T dl = dsqrt(q2);
+                    sv[u] = dl;
+                    dmin = dl < dmin ? dl : dmin;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const T other = __shfl_xor(dmin, o, 64);
+                dmin = other < dmin ? other : dmin;
+            }
+            T l = 0, pe = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (lane + 64 * u < Q) {
+                    pt[u] = dexp(dmin - sv[u]);
+                    l += pt[u];
+                    pe += pt[u] * ev[u];
+                }
+            }
+            l = wave_sum(l);
+            pe = wave_sum(pe) / l;
+            T gs = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = lane + 64 * u;
+                if (j < Q) {
+                    const T dl = sv[u];
+                    const T p = pt[u] / l;
+                    const T t = p * (ev[u] - pe);
+                    const T G = dl > (T)0 ? t / dl : (T)0;
+                    Sr[j] = G;
+                    Er[j] = p + (j == code ? (T)1 : (T)0);
+                    gs += G;
+                }
+            }
+            gs = wave_sum(gs);
+            if (lane == 0) rowG[r] = gs;
+            continue;
+        }
         // distances (kept in S) and their minimum
         T dmin = -neg_inf<T>();
         for (int j = lane; j < Q; j += 64) {
@@ -726,7 +790,6 @@ __global__ void __launch_bounds__(kGT) k_vq_bwd_rows(int64_t R, int Q, int dseg,
         }
         l = wave_sum(l);
         pe = wave_sum(pe) / l;
-        const int code = codes[r * H + h];
         T gs = 0;
         for (int j = lane; j < Q; j += 64) {
             const T dl = Sr[j];
