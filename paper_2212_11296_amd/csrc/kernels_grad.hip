@@ -411,6 +411,9 @@ hipError_t launch_fill_t(T* p, int64_t n, T v, hipStream_t st) {
 // ------------------------------------------------------------- LayerNorm
 // One wave per row: y = xh * g + b with xh = (x - mean) * rstd (biased
 // variance, eps 1e-5); xh and rstd are kept for the backward.
+// Rows up to 64 kLnCols wide are held in registers by the LN kernels.
+constexpr int kLnCols = 4;
+
 template <typename T>
 __global__ void __launch_bounds__(kGT) k_ln_save(int64_t R, int d, const T* x,
                                                  const T* g, const T* b, T* y,
@@ -420,6 +423,39 @@ __global__ void __launch_bounds__(kGT) k_ln_save(int64_t R, int d, const T* x,
     for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
          r += (int64_t)gridDim.x * wpb) {
         const T* xr = x + r * d;
+        if (d <= 64 * kLnCols) {
+            // the row in registers, read once; the same operations in the
+            // same order as the general form below
+            T xv[kLnCols];
+#pragma unroll
+            for (int u = 0; u < kLnCols; ++u)
+                if (lane + 64 * u < d) xv[u] = xr[lane + 64 * u];
+            T s = 0;
+#pragma unroll
+            for (int u = 0; u < kLnCols; ++u)
+                if (lane + 64 * u < d) s += xv[u];
+            const T mean = wave_sum(s) / (T)d;
+            T v = 0;
+#pragma unroll
+            for (int u = 0; u < kLnCols; ++u)
+                if (lane + 64 * u < d) {
+                    const T t = xv[u] - mean;
+                    v += t * t;
+                }
+            v = wave_sum(v) / (T)d;
+            const T rs = (T)1 / dsqrt(v + (T)1e-5);
+#pragma unroll
+            for (int u = 0; u < kLnCols; ++u) {
+                const int k = lane + 64 * u;
+                if (k < d) {
+                    const T h = (xv[u] - mean) * rs;
+                    xh[r * d + k] = h;
+                    y[r * d + k] = h * g[k] + b[k];
+                }
+            }
+            if (lane == 0) rstd[r] = rs;
+            continue;
+        }
         T s = 0;
         for (int k = lane; k < d; k += 64) s += xr[k];
         const T mean = wave_sum(s) / (T)d;
@@ -459,6 +495,38 @@ __global__ void __launch_bounds__(kGT) k_ln_bwd(int64_t R, int d, const T* xh,
     const int64_t wpb = kGT / 64;
     for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
          r += (int64_t)gridDim.x * wpb) {
+        if (d <= 64 * kLnCols) {
+            // e and xh of the row in registers, read once; the same
+            // operations in the same order as the general form below
+            T ev[kLnCols], hv[kLnCols];
+            T s1 = 0, s2 = 0;
+#pragma unroll
+            for (int u = 0; u < kLnCols; ++u) {
+                const int k = lane + 64 * u;
+                if (k < d) {
+                    ev[u] = g[k] * dy[r * d + k];
+                    hv[u] = xh[r * d + k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kLnCols; ++u)
+                if (lane + 64 * u < d) {
+                    s1 += ev[u];
+                    s2 += ev[u] * hv[u];
+                }
+            s1 = wave_sum(s1) / (T)d;
+            s2 = wave_sum(s2) / (T)d;
+            const T rs = rstd[r];
+#pragma unroll
+            for (int u = 0; u < kLnCols; ++u) {
+                const int k = lane + 64 * u;
+                if (k < d) {
+                    const T v = rs * (ev[u] - s1 - hv[u] * s2);
+                    out[r * d + k] = base ? base[r * d + k] + v : v;
+                }
+            }
+            continue;
+        }
         T s1 = 0, s2 = 0;
         for (int k = lane; k < d; k += 64) {
             const T e = g[k] * dy[r * d + k];
