@@ -333,7 +333,23 @@ __global__ void __launch_bounds__(kGT) k_colsum(int64_t groups, int64_t rows,
         const int64_t g = e / cols;
         const int c = (int)(e - g * cols);
         T s = 0;
-        for (int64_t r = 0; r < rows; ++r) {
+        // eight rows' loads in flight together; the sum runs in row order
+        int64_t r = 0;
+        for (; r + 8 <= rows; r += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = A[(g * rows + r + u) * lda + c];
+            if (B) {
+                T w[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) w[u] = B[(g * rows + r + u) * ldb + c];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] *= w[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; r < rows; ++r) {
             const int64_t row = g * rows + r;
             T v = A[row * lda + c];
             if (B) v *= B[row * ldb + c];
