@@ -380,7 +380,16 @@ __global__ void __launch_bounds__(kGT) k_reduce_samples(int64_t n, int64_t P,
     for (int64_t p = (int64_t)blockIdx.x * kGT + threadIdx.x; p < P;
          p += (int64_t)gridDim.x * kGT) {
         T s = beta ? grad[p] : (T)0;
-        for (int64_t i = 0; i < n; ++i) s += part[i * P + p];
+        // eight samples' loads in flight together, added in sample order
+        int64_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(i + u) * P + p];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; i < n; ++i) s += part[i * P + p];
         grad[p] = s;
     }
 }
