@@ -174,9 +174,11 @@ vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
 /* Gradient of log psi with respect to the flat parameters, with the
  * straight-through quantizer of eqs. (7)-(8): the forward value is the
  * nearest codeword; the backward passes the gradient g reaching the
- * quantized vector to the chosen codeword (one-hot term) and through
- * p = softmax(-||u - W_j||) over all codewords of that quantizer head to the
- * codewords and to the attention output u (softmax term).  Everything else
+ * quantized vector to the chosen codeword (the codebook factor of
+ * g(D)^T W, whose value is the one-hot vector: the stop gradient of eq. 8
+ * acts on the softmax output only) and through the distances inside
+ * p = softmax(-||u - W_j||) to every codeword of that quantizer head and
+ * to the attention output u (softmax term).  Everything else
  * is differentiated exactly (log psi = 1/2 log P, Sec. 2).  The forward
  * keeps only every layer's input; each layer is recomputed with the forward
  * kernels (same codes) before its backward (layer checkpointing).

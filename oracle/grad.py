@@ -9,14 +9,18 @@ a softmax over the negative unsquared distances to all codewords (eq. 8).
 This module writes that estimator as a relaxed surrogate, per quantizer
 head h of every layer,
 
-    V_h(theta) = W_h(theta)[c0] + p(theta)^T W_h(theta) - [p^T W_h](theta0),
+    V_h(theta) = W_h(theta)[c0] + (p(theta) - p(theta0))^T W_h(theta),
     p_j(theta) = softmax_j( -|| a_h(theta) - W_hj(theta) || ),
 
-with the codes c0 fixed at their values at theta0.  At theta0 its value is
+with the codes c0 fixed at their values at theta0.  Eq. (8) multiplies the
+un-stopped codebook by g = SG[onehot] + softmax - SG[softmax]; the stop
+gradient acts on the softmax output only, so the codebook's own factor in
+V is the value of g, the one-hot vector.  At theta0 the surrogate's value is
 the forward pass of ``oracle.network``; its true derivative there is the
-straight-through gradient: the one-hot term carries the gradient to the
-selected codeword, the softmax term carries it to every codeword and to the
-attention output a_h (reading C10: both paths; no commitment loss).
+straight-through gradient: the selected codeword receives the upstream
+gradient through the one-hot factor, and every codeword and the attention
+output a_h receive it through the distances inside the softmax (no
+commitment loss).
 
 The rest of the network is differentiated exactly.  Everything runs in
 torch float64 on the CPU; gradients come from torch autograd.
@@ -84,13 +88,15 @@ def _attention(q, k, v, n_heads):
     return (p @ heads(v)).transpose(1, 2).reshape(S, N, d)
 
 
-def _vq_surrogate(a, codebook, frozen=None):
+def vq_surrogate(a, codebook, frozen=None):
     """Straight-through quantizer of a [S, N, d] (eqs. 7-8).
 
-    frozen: None for the autograd form (the subtracted term is the detached
-    soft value), else a dict with the codes and the soft values at theta0
-    (the finite-difference form).  Returns (z, codes, soft) where soft holds
-    the soft values p^T W_h of every head."""
+    Per head h: z_h = W_h[c] + (p - SG[p])^T W_h with p = softmax(-D_h),
+    D_hj = ||a_h - W_hj|| (eq. 8, SG on the softmax only, the codebook
+    factor live).  frozen: None for the autograd form (SG[p] is the detached
+    softmax), else a dict with the codes and the softmax values at theta0
+    (the finite-difference form, where p(theta0) is a constant).  Returns
+    (z, codes, probs) with probs the detached softmax of every head."""
     H, Q, m = codebook.shape
     S, N, d = a.shape
     flat = a.reshape(S * N, d)
@@ -100,24 +106,23 @@ def _vq_surrogate(a, codebook, frozen=None):
                           for h in range(H)], axis=1)
     else:
         codes = frozen["codes"]
-    segs, softs = [], []
+    segs, probs = [], []
     for h in range(H):
         seg = flat[:, h * m:(h + 1) * m]
         dist = torch.cdist(seg, codebook[h],
                            compute_mode="donot_use_mm_for_euclid_dist")
         p = torch.softmax(-dist, dim=-1)                 # eq. (8)
-        soft = p @ codebook[h]
+        p_sg = p.detach() if frozen is None else frozen["probs"][h]
         hard = codebook[h][torch.as_tensor(codes[:, h])]
-        ref = soft.detach() if frozen is None else frozen["soft"][h]
-        segs.append(hard + soft - ref)                   # eq. (7)
-        softs.append(soft.detach())
+        segs.append(hard + (p - p_sg) @ codebook[h])     # g(D)^T W, eq. (8)
+        probs.append(p.detach())
     z = torch.cat(segs, dim=1).reshape(S, N, d)
-    return z, codes, softs
+    return z, codes, probs
 
 
 def _forward(cfg, th, spins, frozen=None):
     """log psi [S] through the straight-through surrogate; also returns the
-    per-layer frozen state (codes, soft values) of this evaluation."""
+    per-layer frozen state (codes, softmax values) of this evaluation."""
     P = _unpack(cfg, th)
     t, u = onet.tokens(spins)
     t = torch.as_tensor(t)
@@ -130,9 +135,9 @@ def _forward(cfg, th, spins, frozen=None):
         qkv = h @ lay["W_qkv"] + lay["b_qkv"]
         a = _attention(qkv[..., :d], qkv[..., d:2 * d], qkv[..., 2 * d:],
                        cfg.n_heads)
-        z, codes, softs = _vq_surrogate(a, lay["codebook"],
-                                        None if frozen is None else frozen[l])
-        state.append({"codes": codes, "soft": softs})
+        z, codes, probs = vq_surrogate(a, lay["codebook"],
+                                       None if frozen is None else frozen[l])
+        state.append({"codes": codes, "probs": probs})
         xp = x + z @ lay["W_o"] + lay["b_o"]
         hid = _gelu(_ln(xp, lay["ln2_g"], lay["ln2_b"]) @ lay["W1"] + lay["b1"])
         x = xp + hid @ lay["W2"] + lay["b2"]
@@ -173,7 +178,7 @@ def grad_logpsi(cfg, theta, spins, weights=None):
 
 
 def frozen_state(cfg, theta, spins):
-    """Codes and soft values at theta (for the finite-difference form)."""
+    """Codes and softmax values at theta (for the finite-difference form)."""
     th = torch.tensor(np.asarray(theta, dtype=np.float64))
     with torch.no_grad():
         _, st = _forward(cfg, th, np.atleast_2d(spins))
@@ -181,9 +186,9 @@ def frozen_state(cfg, theta, spins):
 
 
 def surrogate_logpsi(cfg, theta, spins, frozen):
-    """log psi [S] of the surrogate with codes and subtracted soft values
-    held at their theta0 values (``frozen_state``): a smooth function of
-    theta whose derivative at theta0 is the straight-through gradient."""
+    """log psi [S] of the surrogate with the codes and the subtracted
+    softmax held at their theta0 values (``frozen_state``): a smooth function
+    of theta whose derivative at theta0 is the straight-through gradient."""
     th = torch.tensor(np.asarray(theta, dtype=np.float64))
     with torch.no_grad():
         lp, _ = _forward(cfg, th, np.atleast_2d(spins), frozen=frozen)

@@ -603,10 +603,15 @@ struct Runner {
                                      w.da + h * ds, d, 0, 0, 1));
                 LK("grad_vq", launch_da_fix<acc>(R, (int)ds, (int)d, ah, w.rowG,
                                                  w.da + h * ds, st));
-                LK("grad_gemm", gemm(Q, ds, N, w.E, Q, N * Q, 1, w.dT + h * ds,
-                                     d, N * d, 0, dcb, ds, NP, 0, n));
+                // codebook: softmax path through the distances, then the
+                // one-hot factor of eq. (8) (the upstream rows added to the
+                // chosen codewords)
                 LK("grad_gemm", gemm(Q, ds, N, w.S, Q, N * Q, 1, ah, d, N * d, 0,
-                                     dcb, ds, NP, 1, n));
+                                     dcb, ds, NP, 0, n));
+                LK("grad_vq", launch_onehot_scatter<acc>(n, (int)N, (int)ds,
+                                                         (int)d, m.H, h, w.gcode,
+                                                         w.dT + h * ds, dcb, NP,
+                                                         st));
                 LK("grad_colsum", colsum(n, (int)Q, w.S, Q, nullptr, 0, w.colG, Q));
                 LK("grad_vq", launch_cb_fix<acc>(n, (int)Q, (int)ds, w.colG, cb,
                                                  dcb, NP, st));

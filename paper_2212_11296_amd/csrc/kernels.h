@@ -248,6 +248,10 @@ template <typename T>
 hipError_t launch_cb_fix(int64_t n, int Q, int dseg, const T* colG, const T* cb,
                          T* dcb, int64_t P, hipStream_t st);
 template <typename T>
+hipError_t launch_onehot_scatter(int64_t n, int N, int dseg, int ld, int H,
+                                 int h, const int32_t* codes, const T* g,
+                                 T* dcb, int64_t P, hipStream_t st);
+template <typename T>
 hipError_t launch_attn_bwd(int64_t n, const ModelDims& m, const T* q,
                            const T* k, const T* v, const T* o, const T* dO,
                            T* lse, T* Dd, T* dqkv, hipStream_t st);

@@ -9,9 +9,11 @@
 //   p = softmax(-delta), delta_j = ||u - W_j||, e_j = g . W_j,
 //   t_j = p_j (e_j - p.e),  G_j = t_j / delta_j,
 //   dL/du   = -(sum_j G_j) u + sum_j G_j W_j,
-//   dL/dW_j = (p_j + [j == code]) g + G_j u - G_j W_j,
-// where g is the gradient reaching the quantized vector (eq. 7: the
-// one-hot term carries g to the chosen codeword, the softmax term to all).
+//   dL/dW_j = [j == code] g + G_j u - G_j W_j,
+// where g is the gradient reaching the quantized vector.  Eq. (8) writes
+// the quantized vector as g(D)^T W with the stop gradient on the softmax
+// output only: the codebook's own factor is the value of g(D), the one-hot
+// vector, and the softmax reaches every codeword and u through D.
 //
 // Every parameter gradient is formed per sample (one group of N rows) into
 // a [sample][P] array, so per-sample gradients need no extra pass and the
@@ -778,8 +780,8 @@ hipError_t launch_embed_bwd(int64_t n, int N, int d, const int8_t* spins,
 
 // -------------------------------------------------------------- quantizer
 // One wave per row, quantizer head h: S holds a_h . W_j and E holds
-// g_h . W_j on entry; on exit S holds G_j = t_j / delta_j and E holds
-// p_j + [j == code]; rowG[r] = sum_j G_j.
+// g_h . W_j on entry; on exit S holds G_j = t_j / delta_j and
+// rowG[r] = sum_j G_j (E is left as it was).
 // Codebooks up to 64 kVqBwdCols codes keep a row's values in registers.
 constexpr int kVqBwdCols = 16;
 
@@ -853,7 +855,6 @@ __global__ void __launch_bounds__(kGT) k_vq_bwd_rows(int64_t R, int Q, int dseg,
                     const T t = p * (ev[u] - pe);
                     const T G = dl > (T)0 ? t / dl : (T)0;
                     Sr[j] = G;
-                    Er[j] = p + (j == code ? (T)1 : (T)0);
                     gs += G;
                 }
             }
@@ -890,7 +891,6 @@ __global__ void __launch_bounds__(kGT) k_vq_bwd_rows(int64_t R, int Q, int dseg,
             const T t = p * (Er[j] - pe);
             const T G = dl > (T)0 ? t / dl : (T)0;
             Sr[j] = G;
-            Er[j] = p + (j == code ? (T)1 : (T)0);
             gs += G;
         }
         gs = wave_sum(gs);
@@ -954,6 +954,37 @@ hipError_t launch_cb_fix(int64_t n, int Q, int dseg, const T* colG, const T* cb,
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_cb_fix<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
                        dim3(kGT), 0, st, n, Q, dseg, colG, cb, dcb, P);
+    return hipGetLastError();
+}
+
+// The one-hot factor of eq. (8): dcb[g][code_r][c] += g_r[c] over the rows
+// r of sample g in row order (one workgroup per sample, a thread per
+// column), so the codebook gradient needs no product with a one-hot matrix.
+template <typename T>
+__global__ void __launch_bounds__(kGT) k_onehot_scatter(int64_t n, int N,
+                                                        int dseg, int ld, int H,
+                                                        int h,
+                                                        const int32_t* codes,
+                                                        const T* g, T* dcb,
+                                                        int64_t P) {
+    for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
+        T* out = dcb + s * P;
+        const int32_t* cs = codes + s * (int64_t)N * H + h;
+        const T* gs = g + s * (int64_t)N * ld;
+        for (int c = threadIdx.x; c < dseg; c += kGT)
+            for (int r = 0; r < N; ++r)
+                out[(int64_t)cs[(int64_t)r * H] * dseg + c] +=
+                    gs[(int64_t)r * ld + c];
+    }
+}
+
+template <typename T>
+hipError_t launch_onehot_scatter(int64_t n, int N, int dseg, int ld, int H,
+                                 int h, const int32_t* codes, const T* g,
+                                 T* dcb, int64_t P, hipStream_t st) {
+    if (n <= 0 || N <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_onehot_scatter<T>), dim3(cap_grid(n)), dim3(kGT), 0,
+                       st, n, N, dseg, ld, H, h, codes, g, dcb, P);
     return hipGetLastError();
 }
 
@@ -1304,6 +1335,9 @@ hipError_t launch_attn_bwd(int64_t n, const ModelDims& m, const T* q,
                                          T*, hipStream_t);                      \
     template hipError_t launch_cb_fix<T>(int64_t, int, int, const T*, const T*, \
                                          T*, int64_t, hipStream_t);             \
+    template hipError_t launch_onehot_scatter<T>(int64_t, int, int, int, int,   \
+                                                 int, const int32_t*, const T*, \
+                                                 T*, int64_t, hipStream_t);     \
     template hipError_t launch_attn_bwd<T>(int64_t, const ModelDims&, const T*, \
                                            const T*, const T*, const T*,        \
                                            const T*, T*, T*, T*, hipStream_t);

@@ -56,6 +56,32 @@ def test_grad_f64_per_sample_and_weighted(mc):
     assert rel_max(host(gw), w @ ref) < 1e-9
 
 
+Q2_W1 = replace(CONFIGS["small"], name="q2_w1", L=4, d_model=4, n_layers=2,
+                n_heads=1, d_ff=8, codebook_size=2, vq_heads=4, batch=3,
+                spin_seed=1703)
+Q3_W2 = replace(CONFIGS["small"], name="q3_w2", L=4, d_model=4, n_layers=2,
+                n_heads=1, d_ff=8, codebook_size=3, vq_heads=2, batch=3,
+                spin_seed=1707)
+
+
+@pytest.mark.parametrize("mc", [Q2_W1, Q3_W2], ids=["q2_w1", "q3_w2"])
+def test_grad_f64_small_quantizers(mc):
+    """The quantizers of the oracle's closed-form pins of eq. (8) (two
+    codewords of width 1; three codewords of width 2, two heads) inside a
+    whole network, FP64 through the C ABI, per sample and weighted."""
+    say(f"grad f64 {mc.name}")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "f64"), dev_spins(s)
+    g = host(vq.grad_logpsi(cfg, p, sp))
+    ref = og.grad_logpsi(mc, theta, s)
+    assert rel_max(g, ref) < 1e-9
+    w = np.array([0.25, -1.5, 1.0])
+    gw = host(vq.grad_logpsi(cfg, p, sp, weights=torch.tensor(w, device="cuda")))
+    assert rel_max(gw, w @ ref) < 1e-9
+
+
 def test_grad_f32_medium():
     mc = with_batch(CONFIGS["medium"], 2)
     say("grad f32 medium")
