@@ -52,7 +52,9 @@
  * processes the batch in chunks of as many samples as fit; the minimum that
  * works is vqnqs_workspace_size(cfg, batch, mode, 1, &bytes).  Concurrent
  * calls must use distinct workspaces.  Identical inputs give bitwise
- * identical outputs.
+ * identical outputs.  (vqnqs_local_energy_static is the one entry point
+ * without a workspace argument: it runs in a static device array of the
+ * library's own.)
  */
 #ifndef VQNQS_H
 #define VQNQS_H
@@ -72,7 +74,9 @@ typedef enum {
     VQNQS_ERR_WORKSPACE_TOO_SMALL = 4,
     VQNQS_ERR_UNSUPPORTED = 5,       /* valid but not implemented (e.g. d/n_heads) */
     VQNQS_ERR_BAD_SPIN = 6,          /* a spin value other than +1/-1          */
-    VQNQS_ERR_HIP = 7                /* a HIP runtime call failed             */
+    VQNQS_ERR_HIP = 7,               /* a HIP runtime call failed             */
+    VQNQS_ERR_EXCEEDS_STATIC_SCRATCH = 8 /* one sample's workspace is larger
+                                            than the library's static scratch */
 } vqnqs_status;
 
 typedef enum { VQNQS_F64 = 0, VQNQS_F32 = 1, VQNQS_BF16 = 2 } vqnqs_precision;
@@ -199,6 +203,32 @@ vqnqs_status vqnqs_grad_logpsi(const vqnqs_config* cfg, const void* params,
                                const double* weights, void* grad,
                                double* logpsi, void* ws, size_t ws_bytes,
                                void* stream);
+
+/* Local energy (same arguments, results and errors as vqnqs_local_energy)
+ * for callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation.  The workspace
+ * is the library's own static device array of VQNQS_STATIC_SCRATCH_MIB MiB
+ * (one per device, held from the first call on that device until the
+ * process ends); the call allocates and frees nothing.  The batch is
+ * processed in chunks of as many samples as the array holds, so any batch
+ * size works as long as one sample's workspace,
+ * vqnqs_workspace_size(cfg, 1, mode, 1, &bytes), fits; otherwise the call
+ * returns VQNQS_ERR_EXCEEDS_STATIC_SCRATCH before enqueueing anything.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (several streams or threads) race and give undefined results;
+ * calls ordered on one stream are safe.  The array keeps the last call's
+ * contents; the call initialises everything it reads.
+ *   status [1] int32 DEVICE out, nullable: the call's status word once the
+ *          enqueued work has run (VQNQS_OK or VQNQS_ERR_BAD_SPIN), the value
+ *          vqnqs_workspace_status reports for a caller's workspace      */
+#define VQNQS_STATIC_SCRATCH_MIB 512
+vqnqs_status vqnqs_local_energy_static(const vqnqs_config* cfg,
+                                       const void* params,
+                                       const int8_t* spins, int64_t batch,
+                                       int32_t mode, double* eloc,
+                                       double* stats, double* ratios,
+                                       int64_t* counters, int32_t* status,
+                                       void* stream);
 
 /* One lattice of a multi-lattice batch: its own model, parameters and
  * samples, with the outputs of vqnqs_local_energy (same meanings). */

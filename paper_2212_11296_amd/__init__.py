@@ -12,7 +12,7 @@ from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
                   make_config, profile_enable, profile_reset, profile_read,
                   WS_FORWARD, WS_GRAD, MULTI_CONCURRENT, MULTI_GRAPH,
                   local_energy_multi, workspace_size_multi, autotune,
-                  set_tuning)
+                  set_tuning, local_energy_static, STATIC_SCRATCH_BYTES)
 
 __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "FLAG_CERTIFIED_VQ", "NCOUNTERS", "CTR", "VQNQSError",
@@ -21,4 +21,5 @@ __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "grad_logpsi", "logpsi", "make_config", "profile_enable",
            "profile_reset", "profile_read", "WS_FORWARD", "WS_GRAD",
            "MULTI_CONCURRENT", "MULTI_GRAPH", "local_energy_multi",
-           "workspace_size_multi", "autotune", "set_tuning"]
+           "workspace_size_multi", "autotune", "set_tuning",
+           "local_energy_static", "STATIC_SCRATCH_BYTES"]

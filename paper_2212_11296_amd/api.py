@@ -13,12 +13,15 @@ CTR = dict(samples=0, neighbours=1, attn_rows=2, attn_pairs=3, vq_rows=4,
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16}
 _STATUS = {0: "ok", 1: "null pointer", 2: "invalid config", 3: "invalid shape",
            4: "workspace too small", 5: "unsupported configuration",
-           6: "spin value other than +1/-1", 7: "HIP runtime error"}
+           6: "spin value other than +1/-1", 7: "HIP runtime error",
+           8: "one sample's workspace exceeds the static scratch"}
+STATIC_SCRATCH_BYTES = 512 << 20
 
 WS_FORWARD, WS_GRAD = -1, -3
 MULTI_CONCURRENT, MULTI_GRAPH = 1, 2
 EXPORTS = ["vqnqs_param_count", "vqnqs_workspace_size", "vqnqs_neighbours",
            "vqnqs_forward_logpsi", "vqnqs_local_energy", "vqnqs_grad_logpsi",
+           "vqnqs_local_energy_static",
            "vqnqs_workspace_size_multi", "vqnqs_local_energy_multi",
            "vqnqs_autotune", "vqnqs_set_tuning",
            "vqnqs_workspace_status", "vqnqs_status_string",
@@ -88,6 +91,9 @@ def load_library():
     lib.vqnqs_local_energy.argtypes = [C, P, P, I64, I32, P, P, P, P, P, SZ,
                                        P]
     lib.vqnqs_local_energy.restype = ctypes.c_int
+    lib.vqnqs_local_energy_static.argtypes = [C, P, P, I64, I32, P, P, P, P,
+                                              P, P]
+    lib.vqnqs_local_energy_static.restype = ctypes.c_int
     lib.vqnqs_grad_logpsi.argtypes = [C, P, P, I64, P, P, P, P, SZ, P]
     lib.vqnqs_grad_logpsi.restype = ctypes.c_int
     J = ctypes.POINTER(Job)
@@ -248,6 +254,38 @@ def local_energy(cfg, params, spins, mode=DEDUP, stats=True, ratios=False,
         _ptr(o.get("counters")), _ptr(ws), ws.numel(), _stream()))
     if check:
         _check_status(ws)
+    return o
+
+
+def local_energy_static(cfg, params, spins, mode=DEDUP, stats=True,
+                        ratios=False, counters=False, check=True, out=None):
+    """vqnqs_local_energy_static: the local energy in the library's own
+    static device array (no workspace argument, nothing allocated by the
+    call).  Same outputs as local_energy plus "status" [1] int32, the call's
+    status word."""
+    import torch
+    B = spins.shape[0]
+    N = cfg.L * cfg.L
+    o = out if out is not None else {}
+    if "eloc" not in o:
+        o["eloc"] = torch.empty(B, dtype=torch.float64, device="cuda")
+    if stats and "stats" not in o:
+        o["stats"] = torch.empty(2, dtype=torch.float64, device="cuda")
+    if ratios and "ratios" not in o:
+        o["ratios"] = torch.empty((B, 2 * N), dtype=torch.float64,
+                                  device="cuda")
+    if counters and "counters" not in o:
+        o["counters"] = torch.empty(NCOUNTERS, dtype=torch.int64,
+                                    device="cuda")
+    if "status" not in o:
+        o["status"] = torch.empty(1, dtype=torch.int32, device="cuda")
+    _check("vqnqs_local_energy_static",
+           load_library().vqnqs_local_energy_static(
+               ctypes.byref(cfg), _ptr(params), _ptr(spins), B, mode,
+               _ptr(o["eloc"]), _ptr(o.get("stats")), _ptr(o.get("ratios")),
+               _ptr(o.get("counters")), _ptr(o["status"]), _stream()))
+    if check:
+        _check("vqnqs_local_energy_static", int(o["status"].item()))
     return o
 
 

@@ -17,7 +17,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvqnqs.so")
 
 SOURCES = ["abi.cpp", "engine.cpp", "profiler.cpp", "kernels_lattice.hip", "kernels_layer.hip",
-           "kernels_mfma.hip", "kernels_attn.hip", "kernels_grad.hip"]
+           "kernels_mfma.hip", "kernels_attn.hip", "kernels_grad.hip",
+           "static_scratch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -127,6 +127,24 @@ vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
                             counters, ws, ws_bytes, (hipStream_t)stream);
 }
 
+vqnqs_status vqnqs_local_energy_static(const vqnqs_config* cfg,
+                                       const void* params,
+                                       const int8_t* spins, int64_t batch,
+                                       int32_t mode, double* eloc,
+                                       double* stats, double* ratios,
+                                       int64_t* counters, int32_t* status,
+                                       void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP) return VQNQS_ERR_INVALID_CONFIG;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (batch > 0 && (!params || !spins || !eloc)) return VQNQS_ERR_NULL_POINTER;
+    return vq::local_energy_static(m, params, spins, batch, mode, eloc, stats,
+                                   ratios, counters, status,
+                                   (hipStream_t)stream);
+}
+
 vqnqs_status vqnqs_grad_logpsi(const vqnqs_config* cfg, const void* params,
                                const int8_t* spins, int64_t batch,
                                const double* weights, void* grad,
@@ -241,6 +259,8 @@ const char* vqnqs_status_string(vqnqs_status s) {
         case VQNQS_ERR_UNSUPPORTED: return "unsupported configuration";
         case VQNQS_ERR_BAD_SPIN: return "spin value other than +1/-1";
         case VQNQS_ERR_HIP: return "HIP runtime error";
+        case VQNQS_ERR_EXCEEDS_STATIC_SCRATCH:
+            return "one sample's workspace exceeds the static scratch";
     }
     return "unknown status";
 }

@@ -14,6 +14,12 @@ vqnqs_status local_energy(const ModelDims& m, const void* params,
                           double* eloc, double* stats, double* ratios,
                           int64_t* counters, void* ws, size_t ws_bytes,
                           hipStream_t st);
+// local_energy with the library's static device array as its workspace
+vqnqs_status local_energy_static(const ModelDims& m, const void* params,
+                                 const int8_t* spins, int64_t batch, int mode,
+                                 double* eloc, double* stats, double* ratios,
+                                 int64_t* counters, int32_t* status,
+                                 hipStream_t st);
 vqnqs_status forward_logpsi(const ModelDims& m, const void* params,
                             const int8_t* spins, int64_t batch, double* logpsi,
                             int32_t* codes, void* ws, size_t ws_bytes,
