@@ -132,10 +132,14 @@ int64_t vqnqs_param_count(const vqnqs_config* cfg);
 /* Workspace bytes needed to evaluate `batch` samples in `mode` processing
  * `chunk` samples at a time (chunk <= 0 means the whole batch at once).
  * mode is a vqnqs_mode for vqnqs_local_energy, VQNQS_WS_FORWARD for
- * vqnqs_forward_logpsi / vqnqs_neighbours, or VQNQS_WS_GRAD for
- * vqnqs_grad_logpsi. */
+ * vqnqs_forward_logpsi / vqnqs_neighbours, VQNQS_WS_GRAD for
+ * vqnqs_grad_logpsi, VQNQS_WS_SAMPLE for vqnqs_sample, or VQNQS_WS_VMC
+ * for vqnqs_vmc_step (its own per-step buffers hold the whole batch; the
+ * calls inside the step run `chunk` samples at a time). */
 #define VQNQS_WS_FORWARD (-1)
 #define VQNQS_WS_GRAD (-3)
+#define VQNQS_WS_SAMPLE (-4)
+#define VQNQS_WS_VMC (-5)
 vqnqs_status vqnqs_workspace_size(const vqnqs_config* cfg, int64_t batch,
                                   int32_t mode, int64_t chunk, size_t* bytes);
 
@@ -162,6 +166,21 @@ vqnqs_status vqnqs_forward_logpsi(const vqnqs_config* cfg, const void* params,
                                   double* logpsi, int32_t* codes, void* ws,
                                   size_t ws_bytes, void* stream);
 
+/* vqnqs_forward_logpsi that also returns every layer's attention output,
+ * the vector the quantizer of eq. (5) receives (measurement support for
+ * parity checks: a quantizer code is decided in floating point, and this
+ * output lets a caller check a code against the input it was chosen for).
+ *   attn [batch][n_layers][N][d] DEVICE out: double for VQNQS_F64, float
+ *        otherwise (the BF16 mode keeps activations in FP32)
+ *   logpsi, codes: as for vqnqs_forward_logpsi (codes nullable)
+ * Workspace, errors and results otherwise as vqnqs_forward_logpsi. */
+vqnqs_status vqnqs_forward_activations(const vqnqs_config* cfg,
+                                       const void* params,
+                                       const int8_t* spins, int64_t batch,
+                                       double* logpsi, int32_t* codes,
+                                       void* attn, void* ws, size_t ws_bytes,
+                                       void* stream);
+
 /* Local energy of eq. (2) for every sample, in `mode`.
  *   eloc     [batch] double DEVICE out
  *   stats    [2] double DEVICE out, nullable: batch mean and (biased)
@@ -174,6 +193,51 @@ vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
                                 int32_t mode, double* eloc, double* stats,
                                 double* ratios, int64_t* counters, void* ws,
                                 size_t ws_bytes, void* stream);
+
+/* Direct sampling of s ~ |psi(s)|^2 = P(s) through the chain rule
+ * P(s) = prod_i P(s_i | s_<i) of the autoregressive network (Sec. 2: the
+ * distribution supports exact sampling at the cost of evaluating it).
+ * Position by position, row i of every sample goes through every layer
+ * (the keys and values of positions < i are kept per layer), and the head's
+ * conditional decides s_i = +1 iff uniforms[b][i] < P(s_i = +1 | s_<i),
+ * compared in FP64.  The random numbers are the caller's, so a call is
+ * deterministic.  No Sz = 0 constraint is imposed.
+ *   uniforms [batch][N] double DEVICE in: numbers in [0, 1), one per site
+ *   spins    [batch][N] int8 DEVICE out: the samples (+1 / -1)
+ *   logpsi   [batch] double DEVICE out, nullable: log psi of every sample,
+ *            1/2 the sum of the drawn conditionals' logs in site order
+ *            (the same sum vqnqs_forward_logpsi forms)
+ * Workspace: vqnqs_workspace_size(cfg, batch, VQNQS_WS_SAMPLE, chunk, ..). */
+vqnqs_status vqnqs_sample(const vqnqs_config* cfg, const void* params,
+                          const double* uniforms, int64_t batch,
+                          int8_t* spins, double* logpsi, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* One variational Monte Carlo step (Sec. 2): direct samples s_i ~ psi^2
+ * (vqnqs_sample with the caller's uniform numbers), their local energies
+ * (eq. 2, deduplicated form), the energy gradient
+ *     dE/dtheta = (2/B) sum_i (E_loc(s_i) - mean E_loc) d log psi(s_i)/dtheta
+ * (eq. 3 for a real psi, as a batch mean; the straight-through gradient of
+ * vqnqs_grad_logpsi), and the parameter update, all enqueued on `stream`.
+ *   params    DEVICE in/out, the flat parameters (element type as for
+ *             vqnqs_local_energy), updated in place
+ *   opt_state DEVICE in/out, nullable: NULL = gradient descent,
+ *             theta -= lr g; else Adam (b1 = 0.9, b2 = 0.999, eps = 1e-8)
+ *             with its first and second moments [2][P] in the parameters'
+ *             type (zero them before step 1)
+ *   step      Adam step number t >= 1 (bias correction 1 - b^t)
+ *   lr        learning rate
+ *   uniforms  [batch][N] double DEVICE in, numbers in [0, 1)
+ *   spins     [batch][N] int8 DEVICE out, nullable: this step's samples
+ *   eloc      [batch] double DEVICE out, nullable: their local energies
+ *   stats     [2] double DEVICE out, nullable: mean and variance of E_loc
+ *             (the energy estimate of the parameters before the update)
+ * Workspace: vqnqs_workspace_size(cfg, batch, VQNQS_WS_VMC, chunk, ..). */
+vqnqs_status vqnqs_vmc_step(const vqnqs_config* cfg, void* params,
+                            void* opt_state, int64_t step, double lr,
+                            const double* uniforms, int64_t batch,
+                            int8_t* spins, double* eloc, double* stats,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* Gradient of log psi with respect to the flat parameters, with the
  * straight-through quantizer of eqs. (7)-(8): the forward value is the
@@ -264,6 +328,9 @@ vqnqs_status vqnqs_workspace_size_multi(const vqnqs_job* jobs, int32_t njobs,
  * pointers, sizes, stream and tuning), one launch in place of thousands;
  * the graph reads the buffers' current contents at every replay.  The
  * legacy NULL stream cannot be captured: the call then runs directly.
+ * The library keeps the 16 most recently captured graphs; capturing a 17th
+ * drops the oldest once its last launch has finished (the host waits for
+ * it: the one case in which this call synchronises).
  * Results equal those of one vqnqs_local_energy call per job, bit for bit.
  * Calls that overlap on one device must not share a workspace; the internal
  * streams are shared, so such calls also serialise. */
@@ -309,6 +376,16 @@ void vqnqs_profile_enable(int on);
 void vqnqs_profile_reset(void);
 int  vqnqs_profile_read(char* names, int name_len, double* total_ms,
                         long long* count, int max);
+
+/* Measurement support: the rate at which the device's vector units issue
+ * the FP32 exponential (v_exp_f32), the operation that bounds attention
+ * at small head widths (one exponential per query-key pair).  Runs
+ * independent exponential chains on every SIMD (about 0.1 s), timed with
+ * HIP events on `stream`; synchronises the stream.
+ *   sink       DEVICE, one float the kernel writes (keeps the chains live)
+ *   exps_per_s HOST out: exponentials per second over the whole device  */
+vqnqs_status vqnqs_probe_exp_rate(float* sink, void* stream,
+                                  double* exps_per_s);
 
 #ifdef __cplusplus
 }

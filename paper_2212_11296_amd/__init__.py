@@ -12,7 +12,9 @@ from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
                   make_config, profile_enable, profile_reset, profile_read,
                   WS_FORWARD, WS_GRAD, MULTI_CONCURRENT, MULTI_GRAPH,
                   local_energy_multi, workspace_size_multi, autotune,
-                  set_tuning, local_energy_static, STATIC_SCRATCH_BYTES)
+                  set_tuning, local_energy_static, STATIC_SCRATCH_BYTES,
+                  forward_activations, probe_exp_rate, sample, WS_SAMPLE,
+                  vmc_step, WS_VMC)
 
 __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "FLAG_CERTIFIED_VQ", "NCOUNTERS", "CTR", "VQNQSError",
@@ -22,4 +24,6 @@ __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "profile_reset", "profile_read", "WS_FORWARD", "WS_GRAD",
            "MULTI_CONCURRENT", "MULTI_GRAPH", "local_energy_multi",
            "workspace_size_multi", "autotune", "set_tuning",
-           "local_energy_static", "STATIC_SCRATCH_BYTES"]
+           "local_energy_static", "STATIC_SCRATCH_BYTES",
+           "forward_activations", "probe_exp_rate", "sample", "WS_SAMPLE",
+           "vmc_step", "WS_VMC"]

@@ -17,11 +17,12 @@ _STATUS = {0: "ok", 1: "null pointer", 2: "invalid config", 3: "invalid shape",
            8: "one sample's workspace exceeds the static scratch"}
 STATIC_SCRATCH_BYTES = 512 << 20
 
-WS_FORWARD, WS_GRAD = -1, -3
+WS_FORWARD, WS_GRAD, WS_SAMPLE, WS_VMC = -1, -3, -4, -5
 MULTI_CONCURRENT, MULTI_GRAPH = 1, 2
 EXPORTS = ["vqnqs_param_count", "vqnqs_workspace_size", "vqnqs_neighbours",
            "vqnqs_forward_logpsi", "vqnqs_local_energy", "vqnqs_grad_logpsi",
-           "vqnqs_local_energy_static",
+           "vqnqs_local_energy_static", "vqnqs_forward_activations",
+           "vqnqs_probe_exp_rate", "vqnqs_sample", "vqnqs_vmc_step",
            "vqnqs_workspace_size_multi", "vqnqs_local_energy_multi",
            "vqnqs_autotune", "vqnqs_set_tuning",
            "vqnqs_workspace_status", "vqnqs_status_string",
@@ -88,12 +89,20 @@ def load_library():
     lib.vqnqs_neighbours.restype = ctypes.c_int
     lib.vqnqs_forward_logpsi.argtypes = [C, P, P, I64, P, P, P, SZ, P]
     lib.vqnqs_forward_logpsi.restype = ctypes.c_int
+    lib.vqnqs_forward_activations.argtypes = [C, P, P, I64, P, P, P, P, SZ,
+                                              P]
+    lib.vqnqs_forward_activations.restype = ctypes.c_int
     lib.vqnqs_local_energy.argtypes = [C, P, P, I64, I32, P, P, P, P, P, SZ,
                                        P]
     lib.vqnqs_local_energy.restype = ctypes.c_int
     lib.vqnqs_local_energy_static.argtypes = [C, P, P, I64, I32, P, P, P, P,
                                               P, P]
     lib.vqnqs_local_energy_static.restype = ctypes.c_int
+    lib.vqnqs_sample.argtypes = [C, P, P, I64, P, P, P, SZ, P]
+    lib.vqnqs_sample.restype = ctypes.c_int
+    lib.vqnqs_vmc_step.argtypes = [C, P, P, I64, ctypes.c_double, P, I64, P,
+                                   P, P, P, SZ, P]
+    lib.vqnqs_vmc_step.restype = ctypes.c_int
     lib.vqnqs_grad_logpsi.argtypes = [C, P, P, I64, P, P, P, P, SZ, P]
     lib.vqnqs_grad_logpsi.restype = ctypes.c_int
     J = ctypes.POINTER(Job)
@@ -108,6 +117,8 @@ def load_library():
     lib.vqnqs_set_tuning.restype = ctypes.c_int
     lib.vqnqs_workspace_status.argtypes = [P, P]
     lib.vqnqs_workspace_status.restype = ctypes.c_int
+    lib.vqnqs_probe_exp_rate.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.vqnqs_probe_exp_rate.restype = ctypes.c_int
     lib.vqnqs_status_string.argtypes = [ctypes.c_int]
     lib.vqnqs_status_string.restype = ctypes.c_char_p
     lib.vqnqs_profile_enable.argtypes = [ctypes.c_int]
@@ -149,6 +160,16 @@ def profile_read(max_kernels=64):
         nm = names.raw[k * L:(k + 1) * L].split(b"\0", 1)[0].decode()
         out[nm] = (ms[k], cnt[k])
     return out
+
+
+def probe_exp_rate():
+    """Exponentials per second the device's vector units issue."""
+    import torch
+    sink = torch.empty(1, dtype=torch.float32, device="cuda")
+    out = ctypes.c_double(0.0)
+    _check("vqnqs_probe_exp_rate", load_library().vqnqs_probe_exp_rate(
+        _ptr(sink), _stream(), ctypes.byref(out)))
+    return out.value
 
 
 def _check(fn, st):
@@ -228,6 +249,29 @@ def forward_logpsi(cfg, params, spins, codes=False, ws=None,
     return (lp, cd) if codes else lp
 
 
+def forward_activations(cfg, params, spins, ws=None, budget=8 << 30,
+                        check=True):
+    """log psi [B], codes [B][n_layers][N][H] and every layer's attention
+    output [B][n_layers][N][d] (float64 in the F64 mode, else float32)."""
+    import torch
+    B = spins.shape[0]
+    N = cfg.L * cfg.L
+    ws = _workspace(cfg, B, -1, ws, budget)
+    lp = torch.empty(B, dtype=torch.float64, device="cuda")
+    cd = torch.empty((B, cfg.n_layers, N, cfg.vq_heads), dtype=torch.int32,
+                     device="cuda")
+    at = torch.empty((B, cfg.n_layers, N, cfg.d_model),
+                     dtype=torch.float64 if cfg.precision == F64
+                     else torch.float32, device="cuda")
+    _check("vqnqs_forward_activations",
+           load_library().vqnqs_forward_activations(
+               ctypes.byref(cfg), _ptr(params), _ptr(spins), B, _ptr(lp),
+               _ptr(cd), _ptr(at), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)
+    return lp, cd, at
+
+
 def local_energy(cfg, params, spins, mode=DEDUP, stats=True, ratios=False,
                  counters=False, ws=None, budget=8 << 30, check=True,
                  out=None):
@@ -286,6 +330,63 @@ def local_energy_static(cfg, params, spins, mode=DEDUP, stats=True,
                _ptr(o.get("counters")), _ptr(o["status"]), _stream()))
     if check:
         _check("vqnqs_local_energy_static", int(o["status"].item()))
+    return o
+
+
+def sample(cfg, params, uniforms, ws=None, budget=8 << 30, check=True,
+           out=None):
+    """Direct samples s ~ psi^2 (chain rule) drawn with the caller's
+    uniform numbers (device float64 [B][N]); returns (spins int8 [B][N],
+    log psi float64 [B])."""
+    import torch
+    B, N = uniforms.shape
+    assert N == cfg.L * cfg.L and uniforms.dtype == torch.float64
+    ws = _workspace(cfg, B, WS_SAMPLE, ws, budget)
+    o = out if out is not None else {}
+    if "spins" not in o:
+        o["spins"] = torch.empty((B, N), dtype=torch.int8, device="cuda")
+    if "logpsi" not in o:
+        o["logpsi"] = torch.empty(B, dtype=torch.float64, device="cuda")
+    u = uniforms.contiguous()
+    _check("vqnqs_sample", load_library().vqnqs_sample(
+        ctypes.byref(cfg), _ptr(params), _ptr(u), B, _ptr(o["spins"]),
+        _ptr(o["logpsi"]), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)
+    return o["spins"], o["logpsi"]
+
+
+def vmc_step(cfg, params, uniforms, lr, opt_state=None, step=1, ws=None,
+             budget=8 << 30, check=True, out=None):
+    """One VMC step on the device (sample, local energy, energy gradient,
+    update of ``params`` in place).  opt_state: None for gradient descent,
+    else a zeroed device tensor [2][P] of the parameters' dtype (Adam).
+    Returns a dict with spins [B][N], eloc [B] and stats [2] of the step."""
+    import torch
+    B, N = uniforms.shape
+    assert N == cfg.L * cfg.L and uniforms.dtype == torch.float64
+    if ws is None:
+        need = workspace_size(cfg, B, WS_VMC, 0)
+        if need > budget:
+            c = 1
+            while (c * 2 <= B
+                   and workspace_size(cfg, B, WS_VMC, c * 2) <= budget):
+                c *= 2
+            need = workspace_size(cfg, B, WS_VMC, c)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    o = out if out is not None else {}
+    if "spins" not in o:
+        o["spins"] = torch.empty((B, N), dtype=torch.int8, device="cuda")
+    if "eloc" not in o:
+        o["eloc"] = torch.empty(B, dtype=torch.float64, device="cuda")
+    if "stats" not in o:
+        o["stats"] = torch.empty(2, dtype=torch.float64, device="cuda")
+    _check("vqnqs_vmc_step", load_library().vqnqs_vmc_step(
+        ctypes.byref(cfg), _ptr(params), _ptr(opt_state), int(step),
+        float(lr), _ptr(uniforms.contiguous()), B, _ptr(o["spins"]),
+        _ptr(o["eloc"]), _ptr(o["stats"]), _ptr(ws), ws.numel(), _stream()))
+    if check:
+        _check_status(ws)
     return o
 
 

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libvqnqs.so")
 
 SOURCES = ["abi.cpp", "engine.cpp", "profiler.cpp", "kernels_lattice.hip", "kernels_layer.hip",
            "kernels_mfma.hip", "kernels_attn.hip", "kernels_grad.hip",
-           "static_scratch.hip"]
+           "static_scratch.hip", "kernels_vmc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -76,8 +76,17 @@ vqnqs_status vqnqs_workspace_size(const vqnqs_config* cfg, int64_t batch,
     if (!bytes) return VQNQS_ERR_NULL_POINTER;
     if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
     if (mode != VQNQS_PLAIN && mode != VQNQS_DEDUP &&
-        mode != VQNQS_WS_FORWARD && mode != VQNQS_WS_GRAD)
+        mode != VQNQS_WS_FORWARD && mode != VQNQS_WS_GRAD &&
+        mode != VQNQS_WS_SAMPLE && mode != VQNQS_WS_VMC)
         return VQNQS_ERR_INVALID_CONFIG;
+    if (mode == VQNQS_WS_VMC) {
+        // the step's own buffers hold the whole batch; the calls inside
+        // it process `chunk` samples at a time
+        const int64_t c = chunk <= 0 || chunk > batch ? (batch > 0 ? batch : 1)
+                                                      : chunk;
+        *bytes = vq::vmc_workspace_bytes(m, batch > 0 ? batch : 1, c);
+        return VQNQS_OK;
+    }
     if (chunk <= 0 || chunk > batch) chunk = batch > 0 ? batch : 1;
     *bytes = vq::workspace_bytes(m, mode, chunk);
     return VQNQS_OK;
@@ -107,8 +116,24 @@ vqnqs_status vqnqs_forward_logpsi(const vqnqs_config* cfg, const void* params,
     if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
     if (!ws || (batch > 0 && (!params || !spins || !logpsi)))
         return VQNQS_ERR_NULL_POINTER;
-    return vq::forward_logpsi(m, params, spins, batch, logpsi, codes, ws,
-                              ws_bytes, (hipStream_t)stream);
+    return vq::forward_logpsi(m, params, spins, batch, logpsi, codes, nullptr,
+                              ws, ws_bytes, (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_forward_activations(const vqnqs_config* cfg,
+                                       const void* params,
+                                       const int8_t* spins, int64_t batch,
+                                       double* logpsi, int32_t* codes,
+                                       void* attn, void* ws, size_t ws_bytes,
+                                       void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (!ws || (batch > 0 && (!params || !spins || !logpsi || !attn)))
+        return VQNQS_ERR_NULL_POINTER;
+    return vq::forward_logpsi(m, params, spins, batch, logpsi, codes, attn,
+                              ws, ws_bytes, (hipStream_t)stream);
 }
 
 vqnqs_status vqnqs_local_energy(const vqnqs_config* cfg, const void* params,
@@ -143,6 +168,36 @@ vqnqs_status vqnqs_local_energy_static(const vqnqs_config* cfg,
     return vq::local_energy_static(m, params, spins, batch, mode, eloc, stats,
                                    ratios, counters, status,
                                    (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_sample(const vqnqs_config* cfg, const void* params,
+                          const double* uniforms, int64_t batch,
+                          int8_t* spins, double* logpsi, void* ws,
+                          size_t ws_bytes, void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (!ws || (batch > 0 && (!params || !uniforms || !spins)))
+        return VQNQS_ERR_NULL_POINTER;
+    return vq::sample(m, params, uniforms, batch, spins, logpsi, ws, ws_bytes,
+                      (hipStream_t)stream);
+}
+
+vqnqs_status vqnqs_vmc_step(const vqnqs_config* cfg, void* params,
+                            void* opt_state, int64_t step, double lr,
+                            const double* uniforms, int64_t batch,
+                            int8_t* spins, double* eloc, double* stats,
+                            void* ws, size_t ws_bytes, void* stream) {
+    vq::ModelDims m;
+    vqnqs_status e;
+    if (!dims_from(cfg, &m, &e)) return e;
+    if (batch < 1) return VQNQS_ERR_INVALID_SHAPE;
+    if (!std::isfinite(lr) || (opt_state && step < 1))
+        return VQNQS_ERR_INVALID_CONFIG;
+    if (!ws || !params || !uniforms) return VQNQS_ERR_NULL_POINTER;
+    return vq::vmc_step(m, params, opt_state, step, lr, uniforms, batch, spins,
+                        eloc, stats, ws, ws_bytes, (hipStream_t)stream);
 }
 
 vqnqs_status vqnqs_grad_logpsi(const vqnqs_config* cfg, const void* params,
@@ -247,6 +302,14 @@ int vqnqs_profile_read(char* names, int name_len, double* total_ms,
                        long long* count, int max) {
     if (max < 0 || (names && name_len < 2)) return -1;
     return vq::Profiler::get().read(names, name_len, total_ms, count, max);
+}
+
+vqnqs_status vqnqs_probe_exp_rate(float* sink, void* stream,
+                                  double* exps_per_s) {
+    if (!sink || !exps_per_s) return VQNQS_ERR_NULL_POINTER;
+    if (vq::probe_exp_rate(sink, (hipStream_t)stream, exps_per_s) != hipSuccess)
+        return VQNQS_ERR_HIP;
+    return VQNQS_OK;
 }
 
 const char* vqnqs_status_string(vqnqs_status s) {

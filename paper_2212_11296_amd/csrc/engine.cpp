@@ -103,7 +103,7 @@ struct Workspace {
     size_t bytes;
 };
 
-enum class Job { Forward, Plain, Dedup, Neighbours, Grad };
+enum class Job { Forward, Plain, Dedup, Neighbours, Grad, Sample };
 
 template <class P>
 static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
@@ -139,6 +139,22 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     w.list_n = c.take<int32_t>(1);
     w.vq_n = c.take<int32_t>(1);
     if (job == Job::Neighbours) {
+        w.bytes = c.off;
+        return w;
+    }
+    if (job == Job::Sample) {
+        // one position of every sample at a time: the residual rows, query
+        // and attention rows, the keys and values of every layer (the
+        // positions drawn so far), codes, the row list and FP64 sums
+        const int64_t R = n * N;
+        w.bx = c.take<acc>(R * d);
+        w.bq = c.take<act>(R * d);
+        w.ba = c.take<act>(R * d);
+        w.bk = c.take<act>((size_t)m.nl * R * d);
+        w.bv = c.take<act>((size_t)m.nl * R * d);
+        w.bcode = c.take<int32_t>(R * H);
+        w.list = c.take<int64_t>(n);
+        w.logpsi_s = c.take<double>(n);
         w.bytes = c.off;
         return w;
     }
@@ -225,11 +241,31 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     return w;
 }
 
+// Variational Monte Carlo step: the per-step buffers (samples, local
+// energies, statistics, gradient weights, gradient) after the region the
+// sampling, local-energy and gradient calls share in turn.
+static size_t vmc_front_bytes(const ModelDims& m, int64_t B) {
+    const size_t a = m.precision == VQNQS_F64 ? 8 : 4;
+    return al256((size_t)B * m.N) + 3 * al256((size_t)B * 8) + 256 +
+           al256((size_t)param_count(m) * a);
+}
+
+static size_t vmc_sub_bytes(const ModelDims& m, int64_t chunk) {
+    return std::max(workspace_bytes(m, -4, chunk),
+                    std::max(workspace_bytes(m, VQNQS_DEDUP, chunk),
+                             workspace_bytes(m, -3, chunk)));
+}
+
+size_t vmc_workspace_bytes(const ModelDims& m, int64_t batch, int64_t chunk) {
+    return al256(vmc_sub_bytes(m, chunk)) + vmc_front_bytes(m, batch);
+}
+
 size_t workspace_bytes(const ModelDims& m, int mode, int64_t chunk) {
     const Job job = mode == VQNQS_PLAIN   ? Job::Plain
                     : mode == VQNQS_DEDUP ? Job::Dedup
                     : mode == -2          ? Job::Neighbours
                     : mode == -3          ? Job::Grad
+                    : mode == -4          ? Job::Sample
                                           : Job::Forward;
     switch (m.precision) {
         case VQNQS_F64: return carve<PrecF64>(m, job, chunk, nullptr).bytes;
@@ -439,6 +475,7 @@ struct Runner {
         bool cache;
         int32_t* codes_out;   // nullable [n][nl][N][H]
         bool keep_x = false;  // block inputs per layer only (checkpoints)
+        act* attn_out = nullptr;  // nullable [n][nl][N][d] attention outputs
     };
 
     vqnqs_status forward(const SeqBufs& b, const int32_t* n_dev, int64_t n,
@@ -462,6 +499,9 @@ struct Runner {
             qio.x = const_cast<acc*>(io.x_in);
             LK("qkv", qkv(layer(l), rs, qio));
             LK("attention_seq", attn_seq(n_dev, n, io, count_rows ? ctr : nullptr));
+            if (b.attn_out)
+                LK("copy_attn", launch_copy_layer<act>(io.a, n, (int64_t)m.N * m.d, m.nl, l,
+                                                       b.attn_out, st));
             LK("vq", vqs(layer(l), rs, io));
             LK("mlp", mlp(layer(l), rs, io));
             if (b.codes_out)
@@ -649,6 +689,40 @@ struct Runner {
         return VQNQS_OK;
     }
 
+    // Direct autoregressive sampling of n samples (chain rule, Sec. 2):
+    // position by position, every layer's per-row kernels on row i of all
+    // samples, attention of row i over the cached keys and values 0..i,
+    // then the head draws s_i with the caller's uniform numbers.
+    vqnqs_status sample_chunk(const double* uni, int64_t n, int8_t* spins,
+                              double* logpsi) {
+        const int64_t N = m.N, R = n * N, sd = R * m.d;
+        RowSet rs{w.list, nullptr, n, 1};
+        for (int i = 0; i < N; ++i) {
+            LK("sample_embed", launch_sample_embed<P>(m, head(), n, i, spins, w.bx,
+                                                      w.list, w.logpsi_s, st));
+            for (int l = 0; l < m.nl; ++l) {
+                BlockIO<P> io{};
+                io.x = w.bx;
+                io.x_in = w.bx;
+                io.q = w.bq;
+                io.k = w.bk + (int64_t)l * sd;
+                io.v = w.bv + (int64_t)l * sd;
+                io.a = w.ba;
+                io.codes = w.bcode;
+                io.margin = nullptr;
+                LK("qkv", qkv(layer(l), rs, io));
+                LK("attention_rows", launch_attn_rows<P>(m, n, i, io, st));
+                LK("vq", vqs(layer(l), rs, io));
+                LK("mlp", mlp(layer(l), rs, io));
+            }
+            LK("sample_head", launch_sample_head<P>(m, head(), n, i, w.bx,
+                                                    uni + 0, spins, w.logpsi_s,
+                                                    logpsi, st));
+        }
+        (void)R;
+        return VQNQS_OK;
+    }
+
     vqnqs_status plain_chunk(const int8_t* spins, int64_t n) {
         vqnqs_status s = neighbours(spins, n);
         if (s) return s;
@@ -813,8 +887,9 @@ vqnqs_status local_energy(const ModelDims& m, const void* params,
 template <class P>
 static vqnqs_status run_forward(const ModelDims& m, const void* params,
                                 const int8_t* spins, int64_t batch,
-                                double* logpsi, int32_t* codes, void* ws,
-                                size_t ws_bytes, hipStream_t st) {
+                                double* logpsi, int32_t* codes, void* attn,
+                                void* ws, size_t ws_bytes, hipStream_t st) {
+    using act = typename P::act;
     const int64_t chunk = pick_chunk(m, -1, batch, ws_bytes);
     if (batch > 0 && chunk <= 0) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
     Runner<P> r{m, static_cast<const typename P::acc*>(params),
@@ -833,6 +908,8 @@ static vqnqs_status run_forward(const ModelDims& m, const void* params,
             sp, r.w.bx, r.w.bq, r.w.bk, r.w.bv, r.w.ba, r.w.bcode, nullptr,
             nullptr, logpsi + c0, false,
             codes ? codes + c0 * (int64_t)m.nl * m.N * m.H : nullptr};
+        if (attn)
+            sb.attn_out = static_cast<act*>(attn) + c0 * (int64_t)m.nl * m.N * m.d;
         s = r.forward(sb, nullptr, n, false);
         if (s) return s;
     }
@@ -841,19 +918,106 @@ static vqnqs_status run_forward(const ModelDims& m, const void* params,
 
 vqnqs_status forward_logpsi(const ModelDims& m, const void* params,
                             const int8_t* spins, int64_t batch, double* logpsi,
-                            int32_t* codes, void* ws, size_t ws_bytes,
-                            hipStream_t st) {
+                            int32_t* codes, void* attn, void* ws,
+                            size_t ws_bytes, hipStream_t st) {
     switch (m.precision) {
         case VQNQS_F64:
             return run_forward<PrecF64>(m, params, spins, batch, logpsi, codes,
-                                        ws, ws_bytes, st);
+                                        attn, ws, ws_bytes, st);
         case VQNQS_F32:
             return run_forward<PrecF32>(m, params, spins, batch, logpsi, codes,
-                                        ws, ws_bytes, st);
+                                        attn, ws, ws_bytes, st);
         default:
             return run_forward<PrecBF16>(m, params, spins, batch, logpsi, codes,
-                                         ws, ws_bytes, st);
+                                         attn, ws, ws_bytes, st);
     }
+}
+
+template <class P>
+static vqnqs_status run_sample(const ModelDims& m, const void* params,
+                               const double* uniforms, int64_t batch,
+                               int8_t* spins, double* logpsi, void* ws,
+                               size_t ws_bytes, hipStream_t st) {
+    const int64_t chunk = pick_chunk(m, -4, batch, ws_bytes);
+    if (batch > 0 && chunk <= 0) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
+    Runner<P> r{m, static_cast<const typename P::acc*>(params),
+                carve<P>(m, Job::Sample, chunk, ws), st, nullptr};
+    CK(launch_fill_i32(r.w.status, 1, 0, st));
+    if (batch == 0) return VQNQS_OK;
+    vqnqs_status s = r.prepare();
+    if (s) return s;
+    for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
+        const int64_t n = std::min(chunk, batch - c0);
+        s = r.sample_chunk(uniforms + c0 * m.N, n, spins + c0 * m.N,
+                           logpsi ? logpsi + c0 : nullptr);
+        if (s) return s;
+    }
+    return VQNQS_OK;
+}
+
+vqnqs_status sample(const ModelDims& m, const void* params,
+                    const double* uniforms, int64_t batch, int8_t* spins,
+                    double* logpsi, void* ws, size_t ws_bytes,
+                    hipStream_t st) {
+    switch (m.precision) {
+        case VQNQS_F64:
+            return run_sample<PrecF64>(m, params, uniforms, batch, spins,
+                                       logpsi, ws, ws_bytes, st);
+        case VQNQS_F32:
+            return run_sample<PrecF32>(m, params, uniforms, batch, spins,
+                                       logpsi, ws, ws_bytes, st);
+        default:
+            return run_sample<PrecBF16>(m, params, uniforms, batch, spins,
+                                        logpsi, ws, ws_bytes, st);
+    }
+}
+
+vqnqs_status vmc_step(const ModelDims& m, void* params, void* opt_state,
+                      int64_t step, double lr, const double* uniforms,
+                      int64_t B, int8_t* spins_out, double* eloc_out,
+                      double* stats_out, void* ws, size_t ws_bytes,
+                      hipStream_t st) {
+    const size_t front = vmc_front_bytes(m, B);
+    if (ws_bytes <= front) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
+    const size_t sub = (ws_bytes - front) & ~(size_t)255;
+    char* f = static_cast<char*>(ws) + sub;
+    int8_t* spins = reinterpret_cast<int8_t*>(f);
+    f += al256((size_t)B * m.N);
+    double* eloc = reinterpret_cast<double*>(f);
+    f += al256((size_t)B * 8);
+    double* w = reinterpret_cast<double*>(f);
+    f += al256((size_t)B * 8);
+    double* stats = reinterpret_cast<double*>(f);
+    f += 256;
+    void* grad = f;
+    if (spins_out) spins = spins_out;
+    if (eloc_out) eloc = eloc_out;
+    if (stats_out) stats = stats_out;
+    // one sample's sub-call workspace must fit
+    if (sub < vmc_sub_bytes(m, 1)) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
+    vqnqs_status s = sample(m, params, uniforms, B, spins, nullptr, ws, sub, st);
+    if (s) return s;
+    s = local_energy(m, params, spins, B, VQNQS_DEDUP, eloc, stats, nullptr,
+                     nullptr, ws, sub, st);
+    if (s) return s;
+    LK("vmc_weights", launch_vmc_weights(eloc, stats, B, w, st));
+    s = grad_logpsi(m, params, spins, B, w, grad, nullptr, ws, sub, st);
+    if (s) return s;
+    const int64_t P = param_count(m);
+    if (m.precision == VQNQS_F64) {
+        double* mo = static_cast<double*>(opt_state);
+        LK("update", launch_update<double>(static_cast<double*>(params),
+                                           static_cast<const double*>(grad),
+                                           mo, mo ? mo + P : nullptr, P, lr,
+                                           0.9, 0.999, 1e-8, step, st));
+    } else {
+        float* mo = static_cast<float*>(opt_state);
+        LK("update", launch_update<float>(static_cast<float*>(params),
+                                          static_cast<const float*>(grad),
+                                          mo, mo ? mo + P : nullptr, P, lr,
+                                          0.9, 0.999, 1e-8, step, st));
+    }
+    return VQNQS_OK;
 }
 
 template <class P>
@@ -1008,6 +1172,7 @@ struct Pools {
     struct Graph {
         std::vector<int64_t> key;
         hipGraphExec_t exec;
+        hipEvent_t done;   // recorded after every launch of exec
     };
     std::vector<Graph> graphs;
 };
@@ -1174,6 +1339,7 @@ vqnqs_status local_energy_multi(const ModelDims* ms, const vqnqs_job* jobs,
         for (auto& g : p.graphs)
             if (g.key == key) {
                 CK(hipGraphLaunch(g.exec, st));
+                CK(hipEventRecord(g.done, st));
                 return VQNQS_OK;
             }
     }
@@ -1198,15 +1364,26 @@ vqnqs_status local_energy_multi(const ModelDims* ms, const vqnqs_job* jobs,
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return VQNQS_ERR_HIP;
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return VQNQS_ERR_HIP;
+    }
     {
         std::lock_guard<std::mutex> lk(p.mu);
         if (p.graphs.size() >= kMaxGraphs) {
-            (void)hipGraphExecDestroy(p.graphs.front().exec);
+            // the evicted graph may still run on some stream: wait for its
+            // last launch before its resources go
+            Pools::Graph& old = p.graphs.front();
+            (void)hipEventSynchronize(old.done);
+            (void)hipGraphExecDestroy(old.exec);
+            (void)hipEventDestroy(old.done);
             p.graphs.erase(p.graphs.begin());
         }
-        p.graphs.push_back({key, exec});
+        p.graphs.push_back({key, exec, done});
     }
     CK(hipGraphLaunch(exec, st));
+    CK(hipEventRecord(done, st));
     return VQNQS_OK;
 }
 

@@ -57,6 +57,9 @@ hipError_t launch_or_status(char* base, const StatusOffsets& so,
                             hipStream_t st);
 hipError_t launch_copy_codes(const int32_t* src, int64_t n, int N, int H,
                              int nl, int l, int32_t* dst, hipStream_t st);
+template <typename T>
+hipError_t launch_copy_layer(const T* src, int64_t n, int64_t row, int nl,
+                             int l, T* dst, hipStream_t st);
 
 // ---- parameter preparation (tables, norms, BF16 packs)
 template <class P>
@@ -122,6 +125,31 @@ hipError_t launch_head_seq(const ModelDims& m, const HeadW<typename P::acc>& hw,
                            int64_t n_seq, const typename P::acc* x,
                            typename P::acc* lp, double* logpsi,
                            hipStream_t st);
+
+// ---- variational Monte Carlo step
+hipError_t launch_vmc_weights(const double* eloc, const double* stats,
+                              int64_t B, double* w, hipStream_t st);
+template <typename T>
+hipError_t launch_update(T* p, const T* g, T* m, T* v, int64_t n, double lr,
+                         double b1, double b2, double eps, int64_t step,
+                         hipStream_t st);
+
+// ---- autoregressive sampling (one position of every sample per call)
+template <class P>
+hipError_t launch_sample_embed(const ModelDims& m,
+                               const HeadW<typename P::acc>& hw, int64_t n,
+                               int i, const int8_t* spins,
+                               typename P::acc* x, int64_t* list,
+                               double* lpsum, hipStream_t st);
+template <class P>
+hipError_t launch_attn_rows(const ModelDims& m, int64_t n, int i,
+                            const BlockIO<P>& io, hipStream_t st);
+template <class P>
+hipError_t launch_sample_head(const ModelDims& m,
+                              const HeadW<typename P::acc>& hw, int64_t n,
+                              int i, const typename P::acc* x,
+                              const double* uni, int8_t* spins, double* lpsum,
+                              double* logpsi, hipStream_t st);
 
 // ---- deduplicated neighbour evaluation
 template <class P>

@@ -251,6 +251,33 @@ __global__ void k_copy_codes(const int32_t* __restrict__ src, int64_t n, int N,
     }
 }
 
+// Slice l of a per-layer output: src [n][row] -> dst [n][nl][row].
+template <typename T>
+__global__ void k_copy_layer(const T* __restrict__ src, int64_t n,
+                             int64_t row, int nl, int l, T* __restrict__ dst) {
+    const int64_t total = n * row;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = e / row;
+        dst[(s * nl + l) * row + (e - s * row)] = src[e];
+    }
+}
+
+template <typename T>
+hipError_t launch_copy_layer(const T* src, int64_t n, int64_t row, int nl,
+                             int l, T* dst, hipStream_t st) {
+    int64_t blocks = (n * row + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_copy_layer<T>, dim3((unsigned)blocks), dim3(256), 0,
+                       st, src, n, row, nl, l, dst);
+    return hipGetLastError();
+}
+template hipError_t launch_copy_layer<float>(const float*, int64_t, int64_t,
+                                             int, int, float*, hipStream_t);
+template hipError_t launch_copy_layer<double>(const double*, int64_t, int64_t,
+                                              int, int, double*, hipStream_t);
+
 // ------------------------------------------------------------ launchers
 hipError_t launch_counter_add_const(int64_t* ctr, int slot, int64_t v,
                                     hipStream_t st) {

@@ -221,19 +221,20 @@ hipError_t launch_qkv(const ModelDims& m, const LayerW<typename P::acc>& w,
 }
 
 // ------------------------------------------------------------- attention
-// One query row against keys 0..i held in LDS (online softmax).  Shared by
-// the full-sequence and the overlay kernels so both give identical bits.
+// One query row against keys 0..i (online softmax), key j's vector at
+// Ks + j * ld (LDS tiles: ld = DH).  Shared by the full-sequence, overlay
+// and sampling kernels so all give identical bits.
 template <typename C, int DH, typename A>
 __device__ inline void attend_row(const C (&q)[DH], const A* __restrict__ Ks,
                                   const A* __restrict__ Vs, int i,
-                                  C (&o)[DH]) {
+                                  C (&o)[DH], int64_t ld = DH) {
     C mx = neg_inf<C>(), l = 0;
 #pragma unroll
     for (int c = 0; c < DH; ++c) o[c] = 0;
     for (int j = 0; j <= i; ++j) {
         C s = 0;
 #pragma unroll
-        for (int c = 0; c < DH; ++c) s += q[c] * cvt<C>(Ks[j * DH + c]);
+        for (int c = 0; c < DH; ++c) s += q[c] * cvt<C>(Ks[j * ld + c]);
         if (s > mx) {
             const C al = dexp(mx - s);
             l *= al;
@@ -244,7 +245,7 @@ __device__ inline void attend_row(const C (&q)[DH], const A* __restrict__ Ks,
         const C p = dexp(s - mx);
         l += p;
 #pragma unroll
-        for (int c = 0; c < DH; ++c) o[c] += p * cvt<C>(Vs[j * DH + c]);
+        for (int c = 0; c < DH; ++c) o[c] += p * cvt<C>(Vs[j * ld + c]);
     }
     const C inv = (C)1 / l;
 #pragma unroll
@@ -809,6 +810,132 @@ hipError_t launch_head_seq(const ModelDims& m, const HeadW<typename P::acc>& hw,
     return hipGetLastError();
 }
 
+// ------------------------------------------------ autoregressive sampling
+// Direct sampling from the chain rule P(s) = prod_i P(s_i | s_<i) (Sec. 2):
+// position i of every sample is evaluated with the keys and values of
+// positions < i kept per layer, and s_i is drawn from the head's
+// conditional with the caller's uniform number u (s_i = +1 iff
+// u < P(s_i = +1 | s_<i), in FP64).  Row i of every per-row kernel is the
+// row a full forward pass of the finished sequence computes, with the same
+// arithmetic in the same order.
+
+// Step i: block input x of row i (embedding of the previous spin, as
+// k_embed), the row list of step i, and at i = 0 the log-probability sums.
+template <class P>
+__global__ void k_sample_embed(ModelDims m, HeadW<typename P::acc> hw,
+                               int64_t n, int i,
+                               const int8_t* __restrict__ spins,
+                               typename P::acc* __restrict__ x,
+                               int64_t* __restrict__ list,
+                               double* __restrict__ lpsum) {
+    const int64_t total = n * m.d;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = e / m.d;
+        const int col = (int)(e - s * m.d);
+        const int64_t row = s * m.N + i;
+        const int u = i == 0 ? 2 : (spins[row - 1] < 0 ? 1 : 0);
+        x[row * m.d + col] = hw.tok[u * m.d + col] + hw.pos[(int64_t)i * m.d + col];
+        if (col == 0) {
+            list[s] = row;
+            if (i == 0) lpsum[s] = 0.0;
+        }
+    }
+}
+
+template <class P>
+hipError_t launch_sample_embed(const ModelDims& m,
+                               const HeadW<typename P::acc>& hw, int64_t n,
+                               int i, const int8_t* spins,
+                               typename P::acc* x, int64_t* list,
+                               double* lpsum, hipStream_t st) {
+    hipLaunchKernelGGL(k_sample_embed<P>, dim3(grid_for((n * m.d + 255) / 256)),
+                       dim3(256), 0, st, m, hw, n, i, spins, x, list, lpsum);
+    return hipGetLastError();
+}
+
+// Attention of query row i of every (sample, head) over its keys 0..i,
+// one thread per (sample, head), keys read from the per-layer cache.
+template <class P, int DH>
+__global__ void __launch_bounds__(kThreads) k_attn_rows(ModelDims m, int64_t n,
+                                                        int i, BlockIO<P> io) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    const int64_t units = n * m.nh;
+    const acc scale = (acc)1 / dsqrt((acc)DH);
+    const int d = m.d, N = m.N;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < units;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = u / m.nh;
+        const int h = (int)(u - s * m.nh);
+        const int64_t base = s * N * d + h * DH;
+        acc q[DH], o[DH];
+#pragma unroll
+        for (int c = 0; c < DH; ++c)
+            q[c] = cvt<acc>(io.q[base + (int64_t)i * d + c]) * scale;
+        attend_row<acc, DH, act>(q, io.k + base, io.v + base, i, o, d);
+#pragma unroll
+        for (int c = 0; c < DH; ++c)
+            io.a[base + (int64_t)i * d + c] = cvt<act>(o[c]);
+    }
+}
+
+template <class P>
+hipError_t launch_attn_rows(const ModelDims& m, int64_t n, int i,
+                            const BlockIO<P>& io, hipStream_t st) {
+    const dim3 g(grid_for((n * m.nh + kThreads - 1) / kThreads)), b(kThreads);
+    switch (m.dh) {
+        case 4: hipLaunchKernelGGL((k_attn_rows<P, 4>), g, b, 0, st, m, n, i, io); break;
+        case 8: hipLaunchKernelGGL((k_attn_rows<P, 8>), g, b, 0, st, m, n, i, io); break;
+        case 16: hipLaunchKernelGGL((k_attn_rows<P, 16>), g, b, 0, st, m, n, i, io); break;
+        case 32: hipLaunchKernelGGL((k_attn_rows<P, 32>), g, b, 0, st, m, n, i, io); break;
+        case 64: hipLaunchKernelGGL((k_attn_rows<P, 64>), g, b, 0, st, m, n, i, io); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Head of row i of every sample (one wave each, as k_head_seq), the draw of
+// s_i, and the running sum of log P(s_i | s_<i) in position order (FP64, as
+// k_head_seq sums it); at the last position log psi = sum / 2.
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_sample_head(
+    ModelDims m, HeadW<typename P::acc> hw, int64_t n, int i,
+    const typename P::acc* __restrict__ x, const double* __restrict__ uni,
+    int8_t* __restrict__ spins, double* __restrict__ lpsum,
+    double* __restrict__ logpsi) {
+    using acc = typename P::acc;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t s = blockIdx.x * (int64_t)(kThreads / 64) + (threadIdx.x >> 6);
+         s < n; s += waves) {
+        const int64_t row = s * m.N + i;
+        const acc* xr[1] = {x + row * m.d};
+        acc l0[1], l1[1];
+        head_rows<acc, 1>(xr, m.d, hw, l0, l1);
+        if (lane == 0) {
+            const bool up = uni[row] < exp((double)l0[0]);
+            spins[row] = up ? (int8_t)1 : (int8_t)-1;
+            const double acc64 = lpsum[s] + (double)(up ? l0[0] : l1[0]);
+            lpsum[s] = acc64;
+            if (i == m.N - 1 && logpsi) logpsi[s] = 0.5 * acc64;
+        }
+    }
+}
+
+template <class P>
+hipError_t launch_sample_head(const ModelDims& m,
+                              const HeadW<typename P::acc>& hw, int64_t n,
+                              int i, const typename P::acc* x,
+                              const double* uni, int8_t* spins, double* lpsum,
+                              double* logpsi, hipStream_t st) {
+    hipLaunchKernelGGL(k_sample_head<P>,
+                       dim3(grid_for((n + kThreads / 64 - 1) / (kThreads / 64))),
+                       dim3(kThreads), 0, st, m, hw, n, i, x, uni, spins,
+                       lpsum, logpsi);
+    return hipGetLastError();
+}
+
 // ratio = exp(log psi(s') - log psi(s)) for materialised neighbours (FP64)
 __global__ void k_ratio_plain(const double* __restrict__ lnb,
                               const double* __restrict__ ls,
@@ -1274,7 +1401,15 @@ hipError_t launch_head_dedup(const ModelDims& m, const HeadW<typename P::acc>& h
                                             const DedupIO<P>&, hipStream_t);  \
     template hipError_t launch_head_dedup<P>(                                 \
         const ModelDims&, const HeadW<P::acc>&, const DedupIO<P>&,            \
-        const P::acc*, const double*, double*, int64_t*, hipStream_t);
+        const P::acc*, const double*, double*, int64_t*, hipStream_t);        \
+    template hipError_t launch_sample_embed<P>(                               \
+        const ModelDims&, const HeadW<P::acc>&, int64_t, int, const int8_t*,  \
+        P::acc*, int64_t*, double*, hipStream_t);                             \
+    template hipError_t launch_attn_rows<P>(const ModelDims&, int64_t, int,   \
+                                            const BlockIO<P>&, hipStream_t);  \
+    template hipError_t launch_sample_head<P>(                                \
+        const ModelDims&, const HeadW<P::acc>&, int64_t, int, const P::acc*,  \
+        const double*, int8_t*, double*, double*, hipStream_t);
 
 VQ_INST(PrecF64)
 VQ_INST(PrecF32)

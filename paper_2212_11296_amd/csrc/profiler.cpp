@@ -89,4 +89,52 @@ int Profiler::read(char* names, int name_len, double* total_ms,
     return (int)names_.size();
 }
 
+// ------------------------------------------------ exponential issue rate
+// Every lane runs eight independent chains x <- 2^x on the vector unit's
+// exponential instruction (v_exp_f32); the chains saturate to +inf after a
+// few steps, which does not change the instruction's issue rate.  Lane 0
+// of block 0 writes its sum so the chains stay live.
+__global__ void __launch_bounds__(256) k_exp_probe(float* sink, int iters) {
+    float x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = -1.0f - 1e-3f * (float)(threadIdx.x + k);
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = __builtin_amdgcn_exp2f(x[k]);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += x[k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) sink[0] = s;
+}
+
+hipError_t probe_exp_rate(float* sink, hipStream_t st, double* per_s) {
+    // 8 waves per SIMD on 256 CUs x 4 SIMDs
+    const int blocks = 256 * 8, threads = 256, iters = 1 << 16;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    // warm-up launch, then the timed one
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_exp_probe, dim3(blocks), dim3(threads), 0, st,
+                           sink, 256);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_exp_probe, dim3(blocks), dim3(threads), 0, st,
+                           sink, iters);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e == hipSuccess)
+        *per_s = (double)blocks * threads * 8.0 * iters / (ms * 1e-3);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return e;
+}
+
 }  // namespace vq

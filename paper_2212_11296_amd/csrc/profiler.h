@@ -38,4 +38,9 @@ class Profiler {
     hipEvent_t cur_a_ = nullptr;
 };
 
+// Exponentials per second the device's vector units issue (v_exp_f32 on
+// independent chains, all SIMDs busy); synchronises `st`.  sink: one float
+// of device memory the kernel writes.
+hipError_t probe_exp_rate(float* sink, hipStream_t st, double* per_s);
+
 }  // namespace vq
