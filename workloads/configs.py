@@ -9,6 +9,8 @@ self-attention, Sec. 3.1) at the sizes this project measures:
   large   16x16, d=128, 8 layers, 8 heads, MLP 512,  Q=1024, B=8192, bf16
   multi   6x6..20x20 lattices, d=128, 6 layers, 8 heads, MLP 512, Q=512, bf16
   grad    20x20, d=256, 12 layers, 8 heads, MLP 1024, Q=1024, B=2048, bf16
+  tfim    1-D transverse-field Ising chain of 384 sites (open, Gamma = J = 1),
+          d=256, 1 layer, 8 heads, MLP 1024, 4 x 64 codes, B=2048, bf16
 
 Lattices are periodic with J=1 in the Marshall-rotated basis unless stated.
 """
@@ -34,10 +36,12 @@ class ModelConfig:
     batch: int = 256
     spin_seed: int = 1000
     param_seed: int = 0
+    hamiltonian: str = "heisenberg"   # or "tfim": chain of L sites
+    gamma: float = 1.0                # transverse field of the TFIM
 
     @property
     def N(self) -> int:
-        return self.L * self.L
+        return self.L if self.hamiltonian == "tfim" else self.L * self.L
 
     @property
     def d_head(self) -> int:
@@ -61,6 +65,23 @@ CONFIGS = {
                         d_ff=1024, codebook_size=1024, precision="bf16",
                         batch=2048, spin_seed=1005),
 }
+
+# One-dimensional transverse-field Ising chain at the critical field
+# (Gamma = J = 1, open boundaries): the paper's second workload (Sec. 4,
+# Fig. 2: one block, width 256, 8 heads, a quantizer of 4 heads x 64 codes,
+# up to 384 spins).  Spins are uniformly random (no Sz constraint).
+CONFIGS["tfim"] = ModelConfig("tfim", L=384, d_model=256, n_layers=1,
+                              n_heads=8, d_ff=1024, codebook_size=64,
+                              vq_heads=4, periodic=False, marshall=False,
+                              precision="bf16", batch=2048, spin_seed=1006,
+                              hamiltonian="tfim", gamma=1.0)
+CONFIGS["tfim_small"] = ModelConfig("tfim_small", L=10, d_model=16,
+                                    n_layers=1, n_heads=2, d_ff=64,
+                                    codebook_size=16, vq_heads=2,
+                                    periodic=False, marshall=False,
+                                    precision="f64", batch=64,
+                                    spin_seed=1007, hamiltonian="tfim",
+                                    gamma=1.0)
 
 # Mixed-lattice batch: one parameter buffer per lattice, uneven sample counts.
 MULTI_LATTICE = tuple(

@@ -14,7 +14,16 @@ import numpy as np
 from .layout import param_layout, param_count
 
 
-def make_spins(cfg, batch=None, seed=None, sector_sz0=True):
+def make_spins(cfg, batch=None, seed=None, sector_sz0=None):
+    """Spins [B][N]: Sz = 0 permutations for the Heisenberg workloads,
+    independent uniform +-1 for the transverse-field Ising chain (its
+    Hamiltonian does not conserve Sz)."""
+    if sector_sz0 is None:
+        sector_sz0 = getattr(cfg, "hamiltonian", "heisenberg") != "tfim"
+    return _make_spins(cfg, batch, seed, sector_sz0)
+
+
+def _make_spins(cfg, batch, seed, sector_sz0):
     B = cfg.batch if batch is None else batch
     rng = np.random.default_rng(cfg.spin_seed if seed is None else seed)
     N = cfg.N
