@@ -72,7 +72,10 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
       * C_l = C_{l-1} plus the rows whose code changed; those rows get the
         output projection, residual and MLP again,
     and the head is re-applied to C_L and to the two exchanged sites (whose
-    targets change).  With ``certified`` a row keeps s's code without a
+    targets change).  A model with an attention-only half-block (no
+    quantizer) after the blocks recomputes its LN + QKV on C_L and its
+    attention and output projection on every row from the first changed
+    input, which the head then re-reads.  With ``certified`` a row keeps s's code without a
     codebook search when the change of its attention output is smaller than
     half the gap between its best and second-best code distances (triangle
     inequality), less a small floating-point allowance.
@@ -142,6 +145,29 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
                 C = C_new
                 sizes.append(len(C))
                 codes_sp.append(codes)
+            if "tail" in P:
+                # attention-only half-block: no quantizer, so every row at
+                # or after the first changed input changes; LN + QKV on the
+                # rows of C_L, attention and the output projection on all
+                # rows from p_min
+                T, tc = P["tail"], base["tail"]
+                q, k, v = tc["q"][0].copy(), tc["k"][0].copy(), tc["v"][0].copy()
+                if C:
+                    rows = np.array(C)
+                    qkv = net.qkv_rows(dict(ln1_g=T["ln_g"], ln1_b=T["ln_b"],
+                                            W_qkv=T["W_qkv"],
+                                            b_qkv=T["b_qkv"]),
+                                       np.stack([xo[i] for i in rows]))
+                    q[rows], k[rows], v[rows] = (qkv[:, :d], qkv[:, d:2 * d],
+                                                 qkv[:, 2 * d:])
+                att = np.arange(pmin, N)
+                arows += len(att)
+                a = net.causal_attention(q[att], k, v, cfg.n_heads, rows=att)
+                xin = np.stack([xo[i] if i in xo else tc["x"][0][i]
+                                for i in att])
+                xn = xin + a @ T["W_o"] + T["b_o"]
+                xo = {int(i): xn[j] for j, i in enumerate(att)}
+                C = [int(i) for i in att]
             # Head: rows of C_L get new log-probs; the exchanged sites keep
             # s's hidden state but change target.
             delta = 0.0

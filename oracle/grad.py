@@ -56,6 +56,9 @@ def _unpack(cfg, th):
             b_qkv=take(3 * d), codebook=take(H, Q, d // H),
             W_o=take(d, d), b_o=take(d), ln2_g=take(d), ln2_b=take(d),
             W1=take(d, F), b1=take(F), W2=take(F, d), b2=take(d)))
+    if getattr(cfg, "attn_tail", False):
+        P["tail"] = dict(ln_g=take(d), ln_b=take(d), W_qkv=take(d, 3 * d),
+                         b_qkv=take(3 * d), W_o=take(d, d), b_o=take(d))
     P["lnf_g"] = take(d)
     P["lnf_b"] = take(d)
     P["W_head"] = take(d, 2)
@@ -141,6 +144,12 @@ def _forward(cfg, th, spins, frozen=None):
         xp = x + z @ lay["W_o"] + lay["b_o"]
         hid = _gelu(_ln(xp, lay["ln2_g"], lay["ln2_b"]) @ lay["W1"] + lay["b1"])
         x = xp + hid @ lay["W2"] + lay["b2"]
+    if "tail" in P:
+        T = P["tail"]
+        qkv = _ln(x, T["ln_g"], T["ln_b"]) @ T["W_qkv"] + T["b_qkv"]
+        a = _attention(qkv[..., :d], qkv[..., d:2 * d], qkv[..., 2 * d:],
+                       cfg.n_heads)
+        x = x + a @ T["W_o"] + T["b_o"]
     f = _ln(x, P["lnf_g"], P["lnf_b"])
     lp = torch.log_softmax(f @ P["W_head"] + P["b_head"], dim=-1)
     ell = torch.gather(lp, -1, t[..., None])[..., 0]

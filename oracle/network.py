@@ -16,6 +16,9 @@ project's design notes; each is restated where it is used):
       x' = x + z W_o + b_o      (VQ sits before the output projection and
                                  the residual, Sec. 3.1)
       x  = x' + W2 GELU(LN2(x') W1 + b1) + b2
+* Optionally an attention-only half-block after the blocks (the paper's
+  Table 1 networks end with one, with no quantizer): h = LN(x),
+  [q|k|v] = h W_qkv + b, x = x + MHSA(q, k, v) W_o + b_o.
 * Head: final LN, linear d -> 2, log-softmax; log P(s) = sum_i l_i.
 * Zero phase (Sec. 4, Marshall-rotated Heisenberg), so
   log psi(s) = 1/2 log P(s)  (polar form of Sec. 2).
@@ -51,6 +54,9 @@ def unpack(cfg, theta):
             b_qkv=take(3 * d), codebook=take(H, Q, d // H),
             W_o=take(d, d), b_o=take(d), ln2_g=take(d), ln2_b=take(d),
             W1=take(d, F), b1=take(F), W2=take(F, d), b2=take(d)))
+    if getattr(cfg, "attn_tail", False):
+        P["tail"] = dict(ln_g=take(d), ln_b=take(d), W_qkv=take(d, 3 * d),
+                         b_qkv=take(3 * d), W_o=take(d, d), b_o=take(d))
     P["lnf_g"] = take(d)
     P["lnf_b"] = take(d)
     P["W_head"] = take(d, 2)
@@ -65,7 +71,9 @@ def n_params(cfg):
     d, N, Q, F = cfg.d_model, cfg.N, cfg.codebook_size, cfg.d_ff
     per_layer = (2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d
                  + d * F + F + F * d + d)
-    return 3 * d + N * d + cfg.n_layers * per_layer + 2 * d + 2 * d + 2
+    tail = (2 * d + 3 * d * d + 3 * d + d * d + d
+            if getattr(cfg, "attn_tail", False) else 0)
+    return 3 * d + N * d + cfg.n_layers * per_layer + tail + 2 * d + 2 * d + 2
 
 
 def tokens(spins):
@@ -195,6 +203,16 @@ def post_vq_rows(lay, x, z):
     return xp + hid @ lay["W2"] + lay["b2"]
 
 
+def tail_block(T, x, n_heads):
+    """The attention-only half-block: pre-LN causal self-attention and
+    the output projection with its residual, no quantizer, no MLP."""
+    d = x.shape[-1]
+    qkv = layer_norm(x, T["ln_g"], T["ln_b"]) @ T["W_qkv"] + T["b_qkv"]
+    a = causal_attention(qkv[..., :d], qkv[..., d:2 * d], qkv[..., 2 * d:],
+                         n_heads)
+    return x + a @ T["W_o"] + T["b_o"]
+
+
 def head_logprobs(P, x):
     """Log-probabilities of both classes at every position, [..., 2]."""
     f = layer_norm(x, P["lnf_g"], P["lnf_b"])
@@ -227,12 +245,22 @@ def forward(cfg, P, spins, keep=False):
                                d2=d2))
         x = post_vq_rows(lay, x, z)
         codes.append(c)
+    tail_cache = None
+    if "tail" in P:
+        if keep:
+            T = P["tail"]
+            qkv = qkv_rows(dict(ln1_g=T["ln_g"], ln1_b=T["ln_b"],
+                                W_qkv=T["W_qkv"], b_qkv=T["b_qkv"]), x)
+            tail_cache = dict(x=x, q=qkv[..., :d], k=qkv[..., d:2 * d],
+                              v=qkv[..., 2 * d:])
+        x = tail_block(P["tail"], x, cfg.n_heads)
     lp = head_logprobs(P, x)
     ell = np.take_along_axis(lp, t[..., None], axis=-1)[..., 0]
     out = dict(logpsi=0.5 * ell.sum(axis=-1), ell=ell, lp=lp,
                codes=np.stack(codes) if codes else None, x_final=x)
     if keep:
         out["caches"] = caches
+        out["tail"] = tail_cache
     return out
 
 

@@ -91,6 +91,27 @@ def test_post_quantizer_gradient_is_true_derivative():
         assert abs(fd - g[i]) <= 1e-7 * (1 + abs(fd)), (i, fd, g[i])
 
 
+def test_attention_tail_gradient_is_true_derivative():
+    """The attention-only half-block has no quantizer: its parameters (and
+    the final LayerNorm and head) get the true derivative, checked by
+    central differences of the NumPy forward."""
+    cfg = replace(TINY2, attn_tail=True)
+    th = make_params(cfg)
+    s = make_spins(cfg)[:1]
+    g = og.grad_logpsi(cfg, th, s)[0]
+    idx = _slices(cfg, lambda n: n.startswith("tail.")
+                  or n in ("lnf_g", "lnf_b", "W_head", "b_head"))
+    rng = np.random.default_rng(8)
+    pick = rng.choice(idx, 40, replace=False)
+    f = lambda t: onet.forward(cfg, onet.unpack(cfg, t), s)["logpsi"][0]
+    eps = 1e-6
+    for i in pick:
+        e = np.zeros_like(th)
+        e[i] = eps
+        fd = (f(th + e) - f(th - e)) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-7 * (1 + abs(fd)), (i, fd, g[i])
+
+
 def test_single_codeword_closed_forms():
     cfg = replace(TINY2, codebook_size=1)
     th = make_params(cfg)

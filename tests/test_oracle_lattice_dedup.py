@@ -95,3 +95,16 @@ def test_certified_reuse_fires_on_insensitive_codes():
     info = _check_dedup(cfg, 1, True, alpha=8.0)
     assert sum(info["vq_rows"]) < 0.5 * sum(info["att_rows"])
     assert np.mean([c[-1] for c in info["changed"]]) < 4
+
+
+def test_dedup_with_attention_tail_equals_naive():
+    """The deduplicated evaluation of a model ending with the attention-only
+    half-block (every row from the first changed input recomputed there)
+    equals the naive re-evaluation."""
+    from dataclasses import replace
+    cfg = replace(CONFIGS["small"], attn_tail=True, n_layers=2, batch=6)
+    theta = make_params(cfg)
+    s = make_spins(cfg)
+    E_naive = eloc.eloc_network_naive(cfg, theta, s)
+    E_dedup = eloc.eloc_dedup(cfg, theta, s)
+    assert np.allclose(E_dedup, E_naive, rtol=1e-12, atol=0)

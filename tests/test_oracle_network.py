@@ -164,3 +164,21 @@ def test_head_permutation_invariance():
         lay["W_o"][:] = lay["W_o"][cols].copy()
     lp2 = net.forward(cfg, P2, s)["logpsi"]
     assert np.allclose(lp1, lp2, rtol=0, atol=1e-12)
+
+
+def test_attention_tail_normalisation_and_causality():
+    """A model ending with the attention-only half-block is still a
+    normalised autoregressive distribution, and its conditionals at i do
+    not depend on spins at or after i."""
+    from dataclasses import replace
+    cfg = replace(CONFIGS["small"], attn_tail=True)
+    assert net.n_params(cfg) == param_count(cfg)
+    P = net.unpack(cfg, make_params(cfg, std=0.5))
+    assert "tail" in P
+    lp = net.logpsi_fn(cfg, P, chunk=8192)(all_configs(cfg.N))
+    assert abs(np.exp(2.0 * lp).sum() - 1.0) < 1e-12
+    s = make_spins(cfg, batch=2)
+    base = net.forward(cfg, P, s)["lp"]
+    t = s.copy()
+    t[:, 9:] = -t[:, 9:]
+    assert np.array_equal(net.forward(cfg, P, t)["lp"][:, :10], base[:, :10])

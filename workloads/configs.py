@@ -38,6 +38,8 @@ class ModelConfig:
     param_seed: int = 0
     hamiltonian: str = "heisenberg"   # or "tfim": chain of L sites
     gamma: float = 1.0                # transverse field of the TFIM
+    attn_tail: bool = False           # attention-only half-block after the
+                                      # blocks (no quantizer, no MLP)
 
     @property
     def N(self) -> int:

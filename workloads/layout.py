@@ -8,6 +8,9 @@ Every weight matrix is stored [in][out] and applied as x @ W.  Token ids:
     ln1_g[d] ln1_b[d]  W_qkv[d][3d] b_qkv[3d]  codebook[H][Q][d/H]
     W_o[d][d] b_o[d]   ln2_g[d] ln2_b[d]
     W1[d][d_ff] b1[d_ff]  W2[d_ff][d] b2[d]
+  attention-only half-block (when the model has one):
+    tail.ln_g[d] tail.ln_b[d]  tail.W_qkv[d][3d] tail.b_qkv[3d]
+    tail.W_o[d][d] tail.b_o[d]
   lnf_g[d] lnf_b[d]  W_head[d][2] b_head[2]
 
 Each entry carries a ``kind`` tag used only by the seeded initialiser:
@@ -30,6 +33,11 @@ def param_layout(cfg):
             (p + "W1", (d, F), "w"), (p + "b1", (F,), "bias"),
             (p + "W2", (F, d), "w"), (p + "b2", (d,), "bias"),
         ]
+    if getattr(cfg, "attn_tail", False):
+        ent += [("tail.ln_g", (d,), "gain"), ("tail.ln_b", (d,), "bias"),
+                ("tail.W_qkv", (d, 3 * d), "w"),
+                ("tail.b_qkv", (3 * d,), "bias"),
+                ("tail.W_o", (d, d), "w"), ("tail.b_o", (d,), "bias")]
     ent += [("lnf_g", (d,), "gain"), ("lnf_b", (d,), "bias"),
             ("W_head", (d, 2), "w"), ("b_head", (2,), "bias")]
     out, off = [], 0
