@@ -23,16 +23,15 @@ METRIC = ("local-energy evals/sec, VQ-dedup vs plain on 1 MI355X, at "
 UNIT = "local-energy evals/s"
 PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}     # TFLOP/s, dense
 HBM_PEAK = 8000.0                                         # GB/s
-# Attention at head width 16-32 is bound by the vector unit, not by the
-# algorithmic matrix-core work: every (query, key) pair needs one
-# exponential, and v_exp_f32 issues at half the rate of plain FP32 VALU
-# instructions on gfx950 (8 lanes per SIMD per cycle; a timing probe of
-# independent exponential chains gives 7.47 lane-ops per SIMD-cycle against
-# 14.7 for additions).  256 CUs x 4 SIMDs x 8 x 2.4 GHz = 1.97e13
-# exponentials per second bound the pair rate; the attention peak is that
-# rate times the algorithmic FLOPs of a pair (4 d_head: q.k and p.v).
-EXP_RATE = 256 * 4 * 8 * 2.4e9
+# Attention at head width 16-32 has a second, tighter bound than the matrix
+# core: every (query, key) pair needs one exponential on the vector unit.
+# The bench measures the device's exponential issue rate live
+# (vqnqs_probe_exp_rate: independent v_exp_f32 chains on every SIMD) and
+# reports the attention kernel against it beside the matrix-core roofline;
+# the exponential bound in FLOP/s is that rate times the algorithmic FLOPs
+# of a pair (4 d_head: q.k and p.v).
 TRAFFIC_FILE = "profiles/attention_dedup_16x16_bf16__hbm_traffic.json"
+GOLDEN_FILE = "tests/golden/large_bf16_eloc.json"
 
 
 def flops_model(mc, ctr, base_samples):
@@ -83,6 +82,52 @@ def measured_traffic(kernel, mc, launches_per_call):
     return t.get("bytes_per_launch")
 
 
+def golden_parity(mc, out):
+    """Errors of this run's results against the committed FP64 oracle
+    values of the first samples (tests/golden, written from oracle/ only):
+    every neighbour ratio and local energy of those samples and their mean
+    energy.  None when the file covers another workload."""
+    import numpy as np
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        GOLDEN_FILE)
+    try:
+        with open(path) as f:
+            gold = json.load(f)
+    except (OSError, ValueError):
+        return None
+    w = gold.get("workload", {})
+    if (w.get("L") != mc.L or w.get("d_model") != mc.d_model
+            or w.get("n_layers") != mc.n_layers
+            or w.get("codebook_size") != mc.codebook_size
+            or w.get("spin_seed") != mc.spin_seed
+            or w.get("param_seed") != mc.param_seed
+            or w.get("precision") != mc.precision):
+        return None
+    G = gold["samples"]
+    n = len(G)
+    E = out["eloc"][:n].cpu().numpy()
+    R = out["ratios"][:n].cpu().numpy()
+    rel = np.concatenate([np.abs(R[b, :len(g["ratios"])]
+                                 / np.asarray(g["ratios"]) - 1.0)
+                          for b, g in enumerate(G)])
+    E_o = np.array([g["eloc"] for g in G])
+    per = np.abs(E - E_o) / np.abs(E_o)
+    return {
+        "samples": n, "ratios": int(rel.size),
+        "ratio_rel_err": {"median": float(np.median(rel)),
+                          "p99": float(np.quantile(rel, 0.99)),
+                          "max": float(rel.max()),
+                          "n_above_1e-3": int((rel > 1e-3).sum())},
+        "eloc_rel_err": {"median": float(np.median(per)),
+                         "max": float(per.max()),
+                         "n_above_1e-3": int((per > 1e-3).sum())},
+        "mean_energy_rel_err": float(abs(E.mean() - E_o.mean())
+                                     / abs(E_o.mean())),
+        "note": "raw comparison; entries beyond 1e-3 are checked as "
+                "quantizer near-ties by tests/test_gpu_large_golden.py",
+    }
+
+
 def counters_dict(vq, arr, nl):
     out = {k: int(arr[v]) for k, v in vq.CTR.items() if k != "changed0"}
     out["changed"] = [int(arr[vq.CTR["changed0"] + l]) for l in range(nl + 1)]
@@ -97,16 +142,20 @@ def cpu_baseline(mc, theta, spins, gpu_ratios, n_nb0, budget_s):
     import numpy as np
     from oracle import lattice
     from oracle import network as onet
+    from oracle import tfim
     P = onet.unpack(mc, theta)
-    bl = lattice.bonds(mc.L, mc.periodic)
-    nb = lattice.neighbours(spins[0], bl)
-    seqs = [spins[0]]
+    if mc.hamiltonian == "tfim":
+        nbs = [tfim.flip(spins[0], i) for i in range(mc.N)]
+    else:
+        bl = lattice.bonds(mc.L, mc.periodic)
+        nbs = [lattice.swap(spins[0], p1, p2)
+               for _, p1, p2 in lattice.neighbours(spins[0], bl)]
     t0 = time.perf_counter()
     lp0 = onet.forward(mc, P, spins[0:1])["logpsi"][0]
     per = time.perf_counter() - t0
-    k = int(max(4, min(len(nb), budget_s / max(per, 1e-3))))
+    k = int(max(4, min(len(nbs), budget_s / max(per, 1e-3))))
     t0 = time.perf_counter()
-    sub = np.stack([lattice.swap(spins[0], p1, p2) for _, p1, p2 in nb[:k]])
+    sub = np.stack(nbs[:k])
     lps = onet.logpsi_fn(mc, P, chunk=32)(sub)
     dt = time.perf_counter() - t0 + per
     r_ref = np.exp(lps - lp0)
@@ -132,7 +181,7 @@ def cpu_baseline(mc, theta, spins, gpu_ratios, n_nb0, budget_s):
         pass
     return {"value": rate, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": (f"sample 0 of the batch: log psi of the sample and of "
-                       f"its first {k} of {len(nb)} exchange neighbours, "
+                       f"its first {k} of {len(nbs)} neighbours, "
                        f"NumPy float64, {dt:.1f} s; rate scaled by "
                        f"1 + n_neighbours evaluations per local energy")
             }, err
@@ -199,7 +248,7 @@ def bench_grad(args, vq, torch, np, mc, make_params, make_spins):
         avg = prof[dom][0] / launches
         ach = per_launch / (avg / 1e3) / 1e12
         if dom == "grad_attention":
-            bound, peak = "alu", 4.0 * mc.d_head * EXP_RATE / 1e12
+            bound, peak = "alu", PEAK["fp32"]
         else:
             # FP32-accurate products (three bf16 matrix-core passes): the
             # FP32 dense matrix peak
@@ -244,14 +293,19 @@ def bench_grad(args, vq, torch, np, mc, make_params, make_spins):
     print(json.dumps(res))
 
 
-def bench_multi(args, vq, torch, np, make_params, make_spins):
+def bench_multi(args, vq, torch, np, make_params, make_spins, with_batch):
     """Mixed-lattice batch (6x6 .. 20x20, one model each, 512 .. 8192
     samples): one vqnqs_local_energy_multi call per step, replayed as a
     captured graph, against one vqnqs_local_energy call per lattice."""
     from workloads import MULTI_LATTICE
     dev = torch.device("cuda:0")
     jobs = []
-    for mc in MULTI_LATTICE:
+    mix = MULTI_LATTICE
+    if args.batch:
+        # the same lattices and models with this many samples each: a mix in
+        # which no single lattice fills the device
+        mix = [with_batch(mc, args.batch) for mc in MULTI_LATTICE]
+    for mc in mix:
         jobs.append((vq.make_config(mc),
                      torch.tensor(make_params(mc), dtype=torch.float32,
                                   device=dev),
@@ -264,7 +318,12 @@ def bench_multi(args, vq, torch, np, make_params, make_spins):
     cfg16, p16, s16 = jobs[3]
     tune_ws = torch.empty(vq.workspace_size(cfg16, 512, vq.DEDUP, 0)
                           + 8 * 512 + 256, dtype=torch.uint8, device=dev)
-    choices = vq.autotune(cfg16, p16, s16[:512], ws=tune_ws)
+    if args.tuning_cache:
+        from paper_2212_11296_amd import tuning
+        choices, _ = tuning.autotune_cached(cfg16, p16, s16[:512],
+                                            args.tuning_cache, ws=tune_ws)
+    else:
+        choices = vq.autotune(cfg16, p16, s16[:512], ws=tune_ws)
     del tune_ws
     stream = torch.cuda.current_stream()
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -309,7 +368,9 @@ def bench_multi(args, vq, torch, np, make_params, make_spins):
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "lattices 6x6/8x8/12x12/16x16/20x20 with "
-                               "512/1024/2048/4096/8192 seeded Sz=0 samples, "
+                               + ("/".join(str(int(j[2].shape[0]))
+                                           for j in jobs))
+                               + " seeded Sz=0 samples, "
                                "one VQ transformer each (d=128, 6 layers, "
                                "8 heads, MLP 512, Q=512), dedup local energy",
                    "samples": total, "flags": flags},
@@ -326,6 +387,138 @@ def bench_multi(args, vq, torch, np, make_params, make_spins):
     print(json.dumps(res))
 
 
+def bench_sample(args, vq, torch, np, mc, make_params):
+    """Direct autoregressive sampling (chain rule) of the whole batch of
+    the workload, uniform numbers resident in HBM; one JSON line."""
+    B, N = mc.batch, mc.N
+    dev = torch.device("cuda:0")
+    theta = make_params(mc)
+    dt_param = torch.float64 if mc.precision == "f64" else torch.float32
+    p = torch.tensor(theta, dtype=dt_param, device=dev)
+    cfg = vq.make_config(mc)
+    u = torch.rand((B, N), dtype=torch.float64,
+                   generator=torch.Generator().manual_seed(5)).to(dev)
+    need = vq.workspace_size(cfg, B, vq.WS_SAMPLE, 0)
+    ws = torch.empty(min(need, int(args.ws_gb * (1 << 30))),
+                     dtype=torch.uint8, device=dev)
+    out = {"spins": torch.empty((B, N), dtype=torch.int8, device=dev),
+           "logpsi": torch.empty(B, dtype=torch.float64, device=dev)}
+    for _ in range(args.warmup):
+        vq.sample(cfg, p, u, ws=ws, check=False, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    vq.profile_reset()
+    vq.profile_enable(True)
+    e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    e0.record(stream)
+    for _ in range(args.steps):
+        vq.sample(cfg, p, u, ws=ws, check=False, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    vq.profile_enable(False)
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = vq.profile_read()
+    vq.api._check_status(ws)
+    per_kernel = {k: {"ms_per_step": v[0] / args.steps,
+                      "launches_per_step": v[1] / args.steps}
+                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    # the forward FLOPs of every drawn sequence (2 FLOP per multiply-add)
+    d, F, Q = mc.d_model, mc.d_ff, mc.codebook_size
+    fwd = B * mc.n_layers * ((6 * d * d + 4 * d * F + 2 * Q * d + 2 * d * d)
+                             * N + 2 * N * (N + 1) * d)
+    print(json.dumps({
+        "metric": "direct autoregressive samples/sec (chain rule), 1 MI355X",
+        "value": B / (ms / 1e3), "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": mc.precision, "data": "synthetic",
+        "config": {"workload": f"{mc.L}x{mc.L}, VQ transformer "
+                               f"d={mc.d_model} L={mc.n_layers} "
+                               f"heads={mc.n_heads} mlp={mc.d_ff} "
+                               f"Q={mc.codebook_size}, {B} samples",
+                   "batch": B},
+        "algorithmic_tflop_per_step": fwd / 1e12,
+        "achieved_tflops": fwd / (ms / 1e3) / 1e12,
+        "mean_logpsi": float(out["logpsi"].mean().item()),
+        "kernels": per_kernel}))
+
+
+def bench_sweep(args, vq, torch, np, mc, make_params, make_spins):
+    """Redundancy sweep: every codebook scaled by alpha (a larger codebook
+    scale makes the codes less sensitive to a changed input), dedup with and
+    without certified code reuse against plain, on the same spins.  Reports
+    the changed rows per layer, the certified fraction and the speed-up per
+    alpha; one JSON line."""
+    from workloads import scale_codebooks
+    B = mc.batch
+    dev = torch.device("cuda:0")
+    theta = make_params(mc)
+    spins = make_spins(mc)
+    sp = torch.tensor(spins, device=dev)
+    ws_cap = int(args.ws_gb * (1 << 30))
+    out = {"eloc": torch.empty(B, dtype=torch.float64, device=dev),
+           "counters": torch.empty(vq.NCOUNTERS, dtype=torch.int64,
+                                   device=dev)}
+    cfg0 = vq.make_config(mc)
+    need = max(vq.workspace_size(cfg0, B, vq.DEDUP, 0),
+               vq.workspace_size(cfg0, B, vq.PLAIN, 0))
+    ws = torch.empty(min(need, ws_cap), dtype=torch.uint8, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    p1 = torch.tensor(theta, dtype=torch.float32, device=dev)
+    if not args.no_autotune:
+        vq.autotune(cfg0, p1, sp[:min(B, 512)], vq.DEDUP, ws=ws)
+
+    def timed(cfg, p, mode):
+        vq.local_energy(cfg, p, sp, mode, stats=False, counters=True, ws=ws,
+                        check=False, out=out)
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(stream)
+        for _ in range(args.steps):
+            vq.local_energy(cfg, p, sp, mode, stats=False, counters=True,
+                            ws=ws, check=False, out=out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return (a.elapsed_time(b) / args.steps,
+                counters_dict(vq, out["counters"].cpu().numpy(),
+                              mc.n_layers))
+
+    rows = []
+    for alpha in (0.5, 1.0, 2.0, 4.0, 8.0):
+        p = torch.tensor(scale_codebooks(mc, theta, alpha),
+                         dtype=torch.float32, device=dev)
+        ms_p, _ = timed(vq.make_config(mc), p, vq.PLAIN)
+        entry = {"alpha": alpha, "plain_ms": ms_p,
+                 "plain_evals_per_s": B / (ms_p / 1e3)}
+        for flags in (0, vq.FLAG_CERTIFIED_VQ):
+            ms, ctr = timed(vq.make_config(mc, flags=flags), p, vq.DEDUP)
+            nb = max(ctr["neighbours"], 1)
+            searched = ctr["vq_rows"] + ctr["vq_certified"]
+            entry[f"dedup_flags{flags}"] = {
+                "ms": ms, "evals_per_s": B / (ms / 1e3),
+                "speedup_vs_plain": ms_p / ms,
+                "changed_rows_per_neighbour": [c / nb for c in ctr["changed"]],
+                "certified_fraction": (ctr["vq_certified"] / searched
+                                       if searched else 0.0)}
+        entry["u_over_N_last_layer"] = (
+            entry["dedup_flags0"]["changed_rows_per_neighbour"][-1] / mc.N)
+        rows.append(entry)
+        print(f"sweep alpha={alpha}: plain {ms_p:.0f} ms, dedup "
+              f"{entry['dedup_flags0']['ms']:.0f} ms", file=sys.stderr,
+              flush=True)
+        del p
+    print(json.dumps({
+        "metric": "redundancy sweep: dedup vs plain local-energy evals/sec "
+                  "against the codebook scale alpha, 1 MI355X",
+        "config": {"workload": f"{mc.L}x{mc.L} periodic Heisenberg, "
+                               f"d={mc.d_model} L={mc.n_layers} "
+                               f"Q={mc.codebook_size}, {B} seeded Sz=0 "
+                               "samples, codebooks scaled by alpha",
+                   "batch": B, "steps": args.steps},
+        "dtype": mc.precision, "data": "synthetic", "sweep": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,10 +526,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="large")
     ap.add_argument("--workload", default="eloc",
-                    choices=["eloc", "grad", "multi"],
+                    choices=["eloc", "grad", "multi", "sweep", "sample"],
                     help="eloc: local energy (default); grad: weighted "
                          "straight-through gradient of the 20x20 workload; "
-                         "multi: mixed-lattice batch in one call")
+                         "multi: mixed-lattice batch in one call; sweep: "
+                         "codebook-scale redundancy sweep; sample: direct "
+                         "autoregressive sampling")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--flags", type=int, default=0,
@@ -350,6 +545,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of timing "
                          "the variants on the first 512 samples")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON file of launch choices: read them from it "
+                         "when present for this device and model width, "
+                         "else time them and store them there")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB "
                          "once (a kernel of known traffic that calibrates "
@@ -370,7 +569,7 @@ def main():
     from workloads import config_by_name, make_params, make_spins, with_batch
 
     if args.workload == "multi":
-        bench_multi(args, vq, torch, np, make_params, make_spins)
+        bench_multi(args, vq, torch, np, make_params, make_spins, with_batch)
         return
     if args.workload == "grad":
         mc = config_by_name("grad")
@@ -381,6 +580,12 @@ def main():
     mc = config_by_name(args.config)
     if args.batch:
         mc = with_batch(mc, args.batch)
+    if args.workload == "sweep":
+        bench_sweep(args, vq, torch, np, mc, make_params, make_spins)
+        return
+    if args.workload == "sample":
+        bench_sample(args, vq, torch, np, mc, make_params)
+        return
     B = mc.batch
     dev = torch.device("cuda:0")
     theta = make_params(mc)
@@ -403,10 +608,18 @@ def main():
         vq.local_energy(cfg, p, sp, mode, ratios=True, counters=True, ws=w,
                         check=False, out=out)
 
+    exp_rate = None
+    if mc.precision == "bf16":
+        exp_rate = vq.probe_exp_rate()
     choices = None
     if not args.no_autotune:
         nt = min(B, 512)
-        choices = vq.autotune(cfg, p, sp[:nt], vq.DEDUP, ws=ws)
+        if args.tuning_cache:
+            from paper_2212_11296_amd import tuning
+            choices, _ = tuning.autotune_cached(cfg, p, sp[:nt],
+                                                args.tuning_cache, ws=ws)
+        else:
+            choices = vq.autotune(cfg, p, sp[:nt], vq.DEDUP, ws=ws)
 
     if args.copy_probe_mib > 0:
         n_el = args.copy_probe_mib << 18
@@ -436,6 +649,7 @@ def main():
     ctr_d = counters_dict(vq, out["counters"].cpu().numpy(), mc.n_layers)
     stats = out["stats"].cpu().numpy().tolist()
     ratios0 = out["ratios"][0].cpu().numpy()
+    parity = golden_parity(mc, out)
     vq.load_library()
     st = vq.api._check_status(ws)
     value = B / (ms / 1000.0)
@@ -447,23 +661,35 @@ def main():
     dom = next(iter(per_kernel))
     dom_total_ms = prof[dom][0]
     dom_launches = prof[dom][1]
+    mpeak = PEAK["bf16"] if mc.precision == "bf16" else PEAK["fp32"]
     if dom in flops and dom_total_ms > 0:
         flop_per_launch = flops[dom] * args.steps / dom_launches
         avg_ms = dom_total_ms / dom_launches
         achieved = flop_per_launch / (avg_ms / 1e3) / 1e12
-        if dom.startswith("attention"):
-            bound, peak = "alu", 4.0 * mc.d_head * EXP_RATE / 1e12
-        else:
-            bound, peak = "mfma", PEAK["bf16"]
-        roof = {"bound": bound, "kernel": dom, "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+        roof = {"bound": "mfma", "kernel": dom, "achieved": achieved,
+                "peak": mpeak, "unit": "TFLOP/s", "frac": achieved / mpeak,
                 "traffic": measured_traffic(dom, mc,
                                             round(dom_launches / args.steps)),
                 "flop_per_launch": flop_per_launch,
-                "avg_launch_ms": avg_ms}
+                "avg_launch_ms": avg_ms,
+                "launches_per_step": dom_launches / args.steps}
+        if dom.startswith("attention") and exp_rate:
+            pk = 4.0 * mc.d_head * exp_rate / 1e12
+            roof["exp_bound"] = {
+                "exps_per_s": exp_rate, "peak": pk, "unit": "TFLOP/s",
+                "frac": achieved / pk,
+                "what": "one exponential per (query, key) pair at the "
+                        "measured v_exp_f32 issue rate"}
     else:
         roof = {"bound": None, "kernel": dom, "achieved": None, "peak": None,
                 "unit": None, "frac": None, "traffic": None}
+    # matrix-core phases: algorithmic FLOP/s against the dense peak
+    util = {}
+    for k in ("qkv", "mlp", "vq"):
+        if k in prof and prof[k][0] > 0:
+            ach = flops[k] * args.steps / (prof[k][0] / 1e3) / 1e12
+            util[k] = {"achieved": ach, "frac": ach / mpeak,
+                       "ms_per_step": prof[k][0] / args.steps}
 
     plain = None
     if not args.no_plain and args.plain_steps > 0:
@@ -500,15 +726,25 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": mc.precision, "data": "synthetic",
-        "config": {"workload": (f"{mc.L}x{mc.L} periodic Heisenberg, VQ "
-                                f"transformer d={mc.d_model} L={mc.n_layers} "
-                                f"heads={mc.n_heads} mlp={mc.d_ff} "
-                                f"Q={mc.codebook_size}, {B} seeded Sz=0 "
-                                f"samples, dedup local energy"),
+        "config": {"workload": (
+                       (f"{mc.N}-site {'periodic' if mc.periodic else 'open'} "
+                        f"transverse-field Ising chain (Gamma={mc.gamma})"
+                        if mc.hamiltonian == "tfim" else
+                        f"{mc.L}x{mc.L} "
+                        f"{'periodic' if mc.periodic else 'open'} Heisenberg")
+                       + f", VQ transformer d={mc.d_model} L={mc.n_layers}"
+                       + (" + attention-only half-block" if mc.attn_tail
+                          else "") + " "
+                       f"heads={mc.n_heads} mlp={mc.d_ff} "
+                       f"Q={mc.codebook_size}x{mc.vq_heads}, {B} seeded "
+                       + ("uniform" if mc.hamiltonian == "tfim" else "Sz=0")
+                       + " samples, dedup local energy"),
                    "L": mc.L, "batch": B, "mode": "dedup",
                    "flags": args.flags, "precision": mc.precision},
         "roofline": roof,
+        "mfma_utilisation": util,
         "cpu_baseline": cpu,
+        "oracle_parity": parity,
         "plain": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
         "algorithmic_tflop_per_step": sum(flops.values()) / 1e12,

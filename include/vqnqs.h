@@ -37,6 +37,8 @@
  *     per layer: ln1_g[d] ln1_b[d] W_qkv[d][3d] b_qkv[3d]
  *                codebook[H][Q][d/H] W_o[d][d] b_o[d] ln2_g[d] ln2_b[d]
  *                W1[d][d_ff] b1[d_ff] W2[d_ff][d] b2[d]
+ *     with attn_tail = 1, the half-block: tail_ln_g[d] tail_ln_b[d]
+ *         tail_W_qkv[d][3d] tail_b_qkv[3d] tail_W_o[d][d] tail_b_o[d]
  *     lnf_g[d] lnf_b[d] W_head[d][2] b_head[2]
  * The element type is double for VQNQS_F64 and float otherwise (FP32
  * master copy; the BF16 mode converts to bfloat16 inside the workspace).
@@ -45,8 +47,13 @@
  * previous spin's token (beginning-of-sequence at i = 0); pre-LayerNorm
  * blocks  h = LN1(x), [q|k|v] = h W_qkv + b, a = causal MHSA(q,k,v),
  * z = VQ(a) (nearest codeword per quantizer head, lowest index on ties),
- * x' = x + z W_o + b_o, x = x' + W2 GELU(LN2(x') W1 + b1) + b2;  final LN,
- * head d->2, log-softmax;  log psi(s) = 1/2 sum_i log P(s_i | s_<i).
+ * x' = x + z W_o + b_o, x = x' + W2 GELU(LN2(x') W1 + b1) + b2;  with
+ * attn_tail = 1 an attention-only half-block follows (the networks of the
+ * paper's Table 1 end with one; no quantizer, no MLP):
+ * x = x + MHSA(LN(x) W_qkv + b) W_o + b_o;  final LN, head d->2,
+ * log-softmax;  log psi(s) = 1/2 sum_i log P(s_i | s_<i).  In the dedup
+ * form every row from the first changed input passes the half-block's
+ * output projection.
  *
  * Workspace: a DEVICE buffer of ws_bytes bytes, 256-byte aligned.  The call
  * processes the batch in chunks of as many samples as fit; the minimum that
@@ -81,6 +88,17 @@ typedef enum {
 
 typedef enum { VQNQS_F64 = 0, VQNQS_F32 = 1, VQNQS_BF16 = 2 } vqnqs_precision;
 
+/* The two models of Sec. 4.  VQNQS_HEISENBERG_2D: H = J sum_<ij> S_i . S_j
+ * on the L x L square lattice (N = L*L sites, neighbours = exchanges of
+ * anti-aligned bonds, as described above).  VQNQS_TFIM_1D: the transverse-
+ * field Ising chain H = -J sum_<ij> Z_i Z_j - Gamma sum_i X_i (Pauli
+ * matrices) of N = L sites, bonds (i, i+1) and, periodic, (N-1, 0); the
+ * neighbours of s are its N single-spin flips (k-local rows with k = 1,
+ * Sec. 2) with element -Gamma, E_loc(s) = -J sum_<ij> s_i s_j
+ * - Gamma sum_i psi(s^(i))/psi(s); marshall must be 0.  For the chain the
+ * neighbour "bond" lists of vqnqs_neighbours hold the flipped sites. */
+typedef enum { VQNQS_HEISENBERG_2D = 0, VQNQS_TFIM_1D = 1 } vqnqs_hamiltonian;
+
 /* PLAIN re-evaluates psi from scratch on every neighbour (the definition of
  * eq. 2).  DEDUP reuses the sample's own evaluation and recomputes the
  * per-location operations only on rows whose input or VQ code differs
@@ -94,8 +112,27 @@ typedef enum { VQNQS_PLAIN = 0, VQNQS_DEDUP = 1 } vqnqs_mode;
  * with a floating-point allowance).  Results are unchanged by this flag. */
 #define VQNQS_FLAG_CERTIFIED_VQ 1
 
+/* flags (DEDUP only): the attention of the first layers by a rank-|C|
+ * update of the sample's softmax instead of the dense overlay attention
+ * (Sec. 3.2 names attention as the part that stays dense).  A query row
+ * whose own input is unchanged sees the sample's keys except at the rows
+ * C whose inputs changed, so its numerator and normaliser are the sample's
+ * (kept by the sample's forward pass) with the terms of C replaced: cost
+ * O(|C|) per row instead of O(i).  Changed query rows, and rows where the
+ * removed weight exceeds half the normaliser (cancellation), are
+ * evaluated in full.  VQNQS_INC_LAYERS(n) in the flags sets how many
+ * leading layers use it (1..255; 0 means 2); deeper layers, whose changed
+ * sets are larger, keep the dense attention.  Results agree with the dense
+ * form to the rounding of the update; they are not bitwise equal to it.
+ * FP64 and FP32 modes only (VQNQS_ERR_UNSUPPORTED in the BF16 mode, whose
+ * matrix-core dense attention is faster than this vector-unit update). */
+#define VQNQS_FLAG_INCREMENTAL_ATTN 2
+#define VQNQS_INC_LAYERS(n) (((n) & 255) << 8)
+#define VQNQS_INC_LAYERS_OF(flags) (((flags) >> 8) & 255)
+
 typedef struct {
-    int32_t L;             /* lattice side, N = L*L sites (3 <= L when periodic) */
+    int32_t L;             /* lattice side, N = L*L sites (3 <= L when periodic);
+                              chain length N = L for VQNQS_TFIM_1D            */
     int32_t periodic;      /* 1 periodic, 0 open boundaries                      */
     int32_t marshall;      /* 1: off-diagonal -J/2 (needs a bipartite lattice)   */
     double  J;             /* exchange coupling                                  */
@@ -107,6 +144,9 @@ typedef struct {
     int32_t vq_heads;      /* H quantizer heads; d_model % vq_heads == 0         */
     int32_t precision;     /* vqnqs_precision                                    */
     int32_t flags;         /* VQNQS_FLAG_*                                       */
+    int32_t hamiltonian;   /* vqnqs_hamiltonian                                  */
+    double  gamma;         /* transverse field Gamma (VQNQS_TFIM_1D)             */
+    int32_t attn_tail;     /* 1: an attention-only half-block ends the model     */
 } vqnqs_config;
 
 /* Counters written by vqnqs_local_energy (int64, VQNQS_NCOUNTERS entries,
@@ -122,6 +162,7 @@ enum {
     VQNQS_CTR_QKV_ROWS = 6,     /* rows through LN1 + QKV projection        */
     VQNQS_CTR_MLP_ROWS = 7,     /* rows through out-projection + MLP        */
     VQNQS_CTR_HEAD_ROWS = 8,    /* rows through the output head             */
+    VQNQS_CTR_TAIL_ROWS = 9,    /* rows through the half-block's projection */
     VQNQS_CTR_CHANGED0 = 16     /* [16 + l] = sum over neighbours of |C_l|,
                                    l = 0 (changed inputs) .. n_layers       */
 };

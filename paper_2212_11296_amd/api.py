@@ -9,8 +9,11 @@ PLAIN, DEDUP = 0, 1
 FLAG_CERTIFIED_VQ = 1
 NCOUNTERS = 96
 CTR = dict(samples=0, neighbours=1, attn_rows=2, attn_pairs=3, vq_rows=4,
-           vq_certified=5, qkv_rows=6, mlp_rows=7, head_rows=8, changed0=16)
+           vq_certified=5, qkv_rows=6, mlp_rows=7, head_rows=8, tail_rows=9,
+           changed0=16)
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16}
+HEISENBERG_2D, TFIM_1D = 0, 1
+_HAM = {"heisenberg": HEISENBERG_2D, "tfim": TFIM_1D}
 _STATUS = {0: "ok", 1: "null pointer", 2: "invalid config", 3: "invalid shape",
            4: "workspace too small", 5: "unsupported configuration",
            6: "spin value other than +1/-1", 7: "HIP runtime error",
@@ -41,7 +44,9 @@ class Config(ctypes.Structure):
                 ("d_model", ctypes.c_int32), ("n_layers", ctypes.c_int32),
                 ("n_heads", ctypes.c_int32), ("d_ff", ctypes.c_int32),
                 ("codebook_size", ctypes.c_int32), ("vq_heads", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("hamiltonian", ctypes.c_int32), ("gamma", ctypes.c_double),
+                ("attn_tail", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -51,13 +56,22 @@ class Job(ctypes.Structure):
                 ("ratios", ctypes.c_void_p), ("counters", ctypes.c_void_p)]
 
 
+def n_sites(cfg):
+    """Sites N of a config: L*L on the square lattice, L on the chain."""
+    return cfg.L if cfg.hamiltonian == TFIM_1D else cfg.L * cfg.L
+
+
 def make_config(mc, precision=None, flags=0):
     """Config from any object with the workload fields (L, d_model, ...)."""
     prec = mc.precision if precision is None else precision
     prec = _PREC.get(prec, prec)
+    ham = getattr(mc, "hamiltonian", "heisenberg")
+    ham = _HAM.get(ham, ham)
     return Config(mc.L, int(mc.periodic), int(mc.marshall), float(mc.J),
                   mc.d_model, mc.n_layers, mc.n_heads, mc.d_ff,
-                  mc.codebook_size, mc.vq_heads, int(prec), int(flags))
+                  mc.codebook_size, mc.vq_heads, int(prec), int(flags),
+                  int(ham), float(getattr(mc, "gamma", 0.0)),
+                  int(bool(getattr(mc, "attn_tail", False))))
 
 
 _lib = None
@@ -219,7 +233,7 @@ def _check_status(ws):
 def neighbours(cfg, spins, ws=None, check=True):
     import torch
     B = spins.shape[0]
-    N = cfg.L * cfg.L
+    N = n_sites(cfg)
     ws = _workspace(cfg, B, -1, ws, 1 << 20)
     bonds = torch.empty((B, 2 * N), dtype=torch.int16, device="cuda")
     count = torch.empty(B, dtype=torch.int32, device="cuda")
@@ -236,7 +250,7 @@ def forward_logpsi(cfg, params, spins, codes=False, ws=None,
                    budget=8 << 30, check=True):
     import torch
     B = spins.shape[0]
-    N = cfg.L * cfg.L
+    N = n_sites(cfg)
     ws = _workspace(cfg, B, -1, ws, budget)
     lp = torch.empty(B, dtype=torch.float64, device="cuda")
     cd = (torch.empty((B, cfg.n_layers, N, cfg.vq_heads), dtype=torch.int32,
@@ -255,7 +269,7 @@ def forward_activations(cfg, params, spins, ws=None, budget=8 << 30,
     output [B][n_layers][N][d] (float64 in the F64 mode, else float32)."""
     import torch
     B = spins.shape[0]
-    N = cfg.L * cfg.L
+    N = n_sites(cfg)
     ws = _workspace(cfg, B, -1, ws, budget)
     lp = torch.empty(B, dtype=torch.float64, device="cuda")
     cd = torch.empty((B, cfg.n_layers, N, cfg.vq_heads), dtype=torch.int32,
@@ -279,7 +293,7 @@ def local_energy(cfg, params, spins, mode=DEDUP, stats=True, ratios=False,
     (mean, variance), ratios [B][2N], counters [NCOUNTERS]."""
     import torch
     B = spins.shape[0]
-    N = cfg.L * cfg.L
+    N = n_sites(cfg)
     ws = _workspace(cfg, B, mode, ws, budget)
     o = out if out is not None else {}
     if "eloc" not in o:
@@ -309,7 +323,7 @@ def local_energy_static(cfg, params, spins, mode=DEDUP, stats=True,
     status word."""
     import torch
     B = spins.shape[0]
-    N = cfg.L * cfg.L
+    N = n_sites(cfg)
     o = out if out is not None else {}
     if "eloc" not in o:
         o["eloc"] = torch.empty(B, dtype=torch.float64, device="cuda")
@@ -340,7 +354,7 @@ def sample(cfg, params, uniforms, ws=None, budget=8 << 30, check=True,
     log psi float64 [B])."""
     import torch
     B, N = uniforms.shape
-    assert N == cfg.L * cfg.L and uniforms.dtype == torch.float64
+    assert N == n_sites(cfg) and uniforms.dtype == torch.float64
     ws = _workspace(cfg, B, WS_SAMPLE, ws, budget)
     o = out if out is not None else {}
     if "spins" not in o:
@@ -364,7 +378,7 @@ def vmc_step(cfg, params, uniforms, lr, opt_state=None, step=1, ws=None,
     Returns a dict with spins [B][N], eloc [B] and stats [2] of the step."""
     import torch
     B, N = uniforms.shape
-    assert N == cfg.L * cfg.L and uniforms.dtype == torch.float64
+    assert N == n_sites(cfg) and uniforms.dtype == torch.float64
     if ws is None:
         need = workspace_size(cfg, B, WS_VMC, 0)
         if need > budget:
@@ -482,7 +496,7 @@ def local_energy_multi(jobs, mode=DEDUP, flags=MULTI_CONCURRENT | MULTI_GRAPH,
     if outs is None:
         outs = []
         for cfg, params, spins in jobs:
-            B, N = spins.shape[0], cfg.L * cfg.L
+            B, N = spins.shape[0], n_sites(cfg)
             o = {"eloc": torch.empty(B, dtype=torch.float64, device="cuda")}
             if stats:
                 o["stats"] = torch.empty(2, dtype=torch.float64, device="cuda")

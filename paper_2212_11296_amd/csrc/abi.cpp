@@ -15,25 +15,32 @@ bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
         return false;
     }
     *err = VQNQS_ERR_INVALID_CONFIG;
-    if (c->L < 1 || c->L > 32) return false;
+    if (c->hamiltonian != VQNQS_HEISENBERG_2D && c->hamiltonian != VQNQS_TFIM_1D)
+        return false;
+    const bool chain = c->hamiltonian == VQNQS_TFIM_1D;
+    if (c->L < (chain ? 2 : 1) || c->L > (chain ? 1024 : 32)) return false;
     if (c->periodic != 0 && c->periodic != 1) return false;
     if (c->marshall != 0 && c->marshall != 1) return false;
     if (c->periodic && c->L < 3) return false;              // repeated bonds
     if (c->periodic && c->marshall && (c->L & 1)) return false;  // not bipartite
+    if (chain && (c->marshall || !std::isfinite(c->gamma))) return false;
+    if (c->attn_tail != 0 && c->attn_tail != 1) return false;
     if (!std::isfinite(c->J)) return false;
     if (c->d_model < 1 || c->n_layers < 0 || c->n_heads < 1 || c->d_ff < 1 ||
         c->codebook_size < 1 || c->vq_heads < 1)
         return false;
     if (c->d_model % c->n_heads || c->d_model % c->vq_heads) return false;
     if (c->precision < VQNQS_F64 || c->precision > VQNQS_BF16) return false;
-    if (c->flags & ~VQNQS_FLAG_CERTIFIED_VQ) return false;
+    if (c->flags & ~(VQNQS_FLAG_CERTIFIED_VQ | VQNQS_FLAG_INCREMENTAL_ATTN |
+                     VQNQS_INC_LAYERS(255)))
+        return false;
     *err = VQNQS_ERR_UNSUPPORTED;
     const int dh = c->d_model / c->n_heads;
     if (dh != 4 && dh != 8 && dh != 16 && dh != 32 && dh != 64) return false;
     if (c->d_model > 512 || c->d_ff > 4096 || c->n_layers > VQNQS_NCOUNTERS - 17 ||
         c->codebook_size > 65536)
         return false;
-    const int N = c->L * c->L;
+    const int N = chain ? c->L : c->L * c->L;
     const size_t act = c->precision == VQNQS_F64 ? 8 : 4;
     if (2 * (size_t)N * dh * act > 128 * 1024) return false;  // attention K/V in LDS
     m->L = c->L;
@@ -51,6 +58,9 @@ bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
     m->precision = c->precision;
     m->flags = c->flags;
     m->J = c->J;
+    m->chain = chain ? 1 : 0;
+    m->tail = c->attn_tail;
+    m->gamma = chain ? c->gamma : 0.0;
     m->mfma = 0;
     m->mfma = c->precision == VQNQS_BF16 && vq::mfma_shapes_ok(*m);
     *err = VQNQS_OK;

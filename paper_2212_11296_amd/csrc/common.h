@@ -123,7 +123,10 @@ struct ModelDims {
     int L, N, d, nl, nh, dh, dff, Q, H, dseg;
     int periodic, marshall, precision, flags;
     int mfma;      // BF16 products on the matrix core (split activations)
+    int chain;     // 1: transverse-field Ising chain of N = L sites
+    int tail;      // 1: an attention-only half-block ends the model
     double J;
+    double gamma;  // transverse field (chain only)
 };
 
 // Per-layer view of the parameters handed to kernels (by value).

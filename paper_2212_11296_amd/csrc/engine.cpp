@@ -22,6 +22,8 @@ int64_t param_count(const ModelDims& m);
 static int64_t max_overlay_rows(const ModelDims& m) {
     int64_t tot = 0;
     const int L = m.L, N = m.N;
+    // a chain's flip of site i keeps rows i+1 .. N-1
+    if (m.chain) return (int64_t)N * (N - 1) / 2;
     for (int b = 0; b < 2 * N; ++b) {
         const int i = b >> 1, r = i / L, c = i % L;
         int j;
@@ -60,6 +62,7 @@ struct Workspace {
     acc* cnorm;   // [nl][H*Q + H]
     float* prm;   // BF16 mode: parameters rounded to bfloat16
     bf16 *wqkv_p, *w1_p, *w2_p, *cb_p;   // [nl] matrix-core fragment packs
+    bf16* wqkv_tp;                       // the half-block's QKV pack
     float* cnh4;                         // [nl][H*Q*4] -cnorm/2, four copies
     // chunk neighbour bookkeeping
     int16_t* bonds;
@@ -74,6 +77,7 @@ struct Workspace {
     int32_t* bcode;           // [nlc][n][N][H]
     acc* bmargin;             // [nlc][n][N][H][2]
     acc* blp;                 // [n][N][2]
+    acc* bstat;               // [nl][n][N][heads][2] softmax statistics
     // materialised neighbours (plain)
     int8_t* nspins;
     acc* nx;
@@ -126,6 +130,7 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
             w.w2_p = c.take<bf16>((size_t)m.nl * m.dff * d);
             w.cb_p = c.take<bf16>((size_t)m.nl * m.Q * d);
             w.cnh4 = c.take<float>((size_t)m.nl * H * m.Q * 4);
+            if (m.tail) w.wqkv_tp = c.take<bf16>((size_t)d * 3 * d);
         }
     }
     w.bonds = c.take<int16_t>(n * 2 * N);
@@ -150,8 +155,8 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
         w.bx = c.take<acc>(R * d);
         w.bq = c.take<act>(R * d);
         w.ba = c.take<act>(R * d);
-        w.bk = c.take<act>((size_t)m.nl * R * d);
-        w.bv = c.take<act>((size_t)m.nl * R * d);
+        w.bk = c.take<act>((size_t)(m.nl + m.tail) * R * d);
+        w.bv = c.take<act>((size_t)(m.nl + m.tail) * R * d);
         w.bcode = c.take<int32_t>(R * H);
         w.list = c.take<int64_t>(n);
         w.logpsi_s = c.take<double>(n);
@@ -160,7 +165,7 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     }
     if (job == Job::Grad) {
         const int64_t R = n * N, F = m.dff, Q = m.Q;
-        w.gx = c.take<acc>((size_t)(m.nl + 1) * R * d);
+        w.gx = c.take<acc>((size_t)(m.nl + 1 + m.tail) * R * d);
         w.gq = c.take<act>(R * d);
         w.gk = c.take<act>(R * d);
         w.gv = c.take<act>(R * d);
@@ -199,8 +204,9 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     w.ratio = c.take<double>(nbmax);
     w.logpsi_s = c.take<double>(n);
     const bool dedup = job == Job::Dedup;
-    const int64_t nlc = dedup ? m.nl : 1;       // cached layers
-    const int64_t nlx = dedup ? m.nl + 1 : 1;   // block inputs + final
+    // cached layers (and the half-block), block inputs + final output
+    const int64_t nlc = dedup ? m.nl + m.tail : 1;
+    const int64_t nlx = dedup ? m.nl + 1 + m.tail : 1;
     w.bx = c.take<acc>(nlx * n * N * d);
     w.bq = c.take<act>(nlc * n * N * d);
     w.bk = c.take<act>(nlc * n * N * d);
@@ -210,6 +216,8 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     if (dedup) {
         w.bmargin = c.take<acc>(nlc * n * N * H * 2);
         w.blp = c.take<acc>(n * N * 2);
+        if (m.flags & VQNQS_FLAG_INCREMENTAL_ATTN)
+            w.bstat = c.take<acc>(nlc * n * N * m.nh * 2);
     }
     if (job == Job::Plain) {
         w.logpsi_nb = c.take<double>(nbmax);
@@ -323,6 +331,29 @@ static LayerW<C> layer_view(const ModelDims& m, const C* p, int l) {
     return w;
 }
 
+// Parameters of the attention-only half-block after the blocks (tail of
+// the flat layout, before the final LayerNorm).
+static int64_t tail_params(const ModelDims& m) {
+    const int64_t d = m.d;
+    return m.tail ? 2 * d + 3 * d * d + 3 * d + d * d + d : 0;
+}
+
+template <typename C>
+static LayerW<C> tail_view(const ModelDims& m, const C* p) {
+    const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
+    const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
+                        d * F + F + F * d + d;
+    const C* b = p + 3 * d + N * d + per * m.nl;
+    LayerW<C> w{};
+    w.ln1_g = b;
+    w.ln1_b = b + d;
+    w.W_qkv = b + 2 * d;
+    w.b_qkv = w.W_qkv + d * 3 * d;
+    w.W_o = w.b_qkv + 3 * d;
+    w.b_o = w.W_o + d * d;
+    return w;
+}
+
 template <typename C>
 static HeadW<C> head_view(const ModelDims& m, const C* p) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
@@ -331,7 +362,7 @@ static HeadW<C> head_view(const ModelDims& m, const C* p) {
     HeadW<C> h{};
     h.tok = p;
     h.pos = p + 3 * d;
-    const C* t = p + 3 * d + N * d + per * m.nl;
+    const C* t = p + 3 * d + N * d + per * m.nl + tail_params(m);
     h.lnf_g = t;
     h.lnf_b = t + d;
     h.W_head = t + 2 * d;
@@ -343,7 +374,7 @@ int64_t param_count(const ModelDims& m) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
-    return 3 * d + N * d + per * m.nl + 2 * d + 2 * d + 2;
+    return 3 * d + N * d + per * m.nl + tail_params(m) + 2 * d + 2 * d + 2;
 }
 
 #define CK(x)                                  \
@@ -439,6 +470,11 @@ struct Runner {
         return launch_vq<P>(m, lw, rs, io, st);
     }
     HeadW<acc> head() const { return head_view<acc>(m, params); }
+    LayerW<acc> tail() const {
+        LayerW<acc> tw = tail_view<acc>(m, params);
+        if (m.mfma) tw.Wqkv_p = w.wqkv_tp;
+        return tw;
+    }
 
     vqnqs_status prepare() {
         if constexpr (std::is_same<P, PrecBF16>::value) {
@@ -459,6 +495,10 @@ struct Runner {
                                          const_cast<bf16*>(lw.cb_p),
                                          const_cast<float*>(lw.cnh4), st));
         }
+        if constexpr (std::is_same<P, PrecBF16>::value)
+            if (m.mfma && m.tail)
+                LK("pack_layer", launch_pack_qkv(m, tail_view<acc>(m, params).W_qkv,
+                                                 w.wqkv_tp, st));
         return VQNQS_OK;
     }
 
@@ -476,6 +516,7 @@ struct Runner {
         int32_t* codes_out;   // nullable [n][nl][N][H]
         bool keep_x = false;  // block inputs per layer only (checkpoints)
         act* attn_out = nullptr;  // nullable [n][nl][N][d] attention outputs
+        acc* stat = nullptr;      // nullable [nl][n][N][heads][2] softmax stats
     };
 
     vqnqs_status forward(const SeqBufs& b, const int32_t* n_dev, int64_t n,
@@ -494,6 +535,7 @@ struct Runner {
             io.a = b.a + cl * sd;
             io.codes = b.code + cl * sh;
             io.margin = b.margin ? b.margin + cl * sh * 2 : nullptr;
+            io.stat = b.stat ? b.stat + (int64_t)l * rows * m.nh * 2 : nullptr;
             RowSet rs{nullptr, n_dev, rows, (int32_t)m.N};
             BlockIO<P> qio = io;
             qio.x = const_cast<acc*>(io.x_in);
@@ -507,7 +549,29 @@ struct Runner {
             if (b.codes_out)
                 LK("copy_codes", launch_copy_codes(io.codes, n, m.N, m.H, m.nl, l, b.codes_out, st));
         }
-        const acc* xf = b.x + (b.cache || b.keep_x ? (int64_t)m.nl * sd : 0);
+        const bool per_layer_x = b.cache || b.keep_x;
+        if (m.tail) {
+            // attention-only half-block: input slice nl, output slice nl+1
+            // when the layer inputs are kept (in place otherwise)
+            const int64_t cl = b.cache ? m.nl : 0;
+            BlockIO<P> io{};
+            io.x_in = b.x + (per_layer_x ? (int64_t)m.nl * sd : 0);
+            io.x = b.x + (per_layer_x ? (int64_t)(m.nl + 1) * sd : 0);
+            io.q = b.q + cl * sd;
+            io.k = b.k + cl * sd;
+            io.v = b.v + cl * sd;
+            io.a = b.a + cl * sd;
+            io.codes = b.code;
+            RowSet rs{nullptr, n_dev, rows, (int32_t)m.N};
+            BlockIO<P> qio = io;
+            qio.x = const_cast<acc*>(io.x_in);
+            const LayerW<acc> tw = tail();
+            LK("qkv", qkv(tw, rs, qio));
+            LK("attention_seq", attn_seq(n_dev, n, io, count_rows ? ctr : nullptr));
+            LK("tail_proj", launch_out_proj<P>(m, tw.W_o, tw.b_o, rs, io.x_in, io.a,
+                                               io.x, st));
+        }
+        const acc* xf = b.x + (per_layer_x ? (int64_t)(m.nl + m.tail) * sd : 0);
         LK("head_seq", launch_head_seq<P>(m, head(), b.spins, n_dev, n, xf, b.lp, b.logpsi, st));
         if (count_rows && ctr) {
             if (n_dev) {
@@ -564,18 +628,61 @@ struct Runner {
         if (s) return s;
         LK("grad_coef", launch_coef<acc>(n, wts, w.coef, st));
         const HeadW<acc> hw = head();
-        const int64_t off_lnf = layer_offsets(m, m.nl).ln1_g;
+        const int64_t off_tail = layer_offsets(m, m.nl).ln1_g;
+        const int64_t off_lnf = off_tail + tail_params(m);
         const int64_t off_Wh = off_lnf + 2 * d, off_bh = off_Wh + 2 * d;
-        // head: d log psi / d x_L
+        // head: d log psi / d x_L (after the half-block, when there is one)
         LK("grad_head", launch_head_bwd<acc>(n, (int)N, (int)d, hw, sp,
-                                             w.gx + (int64_t)m.nl * sd, w.coef,
-                                             w.h1, w.xh1, w.rs1, w.dz2, w.dT,
-                                             w.dX, st));
+                                             w.gx + (int64_t)(m.nl + m.tail) * sd,
+                                             w.coef, w.h1, w.xh1, w.rs1, w.dz2,
+                                             w.dT, w.dX, st));
         LK("grad_gemm", gemm(d, 2, N, w.h1, d, N * d, 1, w.dz2, 2, 2 * N, 0,
                              gout + off_Wh, 2, NP, 0, n));
         LK("grad_colsum", colsum(n, 2, w.dz2, 2, nullptr, 0, gout + off_bh, NP));
         LK("grad_colsum", colsum(n, d, w.dT, d, w.xh1, d, gout + off_lnf, NP));
         LK("grad_colsum", colsum(n, d, w.dT, d, nullptr, 0, gout + off_lnf + d, NP));
+        if (m.tail) {
+            // attention-only half-block, x = x_in + a W_o + b_o with
+            // a = attention(LN(x_in) W_qkv + b_qkv): recompute, then
+            // backward, the upstream dX at x turning into the one at x_in
+            const LayerW<acc> tw = tail();
+            const acc* xl = w.gx + (int64_t)m.nl * sd;
+            const int64_t o_ln = off_tail, o_Wqkv = off_tail + 2 * d;
+            const int64_t o_bqkv = o_Wqkv + 3 * d * d, o_Wo = o_bqkv + 3 * d;
+            const int64_t o_bo = o_Wo + d * d;
+            BlockIO<P> io{};
+            io.x = const_cast<acc*>(xl);
+            io.x_in = xl;
+            io.q = w.gq;
+            io.k = w.gk;
+            io.v = w.gv;
+            io.a = w.ga;
+            io.codes = w.gcode;
+            const RowSet rs{nullptr, nullptr, R, (int32_t)N};
+            LK("qkv", qkv(tw, rs, io));
+            LK("attention_seq", attn_seq(nullptr, n, io, nullptr));
+            LK("grad_ln", launch_ln_save<acc>(R, (int)d, xl, tw.ln1_g, tw.ln1_b,
+                                              w.h1, w.xh1, w.rs1, st));
+            LK("grad_gemm", gemm(d, d, N, w.ga, d, N * d, 1, w.dX, d, N * d, 0,
+                                 gout + o_Wo, d, NP, 0, n));
+            LK("grad_colsum", colsum(n, d, w.dX, d, nullptr, 0, gout + o_bo, NP));
+            LK("grad_gemm", gemm(R, d, d, w.dX, d, 0, 0, tw.W_o, d, 0, 1, w.da,
+                                 d, 0, 0, 1));
+            LK("grad_attention", launch_attn_bwd<acc>(n, m, w.gq, w.gk, w.gv,
+                                                      w.ga, w.da, w.lse, w.Dd,
+                                                      w.dqkv, st));
+            LK("grad_gemm", gemm(d, 3 * d, N, w.h1, d, N * d, 1, w.dqkv, 3 * d,
+                                 N * 3 * d, 0, gout + o_Wqkv, 3 * d, NP, 0, n));
+            LK("grad_colsum", colsum(n, 3 * (int)d, w.dqkv, 3 * d, nullptr, 0,
+                                     gout + o_bqkv, NP));
+            LK("grad_gemm", gemm(R, d, 3 * d, w.dqkv, 3 * d, 0, 0, tw.W_qkv,
+                                 3 * d, 0, 1, w.dT, d, 0, 0, 1));
+            LK("grad_colsum", colsum(n, d, w.dT, d, w.xh1, d, gout + o_ln, NP));
+            LK("grad_colsum", colsum(n, d, w.dT, d, nullptr, 0, gout + o_ln + d, NP));
+            // the residual carries dX through; LN adds its part in place
+            LK("grad_ln", launch_ln_bwd<acc>(R, (int)d, w.xh1, w.rs1, tw.ln1_g,
+                                             w.dT, w.dX, w.dX, st));
+        }
         for (int l = m.nl - 1; l >= 0; --l) {
             const LayerW<acc> lw = layer(l);
             const LayerOffsets o = layer_offsets(m, l);
@@ -680,7 +787,7 @@ struct Runner {
     vqnqs_status neighbours(const int8_t* spins, int64_t n) {
         LK("neighbours", launch_neighbours(spins, n, m, w.bonds, w.count, w.diag, w.rows_cap,
                              w.status, st));
-        LK("scan_desc", launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, w.nb_off,
+        LK("scan_desc", launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, m.chain, w.nb_off,
                             w.row_off, w.n_nb, w.n_rows, w.desc, st));
         if (ctr) {
             CK(launch_counter_add_const(ctr, VQNQS_CTR_SAMPLES, n, st));
@@ -714,6 +821,21 @@ struct Runner {
                 LK("attention_rows", launch_attn_rows<P>(m, n, i, io, st));
                 LK("vq", vqs(layer(l), rs, io));
                 LK("mlp", mlp(layer(l), rs, io));
+            }
+            if (m.tail) {
+                BlockIO<P> io{};
+                io.x = w.bx;
+                io.x_in = w.bx;
+                io.q = w.bq;
+                io.k = w.bk + (int64_t)m.nl * sd;
+                io.v = w.bv + (int64_t)m.nl * sd;
+                io.a = w.ba;
+                io.codes = w.bcode;
+                const LayerW<acc> tw = tail();
+                LK("qkv", qkv(tw, rs, io));
+                LK("attention_rows", launch_attn_rows<P>(m, n, i, io, st));
+                LK("tail_proj", launch_out_proj<P>(m, tw.W_o, tw.b_o, rs, w.bx, w.ba,
+                                                   w.bx, st));
             }
             LK("sample_head", launch_sample_head<P>(m, head(), n, i, w.bx,
                                                     uni + 0, spins, w.logpsi_s,
@@ -751,6 +873,14 @@ struct Runner {
         SeqBufs sb{spins, w.bx, w.bq, w.bk, w.bv, w.ba, w.bcode,
                    cert ? w.bmargin : nullptr,
                    w.blp, w.logpsi_s, true, nullptr};
+        const bool incr = (m.flags & VQNQS_FLAG_INCREMENTAL_ATTN) != 0;
+        // layers whose attention takes the rank-|C| update (the first ones,
+        // where the changed sets are small)
+        const int inc_layers = incr ? (VQNQS_INC_LAYERS_OF(m.flags) > 0
+                                           ? VQNQS_INC_LAYERS_OF(m.flags)
+                                           : 2)
+                                    : 0;
+        sb.stat = incr ? w.bstat : nullptr;
         s = forward(sb, nullptr, n, true);
         if (s) return s;
         const int64_t nbmax = n * 2 * N;
@@ -806,7 +936,13 @@ struct Runner {
             RowSet cl{w.list, w.list_n, R, 1};
             if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_QKV_ROWS, w.list_n, 1, st));
             LK("qkv", qkv(lw, cl, io));
-            LK("attention_dedup", attn_dedup(dd));
+            if (l < inc_layers) {
+                LK("attention_incr",
+                   launch_attention_incr<P>(m, dd, w.bstat + (int64_t)l * n * N * m.nh * 2,
+                                            ctr, st));
+            } else {
+                LK("attention_dedup", attn_dedup(dd));
+            }
             if (certified) {
                 CK(launch_fill_i32(w.vq_n, 1, 0, st));
                 LK("certify", launch_certify<P>(m, dd, 1, ctr, st));
@@ -826,6 +962,36 @@ struct Runner {
             }
             LK("mlp", mlp(lw, cl, io));
         }
+        if (m.tail) {
+            // the half-block: LN + QKV on C_L, attention on every row from
+            // p_min, its output projection on all of those rows (its input
+            // the neighbour's row where in C_L, else the sample's), whose
+            // results the head then reads for every row from p_min
+            const int64_t lt = m.nl;
+            dd.bx = w.bx + lt * sd;
+            dd.bq = w.bq + lt * sd;
+            dd.bk = w.bk + lt * sd;
+            dd.bv = w.bv + lt * sd;
+            dd.ba = w.ba + lt * sd;
+            BlockIO<P> io{};
+            io.x = w.ox;
+            io.x_in = w.ox;
+            io.q = w.oq;
+            io.k = w.ok;
+            io.v = w.ov;
+            io.a = w.oa;
+            io.codes = w.ocode;
+            const LayerW<acc> tw = tail();
+            RowSet cl{w.list, w.list_n, R, 1};
+            if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_QKV_ROWS, w.list_n, 1, st));
+            LK("qkv", qkv(tw, cl, io));
+            LK("attention_dedup", attn_dedup(dd));
+            LK("tail_proj", launch_out_proj_overlay<P>(m, tw.W_o, tw.b_o, dd, w.oq, st));
+            LK("tail_mask", launch_mask_from_pmin(w.desc, w.n_nb, nbmax, dd.mask_words,
+                                                  m.N, w.mask, st));
+            dd.ox = w.oq;
+            if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_TAIL_ROWS, w.n_rows, 1, st));
+        }
         LK("head_dedup", launch_head_dedup<P>(m, head(), dd, w.blp, nullptr, w.ratio, ctr, st));
         return VQNQS_OK;
     }
@@ -838,6 +1004,9 @@ static vqnqs_status run_local_energy(const ModelDims& m, const void* params,
                                      double* ratios, int64_t* counters,
                                      void* ws, size_t ws_bytes,
                                      hipStream_t st) {
+    // the rank-|C| attention update is built for the FP64 and FP32 modes
+    if ((m.flags & VQNQS_FLAG_INCREMENTAL_ATTN) && m.precision == VQNQS_BF16)
+        return VQNQS_ERR_UNSUPPORTED;
     const int64_t chunk = pick_chunk(m, mode, batch, ws_bytes);
     if (batch > 0 && chunk <= 0) return VQNQS_ERR_WORKSPACE_TOO_SMALL;
     Runner<P> r{m, static_cast<const typename P::acc*>(params),
@@ -849,7 +1018,9 @@ static vqnqs_status run_local_energy(const ModelDims& m, const void* params,
     if (batch == 0) return VQNQS_OK;
     vqnqs_status s = r.prepare();
     if (s) return s;
-    const double h_off = m.marshall ? -0.5 * m.J : 0.5 * m.J;
+    // off-diagonal element per neighbour: -Gamma per flip (chain),
+    // -+J/2 per exchanged bond (Heisenberg, Marshall-rotated or not)
+    const double h_off = m.chain ? -m.gamma : (m.marshall ? -0.5 * m.J : 0.5 * m.J);
     for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
         const int64_t n = std::min(chunk, batch - c0);
         const int8_t* sp = spins + c0 * m.N;
@@ -1305,9 +1476,11 @@ static std::vector<int64_t> graph_key(const ModelDims* ms, const vqnqs_job* jobs
         const vqnqs_job& j = jobs[i];
         const vqnqs_config& c = j.cfg;
         const Tuning t = tuning_get(ms[i]);
-        int64_t jb;
+        int64_t jb, gb;
         std::memcpy(&jb, &c.J, sizeof jb);
-        const int64_t f[] = {c.L, c.periodic, c.marshall, jb, c.d_model,
+        std::memcpy(&gb, &c.gamma, sizeof gb);
+        const int64_t f[] = {c.L, c.periodic, c.marshall, jb, c.hamiltonian, gb,
+                             c.attn_tail, c.d_model,
                              c.n_layers, c.n_heads, c.d_ff, c.codebook_size,
                              c.vq_heads, c.precision, c.flags,
                              (int64_t)(intptr_t)j.params,

@@ -26,6 +26,8 @@ struct BlockIO {
     act* a;            // attention output
     int32_t* codes;    // [row][H]
     acc* margin;       // [row][H] half gap of the two best distances, nullable
+    acc* stat;         // [row][heads][2] softmax reference and normaliser of
+                       // every attention row, nullable (full sequences only)
 };
 
 hipError_t launch_neighbours(const int8_t* spins, int64_t batch,
@@ -33,7 +35,7 @@ hipError_t launch_neighbours(const int8_t* spins, int64_t batch,
                              int32_t* count, double* diag, int64_t* rows_cap,
                              int32_t* status, hipStream_t st);
 hipError_t launch_scan_desc(const int16_t* bonds, const int32_t* count,
-                            const int64_t* rows_cap, int n, int L,
+                            const int64_t* rows_cap, int n, int L, int chain,
                             int32_t* nb_off, int64_t* row_off,
                             int32_t* n_nb_total, int32_t* n_rows_total,
                             NbDesc* desc, hipStream_t st);
@@ -192,6 +194,28 @@ hipError_t launch_dedup_init(const ModelDims& m, const HeadW<typename P::acc>& h
 template <class P>
 hipError_t launch_attention_dedup(const ModelDims& m, const DedupIO<P>& d,
                                   int64_t* ctr, hipStream_t st);
+// ---- attention-only half-block
+template <class P>
+hipError_t launch_out_proj(const ModelDims& m, const typename P::acc* Wo,
+                           const typename P::acc* bo, RowSet rows,
+                           const typename P::acc* x_in,
+                           const typename P::act* a, typename P::acc* x_out,
+                           hipStream_t st);
+template <class P>
+hipError_t launch_out_proj_overlay(const ModelDims& m,
+                                   const typename P::acc* Wo,
+                                   const typename P::acc* bo,
+                                   const DedupIO<P>& dd,
+                                   typename P::acc* out, hipStream_t st);
+hipError_t launch_mask_from_pmin(const NbDesc* desc, const int32_t* n_nb,
+                                 int64_t n_max, int W, int N, uint64_t* mask,
+                                 hipStream_t st);
+hipError_t launch_pack_qkv(const ModelDims& m, const float* W_qkv, bf16* out,
+                           hipStream_t st);
+template <class P>
+hipError_t launch_attention_incr(const ModelDims& m, const DedupIO<P>& d,
+                                 const typename P::acc* bstat, int64_t* ctr,
+                                 hipStream_t st);
 template <class P>
 hipError_t launch_certify(const ModelDims& m, const DedupIO<P>& d,
                           int certified, int64_t* ctr, hipStream_t st);

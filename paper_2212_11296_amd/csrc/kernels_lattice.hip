@@ -1,7 +1,8 @@
 // Lattice-side kernels: spin validation, neighbour enumeration (ballot +
 // prefix compaction), neighbour descriptors, local-energy assembly and the
 // batch statistics.  Paper: eq. (2) local energy; k-local rows (Sec. 2);
-// Heisenberg model with the Marshall sign rule (Sec. 4).
+// Heisenberg model with the Marshall sign rule and the transverse-field
+// Ising chain (Sec. 4).
 #include "kernels.h"
 
 namespace vq {
@@ -25,14 +26,14 @@ __device__ inline bool bond_sites(int b, int L, int periodic, int& i, int& j) {
 // and a popcount of the lanes below give each one its output slot, so the
 // list comes out in increasing bond order without atomics.
 __global__ void __launch_bounds__(64) k_neighbours(
-    const int8_t* __restrict__ spins, int64_t batch, int L, int periodic,
-    double J, int16_t* __restrict__ bonds, int32_t* __restrict__ count,
+    const int8_t* __restrict__ spins, int64_t batch, int L, int chain,
+    int periodic, double J, int16_t* __restrict__ bonds, int32_t* __restrict__ count,
     double* __restrict__ diag, int64_t* __restrict__ rows_cap,
     int32_t* __restrict__ status) {
     const int64_t s = blockIdx.x;
     if (s >= batch) return;
     const int lane = threadIdx.x;
-    const int N = L * L;
+    const int N = chain ? L : L * L;
     const int8_t* sp = spins + s * (int64_t)N;
     int bad = 0;
     for (int i = lane; i < N; i += 64) {
@@ -40,6 +41,28 @@ __global__ void __launch_bounds__(64) k_neighbours(
         bad |= (v != 1 && v != -1);
     }
     if (__any(bad) && lane == 0) atomicOr(status, 1);
+    if (chain) {
+        // transverse-field Ising chain: every site's flip is a neighbour
+        // (listed by site), diagonal -J sum_<ij> s_i s_j over the bonds
+        // (i, i+1) and, periodic, (N-1, 0); a flip of site i changes the
+        // input tokens from i + 1 on
+        int zz = 0;
+        int16_t* out = bonds + s * (int64_t)(2 * N);
+        for (int i = lane; i < N; i += 64) {
+            out[i] = (int16_t)i;
+            out[N + i] = -1;
+            const int si = sp[i] < 0 ? -1 : 1;
+            if (i + 1 < N) zz += si * (sp[i + 1] < 0 ? -1 : 1);
+            else if (periodic && N > 2) zz += si * (sp[0] < 0 ? -1 : 1);
+        }
+        zz = wave_sum(zz);
+        if (lane == 0) {
+            count[s] = N;
+            if (diag) diag[s] = -J * (double)zz;
+            if (rows_cap) rows_cap[s] = (int64_t)N * (N - 1) / 2;
+        }
+        return;
+    }
     int total = 0;
     int zz = 0;          // sum of s_i s_j over existing bonds
     int64_t cap = 0;     // overlay rows: sum over anti bonds of N - p1 - 1
@@ -126,11 +149,11 @@ __global__ void __launch_bounds__(1024) k_scan_chunk(
 __global__ void __launch_bounds__(64) k_descriptors(
     const int16_t* __restrict__ bonds, const int32_t* __restrict__ count,
     const int32_t* __restrict__ nb_off, const int64_t* __restrict__ row_off,
-    int n, int L, NbDesc* __restrict__ desc) {
+    int n, int L, int chain, NbDesc* __restrict__ desc) {
     const int s = blockIdx.x;
     if (s >= n) return;
     const int lane = threadIdx.x;
-    const int N = L * L;
+    const int N = chain ? L : L * L;
     const int cnt = count[s];
     const int16_t* bl = bonds + (int64_t)s * 2 * N;
     int64_t carry = row_off[s];
@@ -139,10 +162,15 @@ __global__ void __launch_bounds__(64) k_descriptors(
         int p1 = 0, p2 = 0;
         int64_t rows = 0;
         if (k < cnt) {
-            int i, j;
-            bond_sites(bl[k], L, 1, i, j);
-            p1 = i < j ? i : j;
-            p2 = i < j ? j : i;
+            if (chain) {
+                // a single flip: p1 == p2 is the flipped site
+                p1 = p2 = bl[k];
+            } else {
+                int i, j;
+                bond_sites(bl[k], L, 1, i, j);
+                p1 = i < j ? i : j;
+                p2 = i < j ? j : i;
+            }
             rows = N - p1 - 1;
         }
         int64_t incl = rows;   // inclusive wave scan
@@ -302,20 +330,20 @@ hipError_t launch_neighbours(const int8_t* spins, int64_t batch,
                              hipStream_t st) {
     if (batch <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_neighbours, dim3((unsigned)batch), dim3(64), 0, st,
-                       spins, batch, m.L, m.periodic, m.J, bonds, count, diag,
-                       rows_cap, status);
+                       spins, batch, m.L, m.chain, m.periodic, m.J, bonds,
+                       count, diag, rows_cap, status);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_desc(const int16_t* bonds, const int32_t* count,
-                            const int64_t* rows_cap, int n, int L,
+                            const int64_t* rows_cap, int n, int L, int chain,
                             int32_t* nb_off, int64_t* row_off,
                             int32_t* n_nb_total, int32_t* n_rows_total,
                             NbDesc* desc, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_chunk, dim3(1), dim3(1024), 0, st, count,
                        rows_cap, n, nb_off, row_off, n_nb_total, n_rows_total);
     hipLaunchKernelGGL(k_descriptors, dim3(n), dim3(64), 0, st, bonds, count,
-                       nb_off, row_off, n, L, desc);
+                       nb_off, row_off, n, L, chain, desc);
     return hipGetLastError();
 }
 

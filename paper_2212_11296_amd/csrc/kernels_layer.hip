@@ -116,10 +116,12 @@ __global__ void k_materialise(const int8_t* __restrict__ spins,
         const int64_t k = e / N;
         const int i = (int)(e - k * N);
         const NbDesc dd = desc[k];
+        // exchange of p1 < p2, or a flip of p1 when p1 == p2
         int src = i;
         if (i == dd.p1) src = dd.p2;
         else if (i == dd.p2) src = dd.p1;
-        out[e] = spins[(int64_t)dd.sigma * N + src];
+        const int8_t v = spins[(int64_t)dd.sigma * N + src];
+        out[e] = (dd.p1 == dd.p2 && i == dd.p1) ? (int8_t)-v : v;
     }
 }
 
@@ -227,7 +229,8 @@ hipError_t launch_qkv(const ModelDims& m, const LayerW<typename P::acc>& w,
 template <typename C, int DH, typename A>
 __device__ inline void attend_row(const C (&q)[DH], const A* __restrict__ Ks,
                                   const A* __restrict__ Vs, int i,
-                                  C (&o)[DH], int64_t ld = DH) {
+                                  C (&o)[DH], int64_t ld = DH,
+                                  C* stat = nullptr) {
     C mx = neg_inf<C>(), l = 0;
 #pragma unroll
     for (int c = 0; c < DH; ++c) o[c] = 0;
@@ -250,6 +253,11 @@ __device__ inline void attend_row(const C (&q)[DH], const A* __restrict__ Ks,
     const C inv = (C)1 / l;
 #pragma unroll
     for (int c = 0; c < DH; ++c) o[c] *= inv;
+    // the softmax statistics: the largest score and sum_j exp(s_j - max)
+    if (stat) {
+        stat[0] = mx;
+        stat[1] = l;
+    }
 }
 
 template <class P, int DH>
@@ -282,7 +290,9 @@ __global__ void __launch_bounds__(kThreads) k_attn_seq(ModelDims m,
 #pragma unroll
             for (int c = 0; c < DH; ++c)
                 q[c] = cvt<acc>(io.q[base + (int64_t)i * d + c]) * scale;
-            attend_row<acc, DH, act>(q, Ks, Vs, i, o);
+            attend_row<acc, DH, act>(
+                q, Ks, Vs, i, o, DH,
+                io.stat ? io.stat + ((s * N + i) * m.nh + h) * 2 : nullptr);
 #pragma unroll
             for (int c = 0; c < DH; ++c)
                 io.a[base + (int64_t)i * d + c] = cvt<act>(o[c]);
@@ -407,6 +417,358 @@ hipError_t launch_attention_dedup(const ModelDims& m, const DedupIO<P>& d,
         case 64: return attn_dedup_dh<P, 64>(m, d, ctr, st);
     }
     return hipErrorInvalidValue;
+}
+
+// Incremental attention of the neighbours: for a query row whose own input
+// did not change (not in C), only the keys and values of the rows of C
+// differ from the sample's, so its softmax sum is the sample's with those
+// terms replaced (a rank-|C| update):
+//   U' = f (l a - sum_C w_old v_old) + sum_C w_new v_new,
+//   L' = f (l - sum_C w_old) + sum_C w_new,      a' = U' / L',
+// with the sample's reference m and normaliser l of the row (cached by its
+// forward pass), w_old = e^(s_old - m), w_new = e^(s_new - m'), m' the
+// larger of m and the new scores, f = e^(m - m').  A row in C (changed
+// query), a neighbour with more C rows
+// than the LDS holds, or a row whose removed weight exceeds half its
+// normaliser (cancellation) is evaluated in full over keys 0..i, in the
+// order and arithmetic of attend_row.
+template <class P, int DH>
+__global__ void __launch_bounds__(kThreads) k_attn_incr(
+    ModelDims m, DedupIO<P> dd, const typename P::acc* __restrict__ bstat,
+    int64_t* ctr) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    constexpr int CAP = 8192 / (DH * (int)sizeof(act));   // 32 KiB of rows
+    __shared__ act Ko[CAP * DH], Vo[CAP * DH], Kn[CAP * DH], Vn[CAP * DH];
+    __shared__ int jr[CAP];
+    const int64_t n = (int64_t)*dd.n_nb;
+    const int64_t units = n * m.nh;
+    const acc scale = (acc)1 / dsqrt((acc)DH);
+    const int d = m.d, N = m.N, W = dd.mask_words;
+    auto ex = [](acc x) -> acc { return dexp(x); };
+    int64_t my_rows = 0, my_pairs = 0;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t nb = u / m.nh;
+        const int h = (int)(u - nb * m.nh);
+        const NbDesc D = dd.desc[nb];
+        const int pmin = D.p1 + 1;
+        const uint64_t* mk = dd.mask + nb * W;
+        const int64_t sb = (int64_t)D.sigma * N * d + h * DH;
+        const int64_t ob = (D.ov - pmin) * (int64_t)d + h * DH;
+        const int cc = dd.ccnt[nb];
+        const bool fits = cc <= CAP;
+        __syncthreads();
+        if (fits) {
+            for (int e = threadIdx.x; e < cc * DH; e += kThreads) {
+                const int c = e / DH, k = e - (e / DH) * DH;
+                const int j = dd.crow[D.ov + c];
+                Ko[e] = dd.bk[sb + (int64_t)j * d + k];
+                Vo[e] = dd.bv[sb + (int64_t)j * d + k];
+                Kn[e] = dd.ok[ob + (int64_t)j * d + k];
+                Vn[e] = dd.ov[ob + (int64_t)j * d + k];
+                if (k == 0) jr[c] = j;
+            }
+        }
+        __syncthreads();
+        for (int i = pmin + threadIdx.x; i < N; i += kThreads) {
+            const bool qchg = mask_bit(mk, i);
+            const act* qsrc = (qchg ? dd.oq + ob : dd.bq + sb) + (int64_t)i * d;
+            acc q[DH], o[DH];
+            bool done = false;
+            if (!qchg && fits) {
+                // the C rows at or before i
+                int nc = 0;
+                while (nc < cc && jr[nc] <= i) ++nc;
+                const acc* st = bstat + (((int64_t)D.sigma * N + i) * m.nh + h) * 2;
+                const acc m0 = st[0], l0 = st[1];
+#pragma unroll
+                for (int c = 0; c < DH; ++c) q[c] = cvt<acc>(qsrc[c]) * scale;
+                acc mn = m0;
+                for (int c = 0; c < nc; ++c) {
+                    acc sn = 0;
+#pragma unroll
+                    for (int k = 0; k < DH; ++k) sn += q[k] * cvt<acc>(Kn[c * DH + k]);
+                    mn = sn > mn ? sn : mn;
+                }
+                acc rw = 0, aw = 0, ro[DH], ao[DH];
+#pragma unroll
+                for (int k = 0; k < DH; ++k) ro[k] = ao[k] = 0;
+                for (int c = 0; c < nc; ++c) {
+                    acc so = 0, sn = 0;
+#pragma unroll
+                    for (int k = 0; k < DH; ++k) {
+                        so += q[k] * cvt<acc>(Ko[c * DH + k]);
+                        sn += q[k] * cvt<acc>(Kn[c * DH + k]);
+                    }
+                    const acc wo = ex(so - m0), wn = ex(sn - mn);
+                    rw += wo;
+                    aw += wn;
+#pragma unroll
+                    for (int k = 0; k < DH; ++k) {
+                        ro[k] += wo * cvt<acc>(Vo[c * DH + k]);
+                        ao[k] += wn * cvt<acc>(Vn[c * DH + k]);
+                    }
+                }
+                if (rw <= (acc)0.5 * l0) {
+                    const acc f = ex(m0 - mn);
+                    const acc L = f * (l0 - rw) + aw;
+                    const act* a0 = dd.ba + sb + (int64_t)i * d;
+#pragma unroll
+                    for (int k = 0; k < DH; ++k)
+                        o[k] = (f * (l0 * cvt<acc>(a0[k]) - ro[k]) + ao[k]) / L;
+                    done = true;
+                    my_pairs += 2 * nc;
+                }
+            }
+            if (!done) {
+                // every key 0..i: the neighbour's overlay rows where they
+                // changed, the sample's elsewhere (attend_row's arithmetic)
+#pragma unroll
+                for (int c = 0; c < DH; ++c) q[c] = cvt<acc>(qsrc[c]) * scale;
+                acc mx = neg_inf<acc>(), l = 0;
+#pragma unroll
+                for (int c = 0; c < DH; ++c) o[c] = 0;
+                for (int j = 0; j <= i; ++j) {
+                    const bool ovl = j >= pmin && mask_bit(mk, j);
+                    const int64_t off = (ovl ? ob : sb) + (int64_t)j * d;
+                    const act* K = (ovl ? dd.ok : dd.bk) + off;
+                    const act* V = (ovl ? dd.ov : dd.bv) + off;
+                    acc sc = 0;
+#pragma unroll
+                    for (int c = 0; c < DH; ++c) sc += q[c] * cvt<acc>(K[c]);
+                    if (sc > mx) {
+                        const acc al = dexp(mx - sc);
+                        l *= al;
+#pragma unroll
+                        for (int c = 0; c < DH; ++c) o[c] *= al;
+                        mx = sc;
+                    }
+                    const acc pj = dexp(sc - mx);
+                    l += pj;
+#pragma unroll
+                    for (int c = 0; c < DH; ++c) o[c] += pj * cvt<acc>(V[c]);
+                }
+                const acc inv = (acc)1 / l;
+#pragma unroll
+                for (int c = 0; c < DH; ++c) o[c] *= inv;
+                my_pairs += i + 1;
+            }
+            act* dst = dd.oa + ob + (int64_t)i * d;
+#pragma unroll
+            for (int c = 0; c < DH; ++c) dst[c] = cvt<act>(o[c]);
+        }
+        if (h == 0 && threadIdx.x == 0) my_rows += N - pmin;
+    }
+    if (ctr) {
+        // pairs summed over the block's threads (rows counted by thread 0)
+        __shared__ unsigned long long red[kThreads / 64];
+        const unsigned long long pw = wave_sum((unsigned long long)my_pairs);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pw;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long pt = 0;
+            for (int w = 0; w < kThreads / 64; ++w) pt += red[w];
+            if (my_rows)
+                atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
+                          (unsigned long long)my_rows);
+            if (pt)
+                atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_PAIRS), pt);
+        }
+    }
+}
+
+template <class P, int DH>
+static hipError_t attn_incr_dh(const ModelDims& m, const DedupIO<P>& d,
+                               const typename P::acc* bstat, int64_t* ctr,
+                               hipStream_t st) {
+    hipLaunchKernelGGL((k_attn_incr<P, DH>), dim3(grid_for(d.n_nb_max * m.nh)),
+                       dim3(kThreads), 0, st, m, d, bstat, ctr);
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_attention_incr(const ModelDims& m, const DedupIO<P>& d,
+                                 const typename P::acc* bstat, int64_t* ctr,
+                                 hipStream_t st) {
+    switch (m.dh) {
+        case 4: return attn_incr_dh<P, 4>(m, d, bstat, ctr, st);
+        case 8: return attn_incr_dh<P, 8>(m, d, bstat, ctr, st);
+        case 16: return attn_incr_dh<P, 16>(m, d, bstat, ctr, st);
+        case 32: return attn_incr_dh<P, 32>(m, d, bstat, ctr, st);
+        case 64: return attn_incr_dh<P, 64>(m, d, bstat, ctr, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------ attention-only half-block
+// Output projection with residual of the half-block that ends the model
+// (no quantizer, no MLP): out = x + a W_o + b_o for a set of rows.  Each
+// wave takes four rows and every lane four output columns, so a row of W_o
+// loaded once serves the four rows; sums over k in order, contraction off
+// so that a row's result does not depend on the other rows of its wave.
+// Rows are addressed through `src`: fn(k) gives (x_in row, a row, out row)
+// of the k-th row of the set.
+constexpr int kOpR = 4;
+template <class P, class F>
+__device__ inline void out_proj_rows(const ModelDims& m,
+                                     const typename P::acc* __restrict__ Wo,
+                                     const typename P::acc* __restrict__ bo,
+                                     int64_t nrows, F fn) {
+#pragma clang fp contract(off)
+    using acc = typename P::acc;
+    using act = typename P::act;
+    const int lane = threadIdx.x & 63;
+    const int d = m.d;
+    const int64_t waves = (int64_t)gridDim.x * (kThreads / 64);
+    for (int64_t r0 = (blockIdx.x * (int64_t)(kThreads / 64) + (threadIdx.x >> 6)) * kOpR;
+         r0 < nrows; r0 += waves * kOpR) {
+        const acc* xin[kOpR];
+        const act* ar[kOpR];
+        acc* out[kOpR];
+        bool ok[kOpR];
+#pragma unroll
+        for (int r = 0; r < kOpR; ++r) {
+            ok[r] = r0 + r < nrows;
+            fn(ok[r] ? r0 + r : r0, xin[r], ar[r], out[r]);
+        }
+        // the rows' attention outputs, 8 columns per lane (d <= 512)
+        acc av[kOpR][8];
+#pragma unroll
+        for (int r = 0; r < kOpR; ++r)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = lane + 64 * j;
+                av[r][j] = k < d ? cvt<acc>(ar[r][k]) : (acc)0;
+            }
+        for (int c0 = 0; c0 < d; c0 += 256) {
+            acc sum[kOpR][4];
+#pragma unroll
+            for (int r = 0; r < kOpR; ++r)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sum[r][u] = 0;
+            for (int k = 0; k < d; ++k) {
+                const int j = k >> 6, src = k & 63;
+                acc w[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int col = c0 + lane + 64 * u;
+                    w[u] = col < d ? Wo[(int64_t)k * d + col] : (acc)0;
+                }
+#pragma unroll
+                for (int r = 0; r < kOpR; ++r) {
+                    acc akv = 0;
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj)
+                        if (jj == j) akv = __shfl(av[r][jj], src, 64);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) sum[r][u] += akv * w[u];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kOpR; ++r) {
+                if (!ok[r]) continue;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int col = c0 + lane + 64 * u;
+                    if (col < d) out[r][col] = xin[r][col] + (sum[r][u] + bo[col]);
+                }
+            }
+        }
+    }
+}
+
+// Rows of a RowSet (full sequences and sampling): in place or into x_out.
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_out_proj(
+    ModelDims m, const typename P::acc* Wo, const typename P::acc* bo,
+    RowSet rows, const typename P::acc* x_in, const typename P::act* a,
+    typename P::acc* x_out) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    const int64_t n = rowset_n(rows);
+    out_proj_rows<P>(m, Wo, bo, n,
+                     [&](int64_t k, const acc*& xi, const act*& ar, acc*& o) {
+                         const int64_t row = rowset_slot(rows, k);
+                         xi = x_in + row * m.d;
+                         ar = a + row * m.d;
+                         o = x_out + row * m.d;
+                     });
+}
+
+template <class P>
+hipError_t launch_out_proj(const ModelDims& m, const typename P::acc* Wo,
+                           const typename P::acc* bo, RowSet rows,
+                           const typename P::acc* x_in,
+                           const typename P::act* a, typename P::acc* x_out,
+                           hipStream_t st) {
+    const int64_t wv = (rows.n_host + kOpR - 1) / kOpR;
+    hipLaunchKernelGGL(k_out_proj<P>, dim3(grid_for((wv + 3) / 4)),
+                       dim3(kThreads), 0, st, m, Wo, bo, rows, x_in, a, x_out);
+    return hipGetLastError();
+}
+
+// The overlay rows of every neighbour (all rows from p_min on): the
+// half-block's input is the neighbour's row where it is in C_L, else the
+// sample's; the output goes to `out` at the same slot.
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_out_proj_overlay(
+    ModelDims m, const typename P::acc* Wo, const typename P::acc* bo,
+    DedupIO<P> dd, typename P::acc* out) {
+    using acc = typename P::acc;
+    using act = typename P::act;
+    const int64_t n = (int64_t)*dd.n_rows;
+    const int W = dd.mask_words;
+    out_proj_rows<P>(m, Wo, bo, n,
+                     [&](int64_t r, const acc*& xi, const act*& ar, acc*& o) {
+                         const int32_t nb = dd.slot_nb[r];
+                         const NbDesc D = dd.desc[nb];
+                         const int i = D.p1 + 1 + (int)(r - D.ov);
+                         const bool inC = mask_bit(dd.mask + (int64_t)nb * W, i);
+                         xi = inC ? dd.ox + r * m.d
+                                  : dd.bx + ((int64_t)D.sigma * m.N + i) * m.d;
+                         ar = dd.oa + r * m.d;
+                         o = out + r * m.d;
+                     });
+}
+
+template <class P>
+hipError_t launch_out_proj_overlay(const ModelDims& m,
+                                   const typename P::acc* Wo,
+                                   const typename P::acc* bo,
+                                   const DedupIO<P>& dd,
+                                   typename P::acc* out, hipStream_t st) {
+    const int64_t wv = (dd.rows_max + kOpR - 1) / kOpR;
+    hipLaunchKernelGGL(k_out_proj_overlay<P>, dim3(grid_for((wv + 3) / 4)),
+                       dim3(kThreads), 0, st, m, Wo, bo, dd, out);
+    return hipGetLastError();
+}
+
+// Every row from p_min on is changed after the half-block: the row masks
+// (read by the output head) become rows p_min .. N-1.
+__global__ void k_mask_from_pmin(const NbDesc* __restrict__ desc,
+                                 const int32_t* n_nb, int W, int N,
+                                 uint64_t* __restrict__ mask) {
+    const int64_t n = (int64_t)*n_nb;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         e < n * W; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t nb = e / W;
+        const int wd = (int)(e - nb * W);
+        const int pmin = desc[nb].p1 + 1;
+        uint64_t v = 0;
+        for (int b = 0; b < 64; ++b) {
+            const int i = wd * 64 + b;
+            if (i >= pmin && i < N) v |= 1ull << b;
+        }
+        mask[e] = v;
+    }
+}
+
+hipError_t launch_mask_from_pmin(const NbDesc* desc, const int32_t* n_nb,
+                                 int64_t n_max, int W, int N, uint64_t* mask,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(k_mask_from_pmin, dim3(grid_for((n_max * W + 255) / 256)),
+                       dim3(256), 0, st, desc, n_nb, W, N, mask);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------- vector quantizer
@@ -983,9 +1345,13 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
             uint64_t* mk = dd.mask + nb * W;
             const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
             const int rowsC[2] = {D.p1 + 1, D.p2 + 1};
-            // spin moved into p1 is s[p2] and vice versa
-            const int tokC[2] = {sp[D.p2] < 0 ? 1 : 0, sp[D.p1] < 0 ? 1 : 0};
-            const int nC = rowsC[1] < N ? 2 : 1;
+            // an exchange moves s[p2] into p1 and s[p1] into p2 (two
+            // changed input tokens, p1 < p2 < N); a flip of p1 (p1 == p2)
+            // changes the one input token at p1 + 1, if there is one
+            const bool flip = D.p1 == D.p2;
+            const int tokC[2] = {flip ? (sp[D.p1] < 0 ? 0 : 1) : (sp[D.p2] < 0 ? 1 : 0),
+                                 sp[D.p1] < 0 ? 1 : 0};
+            const int nC = flip ? (rowsC[0] < N ? 1 : 0) : (rowsC[1] < N ? 2 : 1);
             // every mask word written once, never read back within the kernel
             for (int wd = lane; wd < W; wd += 64) {
                 uint64_t v = 0;
@@ -1013,8 +1379,9 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
                 if (nb >= n) break;
                 const NbDesc D = dd.desc[nb];
                 const int pmin = D.p1 + 1;
-                const int nC = D.p2 + 1 < N ? 2 : 1;
-                dd.list[pos] = D.ov + (D.p1 + 1 - pmin);
+                const int nC = D.p1 == D.p2 ? (pmin < N ? 1 : 0)
+                                            : (D.p2 + 1 < N ? 2 : 1);
+                if (nC >= 1) dd.list[pos] = D.ov + (D.p1 + 1 - pmin);
                 if (nC == 2) dd.list[pos + 1] = D.ov + (D.p2 + 1 - pmin);
                 pos += nC;
             }
@@ -1293,9 +1660,12 @@ __global__ void __launch_bounds__(64) k_head_dedup(
             nc += __popcll(cm);
         }
         __syncthreads();
-        // target of s' at i: exchanged sites swap spins
+        // target of s' at i: exchanged sites swap spins, a flipped site
+        // (p1 == p2) changes sign
+        const bool flip = D.p1 == D.p2;
         auto snew = [&](int i) {
-            return i == D.p1 ? sp[D.p2] : (i == D.p2 ? sp[D.p1] : sp[i]);
+            return i == D.p1 ? (flip ? (int8_t)-sp[i] : sp[D.p2])
+                             : (i == D.p2 ? sp[D.p1] : sp[i]);
         };
         for (int c0 = 0; c0 < nc; c0 += R) {
             const acc* xr[R];
@@ -1335,10 +1705,12 @@ __global__ void __launch_bounds__(64) k_head_dedup(
                 const int64_t brow = (int64_t)D.sigma * N + i;
                 return (double)blp[brow * 2 + tnew] - (double)blp[brow * 2 + told];
             };
-            const double t2 = p2in ? 0.0 : unlisted(D.p2);
+            // a flip has one changed target (p1); an exchange a second one
+            // at p2 unless p2 is a listed row
+            const double t2 = (p2in || flip) ? 0.0 : unlisted(D.p2);
             double delta = 0.0;
             delta += unlisted(D.p1);
-            bool p2done = p2in;
+            bool p2done = p2in || flip;
             for (int c = 0; c < nc; ++c) {
                 if (!p2done && rl[c] > D.p2) {
                     delta += t2;
@@ -1402,6 +1774,15 @@ hipError_t launch_head_dedup(const ModelDims& m, const HeadW<typename P::acc>& h
     template hipError_t launch_head_dedup<P>(                                 \
         const ModelDims&, const HeadW<P::acc>&, const DedupIO<P>&,            \
         const P::acc*, const double*, double*, int64_t*, hipStream_t);        \
+    template hipError_t launch_out_proj<P>(                                   \
+        const ModelDims&, const P::acc*, const P::acc*, RowSet,               \
+        const P::acc*, const P::act*, P::acc*, hipStream_t);                  \
+    template hipError_t launch_out_proj_overlay<P>(                           \
+        const ModelDims&, const P::acc*, const P::acc*, const DedupIO<P>&,    \
+        P::acc*, hipStream_t);                                                \
+    template hipError_t launch_attention_incr<P>(                             \
+        const ModelDims&, const DedupIO<P>&, const P::acc*, int64_t*,         \
+        hipStream_t);                                                         \
     template hipError_t launch_sample_embed<P>(                               \
         const ModelDims&, const HeadW<P::acc>&, int64_t, int, const int8_t*,  \
         P::acc*, int64_t*, double*, hipStream_t);                             \

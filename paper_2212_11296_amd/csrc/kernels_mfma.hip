@@ -134,6 +134,16 @@ hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
     return hipGetLastError();
 }
 
+hipError_t launch_pack_qkv(const ModelDims& m, const float* W_qkv, bf16* out,
+                           hipStream_t st) {
+    const int d = m.d;
+    const int64_t total = (int64_t)d * 3 * d;
+    hipLaunchKernelGGL(k_pack_b, dim3(mgrid((total + 255) / 256)), dim3(256),
+                       0, st, W_qkv, d, 3 * d, (int64_t)3 * d, (int64_t)1, 0,
+                       reinterpret_cast<__bf16*>(out));
+    return hipGetLastError();
+}
+
 bool mfma_shapes_ok(const ModelDims& m) {
     const int KB = m.d / 32;
     return m.d % 32 == 0 && m.dff % 32 == 0 && m.dseg % 32 == 0 &&

@@ -53,6 +53,11 @@ def _cfg(**kw):
     (dict(flags=4), 2),
     (dict(n_heads=16), 5),                # head width 1 unsupported
     (dict(codebook_size=0), 2),
+    (dict(hamiltonian=1), 2),             # chain with the Marshall flag
+    (dict(hamiltonian=1, marshall=0, L=1025), 2),   # chain longer than 1024
+    (dict(hamiltonian=1, marshall=0, L=2), 2),      # periodic chain of 2
+    (dict(hamiltonian=1, marshall=0, gamma=float("nan")), 2),
+    (dict(hamiltonian=5), 2),
 ])
 def test_invalid_configs_rejected(kw, status):
     lib = vq.load_library()

@@ -38,55 +38,13 @@ from workloads import (CONFIGS, MULTI_LATTICE, make_params, make_spins,
                        with_batch)
 
 from gpu_common import dev_params, dev_spins, host, needs_gpu, say
+from gpu_parity import check_ratios
 from near_tie import explain
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
 FP32_RATIO_TOL = 1e-4
 BF16_RATIO_TOL = 1e-3
-
-
-def _check_ratios(mc, P, cfg, p, spins, R, picks, tol):
-    """Compares R[b][k] with the oracle for (b, k) in picks; entries beyond
-    tol must be proven near-ties.  Returns (relative errors, explained)."""
-    bl = lattice.bonds(mc.L, mc.periodic)
-    seqs, owner = [], []
-    for b, ks in picks:
-        nb = lattice.neighbours(spins[b], bl)
-        seqs.append(spins[b])
-        owner.append((b, -1))
-        for k in ks:
-            seqs.append(lattice.swap(spins[b], nb[k][1], nb[k][2]))
-            owner.append((b, k))
-    seqs = np.stack(seqs)
-    ref = net.forward(mc, P, seqs, keep=True)
-    lp0 = {b: ref["logpsi"][j] for j, (b, k) in enumerate(owner) if k < 0}
-    rel = np.array([abs(R[b, k] / np.exp(ref["logpsi"][j] - lp0[b]) - 1)
-                    if k >= 0 else 0.0 for j, (b, k) in enumerate(owner)])
-    bad = [j for j, (b, k) in enumerate(owner) if k >= 0 and rel[j] > tol]
-    explained = []
-    if bad:
-        # the sample's own sequence and the neighbour's, both checked
-        idx = sorted(set(bad) | {owner.index((owner[j][0], -1)) for j in bad})
-        _, gcd, gat = vq.forward_activations(cfg, p, dev_spins(seqs[idx]))
-        gcd, gat = host(gcd), host(gat)
-        ocd = np.transpose(ref["codes"], (1, 0, 2, 3))
-        cbs = [lay["codebook"] for lay in P["layers"]]
-        pos = {j: i for i, j in enumerate(idx)}
-        for j in bad:
-            b, k = owner[j]
-            js = owner.index((b, -1))
-            exs = []
-            for jj in (js, j):
-                oa = np.stack([c["a"][jj] for c in ref["caches"]])
-                exs.append(explain(cbs, gcd[pos[jj]], gat[pos[jj]], ocd[jj],
-                                   oa))
-            say(f"{mc.name} ({b},{k}) rel err {rel[j]:.3e}: {exs}")
-            found = [e for e in exs if e is not None]
-            assert found, f"unexplained ratio error at {(b, k)}: {rel[j]}"
-            assert all(e["ok"] for e in found), ((b, k), found)
-            explained.append((b, k))
-    return rel[[k >= 0 for _, k in owner]], explained
 
 
 def test_medium_fp32_local_energy_every_neighbour():
@@ -113,7 +71,7 @@ def test_medium_fp32_local_energy_every_neighbour():
     bl = lattice.bonds(mc.L, mc.periodic)
     picks = [(b, range(len(lattice.neighbours(s[b], bl))))
              for b in range(mc.batch)]
-    rel, explained = _check_ratios(mc, P, cfg, p, s, R, picks,
+    rel, explained = check_ratios(mc, P, cfg, p, s, R, picks,
                                    FP32_RATIO_TOL)
     say(f"fp32 ratios: n={rel.size} median={np.median(rel):.2e} "
         f"max={rel.max():.2e}, {len(explained)} explained")
@@ -167,7 +125,7 @@ def test_multi_lattice_full_batches_against_oracle():
             ks = (range(len(nb)) if mc.L <= 12 else
                   sorted(rng.choice(len(nb), 8, replace=False)))
             picks.append((int(b), ks))
-        rel, explained = _check_ratios(mc, P, cfg, p, s, R, picks,
+        rel, explained = check_ratios(mc, P, cfg, p, s, R, picks,
                                        BF16_RATIO_TOL)
         say(f"{mc.name}: {rel.size} ratios, median={np.median(rel):.2e} "
             f"max={rel.max():.2e}, {len(explained)} explained")

@@ -3,11 +3,16 @@ against the FP64 oracle, through the C ABI.
 
 FP64: per-sample and weighted gradients within 1e-9 of the largest entry
 (the two sides add in different orders; distances are expanded on the GPU
-and taken directly in the oracle).  FP32: within 1e-4 in norm.  BF16 at the
-20x20 shapes (d=256, 12 layers, Q=1024): the forward decides codes in its
-own precision; on samples whose codes all equal the oracle's, the gradient
-must agree within 2e-3 in norm; samples with a differing code must show a
-valid near-tie there (checked like the forward's codes)."""
+and taken directly in the oracle).  FP32 and BF16: every parameter tensor
+(each embedding, LayerNorm gain and bias, weight matrix, bias and codebook
+of every layer, and the head) separately, its largest entry error within
+FP32_BLOCK_TOL = 1e-4 (FP32) or BF16_BLOCK_TOL = 1e-2 (BF16; the forward
+and its recompute run on the matrix core at the hi/lo split's 2^-17) of
+that tensor's largest entry, so an error in a small tensor cannot hide in
+the norm of the whole vector.  In BF16 the forward decides codes in its own
+precision: samples whose codes all equal the oracle's are compared, and a
+sample with a differing code must be a proven near-tie
+(tests/near_tie.py)."""
 from dataclasses import replace
 
 import numpy as np
@@ -20,6 +25,8 @@ from oracle import network as net
 from workloads import CONFIGS, make_params, make_spins, with_batch
 
 from gpu_common import dev_params, dev_spins, host, needs_gpu, say
+from gpu_parity import check_sequences
+from workloads import param_layout
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -34,6 +41,28 @@ def rel_max(a, b):
 
 def rel_norm(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+FP32_BLOCK_TOL = 1e-4
+BF16_BLOCK_TOL = 1e-2
+
+
+def check_blocks(mc, g, ref, tol, label=""):
+    """Every parameter tensor separately: largest entry error over the
+    tensor's largest reference entry below tol (a tensor whose reference is
+    exactly zero must come out exactly zero)."""
+    worst = ("", 0.0)
+    for name, shape, kind, off, n in param_layout(mc):
+        a, b = g[off:off + n], ref[off:off + n]
+        scale = np.abs(b).max()
+        if scale == 0.0:
+            assert not np.any(a), (label, name)
+            continue
+        e = np.abs(a - b).max() / scale
+        if e > worst[1]:
+            worst = (name, e)
+        assert e < tol, (label, name, e)
+    say(f"{label} worst tensor {worst[0]}: {worst[1]:.2e}")
 
 
 @pytest.mark.parametrize("mc", [with_batch(CONFIGS["small"], 4), TWO_VQ,
@@ -92,27 +121,7 @@ def test_grad_f32_medium():
     ref = og.grad_logpsi(mc, theta, s)
     G = host(g).astype(np.float64)
     for b in range(mc.batch):
-        assert rel_norm(G[b], ref[b]) < 1e-4
-
-
-def _codes_match_or_near_tie(mc, theta, s, gpu_codes):
-    """True where every code equals the oracle's; asserts that a sample with
-    a differing code has a valid near-tie at its first differing layer."""
-    ref = net.forward(mc, net.unpack(mc, theta), s, keep=True)
-    oc = np.transpose(ref["codes"], (1, 0, 2, 3))          # [B][nl][N][H]
-    same = []
-    for b in range(s.shape[0]):
-        diff = gpu_codes[b] != oc[b]
-        if not diff.any():
-            same.append(True)
-            continue
-        l = int(np.nonzero(diff.any(axis=(1, 2)))[0][0])
-        rows, heads = np.nonzero(diff[l])
-        c = ref["caches"][l]
-        gap = c["d2"][b, rows, heads] - c["d1"][b, rows, heads]
-        assert (gap < 1e-3 * (1 + c["d1"][b, rows, heads])).all(), (b, l)
-        same.append(False)
-    return np.array(same)
+        check_blocks(mc, G[b], ref[b], FP32_BLOCK_TOL, f"fp32 sample {b}")
 
 
 def test_grad_bf16_grad_shapes_sampled():
@@ -126,13 +135,12 @@ def test_grad_bf16_grad_shapes_sampled():
     cfg = vq.make_config(mc)
     p, sp = dev_params(theta, "bf16"), dev_spins(s)
     g = host(vq.grad_logpsi(cfg, p, sp)).astype(np.float64)
-    _, codes = vq.forward_logpsi(cfg, p, sp, codes=True)
-    same = _codes_match_or_near_tie(mc, theta, s, host(codes))
-    idx = np.nonzero(same)[0][:2]
+    flips, _ = check_sequences(mc, net.unpack(mc, theta), cfg, p, s, 1e-3)
+    idx = [b for b in range(mc.batch) if b not in flips][:2]
     assert len(idx) >= 1
     ref = og.grad_logpsi(mc, theta, s[idx])
     for j, b in enumerate(idx):
-        assert rel_norm(g[b], ref[j]) < 2e-3, b
+        check_blocks(mc, g[b], ref[j], BF16_BLOCK_TOL, f"bf16 sample {b}")
 
 
 ODD_BF16 = replace(CONFIGS["medium"], name="odd_bf16", L=5, periodic=False,
@@ -152,13 +160,12 @@ def test_grad_bf16_row_count_not_multiple_of_four():
     cfg = vq.make_config(mc)
     p, sp = dev_params(theta, "bf16"), dev_spins(s)
     g = host(vq.grad_logpsi(cfg, p, sp)).astype(np.float64)
-    _, codes = vq.forward_logpsi(cfg, p, sp, codes=True)
-    same = _codes_match_or_near_tie(mc, theta, s, host(codes))
-    idx = np.nonzero(same)[0]
+    flips, _ = check_sequences(mc, net.unpack(mc, theta), cfg, p, s, 1e-3)
+    idx = [b for b in range(mc.batch) if b not in flips]
     assert len(idx) >= 1
     ref = og.grad_logpsi(mc, theta, s[idx])
     for j, b in enumerate(idx):
-        assert rel_norm(g[b], ref[j]) < 2e-3, b
+        check_blocks(mc, g[b], ref[j], BF16_BLOCK_TOL, f"bf16 odd sample {b}")
     w = torch.linspace(-1.0, 1.0, mc.batch, dtype=torch.float64, device="cuda")
     gw = host(vq.grad_logpsi(cfg, p, sp, weights=w)).astype(np.float64)
     assert rel_norm(gw, host(w) @ g) < 1e-5

@@ -9,6 +9,8 @@ self-attention, Sec. 3.1) at the sizes this project measures:
   large   16x16, d=128, 8 layers, 8 heads, MLP 512,  Q=1024, B=8192, bf16
   multi   6x6..20x20 lattices, d=128, 6 layers, 8 heads, MLP 512, Q=512, bf16
   grad    20x20, d=256, 12 layers, 8 heads, MLP 1024, Q=1024, B=2048, bf16
+  table1  the paper's Table 1 network (3 blocks + attention-only half-block,
+          d=256, 8 heads, 64 codes) on the open 8x8 lattice, B=4096, bf16
   tfim    1-D transverse-field Ising chain of 384 sites (open, Gamma = J = 1),
           d=256, 1 layer, 8 heads, MLP 1024, 4 x 64 codes, B=2048, bf16
 
@@ -84,6 +86,15 @@ CONFIGS["tfim_small"] = ModelConfig("tfim_small", L=10, d_model=16,
                                     precision="f64", batch=64,
                                     spin_seed=1007, hamiltonian="tfim",
                                     gamma=1.0)
+
+# The architecture of the paper's Table 1: three VQ transformer blocks and
+# an attention-only half-block (no quantizer), width 256, 8 heads, one
+# quantizer head of 64 codes (the table's 6-bit column), on the open 8x8
+# lattice (Sec. 4); seeded random weights stand in for the distilled ones.
+CONFIGS["table1"] = ModelConfig("table1", L=8, d_model=256, n_layers=3,
+                                n_heads=8, d_ff=1024, codebook_size=64,
+                                vq_heads=1, periodic=False, precision="bf16",
+                                batch=4096, spin_seed=1008, attn_tail=True)
 
 # Mixed-lattice batch: one parameter buffer per lattice, uneven sample counts.
 MULTI_LATTICE = tuple(
