@@ -141,6 +141,7 @@ struct LayerW {
     const bf16* W1_p;
     const bf16* W2_p;
     const bf16* cb_p;
+    const bf16* Wo_p;    // W_o pack of the attention-only half-block
 };
 
 template <typename C>

@@ -62,7 +62,7 @@ struct Workspace {
     acc* cnorm;   // [nl][H*Q + H]
     float* prm;   // BF16 mode: parameters rounded to bfloat16
     bf16 *wqkv_p, *w1_p, *w2_p, *cb_p;   // [nl] matrix-core fragment packs
-    bf16* wqkv_tp;                       // the half-block's QKV pack
+    bf16 *wqkv_tp, *wo_tp;               // the half-block's QKV and W_o packs
     float* cnh4;                         // [nl][H*Q*4] -cnorm/2, four copies
     // chunk neighbour bookkeeping
     int16_t* bonds;
@@ -130,7 +130,10 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
             w.w2_p = c.take<bf16>((size_t)m.nl * m.dff * d);
             w.cb_p = c.take<bf16>((size_t)m.nl * m.Q * d);
             w.cnh4 = c.take<float>((size_t)m.nl * H * m.Q * 4);
-            if (m.tail) w.wqkv_tp = c.take<bf16>((size_t)d * 3 * d);
+            if (m.tail) {
+                w.wqkv_tp = c.take<bf16>((size_t)d * 3 * d);
+                w.wo_tp = c.take<bf16>((size_t)d * d);
+            }
         }
     }
     w.bonds = c.take<int16_t>(n * 2 * N);
@@ -472,8 +475,26 @@ struct Runner {
     HeadW<acc> head() const { return head_view<acc>(m, params); }
     LayerW<acc> tail() const {
         LayerW<acc> tw = tail_view<acc>(m, params);
-        if (m.mfma) tw.Wqkv_p = w.wqkv_tp;
+        if (m.mfma) {
+            tw.Wqkv_p = w.wqkv_tp;
+            tw.Wo_p = w.wo_tp;
+        }
         return tw;
+    }
+    // the half-block's output projection with residual, out = x + a W_o + b_o
+    hipError_t tail_proj(const LayerW<acc>& tw, RowSet rs, const acc* x_in,
+                         const act* a, acc* x_out) {
+        if constexpr (std::is_same<P, PrecBF16>::value)
+            if (m.mfma)
+                return launch_oproj_mfma(m, tw.b_o, tw.Wo_p, rs, x_in, a, x_out, st);
+        return launch_out_proj<P>(m, tw.W_o, tw.b_o, rs, x_in, a, x_out, st);
+    }
+    hipError_t tail_proj_overlay(const LayerW<acc>& tw, const DedupIO<P>& dd,
+                                 acc* out) {
+        if constexpr (std::is_same<P, PrecBF16>::value)
+            if (m.mfma)
+                return launch_oproj_overlay_mfma(m, tw.b_o, tw.Wo_p, dd, out, st);
+        return launch_out_proj_overlay<P>(m, tw.W_o, tw.b_o, dd, out, st);
     }
 
     vqnqs_status prepare() {
@@ -496,9 +517,11 @@ struct Runner {
                                          const_cast<float*>(lw.cnh4), st));
         }
         if constexpr (std::is_same<P, PrecBF16>::value)
-            if (m.mfma && m.tail)
-                LK("pack_layer", launch_pack_qkv(m, tail_view<acc>(m, params).W_qkv,
-                                                 w.wqkv_tp, st));
+            if (m.mfma && m.tail) {
+                const LayerW<acc> tv = tail_view<acc>(m, params);
+                LK("pack_layer", launch_pack_qkv(m, tv.W_qkv, w.wqkv_tp, st));
+                LK("pack_layer", launch_pack_wo(m, tv.W_o, w.wo_tp, st));
+            }
         return VQNQS_OK;
     }
 
@@ -568,8 +591,7 @@ struct Runner {
             const LayerW<acc> tw = tail();
             LK("qkv", qkv(tw, rs, qio));
             LK("attention_seq", attn_seq(n_dev, n, io, count_rows ? ctr : nullptr));
-            LK("tail_proj", launch_out_proj<P>(m, tw.W_o, tw.b_o, rs, io.x_in, io.a,
-                                               io.x, st));
+            LK("tail_proj", tail_proj(tw, rs, io.x_in, io.a, io.x));
         }
         const acc* xf = b.x + (per_layer_x ? (int64_t)(m.nl + m.tail) * sd : 0);
         LK("head_seq", launch_head_seq<P>(m, head(), b.spins, n_dev, n, xf, b.lp, b.logpsi, st));
@@ -834,8 +856,7 @@ struct Runner {
                 const LayerW<acc> tw = tail();
                 LK("qkv", qkv(tw, rs, io));
                 LK("attention_rows", launch_attn_rows<P>(m, n, i, io, st));
-                LK("tail_proj", launch_out_proj<P>(m, tw.W_o, tw.b_o, rs, w.bx, w.ba,
-                                                   w.bx, st));
+                LK("tail_proj", tail_proj(tw, rs, w.bx, w.ba, w.bx));
             }
             LK("sample_head", launch_sample_head<P>(m, head(), n, i, w.bx,
                                                     uni + 0, spins, w.logpsi_s,
@@ -986,7 +1007,7 @@ struct Runner {
             if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_QKV_ROWS, w.list_n, 1, st));
             LK("qkv", qkv(tw, cl, io));
             LK("attention_dedup", attn_dedup(dd));
-            LK("tail_proj", launch_out_proj_overlay<P>(m, tw.W_o, tw.b_o, dd, w.oq, st));
+            LK("tail_proj", tail_proj_overlay(tw, dd, w.oq));
             LK("tail_mask", launch_mask_from_pmin(w.desc, w.n_nb, nbmax, dd.mask_words,
                                                   m.N, w.mask, st));
             dd.ox = w.oq;

@@ -212,6 +212,16 @@ hipError_t launch_mask_from_pmin(const NbDesc* desc, const int32_t* n_nb,
                                  hipStream_t st);
 hipError_t launch_pack_qkv(const ModelDims& m, const float* W_qkv, bf16* out,
                            hipStream_t st);
+hipError_t launch_pack_wo(const ModelDims& m, const float* W_o, bf16* out,
+                          hipStream_t st);
+// the half-block's output projection on the matrix core (BF16 mode)
+hipError_t launch_oproj_mfma(const ModelDims& m, const float* bo,
+                             const bf16* Wo_p, RowSet rows, const float* x_in,
+                             const float* a, float* x_out, hipStream_t st);
+hipError_t launch_oproj_overlay_mfma(const ModelDims& m, const float* bo,
+                                     const bf16* Wo_p,
+                                     const DedupIO<PrecBF16>& dd, float* out,
+                                     hipStream_t st);
 template <class P>
 hipError_t launch_attention_incr(const ModelDims& m, const DedupIO<P>& d,
                                  const typename P::acc* bstat, int64_t* ctr,

@@ -923,6 +923,216 @@ __global__ void __launch_bounds__(kMT)
     }
 }
 
+// ------------------------------------- half-block output projection
+// out = x_in + (a W_o + b_o) for a set of rows (the attention-only block
+// that ends the Table 1 networks): the attention output a, split hi/lo, is
+// the A operand; W_o, packed like the QKV weights, streams through two LDS
+// stages shared by the four waves (global-to-LDS loads one chunk ahead, as
+// in k_qkv_mfma).  The matrix core sums the k-blocks of one row in a fixed
+// order, so a row's result depends on that row only: full sequences,
+// sampled rows and neighbour overlays give equal values for equal inputs.
+// A row source gives, for the k-th row of the set, its residual input, its
+// attention output and its destination (the destination may be the input:
+// every element is read and written by one lane).
+struct OprojRows {
+    RowSet rows;
+    const float* x_in;
+    const float* a;
+    float* x_out;
+    int d;
+    __device__ int64_t n() const { return rs_n(rows); }
+    __device__ void at(int64_t k, const float*& xi, const float*& ar,
+                       float*& o) const {
+        const int64_t s = rs_slot(rows, k) * d;
+        xi = x_in + s;
+        ar = a + s;
+        o = x_out + s;
+    }
+};
+// Overlay rows of the neighbours (every row from p_min on): the input is
+// the neighbour's row where it is in C_L, else the sample's.
+struct OprojOverlay {
+    const int32_t* n_rows;
+    const int32_t* slot_nb;
+    const NbDesc* desc;
+    const uint64_t* mask;
+    int W, N, d;
+    const float* ox;
+    const float* bx;
+    const float* oa;
+    float* out;
+    __device__ int64_t n() const { return (int64_t)*n_rows; }
+    __device__ void at(int64_t r, const float*& xi, const float*& ar,
+                       float*& o) const {
+        const int32_t nb = slot_nb[r];
+        const NbDesc D = desc[nb];
+        const int i = D.p1 + 1 + (int)(r - D.ov);
+        const bool inC = (mask[(int64_t)nb * W + (i >> 6)] >> (i & 63)) & 1ull;
+        xi = inC ? ox + r * d : bx + ((int64_t)D.sigma * N + i) * d;
+        ar = oa + r * d;
+        o = out + r * d;
+    }
+};
+
+template <int KB, class Src>
+__global__ void __launch_bounds__(kMT)
+    __attribute__((amdgpu_waves_per_eu(KB <= 4 ? 3 : 2)))
+    k_oproj_mfma(Src src, const float* __restrict__ bo,
+                 const bf16x8* __restrict__ Bp) {
+    constexpr int D = KB * 32, NBC = 4;
+    constexpr int CHUNK = NBC * KB * 64, PER = CHUNK / kMT;
+    constexpr int NBT = D / 16;
+    constexpr int nchunk = NBT / NBC;
+    static_assert(NBT % NBC == 0, "whole chunks");
+    __shared__ bf16x8 stage0[CHUNK], stage1[CHUNK];
+    __shared__ float bias0[NBC * 16], bias1[NBC * 16];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int gq = lane >> 4, c16 = lane & 15;
+    const int64_t n = src.n();
+    const int64_t ntile = (n + 63) / 64;          // 16 rows per wave
+    auto fetch = [&](int c, bf16x8* st, float* bs) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k)
+            lds_dma16(Bp + (int64_t)c * CHUNK + threadIdx.x + k * kMT,
+                      st + wave * 64 + k * kMT);
+        if (wave == 0) lds_dma4(bo + c * NBC * 16 + lane, bs);
+    };
+    bool ahead = false;      // the tile's first chunk is in stage0
+    for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+        // row c16 of the wave's 16: A fragments of its attention output
+        const int64_t r = t * 64 + wave * 16 + c16;
+        const float *xi = nullptr, *ar = nullptr;
+        float* op = nullptr;
+        if (r < n) src.at(r, xi, ar, op);
+        bf16x8 ah[KB], al[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            float v[8];
+            if (ar) {
+                const float4* p = reinterpret_cast<const float4*>(ar + kb * 32 + 8 * gq);
+                const float4 v0 = p[0], v1 = p[1];
+                v[0] = v0.x; v[1] = v0.y; v[2] = v0.z; v[3] = v0.w;
+                v[4] = v1.x; v[5] = v1.y; v[6] = v1.z; v[7] = v1.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                __bf16 h, l;
+                split1(v[j], h, l);
+                ah[kb][j] = h;
+                al[kb][j] = l;
+            }
+        }
+        // the result layout holds rows 4 gq + q (q = 0..3) of the 16
+        int64_t oxi[4], oo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            oxi[q] = __shfl((int64_t)(uintptr_t)xi, 4 * gq + q, 64);
+            oo[q] = __shfl((int64_t)(uintptr_t)op, 4 * gq + q, 64);
+        }
+        if (!ahead) {
+            __syncthreads();                 // both stages free
+            fetch(0, stage0, bias0);
+        }
+        float ov[NBC][4];                    // a W_o + b_o of the pending chunk
+        float xv[NBC][4];                    // its residual inputs
+        auto load_x = [&](int c) {
+#pragma unroll
+            for (int nbl = 0; nbl < NBC; ++nbl)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int col = (c * NBC + nbl) * 16 + c16;
+                    xv[nbl][q] = oo[q] ? reinterpret_cast<const float*>(oxi[q])[col]
+                                       : 0.0f;
+                }
+        };
+        auto flush = [&](int c) {
+#pragma unroll
+            for (int nbl = 0; nbl < NBC; ++nbl)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int col = (c * NBC + nbl) * 16 + c16;
+                    if (oo[q]) reinterpret_cast<float*>(oo[q])[col] = xv[nbl][q] + ov[nbl][q];
+                }
+        };
+        auto chunk = [&](int c, const bf16x8* sb, const float* bs, bf16x8* nsb,
+                         float* nbs, bool into0) {
+            wait_vmem();
+            __syncthreads();
+            if (c + 1 < nchunk) {
+                fetch(c + 1, nsb, nbs);
+            } else {
+                ahead = into0 && t + gridDim.x < ntile;
+                if (ahead) fetch(0, nsb, nbs);
+            }
+            if (c > 0) flush(c - 1);
+            load_x(c);
+#pragma unroll
+            for (int nbl = 0; nbl < NBC; ++nbl) {
+                f32x4 acc = f32x4{0, 0, 0, 0};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) {
+                    const bf16x8 b = sb[(nbl * KB + kb) * 64 + lane];
+                    acc = mfma(ah[kb], b, acc);
+                    acc = mfma(al[kb], b, acc);
+                }
+                const float bias = bs[nbl * 16 + c16];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ov[nbl][q] = acc[q] + bias;
+            }
+        };
+        for (int c = 0; c < nchunk; c += 2) {
+            chunk(c, stage0, bias0, stage1, bias1, false);
+            if (c + 1 < nchunk) chunk(c + 1, stage1, bias1, stage0, bias0, true);
+        }
+        flush(nchunk - 1);
+    }
+}
+
+template <class Src>
+static hipError_t oproj_go(const ModelDims& m, Src src, int64_t rows_max,
+                           const float* bo, const bf16* Wo_p, hipStream_t st) {
+    if (rows_max <= 0) return hipSuccess;
+    const bf16x8* B = reinterpret_cast<const bf16x8*>(Wo_p);
+    const dim3 g(mgrid((rows_max + 63) / 64));
+    switch (m.d / 32) {
+        case 2: hipLaunchKernelGGL((k_oproj_mfma<2, Src>), g, dim3(kMT), 0, st, src, bo, B); break;
+        case 4: hipLaunchKernelGGL((k_oproj_mfma<4, Src>), g, dim3(kMT), 0, st, src, bo, B); break;
+        case 8: hipLaunchKernelGGL((k_oproj_mfma<8, Src>), g, dim3(kMT), 0, st, src, bo, B); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_oproj_mfma(const ModelDims& m, const float* bo,
+                             const bf16* Wo_p, RowSet rows, const float* x_in,
+                             const float* a, float* x_out, hipStream_t st) {
+    return oproj_go(m, OprojRows{rows, x_in, a, x_out, m.d}, rows.n_host, bo,
+                    Wo_p, st);
+}
+
+hipError_t launch_oproj_overlay_mfma(const ModelDims& m, const float* bo,
+                                     const bf16* Wo_p,
+                                     const DedupIO<PrecBF16>& dd, float* out,
+                                     hipStream_t st) {
+    const OprojOverlay src{dd.n_rows, dd.slot_nb, dd.desc, dd.mask,
+                           dd.mask_words, m.N, m.d, dd.ox, dd.bx, dd.oa, out};
+    return oproj_go(m, src, dd.rows_max, bo, Wo_p, st);
+}
+
+hipError_t launch_pack_wo(const ModelDims& m, const float* W_o, bf16* out,
+                          hipStream_t st) {
+    const int d = m.d;
+    const int64_t total = (int64_t)d * d;
+    hipLaunchKernelGGL(k_pack_b, dim3(mgrid((total + 255) / 256)), dim3(256),
+                       0, st, W_o, d, d, (int64_t)d, (int64_t)1, 0,
+                       reinterpret_cast<__bf16*>(out));
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ launchers
 // Launch choices per model width (rows per wave of the three products).
 // Every row's arithmetic is the same whichever is chosen: the choices trade

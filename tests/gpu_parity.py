@@ -6,6 +6,7 @@ import numpy as np
 import paper_2212_11296_amd as vq
 from oracle import lattice
 from oracle import network as net
+from workloads import param_layout
 
 from gpu_common import dev_spins, host, say
 from near_tie import explain
@@ -92,3 +93,28 @@ def adjusted_eloc(mc, E, E_ref, R, r_ref, explained):
         E_adj[b] -= h * R[b, k]
         E_ref_adj[b] -= h * r_ref[b][k]
     return E_adj, E_ref_adj
+
+
+# Gradient tolerances per parameter tensor: its largest entry error over its
+# largest reference entry (FP32; BF16, whose forward and recompute run on
+# the matrix core at the hi/lo split's 2^-17).
+FP32_BLOCK_TOL = 1e-4
+BF16_BLOCK_TOL = 1e-2
+
+
+def check_blocks(mc, g, ref, tol, label=""):
+    """Every parameter tensor separately: largest entry error over the
+    tensor's largest reference entry below tol (a tensor whose reference is
+    exactly zero must come out exactly zero)."""
+    worst = ("", 0.0)
+    for name, shape, kind, off, n in param_layout(mc):
+        a, b = g[off:off + n], ref[off:off + n]
+        scale = np.abs(b).max()
+        if scale == 0.0:
+            assert not np.any(a), (label, name)
+            continue
+        e = np.abs(a - b).max() / scale
+        if e > worst[1]:
+            worst = (name, e)
+        assert e < tol, (label, name, e)
+    say(f"{label} worst tensor {worst[0]}: {worst[1]:.2e}")

@@ -25,8 +25,8 @@ from oracle import network as net
 from workloads import CONFIGS, make_params, make_spins, with_batch
 
 from gpu_common import dev_params, dev_spins, host, needs_gpu, say
-from gpu_parity import check_sequences
-from workloads import param_layout
+from gpu_parity import (BF16_BLOCK_TOL, FP32_BLOCK_TOL, check_blocks,
+                         check_sequences)
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -42,27 +42,6 @@ def rel_max(a, b):
 def rel_norm(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
-
-FP32_BLOCK_TOL = 1e-4
-BF16_BLOCK_TOL = 1e-2
-
-
-def check_blocks(mc, g, ref, tol, label=""):
-    """Every parameter tensor separately: largest entry error over the
-    tensor's largest reference entry below tol (a tensor whose reference is
-    exactly zero must come out exactly zero)."""
-    worst = ("", 0.0)
-    for name, shape, kind, off, n in param_layout(mc):
-        a, b = g[off:off + n], ref[off:off + n]
-        scale = np.abs(b).max()
-        if scale == 0.0:
-            assert not np.any(a), (label, name)
-            continue
-        e = np.abs(a - b).max() / scale
-        if e > worst[1]:
-            worst = (name, e)
-        assert e < tol, (label, name, e)
-    say(f"{label} worst tensor {worst[0]}: {worst[1]:.2e}")
 
 
 @pytest.mark.parametrize("mc", [with_batch(CONFIGS["small"], 4), TWO_VQ,

@@ -8,7 +8,9 @@ rule) against the FP64 oracle, through the C ABI.
 * FP64, 4x4: the histogram of 2^18 GPU samples over all 2^16
   configurations follows exp(2 log psi) from the oracle's exact enumeration
   (chi-square on bins of expected count >= 10, p > 1e-3).
-* FP32 10x10 and BF16 16x16: every draw of every sample agrees with the
+* FP32 10x10, BF16 16x16 and the BF16 Table 1 network (3 blocks and the
+  attention-only half-block, open 8x8): every draw of every sample agrees
+  with the
   oracle's conditional at the GPU's own prefix (one oracle forward pass of
   each drawn sequence gives all its conditionals), except where the
   uniform number lies within DRAW_TOL of the oracle's probability (the
@@ -104,9 +106,10 @@ def test_sample_fp32_medium_draws_and_logpsi():
     assert np.abs(lp - ref["logpsi"]).max() < 1e-5
 
 
-def test_sample_bf16_large_draws_and_logpsi():
-    mc = with_batch(CONFIGS["large"], 16)
-    say("sample bf16 16x16")
+@pytest.mark.parametrize("name", ["large", "table1"])
+def test_sample_bf16_draws_and_logpsi(name):
+    mc = with_batch(CONFIGS[name], 16)
+    say(f"sample bf16 {name}")
     theta = make_params(mc)
     u = _uniforms(mc.batch, mc.N, 33)
     cfg = vq.make_config(mc)

@@ -11,6 +11,9 @@ paper's Table 1), against the FP64 oracle, through the C ABI.
   near-ties; dedup equal to plain on a small batch.
 * FP64 straight-through gradient through the half-block against the
   oracle's within 1e-9 of its largest entry; a VMC step runs.
+* BF16 Table 1 network (the half-block's projection on the matrix core):
+  the gradient of seeded samples per parameter tensor within 1e-2 of the
+  oracle's (its sampling is checked in tests/test_gpu_sample.py).
 """
 from dataclasses import replace
 
@@ -26,7 +29,8 @@ from oracle import sampling
 from workloads import CONFIGS, make_params, make_spins, with_batch
 
 from gpu_common import dev_params, dev_spins, host, needs_gpu, say
-from gpu_parity import check_ratios
+from gpu_parity import (BF16_BLOCK_TOL, check_blocks, check_ratios,
+                         check_sequences)
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -120,3 +124,20 @@ def test_tail_gradient_fp64_and_vmc_step():
                    generator=torch.Generator(device="cuda").manual_seed(3))
     out = vq.vmc_step(cfg, p, u, 0.01)
     assert np.isfinite(host(out["stats"])).all()
+
+
+def test_tail_bf16_table1_gradient():
+    from oracle import grad as og
+    mc = with_batch(CONFIGS["table1"], 4)
+    say("half-block bf16 table-1 gradient")
+    theta = make_params(mc)
+    cfg = vq.make_config(mc)
+    p = dev_params(theta, "bf16")
+    s = make_spins(mc)
+    g = host(vq.grad_logpsi(cfg, p, dev_spins(s))).astype(np.float64)
+    flips, _ = check_sequences(mc, net.unpack(mc, theta), cfg, p, s, 1e-3)
+    idx = [b for b in range(mc.batch) if b not in flips][:2]
+    assert len(idx) >= 1
+    ref = og.grad_logpsi(mc, theta, s[idx])
+    for j, b in enumerate(idx):
+        check_blocks(mc, g[b], ref[j], BF16_BLOCK_TOL, f"table-1 sample {b}")
