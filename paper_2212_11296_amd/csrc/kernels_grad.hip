@@ -1232,6 +1232,233 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_kv(int64_t n, ModelDims m,
     }
 }
 
+// ------------------------------------ attention backward on the matrix core
+// The dq pass and the key-side pass of the FP32 arithmetic on the matrix
+// core: v_mfma_f32_16x16x4_f32, where lane l holds A[l%16][l/16] and
+// B[l/16][l%16] of a 16x4 by 4x16 product and D[4(l/16)+r][l%16] (r < 4).
+// The quantities are those of k_attn_bwd_q / k_attn_bwd_kv in FP32 (no
+// operand splitting), summed in another order.  A wave owns a tile of 16
+// queries (dq pass) or 16 keys (key-side pass) and walks the blocks of 16
+// keys (queries) it attends to; the other side's rows sit in LDS as FP32
+// rows of stride DH + 4.
+//
+// dq pass, per key block: S^T = K Q^T and dP^T = V dO^T leave lane
+// (g, c) with keys 4g..4g+3 of query c; dS^T = P^T (dP^T - Dd) is then the
+// B operand of dq^T += K^T dS^T when the contraction index of k-step kk in
+// lane group g is key 4g + kk (the A operand reads K in the same order).
+// The key-side pass is the mirror image: S = Q K^T and dP = dO V^T leave
+// lane (g, c) with queries 4g..4g+3 of key c, the B operand of
+// dv^T += dO^T P and dk^T += Q^T dS.
+typedef __attribute__((ext_vector_type(4))) float f32x4b;
+
+__device__ inline f32x4b mfma_f32(float a, float b, f32x4b c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int DH>
+constexpr int kBwdLd = DH + 4;      // LDS row stride in floats
+
+// Rows 0..Np-1 (Np = N rounded up to 16) of one head into an LDS tile of
+// stride LD; rows from N on are zero (they enter products as exact zeros).
+template <int DH, int LD, int NT>
+__device__ inline void fill_rows(float* dst, const float* src, int64_t base,
+                                 int N, int Np, int d) {
+    constexpr int G = DH / 4, U = 4;
+    const int tot = Np * G;
+    for (int e0 = 0; e0 < tot; e0 += NT * U) {
+        float4 v[U];
+        int row[U], c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + NT * u + (int)threadIdx.x;
+            const int ec = e < tot ? e : tot - 1;
+            row[u] = ec / G;
+            c[u] = (ec % G) * 4;
+            const int rr = row[u] < N ? row[u] : N - 1;
+            v[u] = *reinterpret_cast<const float4*>(src + base + (int64_t)rr * d + c[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + NT * u + (int)threadIdx.x < tot)
+                *reinterpret_cast<float4*>(dst + row[u] * LD + c[u]) =
+                    row[u] < N ? v[u] : float4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+// Whether tile i (tiles in falling order of cost) is this wave's: snake
+// order over the waves, largest first.
+template <int NW>
+__device__ inline bool snake_mine(int i, int wave) {
+    const int r = i % (2 * NW);
+    return (r < NW ? r : 2 * NW - 1 - r) == wave;
+}
+
+template <int DH, int NT>
+__global__ void __launch_bounds__(NT) k_attn_bwd_q_mfma(
+    int64_t n, ModelDims m, const float* q, const float* k, const float* v,
+    const float* dO, const float* lse, const float* Dd, float* dqkv) {
+    constexpr int LD = kBwdLd<DH>, KS = DH / 4, MB = DH / 16, NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int N = m.N, d = m.d, nh = m.nh;
+    const int Np = (N + 15) & ~15, NTQ = Np / 16;
+    float* Ks = reinterpret_cast<float*>(smem_raw);
+    float* Vs = Ks + Np * LD;
+    const float scale = 1.0f / sqrtf((float)DH);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    for (int64_t u = blockIdx.x; u < n * nh; u += gridDim.x) {
+        const int64_t s = u / nh;
+        const int h = (int)(u - s * nh);
+        const int64_t base = s * N * d + h * DH;
+        __syncthreads();
+        fill_rows<DH, LD, NT>(Ks, k, base, N, Np, d);
+        fill_rows<DH, LD, NT>(Vs, v, base, N, Np, d);
+        __syncthreads();
+        // query tile t has t + 1 key blocks: the largest first
+        for (int i = 0; i < NTQ; ++i) {
+            if (!snake_mine<NW>(i, wave)) continue;
+            const int t = NTQ - 1 - i;
+            const int iq = t * 16 + c16;              // this lane's query
+            const int iqr = iq < N ? iq : N - 1;
+            float qf[KS], gf[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                qf[ks] = q[base + (int64_t)iqr * d + 4 * ks + g];
+                gf[ks] = dO[base + (int64_t)iqr * d + 4 * ks + g];
+            }
+            const float ls = lse[(s * N + iqr) * nh + h];
+            const float dd = Dd[(s * N + iqr) * nh + h];
+            f32x4b acc[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4b{0, 0, 0, 0};
+            for (int kb = 0; kb <= t; ++kb) {
+                const float* kr = Ks + (kb * 16 + c16) * LD + g;
+                const float* vr = Vs + (kb * 16 + c16) * LD + g;
+                f32x4b sc = f32x4b{0, 0, 0, 0}, dp = f32x4b{0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    sc = mfma_f32(kr[4 * ks], qf[ks], sc);
+                    dp = mfma_f32(vr[4 * ks], gf[ks], dp);
+                }
+                float ds[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int key = kb * 16 + 4 * g + r;
+                    const float p = key <= iq && key < N ? dexp(sc[r] * scale - ls) : 0.0f;
+                    ds[r] = p * (dp[r] - dd);
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const float* ka = Ks + (kb * 16 + 4 * g + kk) * LD + c16;
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+                        acc[mb] = mfma_f32(ka[16 * mb], ds[kk], acc[mb]);
+                }
+            }
+            if (iq < N) {
+                float* out = dqkv + (s * N + iq) * 3 * d + h * DH;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    *reinterpret_cast<float4*>(out + 16 * mb + 4 * g) =
+                        float4{acc[mb][0] * scale, acc[mb][1] * scale,
+                               acc[mb][2] * scale, acc[mb][3] * scale};
+            }
+        }
+    }
+}
+
+template <int DH, int NT>
+__global__ void __launch_bounds__(NT) k_attn_bwd_kv_mfma(
+    int64_t n, ModelDims m, const float* q, const float* k, const float* v,
+    const float* dO, const float* lse, const float* Dd, float* dqkv) {
+    constexpr int LD = kBwdLd<DH>, KS = DH / 4, MB = DH / 16, NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int N = m.N, d = m.d, nh = m.nh;
+    const int Np = (N + 15) & ~15, NTQ = Np / 16;
+    float* Qs = reinterpret_cast<float*>(smem_raw);
+    float* Gs = Qs + Np * LD;
+    float* Ls = Gs + Np * LD;
+    float* Ds = Ls + Np;
+    const float scale = 1.0f / sqrtf((float)DH);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    for (int64_t u = blockIdx.x; u < n * nh; u += gridDim.x) {
+        const int64_t s = u / nh;
+        const int h = (int)(u - s * nh);
+        const int64_t base = s * N * d + h * DH;
+        __syncthreads();
+        fill_rows<DH, LD, NT>(Qs, q, base, N, Np, d);
+        fill_rows<DH, LD, NT>(Gs, dO, base, N, Np, d);
+        for (int i = threadIdx.x; i < Np; i += NT) {
+            Ls[i] = i < N ? lse[(s * N + i) * nh + h] : 0.0f;
+            Ds[i] = i < N ? Dd[(s * N + i) * nh + h] : 0.0f;
+        }
+        __syncthreads();
+        // key tile t has NTQ - t query blocks: the largest first
+        for (int i = 0; i < NTQ; ++i) {
+            if (!snake_mine<NW>(i, wave)) continue;
+            const int t = i;
+            const int jk = t * 16 + c16;              // this lane's key
+            const int jkr = jk < N ? jk : N - 1;
+            float kf[KS], vf[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                kf[ks] = k[base + (int64_t)jkr * d + 4 * ks + g];
+                vf[ks] = v[base + (int64_t)jkr * d + 4 * ks + g];
+            }
+            f32x4b dk[MB], dv[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                dk[mb] = f32x4b{0, 0, 0, 0};
+                dv[mb] = f32x4b{0, 0, 0, 0};
+            }
+            for (int qb = t; qb < NTQ; ++qb) {
+                const float* qr = Qs + (qb * 16 + c16) * LD + g;
+                const float* gr = Gs + (qb * 16 + c16) * LD + g;
+                f32x4b sc = f32x4b{0, 0, 0, 0}, dp = f32x4b{0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    sc = mfma_f32(qr[4 * ks], kf[ks], sc);
+                    dp = mfma_f32(gr[4 * ks], vf[ks], dp);
+                }
+                float p[4], ds[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int qi = qb * 16 + 4 * g + r;
+                    p[r] = qi >= jk && qi < N ? dexp(sc[r] * scale - Ls[qi]) : 0.0f;
+                    ds[r] = p[r] * (dp[r] - Ds[qi]);
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int qrow = (qb * 16 + 4 * g + kk) * LD + c16;
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) {
+                        dv[mb] = mfma_f32(Gs[qrow + 16 * mb], p[kk], dv[mb]);
+                        dk[mb] = mfma_f32(Qs[qrow + 16 * mb], ds[kk], dk[mb]);
+                    }
+                }
+            }
+            if (jk < N) {
+                float* out = dqkv + (s * N + jk) * 3 * d + h * DH;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    *reinterpret_cast<float4*>(out + d + 16 * mb + 4 * g) =
+                        float4{dk[mb][0] * scale, dk[mb][1] * scale,
+                               dk[mb][2] * scale, dk[mb][3] * scale};
+                    *reinterpret_cast<float4*>(out + 2 * d + 16 * mb + 4 * g) =
+                        float4{dv[mb][0], dv[mb][1], dv[mb][2], dv[mb][3]};
+                }
+            }
+        }
+    }
+}
+
+template <int DH>
+static size_t bwd_mfma_lds(const ModelDims& m, bool kv) {
+    const size_t Np = (size_t)((m.N + 15) & ~15);
+    return sizeof(float) * (2 * Np * kBwdLd<DH> + (kv ? 2 * Np : 0));
+}
+
 // Kernels whose dynamic LDS exceeds 64 KiB must opt in before launch.
 template <typename F>
 static hipError_t lds_attr(F f, size_t sm) {
@@ -1268,11 +1495,43 @@ static hipError_t attn_bwd_nt(int64_t n, const ModelDims& m, const T* q,
     return hipGetLastError();
 }
 
+// Statistics pass, then the dq and key-side passes on the matrix core.
+template <int DH, int NT>
+static hipError_t attn_bwd_mfma_nt(int64_t n, const ModelDims& m,
+                                   const float* q, const float* k,
+                                   const float* v, const float* o,
+                                   const float* dO, float* lse, float* Dd,
+                                   float* dqkv, unsigned g, hipStream_t st) {
+    const size_t s1 = sizeof(float) * (size_t)m.N * DH;
+    const size_t sq = bwd_mfma_lds<DH>(m, false), skv = bwd_mfma_lds<DH>(m, true);
+    hipError_t e;
+    if ((e = lds_attr(k_attn_stats<float, DH, kGT>, s1))) return e;
+    hipLaunchKernelGGL((k_attn_stats<float, DH, kGT>), dim3(g), dim3(kGT), s1, st, n, m,
+                       q, k, o, dO, lse, Dd);
+    if ((e = hipGetLastError())) return e;
+    if ((e = lds_attr(k_attn_bwd_q_mfma<DH, NT>, sq))) return e;
+    hipLaunchKernelGGL((k_attn_bwd_q_mfma<DH, NT>), dim3(g), dim3(NT), sq, st, n, m, q,
+                       k, v, dO, lse, Dd, dqkv);
+    if ((e = hipGetLastError())) return e;
+    if ((e = lds_attr(k_attn_bwd_kv_mfma<DH, NT>, skv))) return e;
+    hipLaunchKernelGGL((k_attn_bwd_kv_mfma<DH, NT>), dim3(g), dim3(NT), skv, st, n, m,
+                       q, k, v, dO, lse, Dd, dqkv);
+    return hipGetLastError();
+}
+
 template <typename T, int DH>
 static hipError_t attn_bwd_dh(int64_t n, const ModelDims& m, const T* q,
                               const T* k, const T* v, const T* o, const T* dO,
                               T* lse, T* Dd, T* dqkv, hipStream_t st) {
     const unsigned g = cap_grid(n * m.nh);
+    // FP32: the matrix-core passes where the two row tiles fit the LDS
+    // (1024 threads past 256 rows, whose tiles leave room for one workgroup
+    // per CU only: four waves per SIMD)
+    if constexpr (std::is_same<T, float>::value && DH % 16 == 0 && DH <= 64)
+        if (bwd_mfma_lds<DH>(m, true) <= 160 * 1024)
+            return m.N > kGT
+                       ? attn_bwd_mfma_nt<DH, 4 * kGT>(n, m, q, k, v, o, dO, lse, Dd, dqkv, g, st)
+                       : attn_bwd_mfma_nt<DH, kGT>(n, m, q, k, v, o, dO, lse, Dd, dqkv, g, st);
     // One thread per query (per key in the key-side pass).  Past 256 rows
     // the dq and key-side passes run 512 threads: up to 512 rows in one
     // round, two waves per SIMD where their tiles leave room for one
