@@ -14,7 +14,8 @@ Plain, slow, obviously-correct NumPy float64 code that follows the paper:
   Hamiltonian and Marshall sign rule).
 * ``network``  - the autoregressive transformer with a vector quantizer after
   each self-attention (Sec. 3.1, eqs. 4-6; chain-rule distribution of Sec. 2),
-  log psi = 1/2 log P with zero phase (Sec. 4).
+  log psi = 1/2 log P with zero phase (Sec. 4); tokens of one spin, or of
+  groups of K spins with 2^K values (Sec. 3.1).
 * ``eloc``     - the local energy of eq. (2) by naive re-evaluation of psi on
   every neighbour, and the code-diff deduplicated evaluation of Sec. 3.2 as a
   cross-check with its changed-row counters.
@@ -33,6 +34,9 @@ Pins (tests/test_oracle_*.py):
     head-permutation invariance.
   eloc_dedup: identical codes and equal E_loc to the naive evaluation.
   grad: central finite differences of the relaxed straight-through surrogate.
+  tokens of K spins: the token of a group by hand, the closed form for
+    zero weights but the head bias, normalisation over all states, the
+    sampler's histogram, dedup = plain, central differences.
   The absolute value of log psi for a random network has no external value to
   compare against ("parity unpinned" beyond the structural pins above).
 """

@@ -82,7 +82,7 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
     """
     P = net.unpack(cfg, theta)
     spins = np.atleast_2d(spins)
-    N, d = cfg.N, cfg.d_model
+    K, N, d = net.group(cfg), net.n_tokens(cfg), cfg.d_model
     H = cfg.vq_heads
     m = d // H
     bl = lattice.bonds(cfg.L, cfg.periodic)
@@ -92,17 +92,19 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
     info = dict(ratios=[], changed=[], att_rows=[], vq_rows=[], codes=[])
     for b in range(spins.shape[0]):
         base = net.forward(cfg, P, spins[b:b + 1], keep=True)
-        t0, u0 = net.tokens(spins[b:b + 1])
+        t0, u0 = net.tokens(spins[b:b + 1], K)
         C_base = [{k: v[0] for k, v in c.items()} for c in base["caches"]]
         lp0 = base["lp"][0]
         ell0 = base["ell"][0]
         acc = 0.0
         for _, p1, p2 in lattice.neighbours(spins[b], bl):
             s1 = lattice.swap(spins[b], p1, p2)
-            t1, u1 = net.tokens(s1[None])
+            t1, u1 = net.tokens(s1[None], K)
             t1, u1 = t1[0], u1[0]
             C = changed_inputs(u0[0], u1)
-            pmin = p1 + 1
+            # tokens of the exchanged sites (one token when both fall in it)
+            tp1, tp2 = p1 // K, p2 // K
+            pmin = tp1 + 1
             xo = {i: P["tok"][u1[i]] + P["pos"][i] for i in C}
             sizes, arows, vrows, codes_sp = [len(C)], 0, 0, []
             for l, lay in enumerate(P["layers"]):
@@ -168,10 +170,10 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
                 xn = xin + a @ T["W_o"] + T["b_o"]
                 xo = {int(i): xn[j] for j, i in enumerate(att)}
                 C = [int(i) for i in att]
-            # Head: rows of C_L get new log-probs; the exchanged sites keep
-            # s's hidden state but change target.
+            # Head: rows of C_L get new log-probs; the tokens of the
+            # exchanged sites keep s's hidden state but change target.
             delta = 0.0
-            head_rows = sorted(set(C) | {p1, p2})
+            head_rows = sorted(set(C) | {tp1, tp2})
             lpn = {}
             if C:
                 rows = np.array(C)

@@ -39,8 +39,8 @@ LN_EPS = onet.LN_EPS
 
 def _unpack(cfg, th):
     """Views of the flat torch parameter vector th, in the flat layout."""
-    d, N, Q, H, F = (cfg.d_model, cfg.N, cfg.codebook_size, cfg.vq_heads,
-                     cfg.d_ff)
+    d, Q, H, F = cfg.d_model, cfg.codebook_size, cfg.vq_heads, cfg.d_ff
+    V, T = onet.classes(cfg), onet.n_tokens(cfg)
     pos = [0]
 
     def take(*shape):
@@ -49,7 +49,7 @@ def _unpack(cfg, th):
         pos[0] += n
         return a
 
-    P = {"tok": take(3, d), "pos": take(N, d), "layers": []}
+    P = {"tok": take(V + 1, d), "pos": take(T, d), "layers": []}
     for _ in range(cfg.n_layers):
         P["layers"].append(dict(
             ln1_g=take(d), ln1_b=take(d), W_qkv=take(d, 3 * d),
@@ -61,8 +61,8 @@ def _unpack(cfg, th):
                          b_qkv=take(3 * d), W_o=take(d, d), b_o=take(d))
     P["lnf_g"] = take(d)
     P["lnf_b"] = take(d)
-    P["W_head"] = take(d, 2)
-    P["b_head"] = take(2)
+    P["W_head"] = take(d, V)
+    P["b_head"] = take(V)
     assert pos[0] == th.numel()
     return P
 
@@ -127,7 +127,7 @@ def _forward(cfg, th, spins, frozen=None):
     """log psi [S] through the straight-through surrogate; also returns the
     per-layer frozen state (codes, softmax values) of this evaluation."""
     P = _unpack(cfg, th)
-    t, u = onet.tokens(spins)
+    t, u = onet.tokens(spins, onet.group(cfg))
     t = torch.as_tensor(t)
     u = torch.as_tensor(u)
     d = cfg.d_model

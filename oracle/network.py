@@ -3,11 +3,14 @@
 Model (the readings of points the paper leaves open are listed in the
 project's design notes; each is restated where it is used):
 
-* The distribution network is an autoregressive decoder (Sec. 3.1): one
-  token per spin, token t_i = 0 for s_i = +1 and 1 for s_i = -1.  The input
-  at position i is the previous token (a beginning-of-sequence token 2 at
-  position 0), the target at position i is t_i, so
-  P(s) = prod_i P(s_i | s_<i) (chain rule, Sec. 2).
+* The distribution network is an autoregressive decoder (Sec. 3.1) over
+  tokens that are groups of K = cfg.group consecutive spins (K = 1: one
+  token per spin).  Token t_i of group i is sum_k b_k 2^k with b_k = 1 for
+  spin -1 at the group's k-th site (K = 1: 0 for +1, 1 for -1), one of
+  2^K values.  The input at position i is the previous token (a
+  beginning-of-sequence token 2^K at position 0), the target at position i
+  is t_i, so P(s) = prod_i P(t_i | t_<i) (chain rule, Sec. 2) over the
+  T = N / K tokens.
 * Embedding: learned token + learned absolute position vectors.
 * Each block (pre-LayerNorm):
       h  = LN1(x);  [q|k|v] = h W_qkv + b_qkv
@@ -19,7 +22,7 @@ project's design notes; each is restated where it is used):
 * Optionally an attention-only half-block after the blocks (the paper's
   Table 1 networks end with one, with no quantizer): h = LN(x),
   [q|k|v] = h W_qkv + b, x = x + MHSA(q, k, v) W_o + b_o.
-* Head: final LN, linear d -> 2, log-softmax; log P(s) = sum_i l_i.
+* Head: final LN, linear d -> 2^K, log-softmax; log P(s) = sum_i l_i.
 * Zero phase (Sec. 4, Marshall-rotated Heisenberg), so
   log psi(s) = 1/2 log P(s)  (polar form of Sec. 2).
 
@@ -36,8 +39,8 @@ LN_EPS = 1e-5
 
 def unpack(cfg, theta):
     """Split the flat FP64 parameter vector into named arrays (views)."""
-    d, N, Q, H, F = (cfg.d_model, cfg.N, cfg.codebook_size, cfg.vq_heads,
-                     cfg.d_ff)
+    d, Q, H, F = cfg.d_model, cfg.codebook_size, cfg.vq_heads, cfg.d_ff
+    V, T = classes(cfg), n_tokens(cfg)
     theta = np.asarray(theta, dtype=np.float64)
     pos = [0]
 
@@ -47,7 +50,7 @@ def unpack(cfg, theta):
         pos[0] += n
         return a
 
-    P = {"tok": take(3, d), "pos": take(N, d), "layers": []}
+    P = {"tok": take(V + 1, d), "pos": take(T, d), "layers": []}
     for _ in range(cfg.n_layers):
         P["layers"].append(dict(
             ln1_g=take(d), ln1_b=take(d), W_qkv=take(d, 3 * d),
@@ -59,28 +62,51 @@ def unpack(cfg, theta):
                          b_qkv=take(3 * d), W_o=take(d, d), b_o=take(d))
     P["lnf_g"] = take(d)
     P["lnf_b"] = take(d)
-    P["W_head"] = take(d, 2)
-    P["b_head"] = take(2)
+    P["W_head"] = take(d, V)
+    P["b_head"] = take(V)
     if pos[0] != theta.size:
         raise ValueError(f"parameter vector has {theta.size} entries, "
                          f"model needs {pos[0]}")
     return P
 
 
+def group(cfg):
+    """Spins per token."""
+    return getattr(cfg, "group", 1)
+
+
+def classes(cfg):
+    """Values of a token: 2^K."""
+    return 1 << group(cfg)
+
+
+def n_tokens(cfg):
+    """Sequence length T = N / K."""
+    if cfg.N % group(cfg):
+        raise ValueError("the sites do not split into whole tokens")
+    return cfg.N // group(cfg)
+
+
 def n_params(cfg):
-    d, N, Q, F = cfg.d_model, cfg.N, cfg.codebook_size, cfg.d_ff
+    d, Q, F = cfg.d_model, cfg.codebook_size, cfg.d_ff
+    V, T = classes(cfg), n_tokens(cfg)
     per_layer = (2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d
                  + d * F + F + F * d + d)
     tail = (2 * d + 3 * d * d + 3 * d + d * d + d
             if getattr(cfg, "attn_tail", False) else 0)
-    return 3 * d + N * d + cfg.n_layers * per_layer + tail + 2 * d + 2 * d + 2
+    return ((V + 1) * d + T * d + cfg.n_layers * per_layer + tail + 2 * d
+            + d * V + V)
 
 
-def tokens(spins):
-    """Targets t [S, N] and shifted inputs u [S, N] (BOS = 2 first)."""
-    s = np.asarray(spins)
-    t = (s < 0).astype(np.int64)
-    u = np.concatenate([np.full((s.shape[0], 1), 2, dtype=np.int64),
+def tokens(spins, K=1):
+    """Targets t [S, T] and shifted inputs u [S, T] (BOS = 2^K first) of
+    spins [S, N] in tokens of K consecutive sites: t = sum_k b_k 2^k with
+    b_k = 1 for spin -1 at the token's k-th site."""
+    s = np.atleast_2d(np.asarray(spins))
+    S, N = s.shape
+    b = (s < 0).astype(np.int64).reshape(S, N // K, K)
+    t = (b * (1 << np.arange(K, dtype=np.int64))).sum(axis=-1)
+    u = np.concatenate([np.full((S, 1), 1 << K, dtype=np.int64),
                         t[:, :-1]], axis=1)
     return t, u
 
@@ -214,7 +240,8 @@ def tail_block(T, x, n_heads):
 
 
 def head_logprobs(P, x):
-    """Log-probabilities of both classes at every position, [..., 2]."""
+    """Log-probabilities of every token value at every position,
+    [..., 2^K]."""
     f = layer_norm(x, P["lnf_g"], P["lnf_b"])
     logits = f @ P["W_head"] + P["b_head"]
     m = logits.max(axis=-1, keepdims=True)
@@ -226,12 +253,13 @@ def forward(cfg, P, spins, keep=False):
     """Full forward pass of a batch of sequences spins [S, N].
 
     Returns a dict with ``logpsi`` [S], per-position target log-probs
-    ``ell`` [S, N], both-class log-probs ``lp`` [S, N, 2], per-layer codes
-    ``codes`` [n_layers, S, N, H]; with keep=True also per-layer caches
-    (block input x, q, k, v, attention output a, d1, d2).
+    ``ell`` [S, T], the log-probs of every token value ``lp`` [S, T, 2^K],
+    per-layer codes ``codes`` [n_layers, S, T, H]; with keep=True also
+    per-layer caches (block input x, q, k, v, attention output a, d1, d2).
+    T = N / K positions (K = 1: one per site).
     """
     spins = np.atleast_2d(spins)
-    t, u = tokens(spins)
+    t, u = tokens(spins, group(cfg))
     d = cfg.d_model
     x = P["tok"][u] + P["pos"][None, :, :]
     codes, caches = [], []

@@ -42,10 +42,20 @@ class ModelConfig:
     gamma: float = 1.0                # transverse field of the TFIM
     attn_tail: bool = False           # attention-only half-block after the
                                       # blocks (no quantizer, no MLP)
+    group: int = 1                    # spins per token (Sec. 3.1: tokens are
+                                      # groups of K particles)
 
     @property
     def N(self) -> int:
         return self.L if self.hamiltonian == "tfim" else self.L * self.L
+
+    @property
+    def T(self) -> int:
+        """Sequence length: tokens of ``group`` consecutive sites."""
+        if self.N % self.group:
+            raise ValueError(f"{self.N} sites do not split into tokens of "
+                             f"{self.group}")
+        return self.N // self.group
 
     @property
     def d_head(self) -> int:

@@ -1,9 +1,12 @@
 """Flat parameter layout of the VQ transformer (storage order, row-major).
 
-Every weight matrix is stored [in][out] and applied as x @ W.  Token ids:
-0 = spin +1, 1 = spin -1, 2 = beginning-of-sequence.
+Every weight matrix is stored [in][out] and applied as x @ W.  A token is a
+group of K consecutive spins (K = cfg.group); its id is sum_k b_k 2^k with
+b_k = 1 for spin -1 of the group's k-th site, and id 2^K is the
+beginning-of-sequence token (K = 1: 0 = spin +1, 1 = spin -1, 2 = BOS).
+T = N / K tokens.
 
-  tok_emb[3][d]  pos_emb[N][d]
+  tok_emb[2^K + 1][d]  pos_emb[T][d]
   per layer:
     ln1_g[d] ln1_b[d]  W_qkv[d][3d] b_qkv[3d]  codebook[H][Q][d/H]
     W_o[d][d] b_o[d]   ln2_g[d] ln2_b[d]
@@ -11,7 +14,7 @@ Every weight matrix is stored [in][out] and applied as x @ W.  Token ids:
   attention-only half-block (when the model has one):
     tail.ln_g[d] tail.ln_b[d]  tail.W_qkv[d][3d] tail.b_qkv[3d]
     tail.W_o[d][d] tail.b_o[d]
-  lnf_g[d] lnf_b[d]  W_head[d][2] b_head[2]
+  lnf_g[d] lnf_b[d]  W_head[d][2^K] b_head[2^K]
 
 Each entry carries a ``kind`` tag used only by the seeded initialiser:
 "w" (Gaussian), "gain" (set to 1) or "bias" (set to 0).
@@ -19,9 +22,10 @@ Each entry carries a ``kind`` tag used only by the seeded initialiser:
 
 
 def param_layout(cfg):
-    d, N, Q, H, F = (cfg.d_model, cfg.N, cfg.codebook_size, cfg.vq_heads,
-                     cfg.d_ff)
-    ent = [("tok_emb", (3, d), "w"), ("pos_emb", (N, d), "w")]
+    d, Q, H, F = cfg.d_model, cfg.codebook_size, cfg.vq_heads, cfg.d_ff
+    V = 1 << getattr(cfg, "group", 1)        # classes per token
+    T = cfg.N // getattr(cfg, "group", 1)
+    ent = [("tok_emb", (V + 1, d), "w"), ("pos_emb", (T, d), "w")]
     for l in range(cfg.n_layers):
         p = f"l{l}."
         ent += [
@@ -39,7 +43,7 @@ def param_layout(cfg):
                 ("tail.b_qkv", (3 * d,), "bias"),
                 ("tail.W_o", (d, d), "w"), ("tail.b_o", (d,), "bias")]
     ent += [("lnf_g", (d,), "gain"), ("lnf_b", (d,), "bias"),
-            ("W_head", (d, 2), "w"), ("b_head", (2,), "bias")]
+            ("W_head", (d, V), "w"), ("b_head", (V,), "bias")]
     out, off = [], 0
     for name, shape, kind in ent:
         n = 1
