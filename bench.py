@@ -732,6 +732,8 @@ def main():
                         if mc.hamiltonian == "tfim" else
                         f"{mc.L}x{mc.L} "
                         f"{'periodic' if mc.periodic else 'open'} Heisenberg")
+                       + (f", tokens of {mc.group} spins ({mc.T} positions)"
+                          if mc.group > 1 else "")
                        + f", VQ transformer d={mc.d_model} L={mc.n_layers}"
                        + (" + attention-only half-block" if mc.attn_tail
                           else "") + " "

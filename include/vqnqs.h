@@ -147,6 +147,14 @@ typedef struct {
     int32_t hamiltonian;   /* vqnqs_hamiltonian                                  */
     double  gamma;         /* transverse field Gamma (VQNQS_TFIM_1D)             */
     int32_t attn_tail;     /* 1: an attention-only half-block ends the model     */
+    int32_t group;         /* K spins per token, 1..4 (0 reads as 1): tokens are
+                              groups of K consecutive sites with 2^K values
+                              (Sec. 3.1), T = N/K positions; N % K == 0.
+                              Parameters: tok_emb [2^K + 1][d] (2^K = the
+                              beginning-of-sequence token), pos_emb [T][d],
+                              W_head [d][2^K], b_head [2^K].  Token value
+                              sum_k b_k 2^k, b_k = 1 for spin -1 at the
+                              token's k-th site.                            */
 } vqnqs_config;
 
 /* Counters written by vqnqs_local_energy (int64, VQNQS_NCOUNTERS entries,

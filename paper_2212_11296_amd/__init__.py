@@ -14,7 +14,7 @@ from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
                   local_energy_multi, workspace_size_multi, autotune,
                   set_tuning, local_energy_static, STATIC_SCRATCH_BYTES,
                   forward_activations, probe_exp_rate, sample, WS_SAMPLE,
-                  vmc_step, WS_VMC)
+                  vmc_step, WS_VMC, n_sites, n_tokens)
 
 __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "FLAG_CERTIFIED_VQ", "NCOUNTERS", "CTR", "VQNQSError",
@@ -26,4 +26,4 @@ __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "workspace_size_multi", "autotune", "set_tuning",
            "local_energy_static", "STATIC_SCRATCH_BYTES",
            "forward_activations", "probe_exp_rate", "sample", "WS_SAMPLE",
-           "vmc_step", "WS_VMC"]
+           "vmc_step", "WS_VMC", "n_sites", "n_tokens"]

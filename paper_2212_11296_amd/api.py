@@ -46,7 +46,7 @@ class Config(ctypes.Structure):
                 ("codebook_size", ctypes.c_int32), ("vq_heads", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("hamiltonian", ctypes.c_int32), ("gamma", ctypes.c_double),
-                ("attn_tail", ctypes.c_int32)]
+                ("attn_tail", ctypes.c_int32), ("group", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -61,6 +61,11 @@ def n_sites(cfg):
     return cfg.L if cfg.hamiltonian == TFIM_1D else cfg.L * cfg.L
 
 
+def n_tokens(cfg):
+    """Sequence length: sites / spins per token."""
+    return n_sites(cfg) // (cfg.group if cfg.group else 1)
+
+
 def make_config(mc, precision=None, flags=0):
     """Config from any object with the workload fields (L, d_model, ...)."""
     prec = mc.precision if precision is None else precision
@@ -71,7 +76,8 @@ def make_config(mc, precision=None, flags=0):
                   mc.d_model, mc.n_layers, mc.n_heads, mc.d_ff,
                   mc.codebook_size, mc.vq_heads, int(prec), int(flags),
                   int(ham), float(getattr(mc, "gamma", 0.0)),
-                  int(bool(getattr(mc, "attn_tail", False))))
+                  int(bool(getattr(mc, "attn_tail", False))),
+                  int(getattr(mc, "group", 1)))
 
 
 _lib = None
@@ -265,11 +271,12 @@ def forward_logpsi(cfg, params, spins, codes=False, ws=None,
 
 def forward_activations(cfg, params, spins, ws=None, budget=8 << 30,
                         check=True):
-    """log psi [B], codes [B][n_layers][N][H] and every layer's attention
-    output [B][n_layers][N][d] (float64 in the F64 mode, else float32)."""
+    """log psi [B], codes [B][n_layers][T][H] and every layer's attention
+    output [B][n_layers][T][d] (float64 in the F64 mode, else float32); T
+    token positions (the sites with one spin per token)."""
     import torch
     B = spins.shape[0]
-    N = n_sites(cfg)
+    N = n_tokens(cfg)
     ws = _workspace(cfg, B, -1, ws, budget)
     lp = torch.empty(B, dtype=torch.float64, device="cuda")
     cd = torch.empty((B, cfg.n_layers, N, cfg.vq_heads), dtype=torch.int32,

@@ -40,11 +40,23 @@ bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
     if (c->d_model > 512 || c->d_ff > 4096 || c->n_layers > VQNQS_NCOUNTERS - 17 ||
         c->codebook_size > 65536)
         return false;
-    const int N = chain ? c->L : c->L * c->L;
+    const int S = chain ? c->L : c->L * c->L;
+    const int K = c->group ? c->group : 1;
+    if (K < 1 || K > 4) {
+        *err = VQNQS_ERR_INVALID_CONFIG;
+        return false;
+    }
+    if (S % K) {
+        *err = VQNQS_ERR_INVALID_CONFIG;
+        return false;
+    }
+    const int N = S / K;
     const size_t act = c->precision == VQNQS_F64 ? 8 : 4;
     if (2 * (size_t)N * dh * act > 128 * 1024) return false;  // attention K/V in LDS
     m->L = c->L;
     m->N = N;
+    m->S = S;
+    m->K = K;
     m->d = c->d_model;
     m->nl = c->n_layers;
     m->nh = c->n_heads;

@@ -120,7 +120,10 @@ struct LayerOffsets {
 };
 
 struct ModelDims {
-    int L, N, d, nl, nh, dh, dff, Q, H, dseg;
+    int L;         // lattice side (chain: sites)
+    int N;         // sequence length: tokens per sample (T = S / K)
+    int S, K;      // sites per sample, spins per token
+    int d, nl, nh, dh, dff, Q, H, dseg;
     int periodic, marshall, precision, flags;
     int mfma;      // BF16 products on the matrix core (split activations)
     int chain;     // 1: transverse-field Ising chain of N = L sites
@@ -149,13 +152,39 @@ struct HeadW {
     const C *tok, *pos, *lnf_g, *lnf_b, *W_head, *b_head;
 };
 
-// One neighbour s' of sample `sigma` (the spins of bond sites p1 < p2
-// exchanged).  Rows >= p1+1 are the only ones that can change; overlay rows
-// of s' live at ov + (i - (p1+1)).
+// One neighbour s' of sample `sigma`: the spins of sites s1 < s2
+// exchanged, or site s1 flipped (s1 == s2), in the tokens p1 <= p2.  Token
+// rows >= p1+1 are the only ones whose input can change; overlay rows of s'
+// live at ov + (i - (p1+1)).
 struct NbDesc {
     int32_t sigma;
-    int16_t p1, p2;
+    int16_t p1, p2;   // token positions of the changed sites (p1 <= p2;
+                      // p1 == p2: one changed token)
     int64_t ov;
+    int16_t s1, s2;   // the sites: exchange of s1 < s2, flip when s1 == s2
 };
+
+// Value of token t of one sample's spins sp (sites tK .. tK+K-1):
+// sum_k b_k 2^k with b_k = 1 for spin -1 at the token's k-th site.
+__device__ inline int token_at(const int8_t* sp, int t, int K) {
+    int v = 0;
+    for (int k = 0; k < K; ++k) v |= (sp[t * K + k] < 0 ? 1 : 0) << k;
+    return v;
+}
+
+// The same token of neighbour D of the sample with spins sp: the spins of
+// sites s1, s2 exchanged, or of s1 flipped when s1 == s2.
+__device__ inline int nb_token_at(const int8_t* sp, const NbDesc& D, int t,
+                                  int K) {
+    const bool flip = D.s1 == D.s2;
+    int v = 0;
+    for (int k = 0; k < K; ++k) {
+        const int x = t * K + k;
+        const int8_t s = x == D.s1 ? (flip ? (int8_t)-sp[x] : sp[D.s2])
+                                   : (x == D.s2 ? sp[D.s1] : sp[x]);
+        v |= (s < 0 ? 1 : 0) << k;
+    }
+    return v;
+}
 
 }  // namespace vq

@@ -18,13 +18,17 @@ static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t param_count(const ModelDims& m);
 
 // Worst case, over all configurations, of the overlay rows one sample needs:
-// every bond anti-aligned, each neighbour keeping rows p1+1 .. N-1.
+// every bond anti-aligned, each neighbour keeping token rows p1+1 .. N-1
+// (p1 the token of its first site).
 static int64_t max_overlay_rows(const ModelDims& m) {
     int64_t tot = 0;
-    const int L = m.L, N = m.N;
-    // a chain's flip of site i keeps rows i+1 .. N-1
-    if (m.chain) return (int64_t)N * (N - 1) / 2;
-    for (int b = 0; b < 2 * N; ++b) {
+    const int L = m.L, N = m.N, S = m.S, K = m.K;
+    // a chain's flip of site i keeps rows i/K+1 .. N-1
+    if (m.chain) {
+        for (int i = 0; i < S; ++i) tot += N - i / K - 1;
+        return tot;
+    }
+    for (int b = 0; b < 2 * S; ++b) {
         const int i = b >> 1, r = i / L, c = i % L;
         int j;
         if ((b & 1) == 0) {
@@ -34,7 +38,7 @@ static int64_t max_overlay_rows(const ModelDims& m) {
             if (!m.periodic && r + 1 == L) continue;
             j = ((r + 1) % L) * L + c;
         }
-        tot += N - std::min(i, j) - 1;
+        tot += N - std::min(i, j) / K - 1;
     }
     return tot;
 }
@@ -117,8 +121,10 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     Workspace<P> w{};
     Carver c;
     c.base = static_cast<char*>(base);
-    const int64_t n = chunk, N = m.N, d = m.d, H = m.H;
-    const int64_t nbmax = n * 2 * N;
+    // rows: N token positions per sample; spins and neighbour slots: S sites
+    const int64_t n = chunk, N = m.N, S = m.S, d = m.d, H = m.H;
+    const int64_t V = (int64_t)1 << m.K;
+    const int64_t nbmax = n * 2 * S;
     w.status = c.take<int32_t>(64);
     if (job != Job::Neighbours) {
         w.table = c.take<acc>((size_t)m.nl * H * m.Q * d);
@@ -136,7 +142,7 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
             }
         }
     }
-    w.bonds = c.take<int16_t>(n * 2 * N);
+    w.bonds = c.take<int16_t>(n * 2 * S);
     w.count = c.take<int32_t>(n);
     w.diag = c.take<double>(n);
     w.rows_cap = c.take<int64_t>(n);
@@ -197,7 +203,7 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
         w.E = c.take<acc>(R * Q);
         w.rowG = c.take<acc>(R);
         w.colG = c.take<acc>(n * Q);
-        w.dz2 = c.take<acc>(2 * R);
+        w.dz2 = c.take<acc>(V * R);
         w.coef = c.take<acc>(n);
         w.part = c.take<acc>((size_t)n * param_count(m));
         w.bytes = c.off;
@@ -218,13 +224,13 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
     w.bcode = c.take<int32_t>(nlc * n * N * H);
     if (dedup) {
         w.bmargin = c.take<acc>(nlc * n * N * H * 2);
-        w.blp = c.take<acc>(n * N * 2);
+        w.blp = c.take<acc>(n * N * V);
         if (m.flags & VQNQS_FLAG_INCREMENTAL_ATTN)
             w.bstat = c.take<acc>(nlc * n * N * m.nh * 2);
     }
     if (job == Job::Plain) {
         w.logpsi_nb = c.take<double>(nbmax);
-        w.nspins = c.take<int8_t>(nbmax * N);
+        w.nspins = c.take<int8_t>(nbmax * S);
         w.nx = c.take<acc>(nbmax * N * d);
         w.nq = c.take<act>(nbmax * N * d);
         w.nk = c.take<act>(nbmax * N * d);
@@ -257,7 +263,7 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
 // sampling, local-energy and gradient calls share in turn.
 static size_t vmc_front_bytes(const ModelDims& m, int64_t B) {
     const size_t a = m.precision == VQNQS_F64 ? 8 : 4;
-    return al256((size_t)B * m.N) + 3 * al256((size_t)B * 8) + 256 +
+    return al256((size_t)B * m.S) + 3 * al256((size_t)B * 8) + 256 +
            al256((size_t)param_count(m) * a);
 }
 
@@ -298,7 +304,7 @@ int64_t pick_chunk(const ModelDims& m, int mode, int64_t batch, size_t ws) {
     // bound the chunk so overlay row counts and neighbour ids stay in int32
     const int64_t rows1 = std::max<int64_t>(1, max_overlay_rows(m));
     hi = std::min<int64_t>(hi, ((int64_t)1 << 30) / rows1);
-    hi = std::min<int64_t>(hi, ((int64_t)1 << 30) / (2 * m.N));
+    hi = std::min<int64_t>(hi, ((int64_t)1 << 30) / (2 * m.S));
     // gradient products tile rows by 64 with at most 65535 row tiles
     if (mode == -3) hi = std::min<int64_t>(hi, (int64_t)65535 * 64 / m.N);
     if (hi < 1) hi = 1;
@@ -316,7 +322,7 @@ static LayerW<C> layer_view(const ModelDims& m, const C* p, int l) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
-    const C* b = p + 3 * d + N * d + per * l;
+    const C* b = p + ((1 << m.K) + 1) * d + N * d + per * l;
     LayerW<C> w{};
     w.ln1_g = b;
     w.ln1_b = b + d;
@@ -346,7 +352,7 @@ static LayerW<C> tail_view(const ModelDims& m, const C* p) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
-    const C* b = p + 3 * d + N * d + per * m.nl;
+    const C* b = p + ((1 << m.K) + 1) * d + N * d + per * m.nl;
     LayerW<C> w{};
     w.ln1_g = b;
     w.ln1_b = b + d;
@@ -364,12 +370,13 @@ static HeadW<C> head_view(const ModelDims& m, const C* p) {
                         d * F + F + F * d + d;
     HeadW<C> h{};
     h.tok = p;
-    h.pos = p + 3 * d;
-    const C* t = p + 3 * d + N * d + per * m.nl + tail_params(m);
+    const int64_t V = (int64_t)1 << m.K;      // values of a token
+    h.pos = p + (V + 1) * d;
+    const C* t = p + (V + 1) * d + N * d + per * m.nl + tail_params(m);
     h.lnf_g = t;
     h.lnf_b = t + d;
     h.W_head = t + 2 * d;
-    h.b_head = t + 2 * d + 2 * d;
+    h.b_head = t + 2 * d + V * d;
     return h;
 }
 
@@ -377,7 +384,8 @@ int64_t param_count(const ModelDims& m) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
-    return 3 * d + N * d + per * m.nl + tail_params(m) + 2 * d + 2 * d + 2;
+    const int64_t V = (int64_t)1 << m.K;
+    return (V + 1) * d + N * d + per * m.nl + tail_params(m) + 2 * d + V * d + V;
 }
 
 #define CK(x)                                  \
@@ -403,7 +411,7 @@ static LayerOffsets layer_offsets(const ModelDims& m, int l) {
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
     LayerOffsets o;
-    o.ln1_g = 3 * d + N * d + per * l;
+    o.ln1_g = (((int64_t)1 << m.K) + 1) * d + N * d + per * l;
     o.ln1_b = o.ln1_g + d;
     o.W_qkv = o.ln1_b + d;
     o.b_qkv = o.W_qkv + d * 3 * d;
@@ -652,15 +660,16 @@ struct Runner {
         const HeadW<acc> hw = head();
         const int64_t off_tail = layer_offsets(m, m.nl).ln1_g;
         const int64_t off_lnf = off_tail + tail_params(m);
-        const int64_t off_Wh = off_lnf + 2 * d, off_bh = off_Wh + 2 * d;
+        const int64_t off_Wh = off_lnf + 2 * d, off_bh = off_Wh + ((int64_t)1 << m.K) * d;
         // head: d log psi / d x_L (after the half-block, when there is one)
-        LK("grad_head", launch_head_bwd<acc>(n, (int)N, (int)d, hw, sp,
+        const int64_t V = (int64_t)1 << m.K;
+        LK("grad_head", launch_head_bwd<acc>(n, (int)N, (int)d, m.K, hw, sp,
                                              w.gx + (int64_t)(m.nl + m.tail) * sd,
                                              w.coef, w.h1, w.xh1, w.rs1, w.dz2,
                                              w.dT, w.dX, st));
-        LK("grad_gemm", gemm(d, 2, N, w.h1, d, N * d, 1, w.dz2, 2, 2 * N, 0,
-                             gout + off_Wh, 2, NP, 0, n));
-        LK("grad_colsum", colsum(n, 2, w.dz2, 2, nullptr, 0, gout + off_bh, NP));
+        LK("grad_gemm", gemm(d, V, N, w.h1, d, N * d, 1, w.dz2, V, V * N, 0,
+                             gout + off_Wh, V, NP, 0, n));
+        LK("grad_colsum", colsum(n, (int)V, w.dz2, V, nullptr, 0, gout + off_bh, NP));
         LK("grad_colsum", colsum(n, d, w.dT, d, w.xh1, d, gout + off_lnf, NP));
         LK("grad_colsum", colsum(n, d, w.dT, d, nullptr, 0, gout + off_lnf + d, NP));
         if (m.tail) {
@@ -801,15 +810,15 @@ struct Runner {
             LK("grad_ln", launch_ln_bwd<acc>(R, (int)d, w.xh1, w.rs1, lw.ln1_g,
                                              w.dT, w.dXp, w.dX, st));
         }
-        LK("grad_embed", launch_embed_bwd<acc>(n, (int)N, (int)d, sp, w.dX, gout,
-                                               NP, 0, 3 * d, st));
+        LK("grad_embed", launch_embed_bwd<acc>(n, (int)N, (int)d, m.K, sp, w.dX, gout,
+                                               NP, 0, (V + 1) * d, st));
         return VQNQS_OK;
     }
 
     vqnqs_status neighbours(const int8_t* spins, int64_t n) {
         LK("neighbours", launch_neighbours(spins, n, m, w.bonds, w.count, w.diag, w.rows_cap,
                              w.status, st));
-        LK("scan_desc", launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, m.chain, w.nb_off,
+        LK("scan_desc", launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, m.chain, m.K, w.nb_off,
                             w.row_off, w.n_nb, w.n_rows, w.desc, st));
         if (ctr) {
             CK(launch_counter_add_const(ctr, VQNQS_CTR_SAMPLES, n, st));
@@ -873,8 +882,8 @@ struct Runner {
                    nullptr, w.logpsi_s, false, nullptr};
         s = forward(sb, nullptr, n, true);
         if (s) return s;
-        const int64_t nbmax = n * 2 * m.N;
-        LK("materialise", launch_materialise(spins, w.desc, w.n_nb, nbmax, m.N, w.nspins, st));
+        const int64_t nbmax = n * 2 * m.S;
+        LK("materialise", launch_materialise(spins, w.desc, w.n_nb, nbmax, m.S, w.nspins, st));
         SeqBufs nbuf{w.nspins, w.nx, w.nq, w.nk, w.nv, w.na, w.ncode, nullptr,
                      nullptr, w.logpsi_nb, false, nullptr};
         s = forward(nbuf, w.n_nb, nbmax, true);
@@ -904,7 +913,7 @@ struct Runner {
         sb.stat = incr ? w.bstat : nullptr;
         s = forward(sb, nullptr, n, true);
         if (s) return s;
-        const int64_t nbmax = n * 2 * N;
+        const int64_t nbmax = n * 2 * m.S;
         const int64_t R = n * max_overlay_rows(m);
         DedupIO<P> dd{};
         dd.desc = w.desc;
@@ -1044,12 +1053,12 @@ static vqnqs_status run_local_energy(const ModelDims& m, const void* params,
     const double h_off = m.chain ? -m.gamma : (m.marshall ? -0.5 * m.J : 0.5 * m.J);
     for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
         const int64_t n = std::min(chunk, batch - c0);
-        const int8_t* sp = spins + c0 * m.N;
+        const int8_t* sp = spins + c0 * m.S;
         s = mode == VQNQS_PLAIN ? r.plain_chunk(sp, n) : r.dedup_chunk(sp, n);
         if (s) return s;
-        LK("eloc", launch_eloc(r.w.diag, r.w.count, r.w.nb_off, r.w.ratio, (int)n, m.N,
+        LK("eloc", launch_eloc(r.w.diag, r.w.count, r.w.nb_off, r.w.ratio, (int)n, m.S,
                        h_off, eloc + c0,
-                       ratios ? ratios + c0 * 2 * m.N : nullptr, st));
+                       ratios ? ratios + c0 * 2 * m.S : nullptr, st));
     }
     if (stats) LK("stats", launch_stats(eloc, batch, stats, st));
     return VQNQS_OK;
@@ -1092,7 +1101,7 @@ static vqnqs_status run_forward(const ModelDims& m, const void* params,
     if (s) return s;
     for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
         const int64_t n = std::min(chunk, batch - c0);
-        const int8_t* sp = spins + c0 * m.N;
+        const int8_t* sp = spins + c0 * m.S;
         // spin validation shares the neighbour kernel
         LK("neighbours", launch_neighbours(sp, n, m, r.w.bonds, r.w.count, nullptr, nullptr,
                              r.w.status, st));
@@ -1140,7 +1149,7 @@ static vqnqs_status run_sample(const ModelDims& m, const void* params,
     if (s) return s;
     for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
         const int64_t n = std::min(chunk, batch - c0);
-        s = r.sample_chunk(uniforms + c0 * m.N, n, spins + c0 * m.N,
+        s = r.sample_chunk(uniforms + c0 * m.S, n, spins + c0 * m.S,
                            logpsi ? logpsi + c0 : nullptr);
         if (s) return s;
     }
@@ -1174,7 +1183,7 @@ vqnqs_status vmc_step(const ModelDims& m, void* params, void* opt_state,
     const size_t sub = (ws_bytes - front) & ~(size_t)255;
     char* f = static_cast<char*>(ws) + sub;
     int8_t* spins = reinterpret_cast<int8_t*>(f);
-    f += al256((size_t)B * m.N);
+    f += al256((size_t)B * m.S);
     double* eloc = reinterpret_cast<double*>(f);
     f += al256((size_t)B * 8);
     double* w = reinterpret_cast<double*>(f);
@@ -1237,7 +1246,7 @@ static vqnqs_status run_grad(const ModelDims& m, const void* params,
     for (int64_t c0 = 0; c0 < batch; c0 += chunk) {
         const int64_t n = std::min(chunk, batch - c0);
         acc* gout = weights ? r.w.part : g + c0 * Pn;
-        s = r.grad_chunk(spins + c0 * m.N, n, weights ? weights + c0 : nullptr,
+        s = r.grad_chunk(spins + c0 * m.S, n, weights ? weights + c0 : nullptr,
                          gout, logpsi ? logpsi + c0 : nullptr);
         if (s) return s;
         if (weights)

@@ -726,14 +726,112 @@ __global__ void __launch_bounds__(kGT) k_head_bwd(int64_t n, int N, int d,
     }
 }
 
+// The same for tokens of K spins: V = 2^K values, logits z_c, target
+// t = the token's value (sites iK .. iK+K-1 of the sample), dz[r][c] =
+// coef (1[c == t] - p_c) and df = sum_c dz_c W[:, c] (values in order).
+template <typename T, int V>
+__global__ void __launch_bounds__(kGT) k_head_bwd_v(int64_t n, int N, int d,
+                                                    int K, HeadW<T> hw,
+                                                    const int8_t* spins,
+                                                    const T* x, const T* coef,
+                                                    T* f, T* xh, T* rstd, T* dz,
+                                                    T* df, T* dx) {
+    const int lane = threadIdx.x & 63;
+    const int64_t R = n * N, wpb = kGT / 64;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
+         r += (int64_t)gridDim.x * wpb) {
+        const T* xr = x + r * d;
+        T s = 0;
+        for (int k = lane; k < d; k += 64) s += xr[k];
+        const T mean = wave_sum(s) / (T)d;
+        T v = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T t = xr[k] - mean;
+            v += t * t;
+        }
+        v = wave_sum(v) / (T)d;
+        const T rs = (T)1 / dsqrt(v + (T)1e-5);
+        T z[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) z[c] = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T h = (xr[k] - mean) * rs;
+            const T fk = h * hw.lnf_g[k] + hw.lnf_b[k];
+            xh[r * d + k] = h;
+            f[r * d + k] = fk;
+#pragma unroll
+            for (int c = 0; c < V; ++c) z[c] += fk * hw.W_head[k * V + c];
+        }
+        T mx = neg_inf<T>();
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            z[c] = wave_sum(z[c]) + hw.b_head[c];
+            mx = z[c] > mx ? z[c] : mx;
+        }
+        T sum = 0;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            z[c] = dexp(z[c] - mx);
+            sum += z[c];
+        }
+        const int64_t smp = r / N;
+        const int y = token_at(spins + smp * (int64_t)N * K, (int)(r - smp * N), K);
+        const T cf = coef[smp];
+        T g[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c)
+            g[c] = cf * ((c == y ? (T)1 : (T)0) - z[c] / sum);
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < V; ++c) dz[V * r + c] = g[c];
+            rstd[r] = rs;
+        }
+        T s1 = 0, s2 = 0;
+        for (int k = lane; k < d; k += 64) {
+            T dfk = 0;
+#pragma unroll
+            for (int c = 0; c < V; ++c) dfk += g[c] * hw.W_head[k * V + c];
+            df[r * d + k] = dfk;
+            const T e = hw.lnf_g[k] * dfk;
+            s1 += e;
+            s2 += e * xh[r * d + k];
+        }
+        s1 = wave_sum(s1) / (T)d;
+        s2 = wave_sum(s2) / (T)d;
+        for (int k = lane; k < d; k += 64) {
+            const T e = hw.lnf_g[k] * df[r * d + k];
+            dx[r * d + k] = rs * (e - s1 - xh[r * d + k] * s2);
+        }
+    }
+}
+
 template <typename T>
-hipError_t launch_head_bwd(int64_t n, int N, int d, const HeadW<T>& hw,
+hipError_t launch_head_bwd(int64_t n, int N, int d, int K, const HeadW<T>& hw,
                            const int8_t* spins, const T* x, const T* coef, T* f,
                            T* xh, T* rstd, T* dz, T* df, T* dx, hipStream_t st) {
     const int64_t R = n * N;
     if (R <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_head_bwd<T>), dim3(cap_grid((R + 3) / 4)), dim3(kGT), 0,
-                       st, n, N, d, hw, spins, x, coef, f, xh, rstd, dz, df, dx);
+    const dim3 g(cap_grid((R + 3) / 4)), b(kGT);
+    switch (K) {
+        case 1:
+            hipLaunchKernelGGL((k_head_bwd<T>), g, b, 0, st, n, N, d, hw, spins, x,
+                               coef, f, xh, rstd, dz, df, dx);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_head_bwd_v<T, 4>), g, b, 0, st, n, N, d, K, hw,
+                               spins, x, coef, f, xh, rstd, dz, df, dx);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_head_bwd_v<T, 8>), g, b, 0, st, n, N, d, K, hw,
+                               spins, x, coef, f, xh, rstd, dz, df, dx);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_head_bwd_v<T, 16>), g, b, 0, st, n, N, d, K, hw,
+                               spins, x, coef, f, xh, rstd, dz, df, dx);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -766,15 +864,64 @@ __global__ void __launch_bounds__(kGT) k_embed_bwd(int64_t n, int N, int d,
     }
 }
 
+// The same for tokens of K spins: inputs u_0 = BOS (2^K), u_i = the value
+// of token i-1; V + 1 token rows.
+template <typename T, int V>
+__global__ void __launch_bounds__(kGT) k_embed_bwd_v(int64_t n, int N, int d,
+                                                     int K, const int8_t* spins,
+                                                     const T* dx, T* grad,
+                                                     int64_t P, int64_t tok_off,
+                                                     int64_t pos_off) {
+    const int64_t total = n * d;
+    for (int64_t e = (int64_t)blockIdx.x * kGT + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * kGT) {
+        const int64_t s = e / d;
+        const int c = (int)(e - s * d);
+        T t[V + 1];
+#pragma unroll
+        for (int k = 0; k <= V; ++k) t[k] = 0;
+        T* g = grad + s * P;
+        const int8_t* sp = spins + s * (int64_t)N * K;
+        for (int i = 0; i < N; ++i) {
+            const T v = dx[(s * N + i) * d + c];
+            g[pos_off + (int64_t)i * d + c] = v;
+            const int u = i == 0 ? V : token_at(sp, i - 1, K);
+#pragma unroll
+            for (int k = 0; k <= V; ++k)
+                if (k == u) t[k] += v;
+        }
+#pragma unroll
+        for (int k = 0; k <= V; ++k) g[tok_off + (int64_t)k * d + c] = t[k];
+    }
+}
+
 template <typename T>
-hipError_t launch_embed_bwd(int64_t n, int N, int d, const int8_t* spins,
+hipError_t launch_embed_bwd(int64_t n, int N, int d, int K, const int8_t* spins,
                             const T* dx, T* grad, int64_t P, int64_t tok_off,
                             int64_t pos_off, hipStream_t st) {
     const int64_t total = n * d;
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_embed_bwd<T>), dim3(cap_grid((total + kGT - 1) / kGT)),
-                       dim3(kGT), 0, st, n, N, d, spins, dx, grad, P, tok_off,
-                       pos_off);
+    const dim3 g(cap_grid((total + kGT - 1) / kGT)), b(kGT);
+    switch (K) {
+        case 1:
+            hipLaunchKernelGGL((k_embed_bwd<T>), g, b, 0, st, n, N, d, spins, dx,
+                               grad, P, tok_off, pos_off);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_embed_bwd_v<T, 4>), g, b, 0, st, n, N, d, K, spins,
+                               dx, grad, P, tok_off, pos_off);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_embed_bwd_v<T, 8>), g, b, 0, st, n, N, d, K, spins,
+                               dx, grad, P, tok_off, pos_off);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_embed_bwd_v<T, 16>), g, b, 0, st, n, N, d, K, spins,
+                               dx, grad, P, tok_off, pos_off);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1580,10 +1727,12 @@ hipError_t launch_attn_bwd(int64_t n, const ModelDims& m, const T* q,
     template hipError_t launch_bias_gelu<T>(int64_t, int, T*, const T*, T*,     \
                                             hipStream_t);                       \
     template hipError_t launch_gelu_bwd<T>(int64_t, const T*, T*, hipStream_t); \
-    template hipError_t launch_head_bwd<T>(int64_t, int, int, const HeadW<T>&,  \
+    template hipError_t launch_head_bwd<T>(int64_t, int, int, int,              \
+                                           const HeadW<T>&,                     \
                                            const int8_t*, const T*, const T*,   \
                                            T*, T*, T*, T*, T*, T*, hipStream_t); \
-    template hipError_t launch_embed_bwd<T>(int64_t, int, int, const int8_t*,   \
+    template hipError_t launch_embed_bwd<T>(int64_t, int, int, int,             \
+                                            const int8_t*,                      \
                                             const T*, T*, int64_t, int64_t,     \
                                             int64_t, hipStream_t);              \
     template hipError_t launch_vq_bwd_rows<T>(int64_t, int, int, int, int,      \

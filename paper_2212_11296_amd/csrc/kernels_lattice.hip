@@ -27,7 +27,8 @@ __device__ inline bool bond_sites(int b, int L, int periodic, int& i, int& j) {
 // list comes out in increasing bond order without atomics.
 __global__ void __launch_bounds__(64) k_neighbours(
     const int8_t* __restrict__ spins, int64_t batch, int L, int chain,
-    int periodic, double J, int16_t* __restrict__ bonds, int32_t* __restrict__ count,
+    int periodic, int K, double J, int16_t* __restrict__ bonds,
+    int32_t* __restrict__ count,
     double* __restrict__ diag, int64_t* __restrict__ rows_cap,
     int32_t* __restrict__ status) {
     const int64_t s = blockIdx.x;
@@ -45,7 +46,8 @@ __global__ void __launch_bounds__(64) k_neighbours(
         // transverse-field Ising chain: every site's flip is a neighbour
         // (listed by site), diagonal -J sum_<ij> s_i s_j over the bonds
         // (i, i+1) and, periodic, (N-1, 0); a flip of site i changes the
-        // input tokens from i + 1 on
+        // input tokens from token i/K + 1 on (T = N/K tokens: K rows of
+        // T - t - 1 per token t, K T (T - 1) / 2 in all)
         int zz = 0;
         int16_t* out = bonds + s * (int64_t)(2 * N);
         for (int i = lane; i < N; i += 64) {
@@ -59,13 +61,16 @@ __global__ void __launch_bounds__(64) k_neighbours(
         if (lane == 0) {
             count[s] = N;
             if (diag) diag[s] = -J * (double)zz;
-            if (rows_cap) rows_cap[s] = (int64_t)N * (N - 1) / 2;
+            const int64_t T = N / K;
+            if (rows_cap) rows_cap[s] = (int64_t)K * T * (T - 1) / 2;
         }
         return;
     }
     int total = 0;
     int zz = 0;          // sum of s_i s_j over existing bonds
-    int64_t cap = 0;     // overlay rows: sum over anti bonds of N - p1 - 1
+    int64_t cap = 0;     // overlay rows: sum over anti bonds of T - t1 - 1,
+                         // t1 = p1 / K the token of the first site
+    const int T = N / K;
     int16_t* out = bonds + s * (int64_t)(2 * N);
     for (int b0 = 0; b0 < 2 * N; b0 += 64) {
         const int b = b0 + lane;
@@ -82,7 +87,7 @@ __global__ void __launch_bounds__(64) k_neighbours(
         if (anti) {
             out[total + __popcll(below)] = (int16_t)b;
             const int p1 = i < j ? i : j;
-            cap += N - p1 - 1;
+            cap += T - p1 / K - 1;
         }
         total += __popcll(m);
     }
@@ -149,7 +154,7 @@ __global__ void __launch_bounds__(1024) k_scan_chunk(
 __global__ void __launch_bounds__(64) k_descriptors(
     const int16_t* __restrict__ bonds, const int32_t* __restrict__ count,
     const int32_t* __restrict__ nb_off, const int64_t* __restrict__ row_off,
-    int n, int L, int chain, NbDesc* __restrict__ desc) {
+    int n, int L, int chain, int K, NbDesc* __restrict__ desc) {
     const int s = blockIdx.x;
     if (s >= n) return;
     const int lane = threadIdx.x;
@@ -171,7 +176,7 @@ __global__ void __launch_bounds__(64) k_descriptors(
                 p1 = i < j ? i : j;
                 p2 = i < j ? j : i;
             }
-            rows = N - p1 - 1;
+            rows = N / K - p1 / K - 1;
         }
         int64_t incl = rows;   // inclusive wave scan
 #pragma unroll
@@ -182,9 +187,11 @@ __global__ void __launch_bounds__(64) k_descriptors(
         if (k < cnt) {
             NbDesc d;
             d.sigma = s;
-            d.p1 = (int16_t)p1;
-            d.p2 = (int16_t)p2;
+            d.p1 = (int16_t)(p1 / K);      // tokens of the changed sites
+            d.p2 = (int16_t)(p2 / K);
             d.ov = carry + incl - rows;
+            d.s1 = (int16_t)p1;
+            d.s2 = (int16_t)p2;
             desc[nb_off[s] + k] = d;
         }
         carry += __shfl(incl, 63, 64);
@@ -330,20 +337,20 @@ hipError_t launch_neighbours(const int8_t* spins, int64_t batch,
                              hipStream_t st) {
     if (batch <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_neighbours, dim3((unsigned)batch), dim3(64), 0, st,
-                       spins, batch, m.L, m.chain, m.periodic, m.J, bonds,
+                       spins, batch, m.L, m.chain, m.periodic, m.K, m.J, bonds,
                        count, diag, rows_cap, status);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_desc(const int16_t* bonds, const int32_t* count,
                             const int64_t* rows_cap, int n, int L, int chain,
-                            int32_t* nb_off, int64_t* row_off,
+                            int K, int32_t* nb_off, int64_t* row_off,
                             int32_t* n_nb_total, int32_t* n_rows_total,
                             NbDesc* desc, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_chunk, dim3(1), dim3(1024), 0, st, count,
                        rows_cap, n, nb_off, row_off, n_nb_total, n_rows_total);
     hipLaunchKernelGGL(k_descriptors, dim3(n), dim3(64), 0, st, bonds, count,
-                       nb_off, row_off, n, L, chain, desc);
+                       nb_off, row_off, n, L, chain, K, desc);
     return hipGetLastError();
 }
 

@@ -116,12 +116,12 @@ __global__ void k_materialise(const int8_t* __restrict__ spins,
         const int64_t k = e / N;
         const int i = (int)(e - k * N);
         const NbDesc dd = desc[k];
-        // exchange of p1 < p2, or a flip of p1 when p1 == p2
+        // exchange of sites s1 < s2, or a flip of s1 when s1 == s2
         int src = i;
-        if (i == dd.p1) src = dd.p2;
-        else if (i == dd.p2) src = dd.p1;
+        if (i == dd.s1) src = dd.s2;
+        else if (i == dd.s2) src = dd.s1;
         const int8_t v = spins[(int64_t)dd.sigma * N + src];
-        out[e] = (dd.p1 == dd.p2 && i == dd.p1) ? (int8_t)-v : v;
+        out[e] = (dd.s1 == dd.s2 && i == dd.s1) ? (int8_t)-v : v;
     }
 }
 
@@ -144,8 +144,10 @@ __global__ void k_embed(ModelDims m, HeadW<typename P::acc> hw,
          e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t row = e / m.d;
         const int col = (int)(e - row * m.d);
-        const int i = (int)(row % m.N);
-        const int u = i == 0 ? 2 : (spins[row - 1] < 0 ? 1 : 0);
+        const int64_t s = row / m.N;
+        const int i = (int)(row - s * m.N);
+        // input: the previous token, or the beginning-of-sequence token 2^K
+        const int u = i == 0 ? 1 << m.K : token_at(spins + s * m.S, i - 1, m.K);
         x[e] = hw.tok[u * m.d + col] + hw.pos[(int64_t)i * m.d + col];
     }
 }
@@ -1126,7 +1128,85 @@ __device__ inline void head_rows(const C* const (&x)[R], int d,
     }
 }
 
-template <class P>
+// The same for tokens of V = 2^K values: log-probabilities lp[r][c] of
+// every value.  V = 2 is head_rows itself; wider heads take the three
+// passes over the columns (normalisation statistics, then the logits) with
+// the values' sums kept per lane and reduced at the end, and the
+// log-softmax sums the exponentials in value order.
+template <typename C, int R, int V>
+__device__ inline void head_rows_v(const C* const (&x)[R], int d,
+                                   const HeadW<C>& hw, C (&lp)[R][V]) {
+#pragma clang fp contract(off)
+    if constexpr (V == 2) {
+        C l0[R], l1[R];
+        head_rows<C, R>(x, d, hw, l0, l1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            lp[r][0] = l0[r];
+            lp[r][1] = l1[r];
+        }
+    } else {
+        const int lane = threadIdx.x & 63;
+        C s[R], v[R], mean[R], rstd[R], z[R][V];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            s[r] = v[r] = 0;
+#pragma unroll
+            for (int c = 0; c < V; ++c) z[r][c] = 0;
+        }
+        for (int k = lane; k < d; k += 64)
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[r] += x[r][k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) mean[r] = wave_sum(s[r]) / (C)d;
+        for (int k = lane; k < d; k += 64)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const C t = x[r][k] - mean[r];
+                v[r] += t * t;
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            rstd[r] = (C)1 / dsqrt(wave_sum(v[r]) / (C)d + (C)1e-5);
+        for (int k = lane; k < d; k += 64) {
+            const C g = hw.lnf_g[k], b = hw.lnf_b[k];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const C f = (x[r][k] - mean[r]) * rstd[r] * g + b;
+#pragma unroll
+                for (int c = 0; c < V; ++c) z[r][c] += f * hw.W_head[k * V + c];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            C a[V];
+            C mx = neg_inf<C>();
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                a[c] = wave_sum(z[r][c]) + hw.b_head[c];
+                mx = a[c] > mx ? a[c] : mx;
+            }
+            C sum = 0;
+#pragma unroll
+            for (int c = 0; c < V; ++c) sum += dexp(a[c] - mx);
+            const C lse = mx + dlog(sum);
+#pragma unroll
+            for (int c = 0; c < V; ++c) lp[r][c] = a[c] - lse;
+        }
+    }
+}
+
+// Launch of a head kernel instantiated per token width: V = 2^K values.
+#define VQ_BY_VALUES(K, CALL)        \
+    switch (K) {                     \
+        case 1: { constexpr int V = 2; CALL; break; }  \
+        case 2: { constexpr int V = 4; CALL; break; }  \
+        case 3: { constexpr int V = 8; CALL; break; }  \
+        case 4: { constexpr int V = 16; CALL; break; } \
+        default: return hipErrorInvalidValue;          \
+    }
+
+template <class P, int V>
 __global__ void __launch_bounds__(kThreads) k_head_seq(
     ModelDims m, HeadW<typename P::acc> hw, const int8_t* __restrict__ spins,
     const int32_t* n_dev, int64_t n_seq, const typename P::acc* __restrict__ x,
@@ -1140,14 +1220,13 @@ __global__ void __launch_bounds__(kThreads) k_head_seq(
         for (int i = wave; i < m.N; i += kThreads / 64) {
             const int64_t row = s * m.N + i;
             const acc* xr[1] = {x + row * m.d};
-            acc l0[1], l1[1];
-            head_rows<acc, 1>(xr, m.d, hw, l0, l1);
+            acc l[1][V];
+            head_rows_v<acc, 1, V>(xr, m.d, hw, l);
             if (lane == 0) {
-                ell[i] = (double)(spins[row] < 0 ? l1[0] : l0[0]);
-                if (lp) {
-                    lp[row * 2] = l0[0];
-                    lp[row * 2 + 1] = l1[0];
-                }
+                ell[i] = (double)l[0][token_at(spins + s * m.S, i, m.K)];
+                if (lp)
+#pragma unroll
+                    for (int c = 0; c < V; ++c) lp[row * V + c] = l[0][c];
             }
         }
         __syncthreads();
@@ -1166,9 +1245,9 @@ hipError_t launch_head_seq(const ModelDims& m, const HeadW<typename P::acc>& hw,
                            int64_t n_seq, const typename P::acc* x,
                            typename P::acc* lp, double* logpsi,
                            hipStream_t st) {
-    hipLaunchKernelGGL(k_head_seq<P>, dim3(grid_for(n_seq)), dim3(kThreads),
-                       sizeof(double) * m.N, st, m, hw, spins, n_dev, n_seq, x,
-                       lp, logpsi);
+    VQ_BY_VALUES(m.K, hipLaunchKernelGGL((k_head_seq<P, V>), dim3(grid_for(n_seq)),
+                                         dim3(kThreads), sizeof(double) * m.N, st,
+                                         m, hw, spins, n_dev, n_seq, x, lp, logpsi));
     return hipGetLastError();
 }
 
@@ -1196,7 +1275,7 @@ __global__ void k_sample_embed(ModelDims m, HeadW<typename P::acc> hw,
         const int64_t s = e / m.d;
         const int col = (int)(e - s * m.d);
         const int64_t row = s * m.N + i;
-        const int u = i == 0 ? 2 : (spins[row - 1] < 0 ? 1 : 0);
+        const int u = i == 0 ? 1 << m.K : token_at(spins + s * m.S, i - 1, m.K);
         x[row * m.d + col] = hw.tok[u * m.d + col] + hw.pos[(int64_t)i * m.d + col];
         if (col == 0) {
             list[s] = row;
@@ -1258,9 +1337,13 @@ hipError_t launch_attn_rows(const ModelDims& m, int64_t n, int i,
 }
 
 // Head of row i of every sample (one wave each, as k_head_seq), the draw of
-// s_i, and the running sum of log P(s_i | s_<i) in position order (FP64, as
-// k_head_seq sums it); at the last position log psi = sum / 2.
-template <class P>
+// token i, and the running sum of log P(t_i | t_<i) in position order (FP64,
+// as k_head_seq sums it); at the last position log psi = sum / 2.  One
+// spin per token: s_i = +1 iff u_i < P(+1).  Tokens of K spins: the
+// smallest value c whose cumulative probability (exponentials of the
+// log-probabilities summed in value order, FP64) exceeds the uniform
+// number of the token's first site; the K spins are the bits of c.
+template <class P, int V>
 __global__ void __launch_bounds__(kThreads) k_sample_head(
     ModelDims m, HeadW<typename P::acc> hw, int64_t n, int i,
     const typename P::acc* __restrict__ x, const double* __restrict__ uni,
@@ -1273,12 +1356,28 @@ __global__ void __launch_bounds__(kThreads) k_sample_head(
          s < n; s += waves) {
         const int64_t row = s * m.N + i;
         const acc* xr[1] = {x + row * m.d};
-        acc l0[1], l1[1];
-        head_rows<acc, 1>(xr, m.d, hw, l0, l1);
+        acc l[1][V];
+        head_rows_v<acc, 1, V>(xr, m.d, hw, l);
         if (lane == 0) {
-            const bool up = uni[row] < exp((double)l0[0]);
-            spins[row] = up ? (int8_t)1 : (int8_t)-1;
-            const double acc64 = lpsum[s] + (double)(up ? l0[0] : l1[0]);
+            const int64_t site = s * m.S + (int64_t)i * m.K;
+            int c;
+            if constexpr (V == 2) {
+                c = uni[site] < exp((double)l[0][0]) ? 0 : 1;
+            } else {
+                const double u = uni[site];
+                double cdf = 0.0;
+                c = V - 1;
+                for (int v = 0; v < V; ++v) {
+                    cdf += exp((double)l[0][v]);
+                    if (u < cdf) {
+                        c = v;
+                        break;
+                    }
+                }
+            }
+            for (int k = 0; k < m.K; ++k)
+                spins[site + k] = ((c >> k) & 1) ? (int8_t)-1 : (int8_t)1;
+            const double acc64 = lpsum[s] + (double)l[0][c];
             lpsum[s] = acc64;
             if (i == m.N - 1 && logpsi) logpsi[s] = 0.5 * acc64;
         }
@@ -1291,10 +1390,10 @@ hipError_t launch_sample_head(const ModelDims& m,
                               int i, const typename P::acc* x,
                               const double* uni, int8_t* spins, double* lpsum,
                               double* logpsi, hipStream_t st) {
-    hipLaunchKernelGGL(k_sample_head<P>,
-                       dim3(grid_for((n + kThreads / 64 - 1) / (kThreads / 64))),
-                       dim3(kThreads), 0, st, m, hw, n, i, x, uni, spins,
-                       lpsum, logpsi);
+    VQ_BY_VALUES(m.K, hipLaunchKernelGGL((k_sample_head<P, V>),
+                                         dim3(grid_for((n + kThreads / 64 - 1) / (kThreads / 64))),
+                                         dim3(kThreads), 0, st, m, hw, n, i, x, uni,
+                                         spins, lpsum, logpsi));
     return hipGetLastError();
 }
 
@@ -1343,15 +1442,16 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
             const int pmin = D.p1 + 1;
             for (int i = lane; i < N - pmin; i += 64) dd.slot_nb[D.ov + i] = (int32_t)nb;
             uint64_t* mk = dd.mask + nb * W;
-            const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
+            const int8_t* sp = dd.spins + (int64_t)D.sigma * m.S;
             const int rowsC[2] = {D.p1 + 1, D.p2 + 1};
-            // an exchange moves s[p2] into p1 and s[p1] into p2 (two
-            // changed input tokens, p1 < p2 < N); a flip of p1 (p1 == p2)
-            // changes the one input token at p1 + 1, if there is one
-            const bool flip = D.p1 == D.p2;
-            const int tokC[2] = {flip ? (sp[D.p1] < 0 ? 0 : 1) : (sp[D.p2] < 0 ? 1 : 0),
-                                 sp[D.p1] < 0 ? 1 : 0};
-            const int nC = flip ? (rowsC[0] < N ? 1 : 0) : (rowsC[1] < N ? 2 : 1);
+            // the neighbour's tokens p1 and p2 are the inputs of rows p1 + 1
+            // and p2 + 1: two changed input tokens (p1 < p2 < N), or one at
+            // p1 + 1, if there is one, when both changed sites (or the one
+            // flipped site) lie in token p1 == p2
+            const bool single = D.p1 == D.p2;
+            const int tokC[2] = {nb_token_at(sp, D, D.p1, m.K),
+                                 nb_token_at(sp, D, D.p2, m.K)};
+            const int nC = single ? (rowsC[0] < N ? 1 : 0) : (rowsC[1] < N ? 2 : 1);
             // every mask word written once, never read back within the kernel
             for (int wd = lane; wd < W; wd += 64) {
                 uint64_t v = 0;
@@ -1626,7 +1726,7 @@ hipError_t launch_code_diff(const ModelDims& m, const DedupIO<P>& d,
 // and evaluated four at a time, their new log-probs kept in LDS beside the
 // sample's cached ones (loaded by all lanes at once); lane 0 sums the
 // differences in FP64 in row order from LDS.
-template <class P>
+template <class P, int V>
 __global__ void __launch_bounds__(64) k_head_dedup(
     ModelDims m, HeadW<typename P::acc> hw, DedupIO<P> dd,
     const typename P::acc* __restrict__ blp, double* __restrict__ ratio,
@@ -1645,7 +1745,7 @@ __global__ void __launch_bounds__(64) k_head_dedup(
         const NbDesc D = dd.desc[nb];
         const int pmin = D.p1 + 1;
         const uint64_t* mk = dd.mask + nb * W;
-        const int8_t* sp = dd.spins + (int64_t)D.sigma * N;
+        const int8_t* sp = dd.spins + (int64_t)D.sigma * m.S;
         __syncthreads();
         for (int wd = lane; wd < W; wd += 64) sm[wd] = mk[wd];
         __syncthreads();
@@ -1660,13 +1760,11 @@ __global__ void __launch_bounds__(64) k_head_dedup(
             nc += __popcll(cm);
         }
         __syncthreads();
-        // target of s' at i: exchanged sites swap spins, a flipped site
-        // (p1 == p2) changes sign
-        const bool flip = D.p1 == D.p2;
-        auto snew = [&](int i) {
-            return i == D.p1 ? (flip ? (int8_t)-sp[i] : sp[D.p2])
-                             : (i == D.p2 ? sp[D.p1] : sp[i]);
-        };
+        // target tokens of s' (exchanged sites swap spins, a flipped site
+        // changes sign) and of s at row i; p1 == p2: one changed token
+        const bool single = D.p1 == D.p2;
+        auto tnew = [&](int i) { return nb_token_at(sp, D, i, m.K); };
+        auto told = [&](int i) { return token_at(sp, i, m.K); };
         for (int c0 = 0; c0 < nc; c0 += R) {
             const acc* xr[R];
             int ir[R];
@@ -1675,15 +1773,22 @@ __global__ void __launch_bounds__(64) k_head_dedup(
                 ir[r] = rl[c0 + r < nc ? c0 + r : nc - 1];
                 xr[r] = dd.ox + (D.ov + (ir[r] - pmin)) * (int64_t)m.d;
             }
-            acc l0[R], l1[R];
-            head_rows<acc, R>(xr, m.d, hw, l0, l1);
+            acc l[R][V];
+            head_rows_v<acc, R, V>(xr, m.d, hw, l);
             if (lane < R && c0 + lane < nc) {
+                // lane r takes row r of the group (no dynamic register index)
                 int i = ir[0];
-                acc a0 = l0[0], a1 = l1[0];
 #pragma unroll
-                for (int r = 1; r < R; ++r)
-                    if (lane == r) { i = ir[r]; a0 = l0[r]; a1 = l1[r]; }
-                lnw[c0 + lane] = snew(i) < 0 ? a1 : a0;
+                for (int rr = 1; rr < R; ++rr)
+                    if (lane == rr) i = ir[rr];
+                const int t = tnew(i);
+                acc a = l[0][0];
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                    for (int c = 0; c < V; ++c)
+                        if (lane == rr && c == t) a = l[rr][c];
+                lnw[c0 + lane] = a;
             }
         }
         my_rows += nc;
@@ -1692,7 +1797,7 @@ __global__ void __launch_bounds__(64) k_head_dedup(
         bool p2in = false;
         for (int c = lane; c < nc; c += 64) {
             const int i = rl[c];
-            lold[c] = blp[((int64_t)D.sigma * N + i) * 2 + (sp[i] < 0 ? 1 : 0)];
+            lold[c] = blp[((int64_t)D.sigma * N + i) * V + told(i)];
             p2in |= i == D.p2;
         }
         p2in = __ballot(p2in) != 0;
@@ -1701,16 +1806,15 @@ __global__ void __launch_bounds__(64) k_head_dedup(
             // rows p1, then the listed rows (all after p1) with p2 in its
             // place: the rows and the order of a walk over i = p1 .. N-1
             auto unlisted = [&](int i) {
-                const int tnew = snew(i) < 0 ? 1 : 0, told = sp[i] < 0 ? 1 : 0;
                 const int64_t brow = (int64_t)D.sigma * N + i;
-                return (double)blp[brow * 2 + tnew] - (double)blp[brow * 2 + told];
+                return (double)blp[brow * V + tnew(i)] - (double)blp[brow * V + told(i)];
             };
-            // a flip has one changed target (p1); an exchange a second one
-            // at p2 unless p2 is a listed row
-            const double t2 = (p2in || flip) ? 0.0 : unlisted(D.p2);
+            // one changed token has one changed target (p1); two changed
+            // tokens a second one at p2 unless p2 is a listed row
+            const double t2 = (p2in || single) ? 0.0 : unlisted(D.p2);
             double delta = 0.0;
             delta += unlisted(D.p1);
-            bool p2done = p2in || flip;
+            bool p2done = p2in || single;
             for (int c = 0; c < nc; ++c) {
                 if (!p2done && rl[c] > D.p2) {
                     delta += t2;
@@ -1732,8 +1836,8 @@ hipError_t launch_head_dedup(const ModelDims& m, const HeadW<typename P::acc>& h
                              const DedupIO<P>& d, const typename P::acc* blp,
                              const double*, double* ratio, int64_t* ctr,
                              hipStream_t st) {
-    hipLaunchKernelGGL(k_head_dedup<P>, dim3(grid_for(d.n_nb_max)), dim3(64), 0,
-                       st, m, hw, d, blp, ratio, ctr);
+    VQ_BY_VALUES(m.K, hipLaunchKernelGGL((k_head_dedup<P, V>), dim3(grid_for(d.n_nb_max)),
+                                         dim3(64), 0, st, m, hw, d, blp, ratio, ctr));
     return hipGetLastError();
 }
 

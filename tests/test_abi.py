@@ -58,6 +58,9 @@ def _cfg(**kw):
     (dict(hamiltonian=1, marshall=0, L=2), 2),      # periodic chain of 2
     (dict(hamiltonian=1, marshall=0, gamma=float("nan")), 2),
     (dict(hamiltonian=5), 2),
+    (dict(group=5), 2),                   # at most 4 spins per token
+    (dict(group=3), 2),                   # 16 sites in tokens of 3
+    (dict(group=-1), 2),
 ])
 def test_invalid_configs_rejected(kw, status):
     lib = vq.load_library()

@@ -9,6 +9,8 @@ self-attention, Sec. 3.1) at the sizes this project measures:
   large   16x16, d=128, 8 layers, 8 heads, MLP 512,  Q=1024, B=8192, bf16
   multi   6x6..20x20 lattices, d=128, 6 layers, 8 heads, MLP 512, Q=512, bf16
   grad    20x20, d=256, 12 layers, 8 heads, MLP 1024, Q=1024, B=2048, bf16
+  large_g4 the large model over tokens of 4 spins (64 tokens), B=8192, bf16
+  small_g4 the small model over tokens of 4 spins (4 tokens), B=64, f64
   table1  the paper's Table 1 network (3 blocks + attention-only half-block,
           d=256, 8 heads, 64 codes) on the open 8x8 lattice, B=4096, bf16
   tfim    1-D transverse-field Ising chain of 384 sites (open, Gamma = J = 1),
@@ -105,6 +107,14 @@ CONFIGS["table1"] = ModelConfig("table1", L=8, d_model=256, n_layers=3,
                                 n_heads=8, d_ff=1024, codebook_size=64,
                                 vq_heads=1, periodic=False, precision="bf16",
                                 batch=4096, spin_seed=1008, attn_tail=True)
+
+# Tokens of four spins (Sec. 3.1 groups of K particles; Sec. 3.2 uses
+# groups of 4): the 16x16 model over 64 tokens of 16 values, and a 4x4
+# FP64 model over 4 tokens for oracle parity.
+CONFIGS["large_g4"] = replace(CONFIGS["large"], name="large_g4", group=4,
+                              spin_seed=1009)
+CONFIGS["small_g4"] = replace(CONFIGS["small"], name="small_g4", group=4,
+                              batch=64, spin_seed=1010)
 
 # Mixed-lattice batch: one parameter buffer per lattice, uneven sample counts.
 MULTI_LATTICE = tuple(
