@@ -15,7 +15,8 @@ Plain, slow, obviously-correct NumPy float64 code that follows the paper:
 * ``network``  - the autoregressive transformer with a vector quantizer after
   each self-attention (Sec. 3.1, eqs. 4-6; chain-rule distribution of Sec. 2),
   log psi = 1/2 log P with zero phase (Sec. 4); tokens of one spin, or of
-  groups of K spins with 2^K values (Sec. 3.1).
+  groups of K spins with 2^K values (Sec. 3.1); or the bidirectional
+  encoder with mean pooling as log psi (Sec. 3.1's other network).
 * ``eloc``     - the local energy of eq. (2) by naive re-evaluation of psi on
   every neighbour, and the code-diff deduplicated evaluation of Sec. 3.2 as a
   cross-check with its changed-row counters.
@@ -37,6 +38,9 @@ Pins (tests/test_oracle_*.py):
   tokens of K spins: the token of a group by hand, the closed form for
     zero weights but the head bias, normalisation over all states, the
     sampler's histogram, dedup = plain, central differences.
+  encoder: the closed form for zero weights but the head bias, symmetry
+    under token permutations without position embeddings, bidirectional
+    attention, dedup = plain, central differences.
   The absolute value of log psi for a random network has no external value to
   compare against ("parity unpinned" beyond the structural pins above).
 """

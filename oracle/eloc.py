@@ -83,6 +83,7 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
     P = net.unpack(cfg, theta)
     spins = np.atleast_2d(spins)
     K, N, d = net.group(cfg), net.n_tokens(cfg), cfg.d_model
+    enc = net.encoder(cfg)
     H = cfg.vq_heads
     m = d // H
     bl = lattice.bonds(cfg.L, cfg.periodic)
@@ -93,18 +94,24 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
     for b in range(spins.shape[0]):
         base = net.forward(cfg, P, spins[b:b + 1], keep=True)
         t0, u0 = net.tokens(spins[b:b + 1], K)
+        if enc:
+            u0 = t0                    # the encoder reads the tokens
         C_base = [{k: v[0] for k, v in c.items()} for c in base["caches"]]
-        lp0 = base["lp"][0]
-        ell0 = base["ell"][0]
+        lp0 = None if enc else base["lp"][0]
+        ell0 = None if enc else base["ell"][0]
         acc = 0.0
         for _, p1, p2 in lattice.neighbours(spins[b], bl):
             s1 = lattice.swap(spins[b], p1, p2)
             t1, u1 = net.tokens(s1[None], K)
             t1, u1 = t1[0], u1[0]
+            if enc:
+                u1 = t1
             C = changed_inputs(u0[0], u1)
             # tokens of the exchanged sites (one token when both fall in it)
             tp1, tp2 = p1 // K, p2 // K
-            pmin = tp1 + 1
+            # the decoder's rows before the first changed input see an
+            # unchanged prefix; every encoder row attends to the change
+            pmin = 0 if enc else tp1 + 1
             xo = {i: P["tok"][u1[i]] + P["pos"][i] for i in C}
             sizes, arows, vrows, codes_sp = [len(C)], 0, 0, []
             for l, lay in enumerate(P["layers"]):
@@ -117,7 +124,8 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
                                                  qkv[:, 2 * d:])
                 att = np.arange(pmin, N)
                 arows += len(att)
-                a = net.causal_attention(q[att], k, v, cfg.n_heads, rows=att)
+                a = net.causal_attention(q[att], k, v, cfg.n_heads, rows=att,
+                                         causal=not enc)
                 codes = cb["codes"].copy()
                 search = np.ones(len(att), dtype=bool)
                 if certified:
@@ -170,6 +178,23 @@ def eloc_dedup(cfg, theta, spins, certified=False, return_info=False):
                 xn = xin + a @ T["W_o"] + T["b_o"]
                 xo = {int(i): xn[j] for j, i in enumerate(att)}
                 C = [int(i) for i in att]
+            if enc:
+                # encoder head: the pooled mean changes by the rows of C_L
+                c0 = base["terms"][0]
+                delta = 0.0
+                if C:
+                    rows = np.array(C)
+                    cn = net.pooled_terms(P, np.stack([xo[i] for i in rows]))
+                    for j, i in enumerate(rows):
+                        delta += cn[j] - c0[i]
+                r = np.exp(delta / N)
+                acc += r
+                info["ratios"].append((b, r))
+                info["changed"].append(sizes)
+                info["att_rows"].append(arows)
+                info["vq_rows"].append(vrows)
+                info["codes"].append(np.stack(codes_sp) if codes_sp else None)
+                continue
             # Head: rows of C_L get new log-probs; the tokens of the
             # exchanged sites keep s's hidden state but change target.
             delta = 0.0

@@ -41,6 +41,7 @@ def _unpack(cfg, th):
     """Views of the flat torch parameter vector th, in the flat layout."""
     d, Q, H, F = cfg.d_model, cfg.codebook_size, cfg.vq_heads, cfg.d_ff
     V, T = onet.classes(cfg), onet.n_tokens(cfg)
+    enc = onet.encoder(cfg)
     pos = [0]
 
     def take(*shape):
@@ -49,7 +50,8 @@ def _unpack(cfg, th):
         pos[0] += n
         return a
 
-    P = {"tok": take(V + 1, d), "pos": take(T, d), "layers": []}
+    P = {"tok": take(V if enc else V + 1, d), "pos": take(T, d),
+         "layers": []}
     for _ in range(cfg.n_layers):
         P["layers"].append(dict(
             ln1_g=take(d), ln1_b=take(d), W_qkv=take(d, 3 * d),
@@ -61,8 +63,8 @@ def _unpack(cfg, th):
                          b_qkv=take(3 * d), W_o=take(d, d), b_o=take(d))
     P["lnf_g"] = take(d)
     P["lnf_b"] = take(d)
-    P["W_head"] = take(d, V)
-    P["b_head"] = take(V)
+    P["W_head"] = take(d, 1 if enc else V)
+    P["b_head"] = take(1 if enc else V)
     assert pos[0] == th.numel()
     return P
 
@@ -77,7 +79,7 @@ def _gelu(x):
     return 0.5 * x * (1.0 + torch.erf(x / np.sqrt(2.0)))
 
 
-def _attention(q, k, v, n_heads):
+def _attention(q, k, v, n_heads, causal=True):
     S, N, d = q.shape
     dh = d // n_heads
 
@@ -85,8 +87,9 @@ def _attention(q, k, v, n_heads):
         return t.reshape(S, N, n_heads, dh).transpose(1, 2)
 
     s = heads(q) @ heads(k).transpose(-1, -2) / np.sqrt(dh)
-    mask = torch.triu(torch.ones(N, N, dtype=torch.bool), diagonal=1)
-    s = s.masked_fill(mask, float("-inf"))
+    if causal:
+        mask = torch.triu(torch.ones(N, N, dtype=torch.bool), diagonal=1)
+        s = s.masked_fill(mask, float("-inf"))
     p = torch.softmax(s, dim=-1)
     return (p @ heads(v)).transpose(1, 2).reshape(S, N, d)
 
@@ -128,6 +131,9 @@ def _forward(cfg, th, spins, frozen=None):
     per-layer frozen state (codes, softmax values) of this evaluation."""
     P = _unpack(cfg, th)
     t, u = onet.tokens(spins, onet.group(cfg))
+    enc = onet.encoder(cfg)
+    if enc:
+        u = t                          # the encoder reads the tokens
     t = torch.as_tensor(t)
     u = torch.as_tensor(u)
     d = cfg.d_model
@@ -137,7 +143,7 @@ def _forward(cfg, th, spins, frozen=None):
         h = _ln(x, lay["ln1_g"], lay["ln1_b"])
         qkv = h @ lay["W_qkv"] + lay["b_qkv"]
         a = _attention(qkv[..., :d], qkv[..., d:2 * d], qkv[..., 2 * d:],
-                       cfg.n_heads)
+                       cfg.n_heads, causal=not enc)
         z, codes, probs = vq_surrogate(a, lay["codebook"],
                                        None if frozen is None else frozen[l])
         state.append({"codes": codes, "probs": probs})
@@ -151,6 +157,8 @@ def _forward(cfg, th, spins, frozen=None):
                        cfg.n_heads)
         x = x + a @ T["W_o"] + T["b_o"]
     f = _ln(x, P["lnf_g"], P["lnf_b"])
+    if enc:
+        return (f @ P["W_head"])[..., 0].mean(dim=-1) + P["b_head"][0], state
     lp = torch.log_softmax(f @ P["W_head"] + P["b_head"], dim=-1)
     ell = torch.gather(lp, -1, t[..., None])[..., 0]
     return 0.5 * ell.sum(dim=-1), state

@@ -25,6 +25,12 @@ project's design notes; each is restated where it is used):
 * Head: final LN, linear d -> 2^K, log-softmax; log P(s) = sum_i l_i.
 * Zero phase (Sec. 4, Marshall-rotated Heisenberg), so
   log psi(s) = 1/2 log P(s)  (polar form of Sec. 2).
+* The other network of Sec. 3.1, the bidirectional encoder (cfg.encoder),
+  used as log psi: the same blocks over the tokens themselves (no shift,
+  no beginning-of-sequence token) with attention over all positions; the
+  last layer's hidden states are pooled (their mean after the final LN)
+  and a linear map gives the scalar: log psi(s) = mean_i LN(x_i) . w + b.
+  It is not autoregressive (no direct sampling).
 
 Vector quantizer (eqs. 4-6): the input vector is split into H contiguous
 segments; segment h picks the codeword of codebook W_h nearest in Euclidean
@@ -41,6 +47,9 @@ def unpack(cfg, theta):
     """Split the flat FP64 parameter vector into named arrays (views)."""
     d, Q, H, F = cfg.d_model, cfg.codebook_size, cfg.vq_heads, cfg.d_ff
     V, T = classes(cfg), n_tokens(cfg)
+    enc = encoder(cfg)
+    if enc and getattr(cfg, "attn_tail", False):
+        raise ValueError("the encoder has no attention-only half-block")
     theta = np.asarray(theta, dtype=np.float64)
     pos = [0]
 
@@ -50,7 +59,8 @@ def unpack(cfg, theta):
         pos[0] += n
         return a
 
-    P = {"tok": take(V + 1, d), "pos": take(T, d), "layers": []}
+    P = {"tok": take(V if enc else V + 1, d), "pos": take(T, d),
+         "layers": []}
     for _ in range(cfg.n_layers):
         P["layers"].append(dict(
             ln1_g=take(d), ln1_b=take(d), W_qkv=take(d, 3 * d),
@@ -62,8 +72,8 @@ def unpack(cfg, theta):
                          b_qkv=take(3 * d), W_o=take(d, d), b_o=take(d))
     P["lnf_g"] = take(d)
     P["lnf_b"] = take(d)
-    P["W_head"] = take(d, V)
-    P["b_head"] = take(V)
+    P["W_head"] = take(d, 1 if enc else V)
+    P["b_head"] = take(1 if enc else V)
     if pos[0] != theta.size:
         raise ValueError(f"parameter vector has {theta.size} entries, "
                          f"model needs {pos[0]}")
@@ -87,9 +97,18 @@ def n_tokens(cfg):
     return cfg.N // group(cfg)
 
 
+def encoder(cfg):
+    """The bidirectional encoder with pooling in place of the decoder."""
+    return bool(getattr(cfg, "encoder", False))
+
+
 def n_params(cfg):
     d, Q, F = cfg.d_model, cfg.codebook_size, cfg.d_ff
     V, T = classes(cfg), n_tokens(cfg)
+    if encoder(cfg):
+        per_layer = (2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d
+                     + d * F + F + F * d + d)
+        return V * d + T * d + cfg.n_layers * per_layer + 2 * d + d + 1
     per_layer = (2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d
                  + d * F + F + F * d + d)
     tail = (2 * d + 3 * d * d + 3 * d + d * d + d
@@ -121,17 +140,20 @@ def gelu(x):
     return 0.5 * x * (1.0 + erf(x / np.sqrt(2.0)))
 
 
-def causal_attention(q, k, v, n_heads, rows=None):
+def causal_attention(q, k, v, n_heads, rows=None, causal=True):
     """Causal multi-head attention.
 
     q: [..., R, d] queries at sequence positions ``rows`` (default all N);
-    k, v: [..., N, d].  Query at position i attends to keys j <= i.
+    k, v: [..., N, d].  Query at position i attends to keys j <= i
+    (every key when causal is False: the bidirectional encoder).
     """
     N, d = k.shape[-2], k.shape[-1]
     R = q.shape[-2]
     dh = d // n_heads
     rows = np.arange(N) if rows is None else np.asarray(rows)
     masked = np.arange(N)[None, :] > rows[:, None]            # [R, N]
+    if not causal:
+        masked = np.zeros_like(masked)
 
     def heads(t, n):        # [..., n, d] -> [..., heads, n, dh]
         return np.swapaxes(t.reshape(t.shape[:-1] + (n_heads, dh)), -2, -3)
@@ -249,6 +271,13 @@ def head_logprobs(P, x):
                                                          keepdims=True)))
 
 
+def pooled_terms(P, x):
+    """Encoder head: every position's LN(x_i) . w, [..., T]; log psi is
+    their mean plus the bias."""
+    f = layer_norm(x, P["lnf_g"], P["lnf_b"])
+    return (f @ P["W_head"])[..., 0]
+
+
 def forward(cfg, P, spins, keep=False):
     """Full forward pass of a batch of sequences spins [S, N].
 
@@ -260,13 +289,16 @@ def forward(cfg, P, spins, keep=False):
     """
     spins = np.atleast_2d(spins)
     t, u = tokens(spins, group(cfg))
+    enc = encoder(cfg)
+    if enc:
+        u = t                          # the encoder reads the tokens
     d = cfg.d_model
     x = P["tok"][u] + P["pos"][None, :, :]
     codes, caches = [], []
     for lay in P["layers"]:
         qkv = qkv_rows(lay, x)
         q, k, v = qkv[..., :d], qkv[..., d:2 * d], qkv[..., 2 * d:]
-        a = causal_attention(q, k, v, cfg.n_heads)
+        a = causal_attention(q, k, v, cfg.n_heads, causal=not enc)
         c, z, d1, d2 = quantize(a, lay["codebook"])
         if keep:
             caches.append(dict(x=x, q=q, k=k, v=v, a=a, codes=c, d1=d1,
@@ -282,6 +314,15 @@ def forward(cfg, P, spins, keep=False):
             tail_cache = dict(x=x, q=qkv[..., :d], k=qkv[..., d:2 * d],
                               v=qkv[..., 2 * d:])
         x = tail_block(P["tail"], x, cfg.n_heads)
+    if enc:
+        c = pooled_terms(P, x)
+        out = dict(logpsi=c.mean(axis=-1) + P["b_head"][0], terms=c,
+                   ell=None, lp=None,
+                   codes=np.stack(codes) if codes else None, x_final=x)
+        if keep:
+            out["caches"] = caches
+            out["tail"] = None
+        return out
     lp = head_logprobs(P, x)
     ell = np.take_along_axis(lp, t[..., None], axis=-1)[..., 0]
     out = dict(logpsi=0.5 * ell.sum(axis=-1), ell=ell, lp=lp,

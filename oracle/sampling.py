@@ -28,6 +28,9 @@ def sample(cfg, theta, uniforms):
     over the drawn conditionals; probs are what the draws compared against:
     [S, N] conditional probabilities of +1 for K = 1, [S, T, 2^K] the
     conditional probabilities of every token value for K > 1."""
+    if net.encoder(cfg):
+        raise ValueError("the bidirectional encoder is not autoregressive: "
+                         "no direct sampling")
     P = net.unpack(cfg, theta)
     u = np.asarray(uniforms, dtype=np.float64)
     S, N = u.shape

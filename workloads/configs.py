@@ -46,6 +46,8 @@ class ModelConfig:
                                       # blocks (no quantizer, no MLP)
     group: int = 1                    # spins per token (Sec. 3.1: tokens are
                                       # groups of K particles)
+    encoder: bool = False             # bidirectional encoder with mean
+                                      # pooling as log psi (Sec. 3.1)
 
     @property
     def N(self) -> int:

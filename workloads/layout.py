@@ -16,6 +16,10 @@ T = N / K tokens.
     tail.W_o[d][d] tail.b_o[d]
   lnf_g[d] lnf_b[d]  W_head[d][2^K] b_head[2^K]
 
+The bidirectional encoder (cfg.encoder) reads the tokens themselves, with no
+beginning-of-sequence token: tok_emb[2^K][d]; its head is one output,
+W_head[d][1] b_head[1], averaged over the positions (log psi).
+
 Each entry carries a ``kind`` tag used only by the seeded initialiser:
 "w" (Gaussian), "gain" (set to 1) or "bias" (set to 0).
 """
@@ -25,7 +29,8 @@ def param_layout(cfg):
     d, Q, H, F = cfg.d_model, cfg.codebook_size, cfg.vq_heads, cfg.d_ff
     V = 1 << getattr(cfg, "group", 1)        # classes per token
     T = cfg.N // getattr(cfg, "group", 1)
-    ent = [("tok_emb", (V + 1, d), "w"), ("pos_emb", (T, d), "w")]
+    enc = getattr(cfg, "encoder", False)
+    ent = [("tok_emb", (V if enc else V + 1, d), "w"), ("pos_emb", (T, d), "w")]
     for l in range(cfg.n_layers):
         p = f"l{l}."
         ent += [
@@ -43,7 +48,8 @@ def param_layout(cfg):
                 ("tail.b_qkv", (3 * d,), "bias"),
                 ("tail.W_o", (d, d), "w"), ("tail.b_o", (d,), "bias")]
     ent += [("lnf_g", (d,), "gain"), ("lnf_b", (d,), "bias"),
-            ("W_head", (d, V), "w"), ("b_head", (V,), "bias")]
+            ("W_head", (d, 1 if enc else V), "w"),
+            ("b_head", (1 if enc else V,), "bias")]
     out, off = [], 0
     for name, shape, kind in ent:
         n = 1
