@@ -155,6 +155,15 @@ typedef struct {
                               W_head [d][2^K], b_head [2^K].  Token value
                               sum_k b_k 2^k, b_k = 1 for spin -1 at the
                               token's k-th site.                            */
+    int32_t encoder;       /* 1: the bidirectional encoder with mean pooling as
+                              log psi (Sec. 3.1) in place of the decoder: the
+                              tokens themselves as input (tok_emb [2^K][d], no
+                              beginning-of-sequence token), attention over all
+                              positions, log psi = mean_i LN(x_i) . w + b
+                              (W_head [d][1], b_head [1]).  Not autoregressive:
+                              vqnqs_sample and vqnqs_vmc_step return
+                              VQNQS_ERR_UNSUPPORTED.  FP64 and FP32 modes; no
+                              half-block, no incremental attention.        */
 } vqnqs_config;
 
 /* Counters written by vqnqs_local_energy (int64, VQNQS_NCOUNTERS entries,

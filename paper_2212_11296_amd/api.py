@@ -46,7 +46,8 @@ class Config(ctypes.Structure):
                 ("codebook_size", ctypes.c_int32), ("vq_heads", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("hamiltonian", ctypes.c_int32), ("gamma", ctypes.c_double),
-                ("attn_tail", ctypes.c_int32), ("group", ctypes.c_int32)]
+                ("attn_tail", ctypes.c_int32), ("group", ctypes.c_int32),
+                ("encoder", ctypes.c_int32)]
 
 
 class Job(ctypes.Structure):
@@ -77,7 +78,8 @@ def make_config(mc, precision=None, flags=0):
                   mc.codebook_size, mc.vq_heads, int(prec), int(flags),
                   int(ham), float(getattr(mc, "gamma", 0.0)),
                   int(bool(getattr(mc, "attn_tail", False))),
-                  int(getattr(mc, "group", 1)))
+                  int(getattr(mc, "group", 1)),
+                  int(bool(getattr(mc, "encoder", False))))
 
 
 _lib = None

@@ -25,6 +25,8 @@ bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
     if (c->periodic && c->marshall && (c->L & 1)) return false;  // not bipartite
     if (chain && (c->marshall || !std::isfinite(c->gamma))) return false;
     if (c->attn_tail != 0 && c->attn_tail != 1) return false;
+    if (c->encoder != 0 && c->encoder != 1) return false;
+    if (c->encoder && c->attn_tail) return false;
     if (!std::isfinite(c->J)) return false;
     if (c->d_model < 1 || c->n_layers < 0 || c->n_heads < 1 || c->d_ff < 1 ||
         c->codebook_size < 1 || c->vq_heads < 1)
@@ -35,6 +37,9 @@ bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
                      VQNQS_INC_LAYERS(255)))
         return false;
     *err = VQNQS_ERR_UNSUPPORTED;
+    if (c->encoder && (c->precision == VQNQS_BF16 ||
+                       (c->flags & VQNQS_FLAG_INCREMENTAL_ATTN)))
+        return false;
     const int dh = c->d_model / c->n_heads;
     if (dh != 4 && dh != 8 && dh != 16 && dh != 32 && dh != 64) return false;
     if (c->d_model > 512 || c->d_ff > 4096 || c->n_layers > VQNQS_NCOUNTERS - 17 ||
@@ -57,6 +62,7 @@ bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
     m->N = N;
     m->S = S;
     m->K = K;
+    m->enc = c->encoder;
     m->d = c->d_model;
     m->nl = c->n_layers;
     m->nh = c->n_heads;
@@ -199,6 +205,7 @@ vqnqs_status vqnqs_sample(const vqnqs_config* cfg, const void* params,
     vq::ModelDims m;
     vqnqs_status e;
     if (!dims_from(cfg, &m, &e)) return e;
+    if (m.enc) return VQNQS_ERR_UNSUPPORTED;     // not autoregressive
     if (batch < 0) return VQNQS_ERR_INVALID_SHAPE;
     if (!ws || (batch > 0 && (!params || !uniforms || !spins)))
         return VQNQS_ERR_NULL_POINTER;
@@ -214,6 +221,7 @@ vqnqs_status vqnqs_vmc_step(const vqnqs_config* cfg, void* params,
     vq::ModelDims m;
     vqnqs_status e;
     if (!dims_from(cfg, &m, &e)) return e;
+    if (m.enc) return VQNQS_ERR_UNSUPPORTED;     // needs direct samples
     if (batch < 1) return VQNQS_ERR_INVALID_SHAPE;
     if (!std::isfinite(lr) || (opt_state && step < 1))
         return VQNQS_ERR_INVALID_CONFIG;

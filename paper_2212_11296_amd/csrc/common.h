@@ -123,6 +123,7 @@ struct ModelDims {
     int L;         // lattice side (chain: sites)
     int N;         // sequence length: tokens per sample (T = S / K)
     int S, K;      // sites per sample, spins per token
+    int enc;       // 1: bidirectional encoder with mean pooling as log psi
     int d, nl, nh, dh, dff, Q, H, dseg;
     int periodic, marshall, precision, flags;
     int mfma;      // BF16 products on the matrix core (split activations)
@@ -163,6 +164,15 @@ struct NbDesc {
     int64_t ov;
     int16_t s1, s2;   // the sites: exchange of s1 < s2, flip when s1 == s2
 };
+
+// First token row of neighbour D that can differ from the sample's: the
+// decoder's rows before the first changed input see an unchanged prefix;
+// every encoder row attends to the change.  (The changed input rows are
+// p1 + 1 and p2 + 1 in both: the encoder's descriptors hold the changed
+// tokens minus one.)
+__device__ inline int first_row(const NbDesc& D, const ModelDims& m) {
+    return m.enc ? 0 : D.p1 + 1;
+}
 
 // Value of token t of one sample's spins sp (sites tK .. tK+K-1):
 // sum_k b_k 2^k with b_k = 1 for spin -1 at the token's k-th site.

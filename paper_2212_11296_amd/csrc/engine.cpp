@@ -17,12 +17,23 @@ namespace vq {
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t param_count(const ModelDims& m);
 
+// Token embedding rows: 2^K values plus the decoder's beginning-of-sequence
+// token; head outputs: 2^K log-probabilities, or the encoder's one term.
+static int64_t tok_rows(const ModelDims& m) {
+    return ((int64_t)1 << m.K) + (m.enc ? 0 : 1);
+}
+static int64_t head_outputs(const ModelDims& m) {
+    return m.enc ? 1 : (int64_t)1 << m.K;
+}
+
 // Worst case, over all configurations, of the overlay rows one sample needs:
 // every bond anti-aligned, each neighbour keeping token rows p1+1 .. N-1
 // (p1 the token of its first site).
 static int64_t max_overlay_rows(const ModelDims& m) {
     int64_t tot = 0;
     const int L = m.L, N = m.N, S = m.S, K = m.K;
+    // every encoder row attends to the change: N rows per neighbour
+    if (m.enc) return (int64_t)(m.chain ? S : 2 * S) * N;
     // a chain's flip of site i keeps rows i/K+1 .. N-1
     if (m.chain) {
         for (int i = 0; i < S; ++i) tot += N - i / K - 1;
@@ -322,7 +333,7 @@ static LayerW<C> layer_view(const ModelDims& m, const C* p, int l) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
-    const C* b = p + ((1 << m.K) + 1) * d + N * d + per * l;
+    const C* b = p + tok_rows(m) * d + N * d + per * l;
     LayerW<C> w{};
     w.ln1_g = b;
     w.ln1_b = b + d;
@@ -352,7 +363,7 @@ static LayerW<C> tail_view(const ModelDims& m, const C* p) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
-    const C* b = p + ((1 << m.K) + 1) * d + N * d + per * m.nl;
+    const C* b = p + tok_rows(m) * d + N * d + per * m.nl;
     LayerW<C> w{};
     w.ln1_g = b;
     w.ln1_b = b + d;
@@ -370,9 +381,9 @@ static HeadW<C> head_view(const ModelDims& m, const C* p) {
                         d * F + F + F * d + d;
     HeadW<C> h{};
     h.tok = p;
-    const int64_t V = (int64_t)1 << m.K;      // values of a token
-    h.pos = p + (V + 1) * d;
-    const C* t = p + (V + 1) * d + N * d + per * m.nl + tail_params(m);
+    const int64_t V = head_outputs(m);
+    h.pos = p + tok_rows(m) * d;
+    const C* t = p + tok_rows(m) * d + N * d + per * m.nl + tail_params(m);
     h.lnf_g = t;
     h.lnf_b = t + d;
     h.W_head = t + 2 * d;
@@ -384,8 +395,8 @@ int64_t param_count(const ModelDims& m) {
     const int64_t d = m.d, N = m.N, Q = m.Q, F = m.dff;
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
-    const int64_t V = (int64_t)1 << m.K;
-    return (V + 1) * d + N * d + per * m.nl + tail_params(m) + 2 * d + V * d + V;
+    const int64_t V = head_outputs(m);
+    return tok_rows(m) * d + N * d + per * m.nl + tail_params(m) + 2 * d + V * d + V;
 }
 
 #define CK(x)                                  \
@@ -411,7 +422,7 @@ static LayerOffsets layer_offsets(const ModelDims& m, int l) {
     const int64_t per = 2 * d + d * 3 * d + 3 * d + Q * d + d * d + d + 2 * d +
                         d * F + F + F * d + d;
     LayerOffsets o;
-    o.ln1_g = (((int64_t)1 << m.K) + 1) * d + N * d + per * l;
+    o.ln1_g = tok_rows(m) * d + N * d + per * l;
     o.ln1_b = o.ln1_g + d;
     o.W_qkv = o.ln1_b + d;
     o.b_qkv = o.W_qkv + d * 3 * d;
@@ -660,10 +671,10 @@ struct Runner {
         const HeadW<acc> hw = head();
         const int64_t off_tail = layer_offsets(m, m.nl).ln1_g;
         const int64_t off_lnf = off_tail + tail_params(m);
-        const int64_t off_Wh = off_lnf + 2 * d, off_bh = off_Wh + ((int64_t)1 << m.K) * d;
+        const int64_t off_Wh = off_lnf + 2 * d, off_bh = off_Wh + head_outputs(m) * d;
         // head: d log psi / d x_L (after the half-block, when there is one)
-        const int64_t V = (int64_t)1 << m.K;
-        LK("grad_head", launch_head_bwd<acc>(n, (int)N, (int)d, m.K, hw, sp,
+        const int64_t V = head_outputs(m);
+        LK("grad_head", launch_head_bwd<acc>(n, (int)N, (int)d, m.K, m.enc, hw, sp,
                                              w.gx + (int64_t)(m.nl + m.tail) * sd,
                                              w.coef, w.h1, w.xh1, w.rs1, w.dz2,
                                              w.dT, w.dX, st));
@@ -810,15 +821,15 @@ struct Runner {
             LK("grad_ln", launch_ln_bwd<acc>(R, (int)d, w.xh1, w.rs1, lw.ln1_g,
                                              w.dT, w.dXp, w.dX, st));
         }
-        LK("grad_embed", launch_embed_bwd<acc>(n, (int)N, (int)d, m.K, sp, w.dX, gout,
-                                               NP, 0, (V + 1) * d, st));
+        LK("grad_embed", launch_embed_bwd<acc>(n, (int)N, (int)d, m.K, m.enc, sp, w.dX,
+                                               gout, NP, 0, tok_rows(m) * d, st));
         return VQNQS_OK;
     }
 
     vqnqs_status neighbours(const int8_t* spins, int64_t n) {
         LK("neighbours", launch_neighbours(spins, n, m, w.bonds, w.count, w.diag, w.rows_cap,
                              w.status, st));
-        LK("scan_desc", launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, m.chain, m.K, w.nb_off,
+        LK("scan_desc", launch_scan_desc(w.bonds, w.count, w.rows_cap, (int)n, m.L, m.chain, m.K, m.enc, w.nb_off,
                             w.row_off, w.n_nb, w.n_rows, w.desc, st));
         if (ctr) {
             CK(launch_counter_add_const(ctr, VQNQS_CTR_SAMPLES, n, st));

@@ -36,7 +36,7 @@ hipError_t launch_neighbours(const int8_t* spins, int64_t batch,
                              int32_t* status, hipStream_t st);
 hipError_t launch_scan_desc(const int16_t* bonds, const int32_t* count,
                             const int64_t* rows_cap, int n, int L, int chain,
-                            int K,
+                            int K, int enc,
                             int32_t* nb_off, int64_t* row_off,
                             int32_t* n_nb_total, int32_t* n_rows_total,
                             NbDesc* desc, hipStream_t st);
@@ -293,11 +293,13 @@ hipError_t launch_bias_gelu(int64_t R, int F, T* u, const T* b1, T* g,
 template <typename T>
 hipError_t launch_gelu_bwd(int64_t n, const T* u, T* dg, hipStream_t st);
 template <typename T>
-hipError_t launch_head_bwd(int64_t n, int N, int d, int K, const HeadW<T>& hw,
+hipError_t launch_head_bwd(int64_t n, int N, int d, int K, int enc,
+                           const HeadW<T>& hw,
                            const int8_t* spins, const T* x, const T* coef, T* f,
                            T* xh, T* rstd, T* dz, T* df, T* dx, hipStream_t st);
 template <typename T>
-hipError_t launch_embed_bwd(int64_t n, int N, int d, int K, const int8_t* spins,
+hipError_t launch_embed_bwd(int64_t n, int N, int d, int K, int enc,
+                            const int8_t* spins,
                             const T* dx, T* grad, int64_t P, int64_t tok_off,
                             int64_t pos_off, hipStream_t st);
 template <typename T>

@@ -805,13 +805,69 @@ __global__ void __launch_bounds__(kGT) k_head_bwd_v(int64_t n, int N, int d,
     }
 }
 
+// The encoder's head: log psi = mean_i LN(x_i) . w + b, so the upstream of
+// every row's term is 2 coef / N (coef holds half the weight, the
+// decoder's factor), dz[r] = that value, df = dz w.
 template <typename T>
-hipError_t launch_head_bwd(int64_t n, int N, int d, int K, const HeadW<T>& hw,
+__global__ void __launch_bounds__(kGT) k_head_bwd_enc(int64_t n, int N, int d,
+                                                      HeadW<T> hw, const T* x,
+                                                      const T* coef, T* f,
+                                                      T* xh, T* rstd, T* dz,
+                                                      T* df, T* dx) {
+    const int lane = threadIdx.x & 63;
+    const int64_t R = n * N, wpb = kGT / 64;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < R;
+         r += (int64_t)gridDim.x * wpb) {
+        const T* xr = x + r * d;
+        T s = 0;
+        for (int k = lane; k < d; k += 64) s += xr[k];
+        const T mean = wave_sum(s) / (T)d;
+        T v = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T t = xr[k] - mean;
+            v += t * t;
+        }
+        v = wave_sum(v) / (T)d;
+        const T rs = (T)1 / dsqrt(v + (T)1e-5);
+        for (int k = lane; k < d; k += 64) {
+            const T h = (xr[k] - mean) * rs;
+            xh[r * d + k] = h;
+            f[r * d + k] = h * hw.lnf_g[k] + hw.lnf_b[k];
+        }
+        const T g0 = (T)2 * coef[r / N] / (T)N;
+        if (lane == 0) {
+            dz[r] = g0;
+            rstd[r] = rs;
+        }
+        T s1 = 0, s2 = 0;
+        for (int k = lane; k < d; k += 64) {
+            const T dfk = g0 * hw.W_head[k];
+            df[r * d + k] = dfk;
+            const T e = hw.lnf_g[k] * dfk;
+            s1 += e;
+            s2 += e * xh[r * d + k];
+        }
+        s1 = wave_sum(s1) / (T)d;
+        s2 = wave_sum(s2) / (T)d;
+        for (int k = lane; k < d; k += 64) {
+            const T e = hw.lnf_g[k] * df[r * d + k];
+            dx[r * d + k] = rs * (e - s1 - xh[r * d + k] * s2);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_head_bwd(int64_t n, int N, int d, int K, int enc, const HeadW<T>& hw,
                            const int8_t* spins, const T* x, const T* coef, T* f,
                            T* xh, T* rstd, T* dz, T* df, T* dx, hipStream_t st) {
     const int64_t R = n * N;
     if (R <= 0) return hipSuccess;
     const dim3 g(cap_grid((R + 3) / 4)), b(kGT);
+    if (enc) {
+        hipLaunchKernelGGL((k_head_bwd_enc<T>), g, b, 0, st, n, N, d, hw, x, coef, f,
+                           xh, rstd, dz, df, dx);
+        return hipGetLastError();
+    }
     switch (K) {
         case 1:
             hipLaunchKernelGGL((k_head_bwd<T>), g, b, 0, st, n, N, d, hw, spins, x,
@@ -868,7 +924,8 @@ __global__ void __launch_bounds__(kGT) k_embed_bwd(int64_t n, int N, int d,
 // of token i-1; V + 1 token rows.
 template <typename T, int V>
 __global__ void __launch_bounds__(kGT) k_embed_bwd_v(int64_t n, int N, int d,
-                                                     int K, const int8_t* spins,
+                                                     int K, int enc,
+                                                     const int8_t* spins,
                                                      const T* dx, T* grad,
                                                      int64_t P, int64_t tok_off,
                                                      int64_t pos_off) {
@@ -885,39 +942,47 @@ __global__ void __launch_bounds__(kGT) k_embed_bwd_v(int64_t n, int N, int d,
         for (int i = 0; i < N; ++i) {
             const T v = dx[(s * N + i) * d + c];
             g[pos_off + (int64_t)i * d + c] = v;
-            const int u = i == 0 ? V : token_at(sp, i - 1, K);
+            // the encoder reads the token itself (V rows, no BOS)
+            const int u = enc ? token_at(sp, i, K)
+                              : (i == 0 ? V : token_at(sp, i - 1, K));
 #pragma unroll
             for (int k = 0; k <= V; ++k)
                 if (k == u) t[k] += v;
         }
+        const int rows = enc ? V : V + 1;
 #pragma unroll
-        for (int k = 0; k <= V; ++k) g[tok_off + (int64_t)k * d + c] = t[k];
+        for (int k = 0; k <= V; ++k)
+            if (k < rows) g[tok_off + (int64_t)k * d + c] = t[k];
     }
 }
 
 template <typename T>
-hipError_t launch_embed_bwd(int64_t n, int N, int d, int K, const int8_t* spins,
-                            const T* dx, T* grad, int64_t P, int64_t tok_off,
-                            int64_t pos_off, hipStream_t st) {
+hipError_t launch_embed_bwd(int64_t n, int N, int d, int K, int enc,
+                            const int8_t* spins, const T* dx, T* grad, int64_t P,
+                            int64_t tok_off, int64_t pos_off, hipStream_t st) {
     const int64_t total = n * d;
     if (total <= 0) return hipSuccess;
     const dim3 g(cap_grid((total + kGT - 1) / kGT)), b(kGT);
     switch (K) {
         case 1:
-            hipLaunchKernelGGL((k_embed_bwd<T>), g, b, 0, st, n, N, d, spins, dx,
-                               grad, P, tok_off, pos_off);
+            if (enc)
+                hipLaunchKernelGGL((k_embed_bwd_v<T, 2>), g, b, 0, st, n, N, d, K, enc,
+                                   spins, dx, grad, P, tok_off, pos_off);
+            else
+                hipLaunchKernelGGL((k_embed_bwd<T>), g, b, 0, st, n, N, d, spins, dx,
+                                   grad, P, tok_off, pos_off);
             break;
         case 2:
-            hipLaunchKernelGGL((k_embed_bwd_v<T, 4>), g, b, 0, st, n, N, d, K, spins,
-                               dx, grad, P, tok_off, pos_off);
+            hipLaunchKernelGGL((k_embed_bwd_v<T, 4>), g, b, 0, st, n, N, d, K, enc,
+                               spins, dx, grad, P, tok_off, pos_off);
             break;
         case 3:
-            hipLaunchKernelGGL((k_embed_bwd_v<T, 8>), g, b, 0, st, n, N, d, K, spins,
-                               dx, grad, P, tok_off, pos_off);
+            hipLaunchKernelGGL((k_embed_bwd_v<T, 8>), g, b, 0, st, n, N, d, K, enc,
+                               spins, dx, grad, P, tok_off, pos_off);
             break;
         case 4:
-            hipLaunchKernelGGL((k_embed_bwd_v<T, 16>), g, b, 0, st, n, N, d, K, spins,
-                               dx, grad, P, tok_off, pos_off);
+            hipLaunchKernelGGL((k_embed_bwd_v<T, 16>), g, b, 0, st, n, N, d, K, enc,
+                               spins, dx, grad, P, tok_off, pos_off);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1221,7 +1286,8 @@ __global__ void __launch_bounds__(NT) k_attn_stats(int64_t n, ModelDims m,
                 dd += dO[base + (int64_t)i * d + c] * o[base + (int64_t)i * d + c];
             }
             T mx = neg_inf<T>(), l = 0;
-            for (int j = 0; j <= i; ++j) {
+            const int jmax = m.enc ? N - 1 : i;   // the encoder sees every key
+            for (int j = 0; j <= jmax; ++j) {
                 T sc = dot4<T, DH>(qi, Ks + j * DH);
                 sc *= scale;
                 if (sc > mx) {
@@ -1265,7 +1331,7 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_q(int64_t n, ModelDims m,
             if (wf >= N) continue;
             const int i = i0 + (int)threadIdx.x;
             const int ir = i < N ? i : N - 1;
-            const int jmax = min(wf + 63, N - 1);
+            const int jmax = m.enc ? N - 1 : min(wf + 63, N - 1);
             T qi[DH], gi[DH], acc[DH];
 #pragma unroll
             for (int c = 0; c < DH; ++c) {
@@ -1278,7 +1344,7 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_q(int64_t n, ModelDims m,
                 const T sc = dot4<T, DH>(qi, kc);
                 const T dp = dot4<T, DH>(gi, vc);
                 const T e = dexp(sc * scale - ls);
-                const T p = j <= ir ? e : (T)0;
+                const T p = (m.enc || j <= ir) ? e : (T)0;
                 const T ds = p * (dp - dd);
 #pragma unroll
                 for (int c = 0; c < DH; ++c) acc[c] += ds * kc[c];
@@ -1356,10 +1422,10 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_kv(int64_t n, ModelDims m,
                 dk[c] = 0;
                 dv[c] = 0;
             }
-            for (int i = jw; i < N; ++i) {
+            for (int i = m.enc ? 0 : jw; i < N; ++i) {
                 const T sc = dot4<T, DH>(kj, Qs + i * DH);
                 const T dp = dot4<T, DH>(vj, Gs + i * DH);
-                const T p = i >= j ? dexp(sc * scale - Ls[i]) : (T)0;
+                const T p = (m.enc || i >= j) ? dexp(sc * scale - Ls[i]) : (T)0;
                 const T ds = p * (dp - Ds[i]);
 #pragma unroll
                 for (int c = 0; c < DH; ++c) {
@@ -1478,7 +1544,8 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_q_mfma(
             f32x4b acc[MB];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4b{0, 0, 0, 0};
-            for (int kb = 0; kb <= t; ++kb) {
+            const int kbn = m.enc ? NTQ - 1 : t;      // the encoder: every key
+            for (int kb = 0; kb <= kbn; ++kb) {
                 const float* kr = Ks + (kb * 16 + c16) * LD + g;
                 const float* vr = Vs + (kb * 16 + c16) * LD + g;
                 f32x4b sc = f32x4b{0, 0, 0, 0}, dp = f32x4b{0, 0, 0, 0};
@@ -1491,7 +1558,8 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_q_mfma(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int key = kb * 16 + 4 * g + r;
-                    const float p = key <= iq && key < N ? dexp(sc[r] * scale - ls) : 0.0f;
+                    const float p = (m.enc || key <= iq) && key < N
+                                        ? dexp(sc[r] * scale - ls) : 0.0f;
                     ds[r] = p * (dp[r] - dd);
                 }
 #pragma unroll
@@ -1559,7 +1627,7 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_kv_mfma(
                 dk[mb] = f32x4b{0, 0, 0, 0};
                 dv[mb] = f32x4b{0, 0, 0, 0};
             }
-            for (int qb = t; qb < NTQ; ++qb) {
+            for (int qb = m.enc ? 0 : t; qb < NTQ; ++qb) {
                 const float* qr = Qs + (qb * 16 + c16) * LD + g;
                 const float* gr = Gs + (qb * 16 + c16) * LD + g;
                 f32x4b sc = f32x4b{0, 0, 0, 0}, dp = f32x4b{0, 0, 0, 0};
@@ -1572,7 +1640,8 @@ __global__ void __launch_bounds__(NT) k_attn_bwd_kv_mfma(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int qi = qb * 16 + 4 * g + r;
-                    p[r] = qi >= jk && qi < N ? dexp(sc[r] * scale - Ls[qi]) : 0.0f;
+                    p[r] = (m.enc || qi >= jk) && qi < N ? dexp(sc[r] * scale - Ls[qi])
+                                                         : 0.0f;
                     ds[r] = p[r] * (dp[r] - Ds[qi]);
                 }
 #pragma unroll
@@ -1727,11 +1796,11 @@ hipError_t launch_attn_bwd(int64_t n, const ModelDims& m, const T* q,
     template hipError_t launch_bias_gelu<T>(int64_t, int, T*, const T*, T*,     \
                                             hipStream_t);                       \
     template hipError_t launch_gelu_bwd<T>(int64_t, const T*, T*, hipStream_t); \
-    template hipError_t launch_head_bwd<T>(int64_t, int, int, int,              \
+    template hipError_t launch_head_bwd<T>(int64_t, int, int, int, int,         \
                                            const HeadW<T>&,                     \
                                            const int8_t*, const T*, const T*,   \
                                            T*, T*, T*, T*, T*, T*, hipStream_t); \
-    template hipError_t launch_embed_bwd<T>(int64_t, int, int, int,             \
+    template hipError_t launch_embed_bwd<T>(int64_t, int, int, int, int,        \
                                             const int8_t*,                      \
                                             const T*, T*, int64_t, int64_t,     \
                                             int64_t, hipStream_t);              \

@@ -27,7 +27,7 @@ __device__ inline bool bond_sites(int b, int L, int periodic, int& i, int& j) {
 // list comes out in increasing bond order without atomics.
 __global__ void __launch_bounds__(64) k_neighbours(
     const int8_t* __restrict__ spins, int64_t batch, int L, int chain,
-    int periodic, int K, double J, int16_t* __restrict__ bonds,
+    int periodic, int K, int enc, double J, int16_t* __restrict__ bonds,
     int32_t* __restrict__ count,
     double* __restrict__ diag, int64_t* __restrict__ rows_cap,
     int32_t* __restrict__ status) {
@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(64) k_neighbours(
             count[s] = N;
             if (diag) diag[s] = -J * (double)zz;
             const int64_t T = N / K;
-            if (rows_cap) rows_cap[s] = (int64_t)K * T * (T - 1) / 2;
+            if (rows_cap)
+                rows_cap[s] = enc ? (int64_t)N * T : (int64_t)K * T * (T - 1) / 2;
         }
         return;
     }
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(64) k_neighbours(
         if (anti) {
             out[total + __popcll(below)] = (int16_t)b;
             const int p1 = i < j ? i : j;
-            cap += T - p1 / K - 1;
+            cap += enc ? T : T - p1 / K - 1;
         }
         total += __popcll(m);
     }
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(1024) k_scan_chunk(
 __global__ void __launch_bounds__(64) k_descriptors(
     const int16_t* __restrict__ bonds, const int32_t* __restrict__ count,
     const int32_t* __restrict__ nb_off, const int64_t* __restrict__ row_off,
-    int n, int L, int chain, int K, NbDesc* __restrict__ desc) {
+    int n, int L, int chain, int K, int enc, NbDesc* __restrict__ desc) {
     const int s = blockIdx.x;
     if (s >= n) return;
     const int lane = threadIdx.x;
@@ -176,7 +177,8 @@ __global__ void __launch_bounds__(64) k_descriptors(
                 p1 = i < j ? i : j;
                 p2 = i < j ? j : i;
             }
-            rows = N / K - p1 / K - 1;
+            // decoder: rows after the first changed token; encoder: all
+            rows = enc ? N / K : N / K - p1 / K - 1;
         }
         int64_t incl = rows;   // inclusive wave scan
 #pragma unroll
@@ -187,8 +189,11 @@ __global__ void __launch_bounds__(64) k_descriptors(
         if (k < cnt) {
             NbDesc d;
             d.sigma = s;
-            d.p1 = (int16_t)(p1 / K);      // tokens of the changed sites
-            d.p2 = (int16_t)(p2 / K);
+            // tokens of the changed sites (the encoder's changed input
+            // rows are the tokens themselves: held as token - 1, so that
+            // rows p1 + 1 and p2 + 1 are the changed inputs in both)
+            d.p1 = (int16_t)(p1 / K - enc);
+            d.p2 = (int16_t)(p2 / K - enc);
             d.ov = carry + incl - rows;
             d.s1 = (int16_t)p1;
             d.s2 = (int16_t)p2;
@@ -337,20 +342,20 @@ hipError_t launch_neighbours(const int8_t* spins, int64_t batch,
                              hipStream_t st) {
     if (batch <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_neighbours, dim3((unsigned)batch), dim3(64), 0, st,
-                       spins, batch, m.L, m.chain, m.periodic, m.K, m.J, bonds,
+                       spins, batch, m.L, m.chain, m.periodic, m.K, m.enc, m.J, bonds,
                        count, diag, rows_cap, status);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_desc(const int16_t* bonds, const int32_t* count,
                             const int64_t* rows_cap, int n, int L, int chain,
-                            int K, int32_t* nb_off, int64_t* row_off,
+                            int K, int enc, int32_t* nb_off, int64_t* row_off,
                             int32_t* n_nb_total, int32_t* n_rows_total,
                             NbDesc* desc, hipStream_t st) {
     hipLaunchKernelGGL(k_scan_chunk, dim3(1), dim3(1024), 0, st, count,
                        rows_cap, n, nb_off, row_off, n_nb_total, n_rows_total);
     hipLaunchKernelGGL(k_descriptors, dim3(n), dim3(64), 0, st, bonds, count,
-                       nb_off, row_off, n, L, chain, K, desc);
+                       nb_off, row_off, n, L, chain, K, enc, desc);
     return hipGetLastError();
 }
 

@@ -146,8 +146,10 @@ __global__ void k_embed(ModelDims m, HeadW<typename P::acc> hw,
         const int col = (int)(e - row * m.d);
         const int64_t s = row / m.N;
         const int i = (int)(row - s * m.N);
-        // input: the previous token, or the beginning-of-sequence token 2^K
-        const int u = i == 0 ? 1 << m.K : token_at(spins + s * m.S, i - 1, m.K);
+        // input: the previous token, or the beginning-of-sequence token
+        // 2^K (the encoder reads the token itself)
+        const int u = m.enc ? token_at(spins + s * m.S, i, m.K)
+                            : (i == 0 ? 1 << m.K : token_at(spins + s * m.S, i - 1, m.K));
         x[e] = hw.tok[u * m.d + col] + hw.pos[(int64_t)i * m.d + col];
     }
 }
@@ -292,8 +294,9 @@ __global__ void __launch_bounds__(kThreads) k_attn_seq(ModelDims m,
 #pragma unroll
             for (int c = 0; c < DH; ++c)
                 q[c] = cvt<acc>(io.q[base + (int64_t)i * d + c]) * scale;
+            // keys 0..i (decoder) or all of them (encoder)
             attend_row<acc, DH, act>(
-                q, Ks, Vs, i, o, DH,
+                q, Ks, Vs, m.enc ? N - 1 : i, o, DH,
                 io.stat ? io.stat + ((s * N + i) * m.nh + h) * 2 : nullptr);
 #pragma unroll
             for (int c = 0; c < DH; ++c)
@@ -305,7 +308,8 @@ __global__ void __launch_bounds__(kThreads) k_attn_seq(ModelDims m,
         atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
                   (unsigned long long)(n * N));
         atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_PAIRS),
-                  (unsigned long long)(n * ((int64_t)N * (N + 1) / 2) * m.nh));
+                  (unsigned long long)(n * (m.enc ? (int64_t)N * N
+                                                  : (int64_t)N * (N + 1) / 2) * m.nh));
     }
 }
 
@@ -358,7 +362,7 @@ __global__ void __launch_bounds__(kThreads) k_attn_dedup(ModelDims m,
         const int64_t nb = u / m.nh;
         const int h = (int)(u - nb * m.nh);
         const NbDesc D = dd.desc[nb];
-        const int pmin = D.p1 + 1;
+        const int pmin = first_row(D, m);
         const uint64_t* mk = dd.mask + nb * W;
         const int64_t sb = (int64_t)D.sigma * N * d + h * DH;
         const int64_t ob = (D.ov - pmin) * (int64_t)d + h * DH;   // row i at ob + i*d
@@ -376,14 +380,15 @@ __global__ void __launch_bounds__(kThreads) k_attn_dedup(ModelDims m,
             acc q[DH], o[DH];
 #pragma unroll
             for (int c = 0; c < DH; ++c) q[c] = cvt<acc>(qsrc[c]) * scale;
-            attend_row<acc, DH, act>(q, Ks, Vs, i, o);
+            attend_row<acc, DH, act>(q, Ks, Vs, m.enc ? N - 1 : i, o);
             act* dst = dd.oa + ob + (int64_t)i * d;
 #pragma unroll
             for (int c = 0; c < DH; ++c) dst[c] = cvt<act>(o[c]);
         }
         if (h == 0 && threadIdx.x == 0) {
             my_rows += N - pmin;
-            my_pairs += ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2;
+            my_pairs += m.enc ? (int64_t)N * N
+                              : ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2;
         }
         __syncthreads();
     }
@@ -453,7 +458,7 @@ __global__ void __launch_bounds__(kThreads) k_attn_incr(
         const int64_t nb = u / m.nh;
         const int h = (int)(u - nb * m.nh);
         const NbDesc D = dd.desc[nb];
-        const int pmin = D.p1 + 1;
+        const int pmin = first_row(D, m);
         const uint64_t* mk = dd.mask + nb * W;
         const int64_t sb = (int64_t)D.sigma * N * d + h * DH;
         const int64_t ob = (D.ov - pmin) * (int64_t)d + h * DH;
@@ -724,7 +729,7 @@ __global__ void __launch_bounds__(kThreads) k_out_proj_overlay(
                      [&](int64_t r, const acc*& xi, const act*& ar, acc*& o) {
                          const int32_t nb = dd.slot_nb[r];
                          const NbDesc D = dd.desc[nb];
-                         const int i = D.p1 + 1 + (int)(r - D.ov);
+                         const int i = first_row(D, m) + (int)(r - D.ov);
                          const bool inC = mask_bit(dd.mask + (int64_t)nb * W, i);
                          xi = inC ? dd.ox + r * m.d
                                   : dd.bx + ((int64_t)D.sigma * m.N + i) * m.d;
@@ -1206,6 +1211,76 @@ __device__ inline void head_rows_v(const C* const (&x)[R], int d,
         default: return hipErrorInvalidValue;          \
     }
 
+// Encoder head term of R rows (one wave): LN(x) . w with the final LN and
+// the single-output head (the bias is added once, to the pooled mean);
+// contraction off, each row's operations in one order.
+template <typename C, int R>
+__device__ inline void head_terms(const C* const (&x)[R], int d,
+                                  const HeadW<C>& hw, C (&t)[R]) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    C s[R], v[R], mean[R], rstd[R], z[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[r] = v[r] = z[r] = 0;
+    for (int k = lane; k < d; k += 64)
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] += x[r][k];
+#pragma unroll
+    for (int r = 0; r < R; ++r) mean[r] = wave_sum(s[r]) / (C)d;
+    for (int k = lane; k < d; k += 64)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const C q = x[r][k] - mean[r];
+            v[r] += q * q;
+        }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        rstd[r] = (C)1 / dsqrt(wave_sum(v[r]) / (C)d + (C)1e-5);
+    for (int k = lane; k < d; k += 64) {
+        const C g = hw.lnf_g[k], b = hw.lnf_b[k], w = hw.W_head[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const C f = (x[r][k] - mean[r]) * rstd[r] * g + b;
+            z[r] += f * w;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) t[r] = wave_sum(z[r]);
+}
+
+// Encoder: log psi = (sum of the rows' terms in row order, FP64) / N + b;
+// the terms are kept in lp when given (the samples' cache for the dedup).
+template <class P>
+__global__ void __launch_bounds__(kThreads) k_head_seq_enc(
+    ModelDims m, HeadW<typename P::acc> hw, const int32_t* n_dev,
+    int64_t n_seq, const typename P::acc* __restrict__ x,
+    typename P::acc* __restrict__ lp, double* __restrict__ logpsi) {
+    using acc = typename P::acc;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* ell = reinterpret_cast<double*>(smem_raw);   // [N]
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_seq;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t s = blockIdx.x; s < n; s += gridDim.x) {
+        for (int i = wave; i < m.N; i += kThreads / 64) {
+            const int64_t row = s * m.N + i;
+            const acc* xr[1] = {x + row * m.d};
+            acc t[1];
+            head_terms<acc, 1>(xr, m.d, hw, t);
+            if (lane == 0) {
+                ell[i] = (double)t[0];
+                if (lp) lp[row] = t[0];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double acc64 = 0.0;
+            for (int i = 0; i < m.N; ++i) acc64 += ell[i];
+            logpsi[s] = acc64 / (double)m.N + (double)hw.b_head[0];
+        }
+        __syncthreads();
+    }
+}
+
 template <class P, int V>
 __global__ void __launch_bounds__(kThreads) k_head_seq(
     ModelDims m, HeadW<typename P::acc> hw, const int8_t* __restrict__ spins,
@@ -1245,6 +1320,12 @@ hipError_t launch_head_seq(const ModelDims& m, const HeadW<typename P::acc>& hw,
                            int64_t n_seq, const typename P::acc* x,
                            typename P::acc* lp, double* logpsi,
                            hipStream_t st) {
+    if (m.enc) {
+        hipLaunchKernelGGL((k_head_seq_enc<P>), dim3(grid_for(n_seq)), dim3(kThreads),
+                           sizeof(double) * m.N, st, m, hw, n_dev, n_seq, x, lp,
+                           logpsi);
+        return hipGetLastError();
+    }
     VQ_BY_VALUES(m.K, hipLaunchKernelGGL((k_head_seq<P, V>), dim3(grid_for(n_seq)),
                                          dim3(kThreads), sizeof(double) * m.N, st,
                                          m, hw, spins, n_dev, n_seq, x, lp, logpsi));
@@ -1439,7 +1520,7 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
             const int64_t nb = nb0 + g * stride;
             if (nb >= n) continue;
             const NbDesc D = dd.desc[nb];
-            const int pmin = D.p1 + 1;
+            const int pmin = first_row(D, m);
             for (int i = lane; i < N - pmin; i += 64) dd.slot_nb[D.ov + i] = (int32_t)nb;
             uint64_t* mk = dd.mask + nb * W;
             const int8_t* sp = dd.spins + (int64_t)D.sigma * m.S;
@@ -1449,8 +1530,10 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
             // p1 + 1, if there is one, when both changed sites (or the one
             // flipped site) lie in token p1 == p2
             const bool single = D.p1 == D.p2;
-            const int tokC[2] = {nb_token_at(sp, D, D.p1, m.K),
-                                 nb_token_at(sp, D, D.p2, m.K)};
+            // (the encoder reads token p + 1 itself at row p + 1)
+            const int sh = m.enc ? 1 : 0;
+            const int tokC[2] = {nb_token_at(sp, D, D.p1 + sh, m.K),
+                                 nb_token_at(sp, D, D.p2 + sh, m.K)};
             const int nC = single ? (rowsC[0] < N ? 1 : 0) : (rowsC[1] < N ? 2 : 1);
             // every mask word written once, never read back within the kernel
             for (int wd = lane; wd < W; wd += 64) {
@@ -1478,7 +1561,7 @@ __global__ void __launch_bounds__(64) k_dedup_init(ModelDims m,
                 const int64_t nb = nb0 + g * stride;
                 if (nb >= n) break;
                 const NbDesc D = dd.desc[nb];
-                const int pmin = D.p1 + 1;
+                const int pmin = first_row(D, m);
                 const int nC = D.p1 == D.p2 ? (pmin < N ? 1 : 0)
                                             : (D.p2 + 1 < N ? 2 : 1);
                 if (nC >= 1) dd.list[pos] = D.ov + (D.p1 + 1 - pmin);
@@ -1523,7 +1606,7 @@ __global__ void __launch_bounds__(64) k_certify(ModelDims m, DedupIO<P> dd,
     for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
         const int32_t nb = dd.slot_nb[r];
         const NbDesc D = dd.desc[nb];
-        const int i = D.p1 + 1 + (int)(r - D.ov);
+        const int i = first_row(D, m) + (int)(r - D.ov);
         const int64_t brow = (int64_t)D.sigma * m.N + i;
         bool ok = certified != 0;
         for (int hq = 0; hq < m.H && ok; ++hq) {
@@ -1634,7 +1717,7 @@ __global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
             const int64_t nb = nb0 + g * stride;
             if (nb >= n) continue;
             const NbDesc D = dd.desc[nb];
-            const int pmin = D.p1 + 1;
+            const int pmin = first_row(D, m);
             const uint64_t* mk = dd.mask + nb * W;
             uint64_t* sm = smk[g];
             __syncthreads();
@@ -1690,7 +1773,7 @@ __global__ void __launch_bounds__(64) k_code_diff(ModelDims m, DedupIO<P> dd) {
             const int64_t nb = nb0 + g * stride;
             if (nb >= n) continue;
             const NbDesc D = dd.desc[nb];
-            const int pmin = D.p1 + 1;
+            const int pmin = first_row(D, m);
             const uint64_t* sm = smk[g];
             int k = 0;
             for (int i0 = pmin; i0 < N; i0 += 64) {
@@ -1743,7 +1826,7 @@ __global__ void __launch_bounds__(64) k_head_dedup(
     int64_t my_rows = 0;
     for (int64_t nb = blockIdx.x; nb < n; nb += gridDim.x) {
         const NbDesc D = dd.desc[nb];
-        const int pmin = D.p1 + 1;
+        const int pmin = first_row(D, m);
         const uint64_t* mk = dd.mask + nb * W;
         const int8_t* sp = dd.spins + (int64_t)D.sigma * m.S;
         __syncthreads();
@@ -1831,11 +1914,83 @@ __global__ void __launch_bounds__(64) k_head_dedup(
                   (unsigned long long)my_rows);
 }
 
+// Encoder: log psi(s') - log psi(s) = (sum over the rows of C_L of the
+// new term minus the sample's cached one, in row order, FP64) / N.  Rows
+// of C_L are listed in LDS and evaluated four at a time.
+template <class P>
+__global__ void __launch_bounds__(64) k_head_dedup_enc(
+    ModelDims m, HeadW<typename P::acc> hw, DedupIO<P> dd,
+    const typename P::acc* __restrict__ bterm, double* __restrict__ ratio,
+    int64_t* ctr) {
+    using acc = typename P::acc;
+    constexpr int R = 4;
+    __shared__ uint64_t sm[VQ_MAX_MASK_WORDS];
+    __shared__ int16_t rl[VQ_MAX_MASK_WORDS * 64];
+    __shared__ typename P::acc tnw[VQ_MAX_MASK_WORDS * 64];
+    const int64_t n = (int64_t)*dd.n_nb;
+    const int lane = threadIdx.x;
+    const int N = m.N, W = dd.mask_words;
+    int64_t my_rows = 0;
+    for (int64_t nb = blockIdx.x; nb < n; nb += gridDim.x) {
+        const NbDesc D = dd.desc[nb];
+        const int pmin = first_row(D, m);
+        const uint64_t* mk = dd.mask + nb * W;
+        __syncthreads();
+        for (int wd = lane; wd < W; wd += 64) sm[wd] = mk[wd];
+        __syncthreads();
+        int nc = 0;
+        for (int i0 = 0; i0 < N; i0 += 64) {
+            const int i = i0 + lane;
+            const bool inC = i < N && mask_bit(sm, i);
+            const uint64_t cm = __ballot(inC);
+            const uint64_t below = lane == 0 ? 0ull : (cm & (~0ull >> (64 - lane)));
+            if (inC) rl[nc + __popcll(below)] = (int16_t)i;
+            nc += __popcll(cm);
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < nc; c0 += R) {
+            const acc* xr[R];
+            int ir[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ir[r] = rl[c0 + r < nc ? c0 + r : nc - 1];
+                xr[r] = dd.ox + (D.ov + (ir[r] - pmin)) * (int64_t)m.d;
+            }
+            acc t[R];
+            head_terms<acc, R>(xr, m.d, hw, t);
+            if (lane < R && c0 + lane < nc) {
+                acc a = t[0];
+#pragma unroll
+                for (int r = 1; r < R; ++r)
+                    if (lane == r) a = t[r];
+                tnw[c0 + lane] = a;
+            }
+        }
+        my_rows += nc;
+        __syncthreads();
+        if (lane == 0) {
+            double delta = 0.0;
+            for (int c = 0; c < nc; ++c)
+                delta += (double)tnw[c] -
+                         (double)bterm[(int64_t)D.sigma * N + rl[c]];
+            ratio[nb] = exp(delta / (double)N);
+        }
+    }
+    if (ctr && lane == 0 && my_rows)
+        atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_HEAD_ROWS),
+                  (unsigned long long)my_rows);
+}
+
 template <class P>
 hipError_t launch_head_dedup(const ModelDims& m, const HeadW<typename P::acc>& hw,
                              const DedupIO<P>& d, const typename P::acc* blp,
                              const double*, double* ratio, int64_t* ctr,
                              hipStream_t st) {
+    if (m.enc) {
+        hipLaunchKernelGGL((k_head_dedup_enc<P>), dim3(grid_for(d.n_nb_max)), dim3(64),
+                           0, st, m, hw, d, blp, ratio, ctr);
+        return hipGetLastError();
+    }
     VQ_BY_VALUES(m.K, hipLaunchKernelGGL((k_head_dedup<P, V>), dim3(grid_for(d.n_nb_max)),
                                          dim3(64), 0, st, m, hw, d, blp, ratio, ctr));
     return hipGetLastError();

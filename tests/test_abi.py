@@ -2,6 +2,7 @@
 declared in include/vqnqs.h, counts parameters like the workload layout, and
 rejects bad arguments on the host before any HIP call."""
 import ctypes
+from dataclasses import replace
 import os
 import re
 import subprocess
@@ -61,6 +62,10 @@ def _cfg(**kw):
     (dict(group=5), 2),                   # at most 4 spins per token
     (dict(group=3), 2),                   # 16 sites in tokens of 3
     (dict(group=-1), 2),
+    (dict(encoder=2), 2),
+    (dict(encoder=1, attn_tail=1), 2),    # the half-block is a decoder's
+    (dict(encoder=1, precision=2), 5),    # the encoder runs in FP64/FP32
+    (dict(encoder=1, flags=2), 5),        # no rank-|C| attention update
 ])
 def test_invalid_configs_rejected(kw, status):
     lib = vq.load_library()
@@ -71,6 +76,16 @@ def test_invalid_configs_rejected(kw, status):
                                     ctypes.byref(sz)) == status
     assert lib.vqnqs_local_energy(ctypes.byref(c), None, None, 4, 1, None,
                                   None, None, None, None, 0, None) == status
+
+
+@pytest.mark.parametrize("group", [1, 4])
+def test_encoder_param_count_matches_layout(group):
+    mc = replace(CONFIGS["small"], name="small_enc", encoder=True, group=group)
+    assert vq.param_count(vq.make_config(mc)) == param_count(mc)
+    dec = replace(mc, encoder=False)
+    # one token row fewer (no beginning of sequence) and one head output
+    V = 1 << group
+    assert param_count(dec) - param_count(mc) == mc.d_model + (V - 1) * (mc.d_model + 1)
 
 
 def test_open_odd_lattice_allowed():
