@@ -140,7 +140,7 @@ struct LayerW {
         *ln2_b, *W1, *b1, *W2, *b2;
     const C* table;    // [H][Q][d]: codeword h,c times rows of W_o of segment h
     const C* cnorm;    // [H][Q]: squared norm of every codeword
-    const float* cnh4; // BF16 packs: [H][Q][4], -cnorm/2 four times over
+    const float* cnh;  // BF16 packs: [H][Q], -cnorm/2
     const bf16* Wqkv_p;  // BF16 packs (MFMA fragment order); null otherwise
     const bf16* W1_p;
     const bf16* W2_p;

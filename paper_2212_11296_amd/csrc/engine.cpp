@@ -78,7 +78,7 @@ struct Workspace {
     float* prm;   // BF16 mode: parameters rounded to bfloat16
     bf16 *wqkv_p, *w1_p, *w2_p, *cb_p;   // [nl] matrix-core fragment packs
     bf16 *wqkv_tp, *wo_tp;               // the half-block's QKV and W_o packs
-    float* cnh4;                         // [nl][H*Q*4] -cnorm/2, four copies
+    float* cnh;                          // [nl][H*Q] -cnorm/2
     // chunk neighbour bookkeeping
     int16_t* bonds;
     int32_t *count, *nb_off, *n_nb, *n_rows, *list_n, *vq_n;
@@ -146,7 +146,7 @@ static Workspace<P> carve(const ModelDims& m, Job job, int64_t chunk,
             w.w1_p = c.take<bf16>((size_t)m.nl * d * m.dff);
             w.w2_p = c.take<bf16>((size_t)m.nl * m.dff * d);
             w.cb_p = c.take<bf16>((size_t)m.nl * m.Q * d);
-            w.cnh4 = c.take<float>((size_t)m.nl * H * m.Q * 4);
+            w.cnh = c.take<float>((size_t)m.nl * H * m.Q);
             if (m.tail) {
                 w.wqkv_tp = c.take<bf16>((size_t)d * 3 * d);
                 w.wo_tp = c.take<bf16>((size_t)d * d);
@@ -457,7 +457,7 @@ struct Runner {
             lw.W1_p = w.w1_p + (int64_t)l * m.d * m.dff;
             lw.W2_p = w.w2_p + (int64_t)l * m.dff * m.d;
             lw.cb_p = w.cb_p + (int64_t)l * m.Q * m.d;
-            lw.cnh4 = w.cnh4 + (int64_t)l * m.H * m.Q * 4;
+            lw.cnh = w.cnh + (int64_t)l * m.H * m.Q;
         }
         return lw;
     }
@@ -486,9 +486,10 @@ struct Runner {
                 return launch_attn_dedup_mfma(m, dd, ctr, st);
         return launch_attention_dedup<P>(m, dd, ctr, st);
     }
-    hipError_t vqs(const LayerW<acc>& lw, RowSet rs, const BlockIO<P>& io) {
+    hipError_t vqs(const LayerW<acc>& lw, RowSet rs, const BlockIO<P>& io,
+                   const VqSeed& seed = VqSeed{}) {
         if constexpr (std::is_same<P, PrecBF16>::value)
-            if (m.mfma) return launch_vq_mfma(m, lw, rs, io, st);
+            if (m.mfma) return launch_vq_mfma(m, lw, rs, io, st, seed);
         return launch_vq<P>(m, lw, rs, io, st);
     }
     HeadW<acc> head() const { return head_view<acc>(m, params); }
@@ -533,7 +534,7 @@ struct Runner {
                                          const_cast<bf16*>(lw.W1_p),
                                          const_cast<bf16*>(lw.W2_p),
                                          const_cast<bf16*>(lw.cb_p),
-                                         const_cast<float*>(lw.cnh4), st));
+                                         const_cast<float*>(lw.cnh), st));
         }
         if constexpr (std::is_same<P, PrecBF16>::value)
             if (m.mfma && m.tail) {
@@ -984,15 +985,20 @@ struct Runner {
             } else {
                 LK("attention_dedup", attn_dedup(dd));
             }
+            // the sample's codes of this layer seed the neighbours' searches
+            VqSeed seed;
+            seed.slot_nb = w.slot_nb;
+            seed.desc = w.desc;
+            seed.bcode = dd.bcode;
             if (certified) {
                 CK(launch_fill_i32(w.vq_n, 1, 0, st));
                 LK("certify", launch_certify<P>(m, dd, 1, ctr, st));
                 RowSet vr{w.vq_list, w.vq_n, R, 1};
-                LK("vq", vqs(lw, vr, io));
+                LK("vq", vqs(lw, vr, io, seed));
                 if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_VQ_ROWS, w.vq_n, 1, st));
             } else {
                 RowSet vr{nullptr, w.n_rows, R, 1};
-                LK("vq", vqs(lw, vr, io));
+                LK("vq", vqs(lw, vr, io, seed));
                 if (ctr) CK(launch_counter_add(ctr, VQNQS_CTR_VQ_ROWS, w.n_rows, 1, st));
             }
             CK(launch_fill_i32(w.list_n, 1, 0, st));

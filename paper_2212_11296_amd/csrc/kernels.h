@@ -86,16 +86,23 @@ hipError_t launch_round_bf16(const float* src, int64_t n, float* dst,
                              hipStream_t st);
 hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
                              bf16* Wqkv_p, bf16* W1_p, bf16* W2_p, bf16* cb_p,
-                             float* cnh4, hipStream_t st);
+                             float* cnh, hipStream_t st);
 hipError_t launch_qkv_mfma(const ModelDims& m, const LayerW<float>& w,
                            RowSet rows, const BlockIO<PrecBF16>& io,
                            hipStream_t st);
 hipError_t launch_mlp_mfma(const ModelDims& m, const LayerW<float>& w,
                            RowSet rows, const BlockIO<PrecBF16>& io,
                            hipStream_t st);
+// Seed of a neighbour-row search: the sample's code of the same row and
+// layer (codes [sample][N][H]), found through the row's owning neighbour.
+struct VqSeed {
+    const int32_t* slot_nb = nullptr;   // [rows] owning neighbour, or null
+    const NbDesc* desc = nullptr;
+    const int32_t* bcode = nullptr;
+};
 hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
                           RowSet rows, const BlockIO<PrecBF16>& io,
-                          hipStream_t st);
+                          hipStream_t st, const VqSeed& seed = VqSeed{});
 bool attn_mfma_ok(const ModelDims& m);
 hipError_t launch_attn_seq_mfma(const ModelDims& m, const int32_t* n_dev,
                                 int64_t n_seq, const BlockIO<PrecBF16>& io,

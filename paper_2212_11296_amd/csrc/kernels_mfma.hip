@@ -99,20 +99,18 @@ hipError_t launch_round_bf16(const float* src, int64_t n, float* dst,
     return hipGetLastError();
 }
 
-// out[e][0..3] = -cnorm[e]/2 (exact: halving a normal float), the quantizer
+// out[e] = -cnorm[e]/2 (exact: halving a normal float), the quantizer
 // search's accumulator input.
 __global__ void k_pack_cnorm(const float* __restrict__ cnorm, int64_t n,
-                             f32x4* __restrict__ out) {
+                             float* __restrict__ out) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const float v = -0.5f * cnorm[e];
-        out[e] = f32x4{v, v, v, v};
-    }
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = -0.5f * cnorm[e];
 }
 
 hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
                              bf16* Wqkv_p, bf16* W1_p, bf16* W2_p, bf16* cb_p,
-                             float* cnh4, hipStream_t st) {
+                             float* cnh, hipStream_t st) {
     const int d = m.d, F = m.dff;
     auto go = [&](const float* src, int K, int Nout, int64_t sk, int64_t sc,
                   bf16* out, int hperm = 0) {
@@ -130,7 +128,7 @@ hipError_t launch_pack_layer(const ModelDims& m, const LayerW<float>& w,
            cb_p + (int64_t)h * m.Q * m.dseg);
     const int64_t nc = (int64_t)m.H * m.Q;
     hipLaunchKernelGGL(k_pack_cnorm, dim3(mgrid((nc + 255) / 256)), dim3(256),
-                       0, st, w.cnorm, nc, reinterpret_cast<f32x4*>(cnh4));
+                       0, st, w.cnorm, nc, cnh);
     return hipGetLastError();
 }
 
@@ -725,14 +723,14 @@ template <int KBS, int MB, bool MARGIN>
 __global__ void __launch_bounds__(kMT)
     __attribute__((amdgpu_waves_per_eu(MB <= 2 && !MARGIN ? 3 : 1)))
     k_vq_mfma(ModelDims m, LayerW<float> w, RowSet rows, BlockIO<PrecBF16> io,
-              const bf16x8* __restrict__ cbp) {
+              const bf16x8* __restrict__ cbp, VqSeed seed) {
     constexpr int DS = KBS * 32, WR = MB * 16, CBK = 4;
     constexpr int CHUNK = CBK * KBS * 64;       // fragment lanes per chunk
     constexpr int PER = CHUNK / kMT;             // per thread
     constexpr int CN = CBK * 16;                 // code norms per chunk
     static_assert(CN == 64, "one wave loads a chunk's code norms");
     __shared__ bf16x8 stage0[CHUNK], stage1[CHUNK];
-    __shared__ f32x4 cn0[CN], cn1[CN];
+    __shared__ __align__(16) float cn0[CN], cn1[CN];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t n = rs_n(rows);
@@ -743,7 +741,7 @@ __global__ void __launch_bounds__(kMT)
     const float inf = __builtin_inff();
     // chunk c of head hq into (st, cs): clamped addresses (entries past the
     // codebook are never read)
-    auto fetch = [&](int hq, int c, bf16x8* st, f32x4* cs) {
+    auto fetch = [&](int hq, int c, bf16x8* st, float* cs) {
         const bf16x8* cbh = cbp + (int64_t)hq * cbtot;
         const int64_t e0 = (int64_t)c * CHUNK;
 #pragma unroll
@@ -753,8 +751,7 @@ __global__ void __launch_bounds__(kMT)
         }
         if (wave == 0) {
             const int code = c * CN + lane;
-            lds_dma16(w.cnh4 + ((int64_t)hq * m.Q + (code < m.Q ? code : m.Q - 1)) * 4,
-                      cs);
+            lds_dma4(w.cnh + (int64_t)hq * m.Q + (code < m.Q ? code : m.Q - 1), cs);
         }
     };
     bool ahead = false;      // this head's first chunk is in stage0
@@ -797,11 +794,61 @@ __global__ void __launch_bounds__(kMT)
                 ss += __shfl_xor(ss, 32, 64);
                 nrm[i] = ss;                // |a|^2 of row i*16 + lane%16
             }
-            T2 best[MB][4];
+            // Seeded rows (a neighbour's row, whose sample has a code c0 for
+            // the same row): with g0 = g(c0) from the vector unit, every
+            // product of a code x lies within lo = 2^-8 |a| wmax of its hi
+            // part alone (|a_lo| <= 2^-8 |a| per element after rounding to
+            // nearest), and each FP32 sum within E of its real value.  So a
+            // code whose hi-only value stays below g0 - lo - 4E has
+            // g(x) < g(c0) and is not the nearest; a code block in which that
+            // holds for every row of the wave skips its lo products and the
+            // bookkeeping.  c0's own block always passes, so the chosen code
+            // (the argmax of the same hi-then-lo sums, lowest index on equal
+            // values) is the one the full search finds.  Unseeded: -inf.
+            float ut[MB];
+            {
+                const float wmx = w.cnorm[(int64_t)m.H * m.Q + hq];
 #pragma unroll
-            for (int i = 0; i < MB; ++i)
+                for (int i = 0; i < MB; ++i) {
+                    float gp = 0.0f, cq0 = 0.0f;
+                    const bool sd = seed.slot_nb != nullptr && myslot[i] >= 0;
+                    if (sd) {
+                        const int64_t sl = myslot[i];
+                        const NbDesc D = seed.desc[seed.slot_nb[sl]];
+                        const int row = first_row(D, m) + (int)(sl - D.ov);
+                        const int c0 = seed.bcode[((int64_t)D.sigma * m.N + row) * m.H + hq];
+                        const float* wc = w.codebook + ((int64_t)hq * m.Q + c0) * DS +
+                                          8 * (lane >> 4);
+                        cq0 = -0.5f * w.cnorm[(int64_t)hq * m.Q + c0];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) best[i][r] = T2{-inf, 0, -inf};
+                        for (int kb = 0; kb < KBS; ++kb) {
+                            const float4 w0 = *reinterpret_cast<const float4*>(wc + kb * 32);
+                            const float4 w1 = *reinterpret_cast<const float4*>(wc + kb * 32 + 4);
+                            const float wv[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+                            for (int j = 0; j < 8; ++j)
+                                gp = fmaf((float)ah[i][kb][j] + (float)al[i][kb][j], wv[j], gp);
+                        }
+                    }
+                    gp += __shfl_xor(gp, 16, 64);
+                    gp += __shfl_xor(gp, 32, 64);
+                    float u = -inf;
+                    if (sd) {
+                        const float na = 1.001f * sqrtf(nrm[i]);
+                        const float E = (float)(2 * DS + 8) * 5.9604645e-8f * 1.0625f *
+                                        (0.5f * wmx * wmx + 1.01f * na * wmx);
+                        const float lo = 3.90625e-3f * 1.004f * na * wmx;
+                        u = (cq0 + gp) - lo - 4.0f * E;
+                    }
+                    ut[i] = u;
+                }
+            }
+            // this lane's row i*16 + lane%16 against codes 4g..4g+3 of each
+            // 16-code block (g = lane/16): the products are formed as
+            // W A^T, so a lane's four results are one row's
+            T2 best[MB];
+#pragma unroll
+            for (int i = 0; i < MB; ++i) best[i] = T2{-inf, 0, -inf};
             if (!ahead) {
                 // the first chunk was not fetched ahead (start, or odd
                 // chunk count): both stages are free after the barrier
@@ -811,8 +858,8 @@ __global__ void __launch_bounds__(kMT)
             // chunk c from (sb, cs), the next one into (nsb, ncs).  A head's
             // last chunk fetches the next head's first one (the next tile's
             // first head after the last) into stage0 when it reads stage1.
-            auto chunk = [&](int c, const bf16x8* sb, const f32x4* cs,
-                             bf16x8* nsb, f32x4* ncs, bool into0) {
+            auto chunk = [&](int c, const bf16x8* sb, const float* cs,
+                             bf16x8* nsb, float* ncs, bool into0) {
                 wait_vmem();
                 __syncthreads();
                 // in flight during this chunk's search
@@ -823,8 +870,8 @@ __global__ void __launch_bounds__(kMT)
                     if (ahead) fetch(hq + 1 < m.H ? hq + 1 : 0, 0, nsb, ncs);
                 }
                 // code blocks of this chunk; each block's fragments (and
-                // -|w|^2/2 of this lane's code in all four rows) are read
-                // from LDS while the previous block is searched
+                // -|w|^2/2 of this lane's four codes) are read from LDS
+                // while the previous block is searched
                 const int ncb = min(CBK, QB - c * CBK);
                 bf16x8 bf[2][KBS];
                 f32x4 cqs[2];
@@ -832,7 +879,7 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
                     for (int kb = 0; kb < KBS; ++kb)
                         b[kb] = sb[(cbl * KBS + kb) * 64 + lane];
-                    cq = cs[cbl * 16 + (lane & 15)];
+                    cq = *reinterpret_cast<const f32x4*>(cs + cbl * 16 + 4 * (lane >> 4));
                 };
                 frags(0, bf[0], cqs[0]);
 #pragma unroll
@@ -840,6 +887,9 @@ __global__ void __launch_bounds__(kMT)
                     if (cbl >= ncb) break;
                     const int cb = c * CBK + cbl;
                     if (cbl + 1 < ncb) frags(cbl + 1, bf[(cbl + 1) & 1], cqs[(cbl + 1) & 1]);
+                    // hi products first, then (for a block that may hold
+                    // the nearest code of some row) the lo products: every
+                    // search forms g in this order, seeded or not
                     f32x4 acc[MB];
 #pragma unroll
                     for (int i = 0; i < MB; ++i) acc[i] = cqs[cbl & 1];
@@ -847,29 +897,40 @@ __global__ void __launch_bounds__(kMT)
                     for (int kb = 0; kb < KBS; ++kb) {
                         const bf16x8 b = bf[cbl & 1][kb];
 #pragma unroll
-                        for (int i = 0; i < MB; ++i) {
-                            acc[i] = mfma(ah[i][kb], b, acc[i]);
-                            acc[i] = mfma(al[i][kb], b, acc[i]);
-                        }
+                        for (int i = 0; i < MB; ++i) acc[i] = mfma(b, ah[i][kb], acc[i]);
                     }
-                    const int code = cb * 16 + (lane & 15);
+                    bool need = false;
+#pragma unroll
+                    for (int i = 0; i < MB; ++i) {
+                        const float mx = fmaxf(fmaxf(acc[i][0], acc[i][1]),
+                                               fmaxf(acc[i][2], acc[i][3]));
+                        need |= mx >= ut[i];
+                    }
+                    if (!MARGIN && __ballot(need) == 0) continue;
+#pragma unroll
+                    for (int kb = 0; kb < KBS; ++kb) {
+                        const bf16x8 b = bf[cbl & 1][kb];
+#pragma unroll
+                        for (int i = 0; i < MB; ++i) acc[i] = mfma(b, al[i][kb], acc[i]);
+                    }
+                    const int code0 = cb * 16 + 4 * (lane >> 4);
 #pragma unroll
                     for (int i = 0; i < MB; ++i)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const float g = acc[i][r];
                             if (MARGIN) {
-                                if (g > best[i][r].b) {
-                                    best[i][r].s = best[i][r].b;
-                                    best[i][r].b = g;
-                                    best[i][r].i = code;
-                                } else if (g > best[i][r].s) {
-                                    best[i][r].s = g;
+                                if (g > best[i].b) {
+                                    best[i].s = best[i].b;
+                                    best[i].b = g;
+                                    best[i].i = code0 + r;
+                                } else if (g > best[i].s) {
+                                    best[i].s = g;
                                 }
                             } else {
-                                const bool gt = g > best[i][r].b;
-                                best[i][r].b = gt ? g : best[i][r].b;
-                                best[i][r].i = gt ? code : best[i][r].i;
+                                const bool gt = g > best[i].b;
+                                best[i].b = gt ? g : best[i].b;
+                                best[i].i = gt ? code0 + r : best[i].i;
                             }
                         }
                 }
@@ -882,43 +943,39 @@ __global__ void __launch_bounds__(kMT)
                 chunk(c, stage0, cn0, stage1, cn1, false);
                 if (c + 1 < nchunk) chunk(c + 1, stage1, cn1, stage0, cn0, true);
             }
-            // combine the 16 column lanes of each row group
+            // combine the four code groups of each row (lanes l, l^16,
+            // l^32, l^48)
 #pragma unroll
-            for (int i = 0; i < MB; ++i)
+            for (int i = 0; i < MB; ++i) {
+                T2 v = best[i];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    T2 v = best[i][r];
-#pragma unroll
-                    for (int o = 1; o < 16; o <<= 1) {
-                        T2 y;
-                        y.b = __shfl_xor(v.b, o, 64);
-                        y.i = __shfl_xor(v.i, o, 64);
-                        y.s = MARGIN ? __shfl_xor(v.s, o, 64) : -inf;
-                        v = t2_merge(v, y);
-                    }
-                    best[i][r] = v;
+                for (int o = 16; o < 64; o <<= 1) {
+                    T2 y;
+                    y.b = __shfl_xor(v.b, o, 64);
+                    y.i = __shfl_xor(v.i, o, 64);
+                    y.s = MARGIN ? __shfl_xor(v.s, o, 64) : -inf;
+                    v = t2_merge(v, y);
                 }
+                best[i] = v;
+            }
             const float wmax = w.cnorm[(int64_t)m.H * m.Q + hq];
 #pragma unroll
-            for (int i = 0; i < MB; ++i)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int rw = 4 * (lane >> 4) + r;     // row within block
-                    const float a2 = __shfl(nrm[i], rw, 64);
-                    const int64_t s = __shfl(myslot[i], rw, 64);
-                    if ((lane & 15) == 0 && s >= 0) {
-                        io.codes[s * m.H + hq] = best[i][r].i;
-                        if (MARGIN) {
-                            const float na = sqrtf(a2);
-                            const float E = score_err_split(2 * DS, na, wmax);
-                            // scores |w|^2 - 2 a.w = -2 g (exact scaling)
-                            const float u1 = -2.0f * best[i][r].b + a2 + E;
-                            const float l2 = -2.0f * best[i][r].s + a2 - E;
-                            io.margin[(s * m.H + hq) * 2 + 0] = sqrtf(u1 > 0 ? u1 : 0.0f);
-                            io.margin[(s * m.H + hq) * 2 + 1] = sqrtf(l2 > 0 ? l2 : 0.0f);
-                        }
+            for (int i = 0; i < MB; ++i) {
+                const int64_t s = myslot[i];
+                if ((lane >> 4) == 0 && s >= 0) {
+                    io.codes[s * m.H + hq] = best[i].i;
+                    if (MARGIN) {
+                        const float a2 = nrm[i];
+                        const float na = sqrtf(a2);
+                        const float E = score_err_split(2 * DS, na, wmax);
+                        // scores |w|^2 - 2 a.w = -2 g (exact scaling)
+                        const float u1 = -2.0f * best[i].b + a2 + E;
+                        const float l2 = -2.0f * best[i].s + a2 - E;
+                        io.margin[(s * m.H + hq) * 2 + 0] = sqrtf(u1 > 0 ? u1 : 0.0f);
+                        io.margin[(s * m.H + hq) * 2 + 1] = sqrtf(l2 > 0 ? l2 : 0.0f);
                     }
                 }
+            }
         }
     }
 }
@@ -1224,33 +1281,33 @@ hipError_t launch_mlp_mfma(const ModelDims& m, const LayerW<float>& w,
 template <int KBS, int MB>
 static void vq_go(const ModelDims& m, const LayerW<float>& w, RowSet rows,
                   const BlockIO<PrecBF16>& io, const bf16x8* cb,
-                  hipStream_t st) {
+                  const VqSeed& seed, hipStream_t st) {
     constexpr int R = 64 * MB;    // 16*MB rows per wave, 4 waves
     const dim3 g(mgrid((rows.n_host + R - 1) / R));
     if (io.margin)
         hipLaunchKernelGGL((k_vq_mfma<KBS, MB, true>), g, dim3(kMT), 0, st, m, w,
-                           rows, io, cb);
+                           rows, io, cb, VqSeed{});
     else
         hipLaunchKernelGGL((k_vq_mfma<KBS, MB, false>), g, dim3(kMT), 0, st, m,
-                           w, rows, io, cb);
+                           w, rows, io, cb, seed);
 }
 
 hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
                           RowSet rows, const BlockIO<PrecBF16>& io,
-                          hipStream_t st) {
+                          hipStream_t st, const VqSeed& seed) {
     const bf16x8* cb = reinterpret_cast<const bf16x8*>(w.cb_p);
     const int mb = tuning_get(m).vq_mb;
     switch (m.dseg / 32 * 10 + mb) {
-        case 11: vq_go<1, 1>(m, w, rows, io, cb, st); break;
-        case 12: vq_go<1, 2>(m, w, rows, io, cb, st); break;
-        case 21: vq_go<2, 1>(m, w, rows, io, cb, st); break;
-        case 22: vq_go<2, 2>(m, w, rows, io, cb, st); break;
-        case 14: vq_go<1, 4>(m, w, rows, io, cb, st); break;
-        case 24: vq_go<2, 4>(m, w, rows, io, cb, st); break;
-        case 41: vq_go<4, 1>(m, w, rows, io, cb, st); break;
-        case 42: vq_go<4, 2>(m, w, rows, io, cb, st); break;
-        case 44: vq_go<4, 4>(m, w, rows, io, cb, st); break;
-        case 81: vq_go<8, 1>(m, w, rows, io, cb, st); break;
+        case 11: vq_go<1, 1>(m, w, rows, io, cb, seed, st); break;
+        case 12: vq_go<1, 2>(m, w, rows, io, cb, seed, st); break;
+        case 21: vq_go<2, 1>(m, w, rows, io, cb, seed, st); break;
+        case 22: vq_go<2, 2>(m, w, rows, io, cb, seed, st); break;
+        case 14: vq_go<1, 4>(m, w, rows, io, cb, seed, st); break;
+        case 24: vq_go<2, 4>(m, w, rows, io, cb, seed, st); break;
+        case 41: vq_go<4, 1>(m, w, rows, io, cb, seed, st); break;
+        case 42: vq_go<4, 2>(m, w, rows, io, cb, seed, st); break;
+        case 44: vq_go<4, 4>(m, w, rows, io, cb, seed, st); break;
+        case 81: vq_go<8, 1>(m, w, rows, io, cb, seed, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
