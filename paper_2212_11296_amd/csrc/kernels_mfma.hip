@@ -703,32 +703,34 @@ __device__ inline float score_err_split(int n, float na, float wmax) {
            3.0517578e-5f * (na * wmax + na * na);
 }
 
-// Each wave owns 16*MB rows kept in registers as hi/lo A fragments; the
-// four waves of a workgroup stream the codes of the quantizer head through
-// a double-buffered LDS stage (CBK code blocks of 16 codes per chunk, with
-// -|w|^2/2 of each code four times over: the accumulator input of the
-// code's products, so the matrix core returns g = a.w - |w|^2/2 for every
-// row and the search only compares).  The stages are filled by
-// global-to-LDS loads (no registers, no store instructions), issued one
-// chunk ahead: the next chunk of the head, or after a head's last chunk the
-// first chunk of the next head (or of the next tile's first head) when the
-// chunk count is even.  A chunk starts with this wave's loads complete and a
-// barrier, after which every wave has also finished reading the other stage,
-// which then takes the next chunk.
-// Every codebook fragment read from LDS feeds 2*MB MFMAs.  The second-best
-// value (for the certified-reuse margins) is tracked only when MARGIN;
-// the chosen code is the same either way.  The register cap applies where
-// it costs no spills.
+// Each wave owns 16*MB rows kept in registers as hi/lo fragments; the four
+// waves of a workgroup stream the codes of the quantizer head through a
+// double-buffered LDS stage (CBK code blocks of 16 codes per chunk, with
+// -|w|^2/2 of every code: the accumulator input of the code's products, so
+// the matrix core returns g = a.w - |w|^2/2 and the search only compares).
+// The stages are filled by global-to-LDS loads (no registers, no store
+// instructions), issued one chunk ahead: the next chunk of the head, or
+// after a head's last chunk the first chunk of the next head (or of the
+// next tile's first head) when the chunk count is even.  A chunk starts with
+// this wave's loads complete and a barrier, after which every wave has also
+// finished reading the other stage, which then takes the next chunk.  Eight
+// code blocks per chunk (two workgroups per CU by LDS) took 10% less time
+// than four (three per CU): the per-chunk wait and barrier cost more than
+// the third workgroup hides.
+// Every codebook fragment read from LDS feeds MB MFMAs, and MB more when
+// the block gets its lo products.  The second-best value (for the
+// certified-reuse margins) is tracked only when MARGIN, which searches
+// every block in full; the chosen code is the same either way.
 template <int KBS, int MB, bool MARGIN>
 __global__ void __launch_bounds__(kMT)
     __attribute__((amdgpu_waves_per_eu(MB <= 2 && !MARGIN ? 3 : 1)))
     k_vq_mfma(ModelDims m, LayerW<float> w, RowSet rows, BlockIO<PrecBF16> io,
               const bf16x8* __restrict__ cbp, VqSeed seed) {
-    constexpr int DS = KBS * 32, WR = MB * 16, CBK = 4;
+    constexpr int DS = KBS * 32, WR = MB * 16, CBK = 8;
     constexpr int CHUNK = CBK * KBS * 64;       // fragment lanes per chunk
     constexpr int PER = CHUNK / kMT;             // per thread
     constexpr int CN = CBK * 16;                 // code norms per chunk
-    static_assert(CN == 64, "one wave loads a chunk's code norms");
+    static_assert(CN % 64 == 0 && CN <= 256, "waves 0.. load a chunk's code norms");
     __shared__ bf16x8 stage0[CHUNK], stage1[CHUNK];
     __shared__ __align__(16) float cn0[CN], cn1[CN];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -749,9 +751,10 @@ __global__ void __launch_bounds__(kMT)
             const int64_t e = e0 + threadIdx.x + k * kMT;
             lds_dma16(cbh + (e < cbtot ? e : cbtot - 1), st + wave * 64 + k * kMT);
         }
-        if (wave == 0) {
-            const int code = c * CN + lane;
-            lds_dma4(w.cnh + (int64_t)hq * m.Q + (code < m.Q ? code : m.Q - 1), cs);
+        if (wave < CN / 64) {
+            const int code = c * CN + wave * 64 + lane;
+            lds_dma4(w.cnh + (int64_t)hq * m.Q + (code < m.Q ? code : m.Q - 1),
+                     cs + wave * 64);
         }
     };
     bool ahead = false;      // this head's first chunk is in stage0
