@@ -186,3 +186,41 @@ def test_bf16_quantizer_heads_and_open_boundary(periodic, vq_heads):
     b = vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)
     assert np.allclose(host(b["ratios"]), host(a["ratios"]), rtol=1e-12, atol=0)
     _eloc_every_neighbour(mc, theta, s, cfg, p, b)
+
+
+@pytest.mark.parametrize("vq_heads", [1, 4], ids=["H1", "H4"])
+def test_bf16_duplicate_codewords_lowest_index(vq_heads):
+    """Codebooks with exact duplicates, within a 16-code block (odd codes
+    repeat the even ones) and across blocks (codes 16-31 repeat codes
+    0-15): equal distances go to the lowest index (reading C2).  The
+    neighbours' searches start from the sample's code and skip blocks that
+    cannot hold the nearest one, the full sequences' searches do not; both
+    must choose the same codes, so dedup equals plain, and the forward
+    codes equal the oracle's on every sequence without a near-tie of
+    distinct codewords."""
+    from workloads.layout import param_layout
+    mc = replace(CONFIGS["small"], name="dup", L=6, d_model=128, n_layers=2,
+                 n_heads=8, d_ff=512, codebook_size=64, vq_heads=vq_heads,
+                 precision="bf16", batch=8, spin_seed=1791)
+    say(f"bf16 duplicate codewords H={vq_heads}")
+    theta = make_params(mc)
+    for name, shape, kind, off, n in param_layout(mc):
+        if name.endswith(".codebook"):
+            cb = theta[off:off + n].reshape(shape)
+            cb[:, 1::2] = cb[:, 0::2]
+            cb[:, 16:32] = cb[:, 0:16]
+            theta[off:off + n] = cb.ravel()
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    P = net.unpack(mc, theta)
+    flips, ref = check_sequences(mc, P, cfg, p, s, LOGPSI_TOL)
+    _, cd, _ = vq.forward_activations(cfg, p, sp)
+    cd = host(cd)
+    # every chosen code is the lowest index of its duplicate class
+    assert (cd % 2 == 0).all() and not ((cd >= 16) & (cd < 32)).any()
+    a = vq.local_energy(cfg, p, sp, vq.PLAIN, ratios=True)
+    b = vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)
+    assert np.array_equal(host(b["ratios"]), host(a["ratios"]))
+    assert np.array_equal(host(b["eloc"]), host(a["eloc"]))
+    _eloc_every_neighbour(mc, theta, s, cfg, p, b)
