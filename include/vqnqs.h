@@ -445,6 +445,16 @@ int  vqnqs_profile_read(char* names, int name_len, double* total_ms,
 vqnqs_status vqnqs_probe_exp_rate(float* sink, void* stream,
                                   double* exps_per_s);
 
+/* Introspection: y[i] = GELU(x[i]) = x Phi(x) for FP32 values, by the same
+ * device function the BF16 mode's matrix-core MLP applies to its hidden
+ * layer (Sec. 3.1 block: MLP with a GELU; erf from Abramowitz & Stegun
+ * 7.1.26, absolute error of erf at most 1.5e-7), so that tests can bound
+ * its error against the exact erf form.  Asynchronous on `stream`.
+ *   x  DEVICE [n] FP32 in;  y  DEVICE [n] FP32 out (may equal x)
+ * Errors: NULL_POINTER for null x or y with n > 0, INVALID_SHAPE for n < 0. */
+vqnqs_status vqnqs_probe_gelu(const float* x, float* y, int64_t n,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

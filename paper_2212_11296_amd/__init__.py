@@ -13,7 +13,8 @@ from .api import (Config, PLAIN, DEDUP, F64, F32, BF16, FLAG_CERTIFIED_VQ,
                   WS_FORWARD, WS_GRAD, MULTI_CONCURRENT, MULTI_GRAPH,
                   local_energy_multi, workspace_size_multi, autotune,
                   set_tuning, local_energy_static, STATIC_SCRATCH_BYTES,
-                  forward_activations, probe_exp_rate, sample, WS_SAMPLE,
+                  forward_activations, probe_exp_rate, probe_gelu, sample,
+                  WS_SAMPLE,
                   vmc_step, WS_VMC, n_sites, n_tokens)
 
 __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
@@ -25,5 +26,6 @@ __all__ = ["Config", "PLAIN", "DEDUP", "F64", "F32", "BF16",
            "MULTI_CONCURRENT", "MULTI_GRAPH", "local_energy_multi",
            "workspace_size_multi", "autotune", "set_tuning",
            "local_energy_static", "STATIC_SCRATCH_BYTES",
-           "forward_activations", "probe_exp_rate", "sample", "WS_SAMPLE",
+           "forward_activations", "probe_exp_rate", "probe_gelu", "sample",
+           "WS_SAMPLE",
            "vmc_step", "WS_VMC", "n_sites", "n_tokens"]

@@ -25,7 +25,7 @@ MULTI_CONCURRENT, MULTI_GRAPH = 1, 2
 EXPORTS = ["vqnqs_param_count", "vqnqs_workspace_size", "vqnqs_neighbours",
            "vqnqs_forward_logpsi", "vqnqs_local_energy", "vqnqs_grad_logpsi",
            "vqnqs_local_energy_static", "vqnqs_forward_activations",
-           "vqnqs_probe_exp_rate", "vqnqs_sample", "vqnqs_vmc_step",
+           "vqnqs_probe_exp_rate", "vqnqs_probe_gelu", "vqnqs_sample", "vqnqs_vmc_step",
            "vqnqs_workspace_size_multi", "vqnqs_local_energy_multi",
            "vqnqs_autotune", "vqnqs_set_tuning",
            "vqnqs_workspace_status", "vqnqs_status_string",
@@ -141,6 +141,8 @@ def load_library():
     lib.vqnqs_workspace_status.restype = ctypes.c_int
     lib.vqnqs_probe_exp_rate.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
     lib.vqnqs_probe_exp_rate.restype = ctypes.c_int
+    lib.vqnqs_probe_gelu.argtypes = [P, P, ctypes.c_int64, P]
+    lib.vqnqs_probe_gelu.restype = ctypes.c_int
     lib.vqnqs_status_string.argtypes = [ctypes.c_int]
     lib.vqnqs_status_string.restype = ctypes.c_char_p
     lib.vqnqs_profile_enable.argtypes = [ctypes.c_int]
@@ -192,6 +194,15 @@ def probe_exp_rate():
     _check("vqnqs_probe_exp_rate", load_library().vqnqs_probe_exp_rate(
         _ptr(sink), _stream(), ctypes.byref(out)))
     return out.value
+
+
+def probe_gelu(x):
+    """GELU of a device float32 tensor by the BF16 MLP's device function."""
+    import torch
+    y = torch.empty_like(x)
+    _check("vqnqs_probe_gelu", load_library().vqnqs_probe_gelu(
+        _ptr(x), _ptr(y), x.numel(), _stream()))
+    return y
 
 
 def _check(fn, st):

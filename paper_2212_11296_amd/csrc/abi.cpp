@@ -342,6 +342,16 @@ vqnqs_status vqnqs_probe_exp_rate(float* sink, void* stream,
     return VQNQS_OK;
 }
 
+vqnqs_status vqnqs_probe_gelu(const float* x, float* y, int64_t n,
+                              void* stream) {
+    if (n < 0) return VQNQS_ERR_INVALID_SHAPE;
+    if (n == 0) return VQNQS_OK;
+    if (!x || !y) return VQNQS_ERR_NULL_POINTER;
+    if (vq::launch_probe_gelu(x, y, n, (hipStream_t)stream) != hipSuccess)
+        return VQNQS_ERR_HIP;
+    return VQNQS_OK;
+}
+
 const char* vqnqs_status_string(vqnqs_status s) {
     switch (s) {
         case VQNQS_OK: return "ok";

@@ -100,6 +100,8 @@ struct VqSeed {
     const NbDesc* desc = nullptr;
     const int32_t* bcode = nullptr;
 };
+// y = GELU(x) by the matrix-core MLP's device function.
+hipError_t launch_probe_gelu(const float* x, float* y, int64_t n, hipStream_t st);
 hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
                           RowSet rows, const BlockIO<PrecBF16>& io,
                           hipStream_t st, const VqSeed& seed = VqSeed{});

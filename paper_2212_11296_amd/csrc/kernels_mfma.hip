@@ -446,6 +446,19 @@ __device__ inline float gelu_as(float x) {
     return __builtin_fmaf(-ax, q, __builtin_elementwise_maximum(x, 0.0f));
 }
 
+__global__ void k_probe_gelu(const float* __restrict__ x, float* __restrict__ y,
+                             int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = gelu_as(x[i]);
+}
+
+hipError_t launch_probe_gelu(const float* x, float* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_probe_gelu, dim3(mgrid((n + 255) / 256)), dim3(256), 0, st,
+                       x, y, n);
+    return hipGetLastError();
+}
+
 template <int KB1, int MB>
 __global__ void __launch_bounds__(kMT) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_mfma(ModelDims m, LayerW<float> w,
                                                  RowSet rows, BlockIO<PrecBF16> io,
