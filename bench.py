@@ -186,8 +186,7 @@ def cpu_baseline(mc, theta, spins, gpu_ratios, n_nb0, budget_s):
                       f"1 + n_neighbours evaluations per local energy")}
     # the oracle's deduplicated form (Sec. 3.2) on the same sample, when the
     # plain one left time for it: one whole local energy
-    if mc.hamiltonian != "tfim" and not getattr(mc, "encoder", False) \
-            and dt < budget_s:
+    if mc.hamiltonian != "tfim" and dt < budget_s:
         from oracle import eloc as oeloc
         t0 = time.perf_counter()
         E_d = oeloc.eloc_dedup(mc, theta, spins[0:1])[0]
@@ -751,6 +750,8 @@ def main():
                         f"{'periodic' if mc.periodic else 'open'} Heisenberg")
                        + (f", tokens of {mc.group} spins ({mc.T} positions)"
                           if mc.group > 1 else "")
+                       + (", bidirectional encoder (mean-pooled log psi)"
+                          if mc.encoder else "")
                        + f", VQ transformer d={mc.d_model} L={mc.n_layers}"
                        + (" + attention-only half-block" if mc.attn_tail
                           else "") + " "

@@ -162,8 +162,9 @@ typedef struct {
                               positions, log psi = mean_i LN(x_i) . w + b
                               (W_head [d][1], b_head [1]).  Not autoregressive:
                               vqnqs_sample and vqnqs_vmc_step return
-                              VQNQS_ERR_UNSUPPORTED.  FP64 and FP32 modes; no
-                              half-block, no incremental attention.        */
+                              VQNQS_ERR_UNSUPPORTED.  No half-block
+                              (INVALID_CONFIG), no incremental attention
+                              (UNSUPPORTED).                              */
 } vqnqs_config;
 
 /* Counters written by vqnqs_local_energy (int64, VQNQS_NCOUNTERS entries,

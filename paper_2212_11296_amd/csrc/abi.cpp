@@ -37,9 +37,7 @@ bool dims_from(const vqnqs_config* c, vq::ModelDims* m, vqnqs_status* err) {
                      VQNQS_INC_LAYERS(255)))
         return false;
     *err = VQNQS_ERR_UNSUPPORTED;
-    if (c->encoder && (c->precision == VQNQS_BF16 ||
-                       (c->flags & VQNQS_FLAG_INCREMENTAL_ATTN)))
-        return false;
+    if (c->encoder && (c->flags & VQNQS_FLAG_INCREMENTAL_ATTN)) return false;
     const int dh = c->d_model / c->n_heads;
     if (dh != 4 && dh != 8 && dh != 16 && dh != 32 && dh != 64) return false;
     if (c->d_model > 512 || c->d_ff > 4096 || c->n_layers > VQNQS_NCOUNTERS - 17 ||

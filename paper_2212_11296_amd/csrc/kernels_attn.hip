@@ -198,13 +198,14 @@ struct QTile {
     int t, iq, nblk;
 };
 
-template <int DH>
-__device__ inline void qtile_init(QTile<DH>& q, const Tiles<DH>& T, int t) {
+// CA: causal (keys 0..query); otherwise every key of the sequence.
+template <int DH, bool CA = true>
+__device__ inline void qtile_init(QTile<DH>& q, const Tiles<DH>& T, int t, int N) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, c16 = lane & 15;
     q.t = t;
     q.iq = t * 16 + c16;
-    q.nblk = (t * 16 + 15) / 32 + 1;
+    q.nblk = CA ? (t * 16 + 15) / 32 + 1 : npad32(N) / 32;
     const __bf16* qr = T.Qc + q.iq * 2 * DH;
     if (DH == 16) {
         // [kh(16) | kl(16)] x [qh ; qh]  and  [kh | kl] x [ql ; ql]
@@ -233,7 +234,7 @@ __device__ inline void qtile_init(QTile<DH>& q, const Tiles<DH>& T, int t) {
 // tiles' chains are independent, so the scheduler interleaves one tile's
 // exponentials with another's matrix-core work.  Per query the operations
 // and their order do not depend on NQ or on which tiles share the block.
-template <int DH, int NQ, bool EDGE>
+template <int DH, int NQ, bool EDGE, bool CA = true>
 __device__ inline void qtiles_block(QTile<DH> (&q)[NQ], int N, int blk,
                                     const bf16x8 (&ka)[2], const bf16x8 (&kb)[2],
                                     const bf16x8 (&vh)[DH / 16],
@@ -261,14 +262,14 @@ __device__ inline void qtiles_block(QTile<DH> (&q)[NQ], int N, int blk,
         }
     }
     if (EDGE) {
-        // keys beyond the query (or the sequence)
+        // keys beyond the query (causal) or the sequence
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            if (j0 + 31 > q[i].t * 16 || j0 + 31 >= N) {
+            if ((CA && j0 + 31 > q[i].t * 16) || j0 + 31 >= N) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int key = j0 + (k >> 2) * 16 + 4 * g + (k & 3);
-                    if (key > q[i].iq || key >= N) s[i][k] = -__builtin_inff();
+                    if ((CA && key > q[i].iq) || key >= N) s[i][k] = -__builtin_inff();
                 }
             }
         }
@@ -358,24 +359,24 @@ __device__ inline void block_frags(const Tiles<DH>& T, int blk, bf16x8 (&ka)[2],
 // smallest tile is tq_min.  Blocks 1..last need no mask for any tile
 // (32 blk + 31 <= 16 tq_min and 32 blk + 31 < N): they run the straight-line
 // form, the others the edge form.
-template <int DH, int NQ>
+template <int DH, int NQ, bool CA = true>
 __device__ inline void run_blocks(const Tiles<DH>& T, QTile<DH> (&q)[NQ], int N,
                                   int tq_min, int b0, int b1,
                                   const bf16x8& ones) {
     constexpr int NT = DH / 16;
-    const int jl = min(16 * tq_min - 31, N - 32);
+    const int jl = CA ? min(16 * tq_min - 31, N - 32) : N - 32;
     const int last = jl >= 0 ? jl / 32 : 0;
     const int i0 = max(b0, 1), i1 = min(b1, last + 1);
     auto edge = [&](int blk) {
         bf16x8 ka[2], kb[2], vh[NT], vl[NT];
         block_frags<DH>(T, blk, ka, kb, vh, vl);
-        qtiles_block<DH, NQ, true>(q, N, blk, ka, kb, vh, vl, ones);
+        qtiles_block<DH, NQ, true, CA>(q, N, blk, ka, kb, vh, vl, ones);
     };
     if (b0 == 0 && b1 > 0) edge(0);
     for (int blk = i0; blk < i1; ++blk) {
         bf16x8 ka[2], kb[2], vh[NT], vl[NT];
         block_frags<DH>(T, blk, ka, kb, vh, vl);
-        qtiles_block<DH, NQ, false>(q, N, blk, ka, kb, vh, vl, ones);
+        qtiles_block<DH, NQ, false, CA>(q, N, blk, ka, kb, vh, vl, ones);
     }
     for (int blk = max(i0, i1); blk < b1; ++blk) edge(blk);
 }
@@ -385,7 +386,7 @@ __device__ inline void run_blocks(const Tiles<DH>& T, QTile<DH> (&q)[NQ], int N,
 // fragment read, over the blocks they both have; the larger tile then runs
 // its remaining blocks alone.  Writes rows i >= lo (and < N) through
 // orow(i).
-template <int DH, int NQ, class OF>
+template <int DH, int NQ, bool CA = true, class OF>
 __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ],
                                   int lo, OF orow) {
     const int lane = threadIdx.x & 63;
@@ -393,16 +394,16 @@ __device__ inline void attn_tiles(const Tiles<DH>& T, int N, const int (&tq)[NQ]
     constexpr int NT = DH / 16;
     QTile<DH> q[NQ];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) qtile_init<DH>(q[i], T, tq[i]);
+    for (int i = 0; i < NQ; ++i) qtile_init<DH, CA>(q[i], T, tq[i], N);
     bf16x8 ones;
 #pragma unroll
     for (int k = 0; k < 8; ++k) ones[k] = (__bf16)1.0f;
     QTile<DH>(&q0)[1] = *reinterpret_cast<QTile<DH>(*)[1]>(&q[0]);
     if (NQ == 2) {
-        run_blocks<DH, NQ>(T, q, N, tq[NQ - 1], 0, q[NQ - 1].nblk, ones);
-        run_blocks<DH, 1>(T, q0, N, tq[0], q[NQ - 1].nblk, q[0].nblk, ones);
+        run_blocks<DH, NQ, CA>(T, q, N, tq[NQ - 1], 0, q[NQ - 1].nblk, ones);
+        run_blocks<DH, 1, CA>(T, q0, N, tq[0], q[NQ - 1].nblk, q[0].nblk, ones);
     } else {
-        run_blocks<DH, 1>(T, q0, N, tq[0], 0, q[0].nblk, ones);
+        run_blocks<DH, 1, CA>(T, q0, N, tq[0], 0, q[0].nblk, ones);
     }
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
@@ -431,7 +432,7 @@ constexpr int kPairTiles = 12;
 // to the waves in snake order (0 1 2 3 3 2 1 0 ...), which evens out the
 // blocks per wave.  With fewer, wave w takes tiles NTQ-1-w, NTQ-5-w, ...,
 // two at a time, so that every wave has work.
-template <int DH, class OF>
+template <int DH, bool CA = true, class OF>
 __device__ inline void wave_tiles(const Tiles<DH>& T, int N, int NTQ, int w,
                                   int tmin, int lo, OF orow) {
     if (NTQ - tmin >= kPairTiles) {
@@ -444,10 +445,10 @@ __device__ inline void wave_tiles(const Tiles<DH>& T, int N, int NTQ, int w,
             const int hi = 2 * k + 1, lo2 = 2 * k;
             if (hi < NTQ && lo2 >= tmin) {
                 const int tq[2] = {hi, lo2};
-                attn_tiles<DH, 2>(T, N, tq, lo, orow);
+                attn_tiles<DH, 2, CA>(T, N, tq, lo, orow);
             } else {
                 const int tq[1] = {hi < NTQ ? hi : lo2};
-                attn_tiles<DH, 1>(T, N, tq, lo, orow);
+                attn_tiles<DH, 1, CA>(T, N, tq, lo, orow);
             }
         }
         return;
@@ -455,11 +456,11 @@ __device__ inline void wave_tiles(const Tiles<DH>& T, int N, int NTQ, int w,
     int t = NTQ - 1 - w;
     for (; t - 4 >= tmin; t -= 8) {
         const int tq[2] = {t, t - 4};
-        attn_tiles<DH, 2>(T, N, tq, lo, orow);
+        attn_tiles<DH, 2, CA>(T, N, tq, lo, orow);
     }
     if (t >= tmin) {
         const int tq[1] = {t};
-        attn_tiles<DH, 1>(T, N, tq, lo, orow);
+        attn_tiles<DH, 1, CA>(T, N, tq, lo, orow);
     }
 }
 
@@ -487,7 +488,7 @@ __device__ inline int64_t xcd_unit(int64_t v, int64_t units, int nh) {
 // values.  Elsewhere the uncapped instance runs.
 
 // Full sequences (the samples themselves, or materialised neighbours).
-template <int DH, int WPE>
+template <int DH, int WPE, bool CA = true>
 __global__ void __launch_bounds__(kAT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_attn_seq_mfma(ModelDims m,
                                                       const int32_t* n_dev,
@@ -510,14 +511,15 @@ k_attn_seq_mfma(ModelDims m,
         __syncthreads();
         load_all<DH>(T, N, io.q, io.k, io.v, sb, d, qs);
         __syncthreads();
-        wave_tiles<DH>(T, N, NTQ, wave, 0, 0,
-                       [&](int i) { return io.a + sb + (int64_t)i * d; });
+        wave_tiles<DH, CA>(T, N, NTQ, wave, 0, 0,
+                           [&](int i) { return io.a + sb + (int64_t)i * d; });
     }
     if (ctr && blockIdx.x == 0 && threadIdx.x == 0) {
         atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_ROWS),
                   (unsigned long long)(n * N));
         atomicAdd((unsigned long long*)(ctr + VQNQS_CTR_ATTN_PAIRS),
-                  (unsigned long long)(n * ((int64_t)N * (N + 1) / 2) * m.nh));
+                  (unsigned long long)(n * (CA ? (int64_t)N * (N + 1) / 2
+                                                  : (int64_t)N * N) * m.nh));
     }
 }
 
@@ -529,7 +531,7 @@ k_attn_seq_mfma(ModelDims m,
 // current neighbour's compute and kept in LDS (two buffers by parity, so a
 // neighbour costs two barriers); a step then waits for one batch of 16-byte
 // value loads.
-template <int DH, int WPE>
+template <int DH, int WPE, bool CA = true>
 __global__ void __launch_bounds__(kAT) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_attn_dedup_mfma(ModelDims m,
                                                         DedupIO<PrecBF16> dd,
@@ -589,7 +591,7 @@ k_attn_dedup_mfma(ModelDims m,
             const uint64_t* mk = msk[par];
             // step (k-1 -> k): restore rows of C_{k-1} not in C_k, patch C_k
             const NbDesc D = Dn;
-            const int pmin = D.p1 + 1;
+            const int pmin = CA ? D.p1 + 1 : 0;     // the encoder: every row
             const int cc = ccn;
             const int64_t ob0 = (D.ov - pmin) * (int64_t)d + h * DH;
             const int np = cp * G, tot = (cp + cc) * G;
@@ -648,7 +650,7 @@ k_attn_dedup_mfma(ModelDims m,
             cp = cc;
             pov = D.ov;
             __syncthreads();
-            wave_tiles<DH>(T, N, NTQ, wave, pmin / 16, pmin,
+            wave_tiles<DH, CA>(T, N, NTQ, wave, pmin / 16, pmin,
                            [&](int i) { return dd.oa + ob0 + (int64_t)i * d; });
             // the next neighbour's mask into the other buffer (last read by
             // the previous step, which every wave finished before this
@@ -656,7 +658,8 @@ k_attn_dedup_mfma(ModelDims m,
             if (k + 1 < k1 && threadIdx.x < W) msk[par ^ 1][threadIdx.x] = mnext;
             if (h == 0 && threadIdx.x == 0) {
                 my_rows += N - pmin;
-                my_pairs += ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2;
+                my_pairs += CA ? ((int64_t)N * (N + 1) - (int64_t)pmin * (pmin + 1)) / 2
+                               : (int64_t)N * N;
             }
         }
     }
@@ -709,7 +712,16 @@ hipError_t launch_attn_seq_mfma(const ModelDims& m, const int32_t* n_dev,
         hipLaunchKernelGGL(kern, dim3(g), dim3(kAT), sm, st, m, n_dev, n_seq,
                            io, ctr);
     };
-    if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
+    if (m.enc) {                        // bidirectional encoder
+        if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
+            go(k_attn_seq_mfma<16, 3, false>);
+        else if (m.dh == 16)
+            go(k_attn_seq_mfma<16, 1, false>);
+        else if (m.dh == 32)
+            go(k_attn_seq_mfma<32, 1, false>);
+        else
+            return hipErrorInvalidValue;
+    } else if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
         go(k_attn_seq_mfma<16, 3>);
     else if (m.dh == 16)
         go(k_attn_seq_mfma<16, 1>);
@@ -729,7 +741,16 @@ hipError_t launch_attn_dedup_mfma(const ModelDims& m,
         big_lds(kern, sm);
         hipLaunchKernelGGL(kern, dim3(g), dim3(kAT), sm, st, m, d, ctr);
     };
-    if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
+    if (m.enc) {                        // bidirectional encoder
+        if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
+            go(k_attn_dedup_mfma<16, 3, false>);
+        else if (m.dh == 16)
+            go(k_attn_dedup_mfma<16, 1, false>);
+        else if (m.dh == 32)
+            go(k_attn_dedup_mfma<32, 1, false>);
+        else
+            return hipErrorInvalidValue;
+    } else if (m.dh == 16 && attn_wg_per_cu(m) >= 3)
         go(k_attn_dedup_mfma<16, 3>);
     else if (m.dh == 16)
         go(k_attn_dedup_mfma<16, 1>);

@@ -64,7 +64,6 @@ def _cfg(**kw):
     (dict(group=-1), 2),
     (dict(encoder=2), 2),
     (dict(encoder=1, attn_tail=1), 2),    # the half-block is a decoder's
-    (dict(encoder=1, precision=2), 5),    # the encoder runs in FP64/FP32
     (dict(encoder=1, flags=2), 5),        # no rank-|C| attention update
 ])
 def test_invalid_configs_rejected(kw, status):

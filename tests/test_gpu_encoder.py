@@ -14,6 +14,10 @@ to a scalar) on the GPU against the FP64 oracle, through the C ABI.
 * FP32 10x10, tokens of 4: every ratio within 1e-4 of the oracle or a proven
   near-tie; log psi within 1e-4 (or a proven near-tie) and the gradient of
   three samples per tensor within the FP32 bound.
+* BF16 on the matrix core (6x6, d=128, tokens of 1 and of 4 spins): log
+  psi within 1e-3 of the oracle on every sequence without a quantizer
+  near-tie, the dedup form equal to the plain one, sampled ratios within
+  1e-3 or proven near-ties, the gradient per tensor within the BF16 bound.
 * Direct sampling and the VMC step need an autoregressive network: both
   report VQNQS_ERR_UNSUPPORTED for the encoder.
 """
@@ -32,8 +36,8 @@ from oracle import tfim
 from workloads import CONFIGS, make_params, make_spins, with_batch
 
 from gpu_common import dev_params, dev_spins, host, needs_gpu, say
-from gpu_parity import (FP32_BLOCK_TOL, check_blocks, check_ratios,
-                        check_sequences)
+from gpu_parity import (BF16_BLOCK_TOL, FP32_BLOCK_TOL, check_blocks,
+                        check_ratios, check_sequences)
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -127,3 +131,33 @@ def test_encoder_sampling_and_vmc_rejected():
     with pytest.raises(vq.VQNQSError) as e:
         vq.vmc_step(cfg, p, u, 1e-3)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("group", [1, 4], ids=["K1", "K4"])
+def test_encoder_bf16_matrix_core(group):
+    mc = replace(CONFIGS["small"], name=f"enc_bf16_g{group}", L=6, d_model=128,
+                 n_layers=2, n_heads=8, d_ff=512, codebook_size=64,
+                 precision="bf16", encoder=True, group=group, batch=12,
+                 spin_seed=1801 + group)
+    say(f"encoder bf16 6x6 K={group}")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    P = net.unpack(mc, theta)
+    flips, _ = check_sequences(mc, P, cfg, p, s, 1e-3)
+    a = vq.local_energy(cfg, p, sp, vq.PLAIN, ratios=True)
+    b = vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)
+    assert np.allclose(host(b["ratios"]), host(a["ratios"]), rtol=1e-12, atol=0)
+    R = host(b["ratios"])
+    bl = lattice.bonds(mc.L, mc.periodic)
+    picks = [(k, range(len(lattice.neighbours(s[k], bl)))) for k in range(4)]
+    rel, explained = check_ratios(mc, P, cfg, p, s, R, picks, 1e-3)
+    say(f"encoder bf16 ratios: median {np.median(rel):.2e} max {rel.max():.2e}, "
+        f"{len(explained)} explained")
+    g = host(vq.grad_logpsi(cfg, p, sp)).astype(np.float64)
+    idx = [k for k in range(mc.batch) if k not in flips][:3]
+    assert idx
+    ref = og.grad_logpsi(mc, theta, s[idx])
+    for j, k in enumerate(idx):
+        check_blocks(mc, g[k], ref[j], BF16_BLOCK_TOL, f"encoder bf16 sample {k}")

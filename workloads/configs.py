@@ -118,6 +118,12 @@ CONFIGS["large_g4"] = replace(CONFIGS["large"], name="large_g4", group=4,
 CONFIGS["small_g4"] = replace(CONFIGS["small"], name="small_g4", group=4,
                               batch=64, spin_seed=1010)
 
+# The bidirectional encoder with mean pooling as log psi (Sec. 3.1) at the
+# 16x16 model's sizes: every row attends to every position, so a neighbour
+# re-attends all rows.
+CONFIGS["large_enc"] = replace(CONFIGS["large"], name="large_enc", encoder=True,
+                               spin_seed=1014)
+
 # Mixed-lattice batch: one parameter buffer per lattice, uneven sample counts.
 MULTI_LATTICE = tuple(
     ModelConfig(f"multi_L{L}", L=L, d_model=128, n_layers=6, n_heads=8,
