@@ -726,20 +726,20 @@ __device__ inline float score_err_split(int n, float na, float wmax) {
 // after a head's last chunk the first chunk of the next head (or of the
 // next tile's first head) when the chunk count is even.  A chunk starts with
 // this wave's loads complete and a barrier, after which every wave has also
-// finished reading the other stage, which then takes the next chunk.  Eight
-// code blocks per chunk (two workgroups per CU by LDS) took 10% less time
-// than four (three per CU): the per-chunk wait and barrier cost more than
-// the third workgroup hides.
+// finished reading the other stage, which then takes the next chunk.  For
+// a large codebook, eight code blocks per chunk (two workgroups per CU by
+// LDS) took 10% less time than four (three per CU): the per-chunk wait and
+// barrier cost more than the third workgroup hides.
 // Every codebook fragment read from LDS feeds MB MFMAs, and MB more when
 // the block gets its lo products.  The second-best value (for the
 // certified-reuse margins) is tracked only when MARGIN, which searches
 // every block in full; the chosen code is the same either way.
-template <int KBS, int MB, bool MARGIN>
+template <int KBS, int MB, bool MARGIN, int CBK, bool SEED>
 __global__ void __launch_bounds__(kMT)
     __attribute__((amdgpu_waves_per_eu(MB <= 2 && !MARGIN ? 3 : 1)))
     k_vq_mfma(ModelDims m, LayerW<float> w, RowSet rows, BlockIO<PrecBF16> io,
               const bf16x8* __restrict__ cbp, VqSeed seed) {
-    constexpr int DS = KBS * 32, WR = MB * 16, CBK = 8;
+    constexpr int DS = KBS * 32, WR = MB * 16;
     constexpr int CHUNK = CBK * KBS * 64;       // fragment lanes per chunk
     constexpr int PER = CHUNK / kMT;             // per thread
     constexpr int CN = CBK * 16;                 // code norms per chunk
@@ -822,7 +822,9 @@ __global__ void __launch_bounds__(kMT)
             // (the argmax of the same hi-then-lo sums, lowest index on equal
             // values) is the one the full search finds.  Unseeded: -inf.
             float ut[MB];
-            {
+#pragma unroll
+            for (int i = 0; i < MB; ++i) ut[i] = -inf;
+            if constexpr (SEED) {
                 const float wmx = w.cnorm[(int64_t)m.H * m.Q + hq];
 #pragma unroll
                 for (int i = 0; i < MB; ++i) {
@@ -1300,12 +1302,31 @@ static void vq_go(const ModelDims& m, const LayerW<float>& w, RowSet rows,
                   const VqSeed& seed, hipStream_t st) {
     constexpr int R = 64 * MB;    // 16*MB rows per wave, 4 waves
     const dim3 g(mgrid((rows.n_host + R - 1) / R));
-    if (io.margin)
-        hipLaunchKernelGGL((k_vq_mfma<KBS, MB, true>), g, dim3(kMT), 0, st, m, w,
-                           rows, io, cb, VqSeed{});
-    else
-        hipLaunchKernelGGL((k_vq_mfma<KBS, MB, false>), g, dim3(kMT), 0, st, m,
-                           w, rows, io, cb, seed);
+    // Large codebooks with segments of up to 128: eight code blocks per LDS
+    // chunk (32 KB per stage at 128) and, for neighbour rows, the search
+    // seeded with the sample's code.  Small codebooks (fewer than 256 codes,
+    // a handful of blocks) and segments of 256: four blocks per chunk and no
+    // seed, whose set-up per row tile would cost more than it saves (and its
+    // registers, at segment 256, a wave per SIMD).
+    constexpr int CB8 = KBS <= 4 ? 8 : 4;
+    const bool big = m.Q >= 256;
+    if (io.margin) {
+        if (big)
+            hipLaunchKernelGGL((k_vq_mfma<KBS, MB, true, CB8, false>), g, dim3(kMT), 0,
+                               st, m, w, rows, io, cb, VqSeed{});
+        else
+            hipLaunchKernelGGL((k_vq_mfma<KBS, MB, true, 4, false>), g, dim3(kMT), 0,
+                               st, m, w, rows, io, cb, VqSeed{});
+    } else if (big && KBS <= 4 && seed.slot_nb) {
+        hipLaunchKernelGGL((k_vq_mfma<KBS, MB, false, CB8, KBS <= 4>), g, dim3(kMT), 0,
+                           st, m, w, rows, io, cb, seed);
+    } else if (big) {
+        hipLaunchKernelGGL((k_vq_mfma<KBS, MB, false, CB8, false>), g, dim3(kMT), 0,
+                           st, m, w, rows, io, cb, VqSeed{});
+    } else {
+        hipLaunchKernelGGL((k_vq_mfma<KBS, MB, false, 4, false>), g, dim3(kMT), 0, st,
+                           m, w, rows, io, cb, VqSeed{});
+    }
 }
 
 hipError_t launch_vq_mfma(const ModelDims& m, const LayerW<float>& w,
