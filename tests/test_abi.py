@@ -87,6 +87,13 @@ def test_encoder_param_count_matches_layout(group):
     assert param_count(dec) - param_count(mc) == mc.d_model + (V - 1) * (mc.d_model + 1)
 
 
+def test_gelu_probe_host_errors():
+    lib = vq.load_library()
+    assert lib.vqnqs_probe_gelu(None, None, 0, None) == 0
+    assert lib.vqnqs_probe_gelu(None, None, -1, None) == 3
+    assert lib.vqnqs_probe_gelu(None, None, 4, None) == 1
+
+
 def test_open_odd_lattice_allowed():
     c = _cfg(L=5, periodic=0)
     assert vq.param_count(c) > 0
