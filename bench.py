@@ -455,6 +455,70 @@ def bench_sample(args, vq, torch, np, mc, make_params):
         "kernels": per_kernel}))
 
 
+def bench_vmc(args, vq, torch, np, mc, make_params):
+    """One VMC step of the whole batch (direct samples, their local energies
+    in the dedup form, the energy gradient of eq. (3) through the
+    straight-through estimator, an Adam update of the parameters), every
+    stage on the device; fresh uniform numbers per step.  One JSON line."""
+    B, N = mc.batch, mc.N
+    dev = torch.device("cuda:0")
+    theta = make_params(mc)
+    dt_param = torch.float64 if mc.precision == "f64" else torch.float32
+    p = torch.tensor(theta, dtype=dt_param, device=dev)
+    opt = torch.zeros((2, p.numel()), dtype=dt_param, device=dev)
+    cfg = vq.make_config(mc)
+    gen = torch.Generator().manual_seed(11)
+    us = [torch.rand((B, N), dtype=torch.float64, generator=gen).to(dev)
+          for _ in range(args.warmup + args.steps)]
+    need = vq.workspace_size(cfg, B, vq.WS_VMC, 0)
+    ws = torch.empty(min(need, int(args.ws_gb * (1 << 30))),
+                     dtype=torch.uint8, device=dev)
+    out = {"spins": torch.empty((B, N), dtype=torch.int8, device=dev),
+           "eloc": torch.empty(B, dtype=torch.float64, device=dev),
+           "stats": torch.empty(2, dtype=torch.float64, device=dev)}
+    energies = []
+    k = 0
+    for _ in range(args.warmup):
+        k += 1
+        vq.vmc_step(cfg, p, us[k - 1], 1e-3, opt, step=k, ws=ws, check=False,
+                    out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    vq.profile_reset()
+    vq.profile_enable(True)
+    e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    e0.record(stream)
+    for _ in range(args.steps):
+        k += 1
+        vq.vmc_step(cfg, p, us[k - 1], 1e-3, opt, step=k, ws=ws, check=False,
+                    out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    vq.profile_enable(False)
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = vq.profile_read()
+    vq.api._check_status(ws)
+    per_kernel = {k2: {"ms_per_step": v[0] / args.steps,
+                       "launches_per_step": v[1] / args.steps}
+                  for k2, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    st = out["stats"].cpu().numpy().tolist()
+    print(json.dumps({
+        "metric": "VMC steps/sec (direct samples, dedup local energy, "
+                  "straight-through energy gradient, Adam), 1 MI355X",
+        "value": 1e3 / ms, "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "samples_per_s": B / (ms / 1e3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": mc.precision, "data": "synthetic",
+        "config": {"workload": f"{mc.L}x{mc.L}, VQ transformer "
+                               f"d={mc.d_model} L={mc.n_layers} "
+                               f"heads={mc.n_heads} mlp={mc.d_ff} "
+                               f"Q={mc.codebook_size}, {B} samples per step",
+                   "batch": B},
+        "last_step_energy": {"mean": st[0], "variance": st[1]},
+        "kernels": per_kernel}))
+
+
 def bench_sweep(args, vq, torch, np, mc, make_params, make_spins):
     """Redundancy sweep: every codebook scaled by alpha (a larger codebook
     scale makes the codes less sensitive to a changed input), dedup with and
@@ -538,12 +602,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="large")
     ap.add_argument("--workload", default="eloc",
-                    choices=["eloc", "grad", "multi", "sweep", "sample"],
+                    choices=["eloc", "grad", "multi", "sweep", "sample",
+                             "vmc"],
                     help="eloc: local energy (default); grad: weighted "
                          "straight-through gradient of the 20x20 workload; "
                          "multi: mixed-lattice batch in one call; sweep: "
                          "codebook-scale redundancy sweep; sample: direct "
-                         "autoregressive sampling")
+                         "autoregressive sampling; vmc: one VMC step")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--flags", type=int, default=0,
@@ -597,6 +662,9 @@ def main():
         return
     if args.workload == "sample":
         bench_sample(args, vq, torch, np, mc, make_params)
+        return
+    if args.workload == "vmc":
+        bench_vmc(args, vq, torch, np, mc, make_params)
         return
     B = mc.batch
     dev = torch.device("cuda:0")
