@@ -6,6 +6,7 @@ import numpy as np
 import paper_2212_11296_amd as vq
 from oracle import lattice
 from oracle import network as net
+from oracle import tfim
 from workloads import param_layout
 
 from gpu_common import dev_spins, host, say
@@ -43,15 +44,19 @@ def check_sequences(mc, P, cfg, p, seqs, logpsi_tol):
 def check_ratios(mc, P, cfg, p, spins, R, picks, tol):
     """Compares R[b][k] with the oracle for (b, ks) in picks; an entry beyond
     tol must come from a proven near-tie of the neighbour's or the sample's
-    codes.  Returns (relative errors, explained (b, k) pairs)."""
-    bl = lattice.bonds(mc.L, mc.periodic)
+    codes.  Returns (relative errors, explained (b, k) pairs).  Neighbour k
+    is the k-th swapped antiparallel bond of the Heisenberg lattice, or the
+    flip of site k on the transverse-field Ising chain."""
+    chain = mc.hamiltonian == "tfim"
+    bl = None if chain else lattice.bonds(mc.L, mc.periodic)
     seqs, owner = [], []
     for b, ks in picks:
-        nb = lattice.neighbours(spins[b], bl)
+        nb = None if chain else lattice.neighbours(spins[b], bl)
         seqs.append(spins[b])
         owner.append((b, -1))
         for k in ks:
-            seqs.append(lattice.swap(spins[b], nb[k][1], nb[k][2]))
+            seqs.append(tfim.flip(spins[b], k) if chain else
+                        lattice.swap(spins[b], nb[k][1], nb[k][2]))
             owner.append((b, k))
     seqs = np.stack(seqs)
     ref = net.forward(mc, P, seqs, keep=True)

@@ -18,6 +18,11 @@ to a scalar) on the GPU against the FP64 oracle, through the C ABI.
   psi within 1e-3 of the oracle on every sequence without a quantizer
   near-tie, the dedup form equal to the plain one, sampled ratios within
   1e-3 or proven near-ties, the gradient per tensor within the BF16 bound.
+* BF16 on the matrix core, chain of 64 sites of the transverse-field Ising
+  model (open with tokens of 1, periodic with tokens of 4): log psi within
+  1e-3 or proven near-ties, dedup equal to plain, the local energy
+  assembled as eq. (2) says, sampled flip ratios within 1e-3 or proven
+  near-ties.
 * Direct sampling and the VMC step need an autoregressive network: both
   report VQNQS_ERR_UNSUPPORTED for the encoder.
 """
@@ -161,3 +166,30 @@ def test_encoder_bf16_matrix_core(group):
     ref = og.grad_logpsi(mc, theta, s[idx])
     for j, k in enumerate(idx):
         check_blocks(mc, g[k], ref[j], BF16_BLOCK_TOL, f"encoder bf16 sample {k}")
+
+
+@pytest.mark.parametrize("group,periodic", [(1, False), (4, True)],
+                         ids=["K1-open", "K4-periodic"])
+def test_encoder_bf16_tfim_chain(group, periodic):
+    mc = replace(CONFIGS["tfim"], name=f"enc_tfim_bf16_g{group}", L=64,
+                 d_model=128, n_layers=2, d_ff=512, encoder=True, group=group,
+                 periodic=periodic, batch=16, spin_seed=1811 + group)
+    say(f"encoder bf16 chain of 64 K={group} periodic={periodic}")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    P = net.unpack(mc, theta)
+    check_sequences(mc, P, cfg, p, s, 1e-3)
+    a = vq.local_energy(cfg, p, sp, vq.PLAIN, ratios=True)
+    b = vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)
+    assert np.allclose(host(b["ratios"]), host(a["ratios"]), rtol=1e-12, atol=0)
+    E, R = host(b["eloc"]), host(b["ratios"])
+    diag = tfim.diagonal(s, mc.N, periodic, mc.J)
+    assert np.allclose(E, diag - mc.gamma * R[:, :mc.N].sum(1), rtol=1e-12,
+                       atol=1e-12)
+    rng = np.random.default_rng(group)
+    picks = [(k, sorted(rng.choice(mc.N, 12, replace=False))) for k in range(3)]
+    rel, explained = check_ratios(mc, P, cfg, p, s, R, picks, 1e-3)
+    say(f"encoder bf16 chain ratios: median {np.median(rel):.2e} "
+        f"max {rel.max():.2e}, {len(explained)} explained")

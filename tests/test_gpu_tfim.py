@@ -24,7 +24,7 @@ from oracle import grad as ograd
 from workloads import CONFIGS, make_params, make_spins, with_batch
 
 from gpu_common import dev_params, dev_spins, host, needs_gpu, say
-from near_tie import explain
+from gpu_parity import check_ratios
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -77,7 +77,7 @@ def test_tfim_bf16_paper_chain_full_batch():
             1e-12 * max(1.0, abs(E[b]))
         picks.append((int(b), sorted(rng.choice(mc.N, 8, replace=False))))
 
-    rel, explained = _check_chain_ratios(mc, P, cfg, p, s, R, picks)
+    rel, explained = check_ratios(mc, P, cfg, p, s, R, picks, 1e-3)
     say(f"tfim bf16 ratios: max {rel.max():.2e}, {len(explained)} explained")
     small = with_batch(mc, 4)
     s4 = dev_spins(s[:4])
@@ -86,39 +86,6 @@ def test_tfim_bf16_paper_chain_full_batch():
     rb = host(vq.local_energy(vq.make_config(small), p, s4, vq.DEDUP,
                               ratios=True)["ratios"])
     assert np.allclose(rb, ra, rtol=1e-12, atol=0)
-
-
-def _check_chain_ratios(mc, P, cfg, p, spins, R, picks):
-    seqs, owner = [], []
-    for b, ks in picks:
-        seqs.append(spins[b])
-        owner.append((b, -1))
-        for k in ks:
-            seqs.append(tfim.flip(spins[b], k))
-            owner.append((b, k))
-    seqs = np.stack(seqs)
-    ref = net.forward(mc, P, seqs, keep=True)
-    lp0 = {b: ref["logpsi"][j] for j, (b, k) in enumerate(owner) if k < 0}
-    rel = np.array([abs(R[b, k] / np.exp(ref["logpsi"][j] - lp0[b]) - 1)
-                    if k >= 0 else 0.0 for j, (b, k) in enumerate(owner)])
-    bad = [j for j, (b, k) in enumerate(owner) if k >= 0 and rel[j] > 1e-3]
-    explained = []
-    if bad:
-        _, gcd, gat = vq.forward_activations(cfg, p, dev_spins(seqs))
-        gcd, gat = host(gcd), host(gat)
-        ocd = np.transpose(ref["codes"], (1, 0, 2, 3))
-        cbs = [lay["codebook"] for lay in P["layers"]]
-        for j in bad:
-            b, k = owner[j]
-            js = owner.index((b, -1))
-            exs = [explain(cbs, gcd[jj], gat[jj], ocd[jj],
-                           np.stack([c["a"][jj] for c in ref["caches"]]))
-                   for jj in (js, j)]
-            say(f"tfim ({b},{k}) rel err {rel[j]:.3e}: {exs}")
-            found = [e for e in exs if e is not None]
-            assert found and all(e["ok"] for e in found), ((b, k), exs)
-            explained.append((b, k))
-    return rel[[k >= 0 for _, k in owner]], explained
 
 
 def test_tfim_vmc_step_fp64_equals_oracle():
