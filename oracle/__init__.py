@@ -41,7 +41,12 @@ Pins (tests/test_oracle_*.py):
   encoder: the closed form for zero weights but the head bias, symmetry
     under token permutations without position embeddings, bidirectional
     attention, dedup = plain, central differences.
-  The absolute value of log psi for a random network has no external value to
-  compare against ("parity unpinned" beyond the structural pins above).
+  whole network: closed forms from library routines where the blocks pass
+    their input through (output projection and second MLP matrix at zero)
+    and where every attention score is zero (query and key projections at
+    zero: attention is the running mean of the values), for the decoder with
+    and without the attention-only half-block, tokens of 1, 2 and 4 spins,
+    and the encoder; a dropped residual, a shifted mask, LN2 on the wrong
+    stream, a missing input shift or pooling before the final LN fail them.
 """
 from . import lattice, network, eloc, ed  # noqa: F401
