@@ -18,11 +18,11 @@ to a scalar) on the GPU against the FP64 oracle, through the C ABI.
   psi within 1e-3 of the oracle on every sequence without a quantizer
   near-tie, the dedup form equal to the plain one, sampled ratios within
   1e-3 or proven near-ties, the gradient per tensor within the BF16 bound.
-* BF16 on the matrix core, chain of 64 sites of the transverse-field Ising
-  model (open with tokens of 1, periodic with tokens of 4): log psi within
-  1e-3 or proven near-ties, dedup equal to plain, the local energy
-  assembled as eq. (2) says, sampled flip ratios within 1e-3 or proven
-  near-ties.
+* BF16 on the matrix core, transverse-field Ising chains: 64 sites at head
+  width 16 (open with tokens of 1, periodic with tokens of 4) and 32, and
+  400 sites at head width 16 (two workgroups per CU): log psi within 1e-3
+  or proven near-ties, dedup equal to plain, the local energy assembled as
+  eq. (2) says, sampled flip ratios within 1e-3 or proven near-ties.
 * Direct sampling and the VMC step need an autoregressive network: both
   report VQNQS_ERR_UNSUPPORTED for the encoder.
 """
@@ -168,13 +168,22 @@ def test_encoder_bf16_matrix_core(group):
         check_blocks(mc, g[k], ref[j], BF16_BLOCK_TOL, f"encoder bf16 sample {k}")
 
 
-@pytest.mark.parametrize("group,periodic", [(1, False), (4, True)],
-                         ids=["K1-open", "K4-periodic"])
-def test_encoder_bf16_tfim_chain(group, periodic):
-    mc = replace(CONFIGS["tfim"], name=f"enc_tfim_bf16_g{group}", L=64,
-                 d_model=128, n_layers=2, d_ff=512, encoder=True, group=group,
-                 periodic=periodic, batch=16, spin_seed=1811 + group)
-    say(f"encoder bf16 chain of 64 K={group} periodic={periodic}")
+# (sites, width, tokens of K, periodic): head width 16 with three
+# workgroups per CU, head width 32, and head width 16 at 400 tokens, whose
+# LDS tiles leave room for two workgroups per CU (the uncapped kernel)
+CHAINS = [(64, 128, 1, False), (64, 128, 4, True), (64, 256, 1, True),
+          (400, 128, 1, False)]
+
+
+@pytest.mark.parametrize("L,d,group,periodic", CHAINS,
+                         ids=["64-dh16-K1-open", "64-dh16-K4-periodic",
+                              "64-dh32-K1-periodic", "400-dh16-K1-open"])
+def test_encoder_bf16_tfim_chain(L, d, group, periodic):
+    mc = replace(CONFIGS["tfim"], name=f"enc_tfim_bf16_{L}_{d}_g{group}", L=L,
+                 d_model=d, n_layers=2, d_ff=4 * d, encoder=True, group=group,
+                 periodic=periodic, batch=16 if L <= 64 else 6,
+                 spin_seed=1811 + group + L + d)
+    say(f"encoder bf16 chain of {L} d={d} K={group} periodic={periodic}")
     theta = make_params(mc)
     s = make_spins(mc)
     cfg = vq.make_config(mc)
