@@ -17,6 +17,10 @@ precision, through the C ABI.
   16x16 and 20x20 eight seeded neighbours, each ratio within 1e-3 of the
   oracle or a proven near-tie, and the local energy assembled from the
   ratios exactly as eq. (2) says.
+* The 20x20 gradient workload (d=256, 12 layers, MLP 1024, Q=1024, BF16)
+  as a local-energy call: dedup equal to plain, seeded ratios of two
+  samples within 1e-3 of the oracle or proven near-ties, every local energy
+  assembled as eq. (2) says.
 * BF16 at parameters that are not bfloat16 numbers (FP32 masters from the
   same seeded generator): the library rounds them to bfloat16, the oracle
   evaluates the unrounded ones, so the difference is the cost of the BF16
@@ -158,3 +162,37 @@ def test_bf16_unrounded_fp32_master_parameters_reported():
         f"same parameters: {errs}")
     assert errs["bf16_exact"][0] < 1e-3
     assert errs["fp32_master"][0] < 5e-2
+
+
+def test_grad_workload_20x20_local_energy_sampled():
+    """The 20x20 gradient workload (d=256, 12 layers, 8 heads, MLP 1024,
+    Q=1024, BF16) as a local-energy call: the deduplicated form equal to the
+    plain one, two samples' seeded neighbours within 1e-3 of the oracle or
+    proven near-ties, and every local energy assembled as eq. (2) says
+    (Marshall-rotated: diag - J/2 sum of the ratios)."""
+    mc = with_batch(CONFIGS["grad"], 4)
+    assert mc.precision == "bf16" and mc.L == 20 and mc.marshall
+    say("20x20 d=256 bf16 local energy vs oracle (sampled)")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    a = vq.local_energy(cfg, p, sp, vq.DEDUP, ratios=True)
+    b = vq.local_energy(cfg, p, sp, vq.PLAIN, ratios=True)
+    E, R = host(a["eloc"]), host(a["ratios"])
+    assert np.allclose(R, host(b["ratios"]), rtol=1e-12, atol=0)
+    assert np.allclose(E, host(b["eloc"]), rtol=1e-12, atol=0)
+    bl = lattice.bonds(mc.L, mc.periodic)
+    for k in range(mc.batch):
+        nb = lattice.neighbours(s[k], bl)
+        diag = lattice.diagonal(s[k:k + 1], bl, mc.J)[0]
+        assert np.all(R[k, len(nb):] == 0)
+        assert abs(E[k] - (diag - 0.5 * mc.J * R[k, :len(nb)].sum())) <= \
+            1e-12 * max(1.0, abs(E[k]))
+    rng = np.random.default_rng(20)
+    picks = [(k, sorted(rng.choice(len(lattice.neighbours(s[k], bl)), 10,
+                                   replace=False))) for k in range(2)]
+    P = net.unpack(mc, theta)
+    rel, explained = check_ratios(mc, P, cfg, p, s, R, picks, BF16_RATIO_TOL)
+    say(f"20x20 ratios: n={rel.size} median={np.median(rel):.2e} "
+        f"max={rel.max():.2e}, {len(explained)} explained")
