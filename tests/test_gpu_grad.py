@@ -122,6 +122,26 @@ def test_grad_bf16_grad_shapes_sampled():
         check_blocks(mc, g[b], ref[j], BF16_BLOCK_TOL, f"bf16 sample {b}")
 
 
+def test_grad_bf16_chain_four_quantizer_heads():
+    """The paper's chain network (384 sites, d=256, one layer, 8 heads, a
+    quantizer of 4 heads x 64 codes): the straight-through gradient with
+    several quantizer heads, per tensor against the oracle."""
+    mc = with_batch(CONFIGS["tfim"], 4)
+    assert mc.vq_heads == 4 and mc.precision == "bf16"
+    say("grad bf16 chain of 384, 4 quantizer heads")
+    theta = make_params(mc)
+    s = make_spins(mc)
+    cfg = vq.make_config(mc)
+    p, sp = dev_params(theta, "bf16"), dev_spins(s)
+    g = host(vq.grad_logpsi(cfg, p, sp)).astype(np.float64)
+    flips, _ = check_sequences(mc, net.unpack(mc, theta), cfg, p, s, 1e-3)
+    idx = [b for b in range(mc.batch) if b not in flips][:2]
+    assert len(idx) >= 1
+    ref = og.grad_logpsi(mc, theta, s[idx])
+    for j, b in enumerate(idx):
+        check_blocks(mc, g[b], ref[j], BF16_BLOCK_TOL, f"bf16 chain sample {b}")
+
+
 ODD_BF16 = replace(CONFIGS["medium"], name="odd_bf16", L=5, periodic=False,
                    d_model=64, n_layers=2, n_heads=4, d_ff=256,
                    codebook_size=64, precision="bf16", batch=3, spin_seed=2024)
