@@ -159,7 +159,7 @@ def _blocks_closed_form(cfg, P, x, causal):
     return x, np.stack(codes)
 
 
-@pytest.mark.parametrize("K,tail", [(1, False), (2, True)])
+@pytest.mark.parametrize("K,tail", [(1, False), (2, True), (4, False)])
 def test_uniform_attention_decoder(K, tail):
     cfg = _config(K, tail)
     P = _uniform_attention_params(cfg)
@@ -177,7 +177,7 @@ def test_uniform_attention_decoder(K, tail):
     assert all(len(np.unique(c)) > 1 for c in codes)
 
 
-@pytest.mark.parametrize("K", [1, 2])
+@pytest.mark.parametrize("K", [1, 2, 4])
 def test_uniform_attention_encoder(K):
     cfg = _config(K, encoder=True)
     P = _uniform_attention_params(cfg)
